@@ -1,0 +1,172 @@
+/*
+ * fastuot: fast radial-kernel summation on one MI355X (gfx950), and the unbalanced Sinkhorn and
+ * MMD computations built on it.
+ *
+ * Method: Lakshmanan & Pichler, "Unbalanced Optimal Transport and Maximum Mean Discrepancies:
+ * Interconnections and Rapid Evaluation" (arXiv 2306.13618).  The product computed everywhere is
+ * the kernel sum of eq. (fast_sum),
+ *        s_i = sum_j K(x_i - y_j) v_j,    K radial,
+ * evaluated either directly (O(n m)) or by NFFT fast summation (eq. (1724), Section "NFFT fast
+ * summation"): spreading of the weighted source nodes onto an oversampled grid with a
+ * Kaiser-Bessel window, an FFT, a pointwise product with the kernel's Fourier coefficients b_k,
+ * an inverse FFT and an interpolation (gather) at the target nodes, plus a near-field correction
+ * for the kernels that are not smooth at the origin.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller (HIP device memory, e.g. the data of
+ *    torch tensors), contiguous, row-major.  Points are float32 (count x d); weights float32;
+ *    dual potentials float64.  Outputs are preallocated by the caller.  Scalars written to
+ *    `*_host` pointers are host memory.
+ *  - `stream` is a hipStream_t (may be NULL for the default stream).  Work is enqueued on it;
+ *    calls that return a host scalar, and plan creation, synchronise that stream.
+ *  - The library allocates its own workspace (device memory) and keeps freed blocks in a cache
+ *    for reuse until fs_release_cache() or process exit.  Calls are not thread-safe.
+ *  - Return value: FS_OK (0) on success, a negative fs_status on failure; fs_last_error() then
+ *    describes the failure.  Outputs are unspecified after a failure.
+ *  - Parameters use the temperature convention: the Gibbs kernel of the transport cost |x-y|^r is
+ *    exp(-|x-y|^r / lambda), i.e. lambda here is the reciprocal of the paper's lambda (the paper
+ *    writes exp(-lambda d^r) with an inverse temperature, eq. (W4)).  rho is the paper's marginal
+ *    penalty eta (eta_1 = eta_2 = rho, Remark "hyperparameter tuning").
+ */
+#ifndef FASTUOT_H
+#define FASTUOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FS_OK = 0,
+    FS_EINVAL = -1,       /* bad argument (size, pointer, parameter out of range)           */
+    FS_EDOMAIN = -2,      /* points cannot be mapped into the torus / d unsupported          */
+    FS_ENOMEM = -3,       /* device allocation failed                                       */
+    FS_EHIP = -4,         /* a HIP runtime call or kernel launch failed                      */
+    FS_ENUMERIC = -5,     /* a kernel sum that must be positive was not (log of <= 0)        */
+    FS_EUNSUPPORTED = -6  /* combination not implemented                                     */
+} fs_status;
+
+/* Radial kernels (Table "prominent kernels" and eq. (1492)), r = |x - y| */
+enum {
+    FS_GAUSS = 0,   /* exp(-r^2 / lambda)  (lambda = ell^2 of the table)      */
+    FS_LAPLACE = 1, /* exp(-r / lambda)    (lambda = ell of the table)        */
+    FS_ENERGY = 2   /* -r                  (lambda unused)                    */
+};
+
+/* flags */
+#define FS_FLAG_WARM_START 0x1u   /* uot_sinkhorn: f and g hold starting potentials on entry     */
+#define FS_FLAG_FORCE_VALU 0x2u   /* direct path: use the FP32 VALU kernel even where MFMA applies */
+#define FS_FLAG_NO_NEARFIELD 0x4u /* skip the near-field correction (diagnostics only)          */
+
+/* Parameters of one kernel sum.  Zero-initialise and set what you need; zeros mean defaults. */
+typedef struct fs_params {
+    int kernel;              /* FS_GAUSS, FS_LAPLACE or FS_ENERGY                                 */
+    int grid;                /* oversampled FFT grid points per dimension (even, 16..512);
+                                0 selects direct summation                                         */
+    int window;              /* Kaiser-Bessel window cutoff m: support 2m grid points per dim,
+                                2..8 (0 -> 6)                                                      */
+    int oversampling;        /* sigma = grid / bandwidth N, integer >= 2 (0 -> 2)                 */
+    int smoothness;          /* p: derivatives matched by the regularisation polynomials (0 -> 8) */
+    unsigned flags;          /* FS_FLAG_*                                                         */
+    double lambda;           /* kernel width (see the kernel list); > 0 for Gauss and Laplace     */
+    double nearfield_radius; /* Laplace/energy: radius (data units) inside which the kernel is
+                                summed directly; 0 -> smoothness / bandwidth in torus units        */
+} fs_params;
+
+/* Opaque plan: two point sets mapped to the torus, binned by grid tile, and the kernel's
+ * Fourier multiplier.  Holds device workspace until fs_plan_destroy. */
+typedef struct fs_plan_s *fs_plan;
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *fs_last_error(void);
+
+/* Library version, (major << 16) | minor. */
+int fs_version(void);
+
+/* Release the cached workspace blocks (device memory) of the calling process. */
+void fs_release_cache(void);
+
+/* Kernel sum, eq. (fast_sum):  out_i = sum_j K(x_i - y_j) v_j,  i < n, j < m.
+ *   x (n x d), y (m x d), v (m), out (n): device, float32.  d in 1..3 for the fast path
+ *   (Section "Curse of dimensionality": the method is restricted to d <= 3); any d in 1..128 for
+ *   direct summation (grid = 0), where a Gaussian kernel with d a multiple of 16 uses the MFMA
+ *   Gram path (BF16 hi/lo split products accumulated in FP32) unless FS_FLAG_FORCE_VALU.
+ *   n = 0 or m = 0 is valid (out is zero-filled when m = 0). */
+int fastsum_apply(const float *x, int64_t n, const float *y, int64_t m, int d, const float *v,
+                  float *out, const fs_params *p, void *stream);
+
+/* Plans: fs_plan_create maps x (targets) and y (sources) to the torus and bins them (the plan
+ * keeps copies; the caller may free x and y afterwards).  fs_plan_apply computes
+ *   transpose = 0:  out (n) = K_xy v,  v of length m
+ *   transpose = 1:  out (m) = K_yx v,  v of length n
+ * with K symmetric (radial), so the transpose is the same operator with the roles swapped. */
+int fs_plan_create(const float *x, int64_t n, const float *y, int64_t m, int d,
+                   const fs_params *p, void *stream, fs_plan *plan_out);
+int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void *stream);
+void fs_plan_destroy(fs_plan plan);
+
+/* Unbalanced Sinkhorn, Algorithm 2 (the NFFT-accelerated form of Algorithm 1):
+ *   iters full sweeps; each sweep does the beta half-step then the gamma half-step,
+ *     f_i = -(rho lambda/(rho + lambda)) log sum_j k_ij b_j exp(g_j/lambda)
+ *     g_j = -(rho lambda/(rho + lambda)) log sum_i k_ij a_i exp(f_i/lambda)
+ *   with k_ij = exp(-|x_i - y_j|^r / lambda), r = 2 for FS_GAUSS and r = 1 for FS_LAPLACE
+ *   (eq. (Sinkhorn_uot_iteration) with the paper's lambda replaced by 1/lambda).
+ *   Starts from g = 0 (f = 0) unless FS_FLAG_WARM_START.  a (n), b (m): nonnegative weights.
+ *   f (n), g (m): device float64, the potentials beta and gamma of the paper.
+ *   objective_host (nullable): the dual value of Theorem "dualization" at (f, g), summed in FP64
+ *   with compensation.  The kernel sums run in FP32, the potential updates in FP64. */
+int uot_sinkhorn(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                 int64_t m, int d, const fs_params *p, double rho, int iters, double *f, double *g,
+                 double *objective_host, void *stream);
+
+/* Gradients of the UOT value at converged potentials (envelope theorem on the dual of Theorem
+ * "dualization"), scaled by `scale`:
+ *   dx_i = scale * sum_j pi_ij grad_x |x_i - y_j|^r,    pi_ij = a_i b_j exp((f_i + g_j - C_ij)/lambda)
+ *   da_i = scale * (rho (1 - exp(-f_i/rho)) - lambda sum_j b_j (exp((f_i + g_j - C_ij)/lambda) - 1))
+ *   and symmetrically dy, db.  Any of dx, da, dy, db may be NULL (not computed).  float32 outputs. */
+int uot_sinkhorn_grad(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                      int64_t m, int d, const fs_params *p, double rho, const double *f,
+                      const double *g, double scale, float *dx, float *da, float *dy, float *db,
+                      void *stream);
+
+/* Sinkhorn divergence, eq. (586):
+ *   S = UOT(a,b) - UOT(a,a)/2 - UOT(b,b)/2 + (lambda/2) (sum a - sum b)^2,
+ *   each UOT value the dual value after `iters` sweeps.  Potentials of the three problems are
+ *   written to f_ab (n), g_ab (m), f_aa (n), f_bb (m) (device float64; each may be NULL) for the
+ *   backward pass; terms3_host (nullable) receives the three UOT values. */
+int sinkhorn_divergence(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                        int64_t m, int d, const fs_params *p, double rho, int iters,
+                        double *f_ab, double *g_ab, double *f_aa, double *f_bb,
+                        double *value_host, double *terms3_host, void *stream);
+
+/* Gradient of the Sinkhorn divergence from the potentials written by sinkhorn_divergence
+ * (the symmetric problems contribute twice their one-slot envelope gradient), scaled by `scale`. */
+int sinkhorn_divergence_grad(const float *x, const float *a, int64_t n, const float *y,
+                             const float *b, int64_t m, int d, const fs_params *p, double rho,
+                             const double *f_ab, const double *g_ab, const double *f_aa,
+                             const double *f_bb, double scale, float *dx, float *da, float *dy,
+                             float *db, void *stream);
+
+/* Squared MMD, eq. (1205), as one kernel sum on the union z = (x, y) with weights w = (a, -b):
+ *   MMD^2 = sum_ij w_i w_j K(z_i - z_j)   (V-statistic, diagonal included; signed for the
+ *   energy kernel, which is only conditionally positive definite).  The final dot product is
+ *   summed in FP64 with compensation.  terms3_host (nullable) receives sum a a K, sum a b K,
+ *   sum b b K computed from the same kernel sum. */
+int mmd(const float *x, const float *a, int64_t n, const float *y, const float *b, int64_t m,
+        int d, const fs_params *p, double *mmd2_host, double *terms3_host, void *stream);
+
+/* Gradient of MMD^2, scaled by `scale`:
+ *   dx_i = 2 scale a_i [sum_j a_j gradK(x_i - x_j) - sum_j b_j gradK(x_i - y_j)],
+ *   da_i = 2 scale [sum_j a_j K(x_i - x_j) - sum_j b_j K(x_i - y_j)], and symmetrically for y, b
+ *   (with the sign of b).  Any output may be NULL.  float32 outputs. */
+int mmd_grad(const float *x, const float *a, int64_t n, const float *y, const float *b, int64_t m,
+             int d, const fs_params *p, double scale, float *dx, float *da, float *dy, float *db,
+             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTUOT_H */

@@ -1,0 +1,334 @@
+// extern "C" entry points of libfastuot (declared in include/fastuot.h).
+// Every entry point validates its arguments, runs the work on the caller's stream, converts
+// internal failures (fs::Error) into a negative fs_status and records the message.
+#include <algorithm>
+
+#include "solver.h"
+
+namespace fs {
+const char *last_error();
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_params(const fs_params *p) {
+    FS_REQUIRE(p != nullptr, FS_EINVAL, "params is NULL");
+    FS_REQUIRE(p->grid >= 0, FS_EINVAL, "grid must be >= 0");
+    FS_REQUIRE(p->window >= 0 && p->oversampling >= 0 && p->smoothness >= 0, FS_EINVAL,
+               "window, oversampling and smoothness must be >= 0");
+    FS_REQUIRE(p->nearfield_radius >= 0 && std::isfinite(p->nearfield_radius), FS_EINVAL,
+               "nearfield_radius must be finite and >= 0");
+}
+
+void check_points(const void *ptr, int64_t count, const char *name) {
+    FS_REQUIRE(count >= 0, FS_EINVAL, "%s: negative size", name);
+    FS_REQUIRE(count == 0 || ptr != nullptr, FS_EINVAL, "%s is NULL", name);
+    FS_REQUIRE(count < (int64_t(1) << 31), FS_EINVAL, "%s: more than 2^31 - 1 points", name);
+}
+
+void check_transport(const fs_params *p, double rho) {
+    FS_REQUIRE(p->kernel == FS_GAUSS || p->kernel == FS_LAPLACE, FS_EINVAL,
+               "transport uses the Gibbs kernel of |x-y|^2 (FS_GAUSS) or |x-y| (FS_LAPLACE)");
+    FS_REQUIRE(p->lambda > 0 && std::isfinite(p->lambda), FS_EINVAL, "lambda must be > 0");
+    FS_REQUIRE(rho > 0 && std::isfinite(rho), FS_EINVAL, "rho must be > 0");
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        clear_error();
+        f();
+        return FS_OK;
+    } catch (const Error &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return FS_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return FS_EHIP;
+    }
+}
+
+// Solve one UOT problem with a fresh operator; potentials returned in caller order.
+double solve_uot(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                 int64_t m, int d, const fs_params &p, double rho, int iters, bool warm,
+                 double *f, double *g, hipStream_t s) {
+    auto op = make_op(x, n, y, m, d, p, s);
+    DevBuf<float> ao(n + 1), bo(m + 1);
+    DevBuf<double> fo(n + 1), go(m + 1);
+    op->to_op(0, a, ao.p, s);
+    op->to_op(1, b, bo.p, s);
+    if (warm) {
+        op->to_op64(0, f, fo.p, s);
+        op->to_op64(1, g, go.p, s);
+    }
+    double obj = 0.0;
+    sinkhorn_solve(*op, ao.p, bo.p, p.lambda, rho, iters, warm, fo.p, go.p, &obj, s);
+    if (f) op->from_op64(0, fo.p, f, s);
+    if (g) op->from_op64(1, go.p, g, s);
+    FS_HIP(hipStreamSynchronize(s));
+    return obj;
+}
+
+}  // namespace
+
+}  // namespace fs
+
+using namespace fs;
+
+extern "C" {
+
+const char *fs_last_error(void) { return fs::last_error(); }
+
+int fs_version(void) { return (1 << 16) | 0; }
+
+void fs_release_cache(void) { ws_release_all(); }
+
+int fastsum_apply(const float *x, int64_t n, const float *y, int64_t m, int d, const float *v,
+                  float *out, const fs_params *p, void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_points(x, n, "x");
+        check_points(y, m, "y");
+        check_points(v, m, "v");
+        check_points(out, n, "out");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        hipStream_t s = as_stream(stream);
+        if (n == 0) return;
+        if (m == 0) {
+            fill_f32(out, n, 0.0f, s);
+            return;
+        }
+        auto op = make_op(x, n, y, m, d, *p, s);
+        if (op->fast) {
+            DevBuf<float> wo(m + 1), to(n + 1);
+            op->to_op(1, v, wo.p, s);
+            op->apply(wo.p, to.p, nullptr, 0, s);
+            op->from_op(0, to.p, out, s);
+            FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+        } else {
+            op->apply(v, out, nullptr, 0, s);
+            FS_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+struct fs_plan_s {
+    std::unique_ptr<Op> op;
+};
+
+int fs_plan_create(const float *x, int64_t n, const float *y, int64_t m, int d,
+                   const fs_params *p, void *stream, fs_plan *plan_out) {
+    return guarded([&] {
+        FS_REQUIRE(plan_out != nullptr, FS_EINVAL, "plan_out is NULL");
+        *plan_out = nullptr;
+        check_params(p);
+        check_points(x, n, "x");
+        check_points(y, m, "y");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        hipStream_t s = as_stream(stream);
+        auto pl = std::make_unique<fs_plan_s>();
+        pl->op = make_op(x, n, y, m, d, *p, s);
+        if (!pl->op->fast) {
+            // the direct path reads the points at apply time: keep private copies
+            pl->op->xcopy.alloc(n * d + 1);
+            if (n > 0)
+                FS_HIP(hipMemcpyAsync(pl->op->xcopy.p, x, n * d * sizeof(float), hipMemcpyDeviceToDevice, s));
+            pl->op->x = pl->op->xcopy.p;
+            if (pl->op->same) {
+                pl->op->y = pl->op->xcopy.p;
+            } else {
+                pl->op->ycopy.alloc(m * d + 1);
+                if (m > 0)
+                    FS_HIP(hipMemcpyAsync(pl->op->ycopy.p, y, m * d * sizeof(float), hipMemcpyDeviceToDevice, s));
+                pl->op->y = pl->op->ycopy.p;
+            }
+        }
+        FS_HIP(hipStreamSynchronize(s));
+        *plan_out = pl.release();
+    });
+}
+
+int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void *stream) {
+    return guarded([&] {
+        FS_REQUIRE(plan != nullptr && plan->op, FS_EINVAL, "plan is NULL");
+        Op &op = *plan->op;
+        const int64_t nt = transpose ? op.m : op.n, ns = transpose ? op.n : op.m;
+        check_points(v, ns, "v");
+        check_points(out, nt, "out");
+        hipStream_t s = as_stream(stream);
+        if (nt == 0) return;
+        if (ns == 0) {
+            fill_f32(out, nt, 0.0f, s);
+            return;
+        }
+        if (op.fast) {
+            DevBuf<float> wo(ns + 1), to(nt + 1);
+            op.to_op(transpose ? 0 : 1, v, wo.p, s);
+            op.apply(wo.p, to.p, nullptr, transpose, s);
+            op.from_op(transpose ? 1 : 0, to.p, out, s);
+            FS_HIP(hipStreamSynchronize(s));
+        } else {
+            op.apply(v, out, nullptr, transpose, s);
+        }
+    });
+}
+
+void fs_plan_destroy(fs_plan plan) { delete plan; }
+
+int uot_sinkhorn(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                 int64_t m, int d, const fs_params *p, double rho, int iters, double *f, double *g,
+                 double *objective_host, void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_transport(p, rho);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        check_points(f, n, "f");
+        check_points(g, m, "g");
+        FS_REQUIRE(iters >= 0, FS_EINVAL, "iters must be >= 0");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        const bool warm = (p->flags & FS_FLAG_WARM_START) != 0;
+        const double obj = solve_uot(x, a, n, y, b, m, d, *p, rho, iters, warm, f, g,
+                                     as_stream(stream));
+        if (objective_host) *objective_host = obj;
+    });
+}
+
+int uot_sinkhorn_grad(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                      int64_t m, int d, const fs_params *p, double rho, const double *f,
+                      const double *g, double scale, float *dx, float *da, float *dy, float *db,
+                      void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_transport(p, rho);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        check_points(f, n, "f");
+        check_points(g, m, "g");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        hipStream_t s = as_stream(stream);
+        auto op = make_op(x, n, y, m, d, *p, s);
+        uot_grad_core(*op, a, b, f, g, p->lambda, rho, scale, dx, da, dy, db, s);
+        FS_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int sinkhorn_divergence(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                        int64_t m, int d, const fs_params *p, double rho, int iters,
+                        double *f_ab, double *g_ab, double *f_aa, double *f_bb,
+                        double *value_host, double *terms3_host, void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_transport(p, rho);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        FS_REQUIRE(iters >= 0, FS_EINVAL, "iters must be >= 0");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        hipStream_t s = as_stream(stream);
+        fs_params q = *p;
+        q.flags &= ~FS_FLAG_WARM_START;
+        DevBuf<double> t1(n + 1), t2(m + 1), t3(n + 1), t4(n + 1), t5(m + 1), t6(m + 1);
+        double *fab = f_ab ? f_ab : t1.p, *gab = g_ab ? g_ab : t2.p;
+        double *faa = f_aa ? f_aa : t3.p, *fbb = f_bb ? f_bb : t5.p;
+        const double uab = solve_uot(x, a, n, y, b, m, d, q, rho, iters, false, fab, gab, s);
+        const double uaa = solve_uot(x, a, n, x, a, n, d, q, rho, iters, false, faa, t4.p, s);
+        const double ubb = solve_uot(y, b, m, y, b, m, d, q, rho, iters, false, fbb, t6.p, s);
+        const double Ma = device_sum(a, n, s), Mb = device_sum(b, m, s);
+        // eq. (586) with the paper's 1/lambda equal to the temperature lambda here
+        const double val = uab - 0.5 * uaa - 0.5 * ubb + 0.5 * p->lambda * (Ma - Mb) * (Ma - Mb);
+        if (value_host) *value_host = val;
+        if (terms3_host) {
+            terms3_host[0] = uab;
+            terms3_host[1] = uaa;
+            terms3_host[2] = ubb;
+        }
+    });
+}
+
+int sinkhorn_divergence_grad(const float *x, const float *a, int64_t n, const float *y,
+                             const float *b, int64_t m, int d, const fs_params *p, double rho,
+                             const double *f_ab, const double *g_ab, const double *f_aa,
+                             const double *f_bb, double scale, float *dx, float *da, float *dy,
+                             float *db, void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_transport(p, rho);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        check_points(f_ab, n, "f_ab");
+        check_points(g_ab, m, "g_ab");
+        check_points(f_aa, n, "f_aa");
+        check_points(f_bb, m, "f_bb");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        hipStream_t s = as_stream(stream);
+        const double Ma = device_sum(a, n, s), Mb = device_sum(b, m, s);
+        const double eps = p->lambda;
+        // d/d(x, a) of UOT(a,b) - UOT(a,a)/2: the self term moves both of its slots, which at the
+        // symmetric optimum is twice the one-slot envelope gradient, so the 1/2 cancels.
+        DevBuf<float> gx1(n * d + 1), ga1(n + 1), gx2(n * d + 1), ga2(n + 1);
+        DevBuf<float> gy1(m * d + 1), gb1(m + 1), gy2(m * d + 1), gb2(m + 1);
+        {
+            auto op = make_op(x, n, y, m, d, *p, s);
+            uot_grad_core(*op, a, b, f_ab, g_ab, eps, rho, 1.0, dx ? gx1.p : nullptr,
+                          da ? ga1.p : nullptr, dy ? gy1.p : nullptr, db ? gb1.p : nullptr, s);
+            FS_HIP(hipStreamSynchronize(s));
+        }
+        if (dx || da) {
+            auto op = make_op(x, n, x, n, d, *p, s);
+            uot_grad_core(*op, a, a, f_aa, f_aa, eps, rho, 1.0, dx ? gx2.p : nullptr,
+                          da ? ga2.p : nullptr, nullptr, nullptr, s);
+            FS_HIP(hipStreamSynchronize(s));
+        }
+        if (dy || db) {
+            auto op = make_op(y, m, y, m, d, *p, s);
+            uot_grad_core(*op, b, b, f_bb, f_bb, eps, rho, 1.0, dy ? gy2.p : nullptr,
+                          db ? gb2.p : nullptr, nullptr, nullptr, s);
+            FS_HIP(hipStreamSynchronize(s));
+        }
+        if (dx) combine(gx1.p, gx2.p, n * d, scale, -scale, 0.0, dx, s);
+        if (da) combine(ga1.p, ga2.p, n, scale, -scale, scale * eps * (Ma - Mb), da, s);
+        if (dy) combine(gy1.p, gy2.p, m * d, scale, -scale, 0.0, dy, s);
+        if (db) combine(gb1.p, gb2.p, m, scale, -scale, -scale * eps * (Ma - Mb), db, s);
+        FS_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int mmd(const float *x, const float *a, int64_t n, const float *y, const float *b, int64_t m,
+        int d, const fs_params *p, double *mmd2_host, double *terms3_host, void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        mmd_core(x, a, n, y, b, m, d, *p, mmd2_host, terms3_host, as_stream(stream));
+    });
+}
+
+int mmd_grad(const float *x, const float *a, int64_t n, const float *y, const float *b, int64_t m,
+             int d, const fs_params *p, double scale, float *dx, float *da, float *dy, float *db,
+             void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        mmd_grad_core(x, a, n, y, b, m, d, *p, scale, dx, da, dy, db, as_stream(stream));
+    });
+}
+
+}  // extern "C"

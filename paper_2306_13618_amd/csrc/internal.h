@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP sources of libfastuot (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fastuot.h"
+
+namespace fs {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    int code;
+};
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define FS_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::fs::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),     \
+                            __FILE__, __LINE__);                                       \
+            throw ::fs::Error{FS_EHIP};                                                \
+        }                                                                              \
+    } while (0)
+
+#define FS_REQUIRE(cond, code, ...)          \
+    do {                                     \
+        if (!(cond)) {                       \
+            ::fs::set_error(__VA_ARGS__);    \
+            throw ::fs::Error{code};         \
+        }                                    \
+    } while (0)
+
+#define FS_LAUNCHED() FS_HIP(hipGetLastError())
+
+// ------------------------------------------------------------------ workspace
+// Device allocations come from a per-process cache of freed blocks (exact-size reuse), so that
+// repeated solves do not pay for hipMalloc/hipFree.
+void *ws_alloc(size_t bytes);
+void ws_free(void *p);
+void ws_release_all();
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { reset(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void alloc(size_t count) {
+        reset();
+        n = count;
+        p = count ? static_cast<T *>(ws_alloc(count * sizeof(T))) : nullptr;
+    }
+    void ensure(size_t count) {
+        if (count > n) alloc(count);
+    }
+    void reset() {
+        if (p) ws_free(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *get() const { return p; }
+};
+
+// ------------------------------------------------------------------ launch helpers
+inline unsigned blocks_for(int64_t work, int threads, int64_t cap = 1 << 20) {
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return static_cast<unsigned>(b);
+}
+
+// Device fill (used instead of hipMemsetAsync so that callers may capture the work in a graph).
+void fill_f32(float *p, int64_t n, float v, hipStream_t s);
+void fill_f64(double *p, int64_t n, double v, hipStream_t s);
+void fill_i32(int *p, int64_t n, int v, hipStream_t s);
+
+// ------------------------------------------------------------------ Kaiser-Bessel window
+// Window in grid units (s = distance to the grid point times the grid size), cutoff m, shape b,
+// normalised to phi(0) = 1:
+//   phi(s) = [sinh(b q)/q] / [sinh(b m)/m],  q = sqrt(m^2 - s^2),  |s| < m;  0 otherwise.
+// The NFFT literature's form (1/pi) sinh(b q)/q differs by the constant factor; the Fourier
+// transform used for deconvolution is scaled consistently on the host.
+struct KB {
+    float m, b, inv_one_minus;  // inv_one_minus = 1/(1 - exp(-2 b m))
+};
+
+__device__ __forceinline__ float kb_phi(const KB &w, float s) {
+    float q2 = w.m * w.m - s * s;
+    q2 = fmaxf(q2, 0.0f);
+    float q = sqrtf(q2);
+    // sinh(bq)/sinh(bm) * m/q = exp(b(q - m)) * (1 - exp(-2bq)) / (1 - exp(-2bm)) * m / q
+    float e = __expf(w.b * (q - w.m));
+    float bq = w.b * q;
+    float ratio;  // (1 - exp(-2bq)) / q, with the q -> 0 limit 2b
+    if (bq > 1e-3f)
+        ratio = -expm1f(-2.0f * bq) / q;
+    else
+        ratio = 2.0f * w.b * (1.0f - bq);
+    return e * ratio * w.m * w.inv_one_minus;
+}
+
+// d phi / d s for the same window.
+__device__ __forceinline__ float kb_dphi(const KB &w, float s) {
+    float q2 = fmaxf(w.m * w.m - s * s, 0.0f);
+    float q = sqrtf(q2);
+    float bq = w.b * q;
+    float e = __expf(w.b * (q - w.m));
+    // phi = C e^{b(q-m)} (1 - e^{-2bq})/q,  C = m/(1-e^{-2bm})
+    // dphi/dq = C e^{b(q-m)} [ b(1+e^{-2bq})/q - (1-e^{-2bq})/q^2 ],  dq/ds = -s/q
+    float t;
+    if (bq > 0.1f) {
+        float em = __expf(-2.0f * bq);
+        t = (w.b * (1.0f + em) * q + expm1f(-2.0f * bq)) / (q2 * q);  // [b(1+e)q - (1-e)]/q^3
+    } else {
+        // [b(1+e)q - (1-e)] = 2 e^{-bq} (bq cosh bq - sinh bq) = 2 e^{-bq} ((bq)^3/3 + (bq)^5/30 + ..)
+        t = (2.0f / 3.0f) * w.b * w.b * w.b * __expf(-bq) * (1.0f + 0.1f * bq * bq);
+    }
+    return -s * e * t * w.m * w.inv_one_minus;
+}
+
+}  // namespace fs

@@ -1,0 +1,80 @@
+// NFFT fast summation plan (eq. (1724)): torus scaling, kernel regularisation and Fourier
+// multiplier, node binning, and the spread / FFT / gather / near-field passes.
+#pragma once
+#include "internal.h"
+
+namespace fs {
+
+// A point set mapped to the torus and sorted by grid tile.
+struct Nodes {
+    int64_t n = 0;
+    DevBuf<float4> rec;     // sorted: fractional grid offsets (x, y, z) and packed grid cell in .w
+    DevBuf<int> perm;       // sorted position -> original index
+    DevBuf<float> xs;       // sorted coordinates (n x d, data units)
+    DevBuf<int4> chunks;    // (tile, first node, node count, 0)
+    int nchunks = 0;
+    DevBuf<int> tile_chunk;  // per tile: [first chunk, chunk count]
+    // near-field cell list (sources only): cell-sorted index -> tile-sorted position
+    DevBuf<int> nf_cell_start;  // ncells + 1
+    DevBuf<int> nf_order;       // cell-sorted k -> tile-sorted position
+    DevBuf<float> nf_xs;        // cell-sorted coordinates
+};
+
+enum Regime { REGIME_CUBE = 0, REGIME_BALL = 1 };
+
+struct PlanParams {
+    int d = 0, kind = FS_GAUSS;
+    double lambda = 1.0;
+    int G = 0, N = 0, sigma = 2, m = 6, W = 12, p = 8;
+    int T = 8;          // tile side (grid points)
+    int chunk = 1024;   // nodes per spread/gather chunk
+    double P = 1.0;     // period in data units (torus unit)
+    double center[3] = {0, 0, 0};
+    int regime = REGIME_CUBE;
+    double epsI = 0.0;  // inner regularisation radius (torus units), 0 = none
+    double epsB = 0.0;  // boundary zone width (torus units), 0 = none
+    double ci[16] = {0};  // inner polynomial  sum_k ci[k] r^(2k), k < p   (torus units)
+    double cb[32] = {0};  // boundary polynomial sum_k cb[k] (r - 1/2)^k, k <= 2p-2
+    bool nearfield = false;
+    // near-field cell grid (data units)
+    double nf_h = 0.0;
+    int nf_dims[3] = {1, 1, 1};
+    double nf_lo[3] = {0, 0, 0};
+    KB kb{};
+};
+
+struct Plan {
+    PlanParams pp;
+    unsigned flags = 0;
+    Nodes X, Y;          // targets and sources (transpose swaps the roles)
+    bool same = false;   // Y is X (symmetric problems): Y aliases X
+    DevBuf<float> Mk;    // multiplier (N/2+1)^d
+    DevBuf<float> grid;  // G^d real
+    DevBuf<float2> specA, specB;
+    DevBuf<float2> twiddle;  // exp(-2 pi i q / G), q < G/2
+    DevBuf<float> scratch;   // per-chunk spread boxes
+    DevBuf<float> wbuf;      // sorted weights
+    DevBuf<float> tbuf;      // sorted sums
+    const Nodes &src(int transpose) const { return transpose ? X : (same ? X : Y); }
+    const Nodes &dst(int transpose) const { return transpose ? (same ? X : Y) : X; }
+};
+
+// Plan creation: x (n x d) targets, y (m x d) sources (y == x allowed: symmetric plan).
+void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, int d,
+                const fs_params &p, hipStream_t s);
+
+// Fast kernel sum in sorted order: w_sorted (source order) -> t_sorted (target order), float32.
+// transpose = 0: sources Y, targets X.  With `grad` != NULL also writes the gradient of the sum
+// with respect to the target position (n x d, data units).
+void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *grad,
+                       int transpose, hipStream_t s);
+
+// Permutations between caller order and a node set's sorted order.
+void gather_to_sorted(const Nodes &nd, const float *v, float *v_sorted, hipStream_t s);
+void scatter_from_sorted(const Nodes &nd, const float *v_sorted, float *v, hipStream_t s);
+void gather_to_sorted64(const Nodes &nd, const double *v, double *v_sorted, hipStream_t s);
+void scatter_from_sorted64(const Nodes &nd, const double *v_sorted, double *v, hipStream_t s);
+void scatter_rows_from_sorted(const Nodes &nd, const float *v_sorted, int d, float *v,
+                              hipStream_t s);
+
+}  // namespace fs

@@ -1,0 +1,1544 @@
+// NFFT fast summation (Section "NFFT fast summation", eq. (1724)) on gfx950.
+//
+//   s(x_i) ~= sum_k b_k ( sum_j alpha_j e^{-2 pi i k . y_j} ) e^{2 pi i k . x_i},  k in I_N
+//
+// evaluated as: spread the weighted sources onto an oversampled grid of G = sigma N points per
+// dimension with a Kaiser-Bessel window (adjoint NFFT), FFT, multiply by
+//   M_k = b_k / (G^{2d} phihat(k)^2)        (kernel coefficients and both window deconvolutions)
+// inside the band |k_i| <= N/2 (zero outside), inverse FFT, and interpolate at the targets with the
+// same window (NFFT).  Nodes are scaled to the torus [-1/2, 1/2)^d by x / P (eq. (boundaries)).
+//
+// Hardware mapping:
+//  * nodes are counting-sorted by grid tile (T^d points) once per plan; every spread/gather
+//    workgroup owns one chunk of a tile's nodes and the tile's padded box (T + 2m - 1)^d in LDS;
+//  * spreading accumulates into the LDS box with LDS float atomics (no global atomics); each lane
+//    walks its node's window in a lane-rotated order so lanes whose nodes share a cell hit
+//    different addresses; the boxes go to a scratch array and a fold pass sums, per grid point,
+//    the boxes that cover it in a fixed order;
+//  * FFTs are batched 1-D Stockham radix-2 transforms staged in LDS, one pass per axis, with the
+//    real-to-complex step done two rows at a time and the spectrum pruned to the band after the
+//    first forward pass of each axis; the multiply by M_k is fused between the forward and inverse
+//    transform of the last axis.
+#include <algorithm>
+#include <cstring>
+
+#include "nfft.h"
+
+namespace fs {
+
+// =====================================================================================
+//                                   host-side mathematics
+// =====================================================================================
+namespace {
+
+// Derivatives K^{(j)}(s), j < cnt, of the radial kernel in data units.
+void kernel_derivs(int kind, double lambda, double s, int cnt, double *out) {
+    if (kind == FS_GAUSS) {
+        // K(s) = exp(-u^2), u = s / sqrt(lambda):  d^j/ds^j = lambda^{-j/2} (-1)^j H_j(u) e^{-u^2}
+        // (Rodrigues' formula; H_{j+1} = 2u H_j - 2j H_{j-1}, H_0 = 1, H_{-1} = 0)
+        const double sl = std::sqrt(lambda), u = s / sl, e = std::exp(-u * u);
+        double hprev = 0.0, h = 1.0;
+        for (int j = 0; j < cnt; ++j) {
+            out[j] = ((j & 1) ? -1.0 : 1.0) * h * e / std::pow(sl, j);
+            const double hn = 2.0 * u * h - 2.0 * j * hprev;
+            hprev = h;
+            h = hn;
+        }
+    } else if (kind == FS_LAPLACE) {
+        const double e = std::exp(-s / lambda);
+        for (int j = 0; j < cnt; ++j) out[j] = std::pow(-1.0 / lambda, j) * e;
+    } else {
+        for (int j = 0; j < cnt; ++j) out[j] = (j == 0) ? -s : (j == 1 ? -1.0 : 0.0);
+    }
+}
+
+double kernel_value(int kind, double lambda, double s) {
+    double v;
+    kernel_derivs(kind, lambda, s, 1, &v);
+    return v;
+}
+
+// Solve A x = rhs (n <= 32) by Gaussian elimination with partial pivoting.
+void solve_dense(int n, std::vector<double> A, std::vector<double> rhs, double *x) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        FS_REQUIRE(std::fabs(A[piv * n + c]) > 0, FS_ENUMERIC, "singular regularisation system");
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(rhs[c], rhs[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            rhs[r] -= f * rhs[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double s = rhs[r];
+        for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * x[k];
+        x[r] = s / A[r * n + r];
+    }
+}
+
+double falling(int e, int j) {  // e (e-1) ... (e-j+1)
+    double v = 1.0;
+    for (int t = 0; t < j; ++t) v *= (e - t);
+    return v;
+}
+
+// Inner regularisation: even polynomial in rho = r / epsI (torus units),
+//   q(r) = sum_{k<p} c_k rho^{2k},
+// matching d^j/dr^j K(P r) at r = epsI for j < p, so that K_R is p-1 times differentiable there
+// (and smooth at the origin as a function of the difference vector).  Written in the scaled
+// variable rho so that the linear system has integer coefficients.
+void inner_poly(int kind, double lambda, double P, double epsI, int p, double *c) {
+    std::vector<double> der(p), A(p * p, 0.0), rhs(p);
+    kernel_derivs(kind, lambda, P * epsI, p, der.data());
+    for (int j = 0; j < p; ++j) {
+        rhs[j] = der[j] * std::pow(P * epsI, j);
+        for (int k = 0; k < p; ++k)
+            if (2 * k >= j) A[j * p + k] = falling(2 * k, j);
+    }
+    solve_dense(p, A, rhs, c);
+}
+
+// Boundary regularisation: polynomial in zeta = (r - 1/2) / epsB,
+//   q(r) = sum_{k <= 2p-2} c_k zeta^k,
+// matching d^j/dr^j K(P r) at r_B = 1/2 - epsB (zeta = -1) for j < p, with q^{(j)} = 0 at r = 1/2
+// for 1 <= j < p, so the kernel continues smoothly into the constant q(1/2) = c_0 beyond r = 1/2
+// and its periodic continuation is smooth.
+void boundary_poly(int kind, double lambda, double P, double epsB, int p, double *c) {
+    const int nc = 2 * p - 1;
+    const double rb = 0.5 - epsB;
+    std::vector<double> der(p), A(nc * nc, 0.0), rhs(nc, 0.0);
+    kernel_derivs(kind, lambda, P * rb, p, der.data());
+    int row = 0;
+    for (int j = 0; j < p; ++j, ++row) {
+        for (int k = j; k < nc; ++k) A[row * nc + k] = falling(k, j) * (((k - j) & 1) ? -1.0 : 1.0);
+        rhs[row] = der[j] * std::pow(P * epsB, j);
+    }
+    for (int j = 1; j < p; ++j, ++row) {
+        A[row * nc + j] = falling(j, j);
+        rhs[row] = 0.0;
+    }
+    solve_dense(nc, A, rhs, c);
+}
+
+// Modified Bessel function I_0 by its power series (all terms positive).
+double bessel_i0(double x) {
+    double s = 1.0, t = 1.0, h = 0.25 * x * x;
+    for (int k = 1; k < 500; ++k) {
+        t *= h / ((double)k * k);
+        s += t;
+        if (t < 1e-18 * s) break;
+    }
+    return s;
+}
+
+// Fourier transform of the normalised window (phi(0) = 1) at integer frequency k on a grid of G
+// points:  phihat(k) = (1/G) I_0(m sqrt(b^2 - (2 pi k / G)^2)) / phi0,  phi0 = sinh(b m)/(pi m)
+// (the transform pair of the Kaiser-Bessel window; the (1/pi) sinh form has transform I_0).
+double kb_hat(double m, double b, int G, int k) {
+    const double w = 2.0 * M_PI * k / G;
+    const double arg = m * std::sqrt(std::max(b * b - w * w, 0.0));
+    const double phi0 = std::sinh(b * m) / (M_PI * m);
+    return bessel_i0(arg) / G / phi0;
+}
+
+}  // namespace
+
+// =====================================================================================
+//                                    device helpers
+// =====================================================================================
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Batched complex FFT of NB transforms of length L = 2^logL held in LDS (transform t at
+// a[t L .. t L + L)), Stockham radix-2, natural order in and out.  DIR = -1 forward
+// (e^{-2 pi i jk/L}), +1 inverse (unnormalised).  Returns the buffer holding the result.
+// tw[q] = exp(-2 pi i q / L) for q < L/2.  All threads of the block must call it.
+template <int DIR>
+__device__ float2 *lds_fft(float2 *a, float2 *b, int logL, int NB, const float2 *__restrict__ tw) {
+    const int L = 1 << logL, H = L >> 1;
+    for (int ls = 0; (1 << ls) < L; ++ls) {
+        const int Ns = 1 << ls;
+        const int stride = H >> ls;  // L / (2 Ns)
+        for (int q = threadIdx.x; q < NB * H; q += blockDim.x) {
+            const int t = q >> (logL - 1), j = q & (H - 1);
+            const int k = j & (Ns - 1);
+            float2 a0 = a[t * L + j], a1 = a[t * L + j + H];
+            float2 w = tw[k * stride];
+            if (DIR > 0) w.y = -w.y;
+            a1 = cmul(a1, w);
+            const int o = ((j - k) << 1) + k;
+            b[t * L + o] = make_float2(a0.x + a1.x, a0.y + a1.y);
+            b[t * L + o + Ns] = make_float2(a0.x - a1.x, a0.y - a1.y);
+        }
+        __syncthreads();
+        float2 *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    return a;
+}
+
+constexpr int FFT_THREADS = 256;
+constexpr int FFT_ELEMS = 4096;  // complex elements per LDS buffer (two buffers: 64 KB)
+
+// ------------------------------------------------------------------ scaling and binning
+__global__ void k_bbox(const float *__restrict__ p, int64_t n, int d, float *__restrict__ part,
+                       int *__restrict__ nonfinite) {
+    __shared__ float smin[256 * 3], smax[256 * 3];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int k = 0; k < d; ++k) {
+            float v = p[i * d + k];
+            if (!isfinite(v)) bad = 1;
+            lo[k] = fminf(lo[k], v);
+            hi[k] = fmaxf(hi[k], v);
+        }
+    }
+    if (bad) atomicAdd(nonfinite, 1);
+    for (int k = 0; k < 3; ++k) {
+        smin[threadIdx.x * 3 + k] = lo[k];
+        smax[threadIdx.x * 3 + k] = hi[k];
+    }
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) {
+                smin[threadIdx.x * 3 + k] = fminf(smin[threadIdx.x * 3 + k], smin[(threadIdx.x + s) * 3 + k]);
+                smax[threadIdx.x * 3 + k] = fmaxf(smax[threadIdx.x * 3 + k], smax[(threadIdx.x + s) * 3 + k]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) {
+            part[blockIdx.x * 6 + k] = smin[k];
+            part[blockIdx.x * 6 + 3 + k] = smax[k];
+        }
+}
+
+struct ScaleArgs {
+    double c[3];
+    double inv_P;
+    int G, T, ntd, d;
+};
+
+__global__ void k_keys(const float *__restrict__ p, int64_t n, ScaleArgs sa, int *__restrict__ key,
+                       float4 *__restrict__ tmp, int *__restrict__ hist) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int cell[3] = {0, 0, 0};
+    float fr[3] = {0, 0, 0};
+    for (int k = 0; k < sa.d; ++k) {
+        double u = ((double)p[i * sa.d + k] - sa.c[k]) * sa.inv_P * sa.G + 0.5 * sa.G;
+        double fl = floor(u);
+        int c = (int)fl;
+        double f = u - fl;
+        if (c < 0) { c = 0; f = 0.0; }
+        if (c > sa.G - 1) { c = sa.G - 1; f = 0.99999994; }
+        cell[k] = c;
+        fr[k] = (float)f;
+        if (fr[k] >= 1.0f) fr[k] = 0.99999994f;
+    }
+    int tk = 0;
+    for (int k = sa.d - 1; k >= 0; --k) tk = tk * sa.ntd + cell[k] / sa.T;
+    int packed = 0;
+    for (int k = sa.d - 1; k >= 0; --k) packed = packed * sa.G + cell[k];
+    key[i] = tk;
+    tmp[i] = make_float4(fr[0], fr[1], fr[2], __int_as_float(packed));
+    atomicAdd(&hist[tk], 1);
+}
+
+// Exclusive scans of node counts and chunk counts per tile (single workgroup).
+__global__ void __launch_bounds__(1024) k_scan_tiles(const int *__restrict__ hist, int ntiles,
+                                                     int chunk, int *__restrict__ tile_start,
+                                                     int *__restrict__ tile_chunk,
+                                                     int *__restrict__ totals) {
+    __shared__ int sa[1024], sb[1024];
+    const int per = (ntiles + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(lo + per, ntiles);
+    int s1 = 0, s2 = 0;
+    for (int t = lo; t < hi; ++t) {
+        s1 += hist[t];
+        s2 += (hist[t] + chunk - 1) / chunk;
+    }
+    sa[threadIdx.x] = s1;
+    sb[threadIdx.x] = s2;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int va = (threadIdx.x >= (unsigned)off) ? sa[threadIdx.x - off] : 0;
+        int vb = (threadIdx.x >= (unsigned)off) ? sb[threadIdx.x - off] : 0;
+        __syncthreads();
+        sa[threadIdx.x] += va;
+        sb[threadIdx.x] += vb;
+        __syncthreads();
+    }
+    int r1 = sa[threadIdx.x] - s1, r2 = sb[threadIdx.x] - s2;
+    for (int t = lo; t < hi; ++t) {
+        int c = hist[t], nc = (c + chunk - 1) / chunk;
+        tile_start[t] = r1;
+        tile_chunk[2 * t] = r2;
+        tile_chunk[2 * t + 1] = nc;
+        r1 += c;
+        r2 += nc;
+    }
+    if (threadIdx.x == 1023) {
+        totals[0] = sa[1023];
+        totals[1] = sb[1023];
+    }
+}
+
+__global__ void k_scatter_nodes(const float *__restrict__ p, int64_t n, int d,
+                                const int *__restrict__ key, const float4 *__restrict__ tmp,
+                                const int *__restrict__ tile_start, int *__restrict__ cursor,
+                                float4 *__restrict__ rec, int *__restrict__ perm,
+                                float *__restrict__ xs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int t = key[i];
+    const int pos = tile_start[t] + atomicAdd(&cursor[t], 1);
+    rec[pos] = tmp[i];
+    perm[pos] = (int)i;
+    for (int k = 0; k < d; ++k) xs[(int64_t)pos * d + k] = p[i * d + k];
+}
+
+__global__ void k_fill_chunks(int ntiles, const int *__restrict__ tile_start,
+                              const int *__restrict__ hist, const int *__restrict__ tile_chunk,
+                              int chunk, int4 *__restrict__ chunks) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int c0 = tile_chunk[2 * t], nc = tile_chunk[2 * t + 1];
+    const int s = tile_start[t], cnt = hist[t];
+    for (int c = 0; c < nc; ++c) chunks[c0 + c] = make_int4(t, s + c * chunk, min(chunk, cnt - c * chunk), 0);
+}
+
+// ------------------------------------------------------------------ kernel coefficients b_k
+struct RegArgs {
+    int kind, regime, p;
+    double lambda, P, epsI, epsB;
+    double ci[16], cb[32];
+};
+
+__device__ double kr_eval(const RegArgs &ra, double r) {
+    // regularised kernel K_R at torus distance r (data-unit kernel value K(P r))
+    if (ra.epsI > 0.0 && r < ra.epsI) {
+        double rho2 = (r / ra.epsI) * (r / ra.epsI), v = 0.0;
+        for (int k = ra.p - 1; k >= 0; --k) v = v * rho2 + ra.ci[k];
+        return v;
+    }
+    if (ra.regime == REGIME_BALL && r > 0.5 - ra.epsB) {
+        double z = (fmin(r, 0.5) - 0.5) / ra.epsB, v = 0.0;
+        for (int k = 2 * ra.p - 2; k >= 0; --k) v = v * z + ra.cb[k];
+        return v;
+    }
+    double s = ra.P * r;
+    if (ra.kind == FS_GAUSS) return exp(-s * s / ra.lambda);
+    if (ra.kind == FS_LAPLACE) return exp(-s / ra.lambda);
+    return -s;
+}
+
+__global__ void k_sample_kr(RegArgs ra, int N, int d, double *__restrict__ out) {
+    int64_t total = 1;
+    for (int k = 0; k < d; ++k) total *= N;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        int64_t rem = q;
+        double r2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+            int j = (int)(rem % N);
+            rem /= N;
+            double t = (double)(j - N / 2) / N;
+            r2 += t * t;
+        }
+        out[q] = kr_eval(ra, sqrt(r2));
+    }
+}
+
+// Cosine DFT along one axis: out[a][kk][b] = sum_j in[a][j][b] cos(2 pi (j - N/2) kk / N),
+// kk <= N/2 (the samples are even, so the transform is real and even in kk).
+__global__ void k_cos_dft(const double *__restrict__ in, int64_t A, int N, int64_t B,
+                          const double *__restrict__ costab, double *__restrict__ out) {
+    const int H = N / 2 + 1;
+    const int64_t total = A * H * B;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = q % B;
+        const int kk = (int)((q / B) % H);
+        const int64_t a = q / (B * H);
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) {
+            int ph = (int)(((int64_t)(j - N / 2) * kk) % N);
+            if (ph < 0) ph += N;
+            s += in[(a * N + j) * B + b] * costab[ph];
+        }
+        out[(a * H + kk) * B + b] = s;
+    }
+}
+
+__global__ void k_build_mult(const double *__restrict__ bk, int N, int d,
+                             const double *__restrict__ dconv, double scale,
+                             float *__restrict__ M) {
+    const int H = N / 2 + 1;
+    int64_t total = 1;
+    for (int k = 0; k < d; ++k) total *= H;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        int64_t rem = q;
+        double v = bk[q] * scale;
+        for (int k = 0; k < d; ++k) {
+            int kk = (int)(rem % H);
+            rem /= H;
+            v *= dconv[kk];
+            if (kk == N / 2) v *= 0.5;  // the band edge +-N/2 is split symmetrically
+        }
+        M[q] = (float)v;
+    }
+}
+
+// ------------------------------------------------------------------ spread (adjoint NFFT)
+struct SpreadArgs {
+    KB kb;
+    int G, T, ntd, m;
+};
+
+template <int D>
+__device__ __forceinline__ void unpack_cell(int packed, int G, int *c) {
+    c[0] = packed % G;
+    if (D > 1) c[1] = (packed / G) % G;
+    if (D > 2) c[2] = packed / (G * G);
+}
+
+template <int D>
+__device__ __forceinline__ void tile_coords(int tile, int ntd, int *t) {
+    t[0] = tile % ntd;
+    if (D > 1) t[1] = (tile / ntd) % ntd;
+    if (D > 2) t[2] = tile / (ntd * ntd);
+}
+
+// Fixed-point scale for one chunk: every partial sum of the box is bounded by
+// sum_j |alpha_j| * max(phi)^d <= count * max|alpha| (phi <= 1), so with
+// scale = 2^30 / (count * max|alpha|) all int32 partial sums stay below 2^30 in magnitude.
+// LDS integer atomics are the fast path on gfx950 (LDS float atomics are far slower), and integer
+// addition makes the accumulation order-independent (bitwise reproducible).
+__device__ float chunk_scale(const float *__restrict__ w, int k0, int cnt, float *red) {
+    float mx = 0.0f;
+    for (int k = k0 + threadIdx.x; k < k0 + cnt; k += blockDim.x) mx = fmaxf(mx, fabsf(w[k]));
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    float m = 0.0f;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmaxf(m, red[i]);
+    return (m > 0.0f && cnt > 0) ? 1073741824.0f / ((float)cnt * m) : 1.0f;
+}
+
+template <int D, int W, int T>
+__global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
+                                                const float *__restrict__ w,
+                                                const int4 *__restrict__ chunks, SpreadArgs sa,
+                                                float *__restrict__ scratch) {
+    constexpr int S = T + W - 1;
+    constexpr int BOX = (D == 1) ? S : (D == 2 ? S * S : S * S * S);
+    __shared__ int box[BOX];
+    __shared__ float red[4];
+    const int4 ch = chunks[blockIdx.x];
+    int tc[3] = {0, 0, 0};
+    tile_coords<D>(ch.x, sa.ntd, tc);
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
+    const float scale = chunk_scale(w, ch.y, ch.z, red);
+    const int lane = threadIdx.x & 63;
+    const int ra = lane % W;
+    const float mm1 = (float)(sa.m - 1);
+    for (int k = ch.y + threadIdx.x; k < ch.y + ch.z; k += blockDim.x) {
+        const float4 r = rec[k];
+        int c[3] = {0, 0, 0};
+        unpack_cell<D>(__float_as_int(r.w), sa.G, c);
+        const float alpha = w[k] * scale;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            int a = i + ra;
+            a = (a >= W) ? a - W : a;
+            const float v = alpha * kb_phi(sa.kb, r.x + mm1 - (float)a);
+            atomicAdd(&box[c[0] - tc[0] * T + a], __float2int_rn(v));
+        }
+    }
+    __syncthreads();
+    const float inv = 1.0f / scale;
+    float *dst = scratch + (int64_t)blockIdx.x * BOX;
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
+}
+
+// Wave-cooperative spreading (d = 2, 3).  A wave takes one node at a time; lane l < d W
+// evaluates the window value of dimension l / W at offset l % W, then the lanes cover the W^2
+// (y, x) pairs of the node's window in ceil(W^2 / 64) passes and walk the z offsets together, so
+// every LDS atomic of one instruction hits a distinct address of one contiguous patch.
+template <int D, int W, int T>
+__global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ rec,
+                                                     const float *__restrict__ w,
+                                                     const int4 *__restrict__ chunks,
+                                                     SpreadArgs sa, float *__restrict__ scratch) {
+    constexpr int S = T + W - 1;
+    constexpr int BOX = (D == 2) ? S * S : S * S * S;
+    constexpr int NP = (W * W + 63) / 64;  // passes over the (y, x) pairs
+    __shared__ int box[BOX];
+    __shared__ float red[4];
+    const int4 ch = chunks[blockIdx.x];
+    int tc[3] = {0, 0, 0};
+    tile_coords<D>(ch.x, sa.ntd, tc);
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
+    const float scale = chunk_scale(w, ch.y, ch.z, red);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const float mm1 = (float)(sa.m - 1);
+    // this lane's (y, x) pairs: offsets inside the box row structure
+    int poff[NP];
+    int pa[NP], pb[NP];
+#pragma unroll
+    for (int P = 0; P < NP; ++P) {
+        const int q = P * 64 + lane;
+        pb[P] = (q < W * W) ? q / W : 0;
+        pa[P] = (q < W * W) ? q % W : 0;
+        poff[P] = pb[P] * S + pa[P];
+    }
+    const int wdim = (lane < D * W) ? lane / W : 0;
+    const int woff = lane % W;
+    for (int k = ch.y + wave; k < ch.y + ch.z; k += nwaves) {
+        const float4 r = rec[k];
+        int c[3] = {0, 0, 0};
+        unpack_cell<D>(__float_as_int(r.w), sa.G, c);
+        const float alpha = w[k] * scale;
+        const float fr = (wdim == 0) ? r.x : (wdim == 1 ? r.y : r.z);
+        const float val = (lane < D * W) ? kb_phi(sa.kb, fr + mm1 - (float)woff) : 0.0f;
+        const int ox = c[0] - tc[0] * T, oy = c[1] - tc[1] * T;
+        const int base = oy * S + ox;
+        float wxy[NP];
+#pragma unroll
+        for (int P = 0; P < NP; ++P) {
+            const float vx = __shfl(val, pa[P], 64);
+            const float vy = __shfl(val, W + pb[P], 64);
+            wxy[P] = (P * 64 + lane < W * W) ? alpha * vx * vy : 0.0f;
+        }
+        if (D == 2) {
+#pragma unroll
+            for (int P = 0; P < NP; ++P)
+                if (P * 64 + lane < W * W) atomicAdd(&box[base + poff[P]], __float2int_rn(wxy[P]));
+        } else {
+            const int oz = c[2] - tc[2] * T;
+#pragma unroll
+            for (int l = 0; l < W; ++l) {
+                const float wz = __int_as_float(
+                    __builtin_amdgcn_readlane(__float_as_int(val), 2 * W + l));
+                const int zb = (oz + l) * S * S + base;
+#pragma unroll
+                for (int P = 0; P < NP; ++P)
+                    if (P * 64 + lane < W * W)
+                        atomicAdd(&box[zb + poff[P]], __float2int_rn(wz * wxy[P]));
+            }
+        }
+    }
+    __syncthreads();
+    const float inv = 1.0f / scale;
+    float *dst = scratch + (int64_t)blockIdx.x * BOX;
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
+}
+
+// Sum the boxes of all chunks of a tile into the tile's first chunk box (fixed chunk order).
+__global__ void k_reduce_chunks(float *__restrict__ scratch, const int *__restrict__ tile_chunk,
+                                int ntiles, int box) {
+    for (int t = blockIdx.y; t < ntiles; t += gridDim.y) {
+        const int c0 = tile_chunk[2 * t], nc = tile_chunk[2 * t + 1];
+        if (nc <= 1) continue;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < box; e += gridDim.x * blockDim.x) {
+            float acc = scratch[(int64_t)c0 * box + e];
+            for (int c = 1; c < nc; ++c) acc += scratch[(int64_t)(c0 + c) * box + e];
+            scratch[(int64_t)c0 * box + e] = acc;
+        }
+    }
+}
+
+// Sum the tile boxes covering every grid point (fixed order), after k_reduce_chunks has summed
+// each tile's chunk boxes into its first chunk box.
+template <int D>
+__global__ void k_fold(const float *__restrict__ scratch, const int *__restrict__ tile_chunk,
+                       int G, int T, int ntd, int m, int S, float *__restrict__ grid) {
+    const int BOX = (D == 1) ? S : (D == 2 ? S * S : S * S * S);
+    int64_t total = 1;
+    for (int k = 0; k < D; ++k) total *= G;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        int pc[3] = {0, 0, 0};
+        {
+            int64_t rem = q;
+            for (int k = 0; k < D; ++k) { pc[k] = (int)(rem % G); rem /= G; }
+        }
+        // per dimension: covering (tile, local index) pairs
+        int nt[3] = {1, 1, 1}, tl[3][6], lc[3][6];
+        for (int k = 0; k < D; ++k) {
+            nt[k] = 0;
+            const int t0 = pc[k] / T;
+            int seen[3];
+            int ns = 0;
+            for (int dt = -1; dt <= 1; ++dt) {
+                int t = ((t0 + dt) % ntd + ntd) % ntd;
+                bool dup = false;
+                for (int u = 0; u < ns; ++u) dup |= (seen[u] == t);
+                if (dup) continue;
+                seen[ns++] = t;
+                const int origin = t * T - (m - 1);
+                int loc = ((pc[k] - origin) % G + G) % G;
+                for (; loc < S && nt[k] < 6; loc += G) {
+                    tl[k][nt[k]] = t;
+                    lc[k][nt[k]] = loc;
+                    ++nt[k];
+                }
+            }
+        }
+        float acc = 0.0f;
+        for (int a2 = 0; a2 < (D > 2 ? nt[2] : 1); ++a2)
+            for (int a1 = 0; a1 < (D > 1 ? nt[1] : 1); ++a1)
+                for (int a0 = 0; a0 < nt[0]; ++a0) {
+                    int tile = tl[0][a0], loc = lc[0][a0];
+                    if (D > 1) { tile += ntd * tl[1][a1]; loc += S * lc[1][a1]; }
+                    if (D > 2) { tile += ntd * ntd * tl[2][a2]; loc += S * S * lc[2][a2]; }
+                    const int c0 = tile_chunk[2 * tile], nc = tile_chunk[2 * tile + 1];
+                    if (nc > 0) acc += scratch[(int64_t)c0 * BOX + loc];
+                }
+        grid[q] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ FFT passes
+struct FftArgs {
+    int G, logG, N, KX, nbx;  // nbx: columns per block in the strided passes
+};
+
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_x_r2c(const float *__restrict__ grid,
+                                                            int rows, FftArgs fa,
+                                                            const float2 *__restrict__ tw,
+                                                            float2 *__restrict__ specA) {
+    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    const int G = fa.G, NB = FFT_ELEMS / G;
+    const int pairs = rows / 2;
+    const int p0 = blockIdx.x * NB;
+    const int nb = min(NB, pairs - p0);
+    for (int q = threadIdx.x; q < NB * G; q += blockDim.x) {
+        const int t = q / G, i = q - t * G;
+        float2 v = make_float2(0.f, 0.f);
+        if (t < nb) {
+            const int64_t r0 = (int64_t)(p0 + t) * 2;
+            v = make_float2(grid[r0 * G + i], grid[(r0 + 1) * G + i]);
+        }
+        bufa[q] = v;
+    }
+    __syncthreads();
+    float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, NB, tw);
+    for (int q = threadIdx.x; q < NB * fa.KX; q += blockDim.x) {
+        const int t = q / fa.KX, k = q - t * fa.KX;
+        if (t >= nb) continue;
+        const float2 z = res[t * G + k], zm = res[t * G + ((G - k) & (G - 1))];
+        const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+        const float2 B = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
+        const int64_t r0 = (int64_t)(p0 + t) * 2;
+        specA[r0 * fa.KX + k] = A;
+        specA[(r0 + 1) * fa.KX + k] = B;
+    }
+}
+
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restrict__ specA,
+                                                            int rows, FftArgs fa,
+                                                            const float2 *__restrict__ tw,
+                                                            float *__restrict__ grid) {
+    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    const int G = fa.G, NB = FFT_ELEMS / G, h = fa.N / 2;
+    const int pairs = rows / 2;
+    const int p0 = blockIdx.x * NB;
+    const int nb = min(NB, pairs - p0);
+    for (int q = threadIdx.x; q < NB * G; q += blockDim.x) {
+        const int t = q / G, k = q - t * G;
+        float2 z = make_float2(0.f, 0.f);
+        if (t < nb) {
+            const int64_t r0 = (int64_t)(p0 + t) * 2;
+            if (k <= h) {
+                const float2 A = specA[r0 * fa.KX + k], B = specA[(r0 + 1) * fa.KX + k];
+                z = make_float2(A.x - B.y, A.y + B.x);
+            } else if (k >= G - h) {
+                const int kk = G - k;
+                float2 A = specA[r0 * fa.KX + kk], B = specA[(r0 + 1) * fa.KX + kk];
+                A.y = -A.y;
+                B.y = -B.y;
+                z = make_float2(A.x - B.y, A.y + B.x);
+            }
+        }
+        bufa[q] = z;
+    }
+    __syncthreads();
+    float2 *res = lds_fft<1>(bufa, bufb, fa.logG, NB, tw);
+    for (int q = threadIdx.x; q < NB * G; q += blockDim.x) {
+        const int t = q / G, i = q - t * G;
+        if (t >= nb) continue;
+        const int64_t r0 = (int64_t)(p0 + t) * 2;
+        grid[r0 * G + i] = res[q].x;
+        grid[(r0 + 1) * G + i] = res[q].y;
+    }
+}
+
+// 1-D: whole convolution in one workgroup.
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_1d_conv(float *__restrict__ grid, FftArgs fa,
+                                                              const float2 *__restrict__ tw,
+                                                              const float *__restrict__ M) {
+    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    const int G = fa.G, h = fa.N / 2;
+    for (int q = threadIdx.x; q < G; q += blockDim.x) bufa[q] = make_float2(grid[q], 0.f);
+    __syncthreads();
+    float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, 1, tw);
+    float2 *other = (res == bufa) ? bufb : bufa;
+    for (int q = threadIdx.x; q < G; q += blockDim.x) {
+        int k = (q < G / 2) ? q : q - G;
+        int ak = k < 0 ? -k : k;
+        float mk = (ak <= h) ? M[ak] : 0.0f;
+        res[q] = make_float2(res[q].x * mk, res[q].y * mk);
+    }
+    __syncthreads();
+    res = lds_fft<1>(res, other, fa.logG, 1, tw);
+    for (int q = threadIdx.x; q < G; q += blockDim.x) grid[q] = res[q].x;
+}
+
+// Strided pass along y of layout [z][y][kx] (KX columns).  MODE 0: 3-D forward, store the band
+// ky in [-N/2, N/2] to specB[z][ky + N/2][kx].  MODE 1: 2-D forward, multiply, inverse, in place.
+// MODE 2: 3-D inverse from the band in specB back to specA.
+template <int MODE>
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_y(float2 *__restrict__ specA,
+                                                        float2 *__restrict__ specB, FftArgs fa,
+                                                        const float2 *__restrict__ tw,
+                                                        const float *__restrict__ M) {
+    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    const int G = fa.G, KX = fa.KX, NBX = fa.nbx, h = fa.N / 2, NB1 = fa.N + 1;
+    const int nkb = (KX + NBX - 1) / NBX;
+    const int z = blockIdx.x / nkb, kb = blockIdx.x - z * nkb;
+    const int kx0 = kb * NBX, nbx = min(NBX, KX - kx0);
+    for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
+        const int y = q / NBX, c = q - y * NBX;
+        float2 v = make_float2(0.f, 0.f);
+        if (c < nbx) {
+            if (MODE == 2) {
+                const int ky = (y <= G / 2) ? y : y - G;
+                if (ky >= -h && ky <= h) v = specB[((int64_t)z * NB1 + ky + h) * KX + kx0 + c];
+            } else {
+                v = specA[((int64_t)z * G + y) * KX + kx0 + c];
+            }
+        }
+        bufa[c * G + y] = v;
+    }
+    __syncthreads();
+    float2 *res;
+    if (MODE == 2) {
+        res = lds_fft<1>(bufa, bufb, fa.logG, NBX, tw);
+    } else {
+        res = lds_fft<-1>(bufa, bufb, fa.logG, NBX, tw);
+    }
+    if (MODE == 1) {
+        float2 *other = (res == bufa) ? bufb : bufa;
+        for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
+            const int c = q / G, yi = q - c * G;
+            const int ky = (yi <= G / 2) ? yi : yi - G;
+            const int aky = ky < 0 ? -ky : ky;
+            float mk = (aky <= h && c < nbx) ? M[aky * (h + 1) + kx0 + c] : 0.0f;
+            res[q] = make_float2(res[q].x * mk, res[q].y * mk);
+        }
+        __syncthreads();
+        res = lds_fft<1>(res, other, fa.logG, NBX, tw);
+    }
+    if (MODE == 0) {
+        for (int q = threadIdx.x; q < NBX * NB1; q += blockDim.x) {
+            const int kyb = q / NBX, c = q - kyb * NBX;
+            if (c >= nbx) continue;
+            const int yi = (kyb - h) & (G - 1);
+            specB[((int64_t)z * NB1 + kyb) * KX + kx0 + c] = res[c * G + yi];
+        }
+    } else {
+        for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
+            const int y = q / NBX, c = q - y * NBX;
+            if (c >= nbx) continue;
+            specA[((int64_t)z * G + y) * KX + kx0 + c] = res[c * G + y];
+        }
+    }
+}
+
+// 3-D: along z for every (ky in band, kx): forward, multiply by M, inverse, in place in specB.
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_z_conv(float2 *__restrict__ specB,
+                                                             FftArgs fa,
+                                                             const float2 *__restrict__ tw,
+                                                             const float *__restrict__ M) {
+    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    const int G = fa.G, KX = fa.KX, NBX = fa.nbx, h = fa.N / 2, NB1 = fa.N + 1, H = h + 1;
+    const int nkb = (KX + NBX - 1) / NBX;
+    const int kyb = blockIdx.x / nkb, kb = blockIdx.x - kyb * nkb;
+    const int kx0 = kb * NBX, nbx = min(NBX, KX - kx0);
+    const int ky = kyb - h, aky = ky < 0 ? -ky : ky;
+    for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
+        const int zz = q / NBX, c = q - zz * NBX;
+        bufa[c * G + zz] = (c < nbx) ? specB[((int64_t)zz * NB1 + kyb) * KX + kx0 + c]
+                                     : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, NBX, tw);
+    float2 *other = (res == bufa) ? bufb : bufa;
+    for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
+        const int c = q / G, zi = q - c * G;
+        const int kz = (zi <= G / 2) ? zi : zi - G;
+        const int akz = kz < 0 ? -kz : kz;
+        float mk = (akz <= h && c < nbx) ? M[((int64_t)akz * H + aky) * H + kx0 + c] : 0.0f;
+        res[q] = make_float2(res[q].x * mk, res[q].y * mk);
+    }
+    __syncthreads();
+    res = lds_fft<1>(res, other, fa.logG, NBX, tw);
+    for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
+        const int zz = q / NBX, c = q - zz * NBX;
+        if (c >= nbx) continue;
+        specB[((int64_t)zz * NB1 + kyb) * KX + kx0 + c] = res[c * G + zz];
+    }
+}
+
+// ------------------------------------------------------------------ gather (NFFT)
+template <int D, int W, int T, bool GRAD>
+__global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
+                                                const int4 *__restrict__ chunks, SpreadArgs sa,
+                                                const float *__restrict__ grid,
+                                                float *__restrict__ out, float *__restrict__ gout,
+                                                float gscale) {
+    constexpr int S = T + W - 1;
+    constexpr int BOX = (D == 1) ? S : (D == 2 ? S * S : S * S * S);
+    __shared__ float box[BOX];
+    const int4 ch = chunks[blockIdx.x];
+    int tc[3] = {0, 0, 0};
+    tile_coords<D>(ch.x, sa.ntd, tc);
+    const int G = sa.G;
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) {
+        int l0 = q % S, l1 = (q / S) % S, l2 = q / (S * S);
+        int g0 = (tc[0] * T - (sa.m - 1) + l0 + G) & (G - 1);
+        int64_t gi = g0;
+        if (D > 1) gi += (int64_t)G * ((tc[1] * T - (sa.m - 1) + l1 + G) & (G - 1));
+        if (D > 2) gi += (int64_t)G * G * ((tc[2] * T - (sa.m - 1) + l2 + G) & (G - 1));
+        box[q] = grid[gi];
+    }
+    __syncthreads();
+    const float mm1 = (float)(sa.m - 1);
+    for (int k = ch.y + threadIdx.x; k < ch.y + ch.z; k += blockDim.x) {
+        const float4 r = rec[k];
+        int c[3] = {0, 0, 0};
+        unpack_cell<D>(__float_as_int(r.w), sa.G, c);
+        const float fr[3] = {r.x, r.y, r.z};
+        int o[3];
+        for (int kk = 0; kk < D; ++kk) o[kk] = c[kk] - tc[kk] * T;
+        float wx[W], dwx[W];
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            wx[a] = kb_phi(sa.kb, fr[0] + mm1 - (float)a);
+            if (GRAD) dwx[a] = kb_dphi(sa.kb, fr[0] + mm1 - (float)a);
+        }
+        float val = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        if (D == 1) {
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                val = fmaf(wx[a], box[o[0] + a], val);
+                if (GRAD) g0 = fmaf(dwx[a], box[o[0] + a], g0);
+            }
+        } else {
+            float wy[W], dwy[W];
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                wy[b] = kb_phi(sa.kb, fr[1] + mm1 - (float)b);
+                if (GRAD) dwy[b] = kb_dphi(sa.kb, fr[1] + mm1 - (float)b);
+            }
+            const int nz = (D == 3) ? W : 1;
+            for (int l = 0; l < nz; ++l) {
+                float wz = 1.0f, dwz = 0.0f;
+                int zb = 0;
+                if (D == 3) {
+                    wz = kb_phi(sa.kb, fr[2] + mm1 - (float)l);
+                    if (GRAD) dwz = kb_dphi(sa.kb, fr[2] + mm1 - (float)l);
+                    zb = (o[2] + l) * S * S;
+                }
+                float pv = 0.0f, pgx = 0.0f, pgy = 0.0f;
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    const float *row = box + zb + (o[1] + b) * S + o[0];
+                    float rv = 0.0f, rg = 0.0f;
+#pragma unroll
+                    for (int a = 0; a < W; ++a) {
+                        const float hv = row[a];
+                        rv = fmaf(wx[a], hv, rv);
+                        if (GRAD) rg = fmaf(dwx[a], hv, rg);
+                    }
+                    pv = fmaf(wy[b], rv, pv);
+                    if (GRAD) {
+                        pgx = fmaf(wy[b], rg, pgx);
+                        pgy = fmaf(dwy[b], rv, pgy);
+                    }
+                }
+                val = fmaf(wz, pv, val);
+                if (GRAD) {
+                    g0 = fmaf(wz, pgx, g0);
+                    g1 = fmaf(wz, pgy, g1);
+                    if (D == 3) g2 = fmaf(dwz, pv, g2);
+                }
+            }
+        }
+        out[k] = val;
+        if (GRAD) {
+            gout[(int64_t)k * D] = g0 * gscale;
+            if (D > 1) gout[(int64_t)k * D + 1] = g1 * gscale;
+            if (D > 2) gout[(int64_t)k * D + 2] = g2 * gscale;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ permutations
+__global__ void k_gather_perm(const int *__restrict__ perm, int64_t n, const float *__restrict__ v,
+                              float *__restrict__ vs) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) vs[k] = v[perm[k]];
+}
+__global__ void k_scatter_perm(const int *__restrict__ perm, int64_t n,
+                               const float *__restrict__ vs, float *__restrict__ v) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) v[perm[k]] = vs[k];
+}
+__global__ void k_gather_perm64(const int *__restrict__ perm, int64_t n,
+                                const double *__restrict__ v, double *__restrict__ vs) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) vs[k] = v[perm[k]];
+}
+__global__ void k_scatter_perm64(const int *__restrict__ perm, int64_t n,
+                                 const double *__restrict__ vs, double *__restrict__ v) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n) v[perm[k]] = vs[k];
+}
+__global__ void k_scatter_rows(const int *__restrict__ perm, int64_t n, int d,
+                               const float *__restrict__ vs, float *__restrict__ v) {
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < n)
+        for (int c = 0; c < d; ++c) v[(int64_t)perm[k] * d + c] = vs[k * d + c];
+}
+
+// ------------------------------------------------------------------ near field
+// For Laplace and energy kernels K_R differs from K inside the inner radius; the difference is
+// summed directly over the source points of the neighbouring cells:
+//   t_i += sum_{|x_i - y_j| < epsI P} (K(|x_i - y_j|) - q_I(|x_i - y_j| / P)) alpha_j
+struct NearArgs {
+    int kind, p, d;
+    float lambda_inv, rinv, r2max;  // rinv = 1/(epsI P), r2max = (epsI P)^2
+    float ci[16];
+    float h_inv;
+    float lo[3];
+    int dims[3];
+};
+
+__global__ void k_nf_keys(const float *__restrict__ xs, int64_t n, NearArgs na,
+                          int *__restrict__ key, int *__restrict__ hist) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int kk = 0;
+    for (int c = na.d - 1; c >= 0; --c) {
+        int v = (int)floorf((xs[i * na.d + c] - na.lo[c]) * na.h_inv);
+        v = max(0, min(na.dims[c] - 1, v));
+        kk = kk * na.dims[c] + v;
+    }
+    key[i] = kk;
+    atomicAdd(&hist[kk], 1);
+}
+
+__global__ void k_nf_scatter(const float *__restrict__ xs, int64_t n, int d,
+                             const int *__restrict__ key, const int *__restrict__ start,
+                             int *__restrict__ cursor, int *__restrict__ order,
+                             float *__restrict__ cxs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int pos = start[key[i]] + atomicAdd(&cursor[key[i]], 1);
+    order[pos] = (int)i;
+    for (int c = 0; c < d; ++c) cxs[(int64_t)pos * d + c] = xs[i * d + c];
+}
+
+template <int D, bool GRAD>
+__global__ void __launch_bounds__(256) k_nearfield(const float *__restrict__ txs, int64_t nt,
+                                                   const int *__restrict__ cell_start,
+                                                   const int *__restrict__ order,
+                                                   const float *__restrict__ sxs,
+                                                   const float *__restrict__ w, NearArgs na,
+                                                   float *__restrict__ out,
+                                                   float *__restrict__ gout) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    float xi[3] = {0, 0, 0};
+    int ci[3] = {0, 0, 0};
+    for (int c = 0; c < D; ++c) {
+        xi[c] = txs[i * D + c];
+        ci[c] = max(0, min(na.dims[c] - 1, (int)floorf((xi[c] - na.lo[c]) * na.h_inv)));
+    }
+    float acc = 0.0f, g[3] = {0, 0, 0};
+    const int z0 = (D > 2) ? max(ci[2] - 1, 0) : 0, z1 = (D > 2) ? min(ci[2] + 1, na.dims[2] - 1) : 0;
+    const int y0 = (D > 1) ? max(ci[1] - 1, 0) : 0, y1 = (D > 1) ? min(ci[1] + 1, na.dims[1] - 1) : 0;
+    const int x0 = max(ci[0] - 1, 0), x1 = min(ci[0] + 1, na.dims[0] - 1);
+    for (int cz = z0; cz <= z1; ++cz)
+        for (int cy = y0; cy <= y1; ++cy) {
+            const int rowc = (cz * na.dims[1] + cy) * na.dims[0];
+            const int s0 = cell_start[rowc + x0], s1 = cell_start[rowc + x1 + 1];
+            for (int k = s0; k < s1; ++k) {
+                float dv[3], r2 = 0.0f;
+                for (int c = 0; c < D; ++c) {
+                    dv[c] = xi[c] - sxs[(int64_t)k * D + c];
+                    r2 = fmaf(dv[c], dv[c], r2);
+                }
+                if (r2 >= na.r2max) continue;
+                const float wj = w[order[k]];
+                const float r = sqrtf(r2);
+                // inner polynomial in rho^2, rho = r / (epsI P)
+                const float rho2 = r2 * na.rinv * na.rinv;
+                float q = 0.0f, dq = 0.0f;
+                for (int kk = na.p - 1; kk >= 0; --kk) q = fmaf(q, rho2, na.ci[kk]);
+                float kv, dk = 0.0f;  // K(r) and dK/dr
+                if (na.kind == FS_LAPLACE) {
+                    kv = __expf(-r * na.lambda_inv);
+                    dk = -na.lambda_inv * kv;
+                } else if (na.kind == FS_ENERGY) {
+                    kv = -r;
+                    dk = -1.0f;
+                } else {
+                    kv = __expf(-r2 * na.lambda_inv);
+                    dk = -2.0f * r * na.lambda_inv * kv;
+                }
+                acc = fmaf(kv - q, wj, acc);
+                if (GRAD) {
+                    // dq/dr = rinv^2 r sum_{k>=1} 2k c_k rho^{2(k-1)}
+                    for (int kk = na.p - 1; kk >= 1; --kk) dq = fmaf(dq, rho2, 2.0f * kk * na.ci[kk]);
+                    const float dqdr = dq * r * na.rinv * na.rinv;
+                    const float coef = (r > 0.0f) ? (dk - dqdr) * wj / r : 0.0f;
+                    for (int c = 0; c < D; ++c) g[c] = fmaf(coef, dv[c], g[c]);
+                }
+            }
+        }
+    out[i] += acc;
+    if (GRAD)
+        for (int c = 0; c < D; ++c) gout[i * D + c] += g[c];
+}
+
+}  // namespace
+
+// =====================================================================================
+//                                        host side
+// =====================================================================================
+
+void gather_to_sorted(const Nodes &nd, const float *v, float *vs, hipStream_t s) {
+    if (nd.n == 0) return;
+    hipLaunchKernelGGL(k_gather_perm, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256),
+                       0, s, nd.perm.p, nd.n, v, vs);
+    FS_LAUNCHED();
+}
+void scatter_from_sorted(const Nodes &nd, const float *vs, float *v, hipStream_t s) {
+    if (nd.n == 0) return;
+    hipLaunchKernelGGL(k_scatter_perm, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256),
+                       0, s, nd.perm.p, nd.n, vs, v);
+    FS_LAUNCHED();
+}
+void gather_to_sorted64(const Nodes &nd, const double *v, double *vs, hipStream_t s) {
+    if (nd.n == 0) return;
+    hipLaunchKernelGGL(k_gather_perm64, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256),
+                       0, s, nd.perm.p, nd.n, v, vs);
+    FS_LAUNCHED();
+}
+void scatter_from_sorted64(const Nodes &nd, const double *vs, double *v, hipStream_t s) {
+    if (nd.n == 0) return;
+    hipLaunchKernelGGL(k_scatter_perm64, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)),
+                       dim3(256), 0, s, nd.perm.p, nd.n, vs, v);
+    FS_LAUNCHED();
+}
+void scatter_rows_from_sorted(const Nodes &nd, const float *vs, int d, float *v, hipStream_t s) {
+    if (nd.n == 0) return;
+    hipLaunchKernelGGL(k_scatter_rows, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256),
+                       0, s, nd.perm.p, nd.n, d, vs, v);
+    FS_LAUNCHED();
+}
+
+namespace {
+
+void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s) {
+    nd.n = n;
+    const int d = pp.d, G = pp.G, T = pp.T, ntd = G / T;
+    int64_t ntiles = 1;
+    for (int k = 0; k < d; ++k) ntiles *= ntd;
+    nd.rec.alloc(n + 1);
+    nd.perm.alloc(n + 1);
+    nd.xs.alloc(n * d + 1);
+    nd.tile_chunk.alloc(2 * ntiles);
+    DevBuf<int> key(n + 1), hist(ntiles), cursor(ntiles), tstart(ntiles), totals(2);
+    DevBuf<float4> tmp(n + 1);
+    fill_i32(hist.p, ntiles, 0, s);
+    fill_i32(cursor.p, ntiles, 0, s);
+    ScaleArgs sa{};
+    for (int k = 0; k < 3; ++k) sa.c[k] = pp.center[k];
+    sa.inv_P = 1.0 / pp.P;
+    sa.G = G;
+    sa.T = T;
+    sa.ntd = ntd;
+    sa.d = d;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256), 0, s,
+                           pts, n, sa, key.p, tmp.p, hist.p);
+        FS_LAUNCHED();
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, hist.p, (int)ntiles, pp.chunk,
+                       tstart.p, nd.tile_chunk.p, totals.p);
+    FS_LAUNCHED();
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter_nodes, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256),
+                           0, s, pts, n, d, key.p, tmp.p, tstart.p, cursor.p, nd.rec.p,
+                           nd.perm.p, nd.xs.p);
+        FS_LAUNCHED();
+    }
+    int tot[2] = {0, 0};
+    FS_HIP(hipMemcpyAsync(tot, totals.p, sizeof(tot), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    nd.nchunks = tot[1];
+    nd.chunks.alloc(nd.nchunks + 1);
+    if (nd.nchunks > 0) {
+        hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
+                           (int)ntiles, tstart.p, hist.p, nd.tile_chunk.p, pp.chunk, nd.chunks.p);
+        FS_LAUNCHED();
+    }
+    FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+}
+
+void build_nearfield_cells(Nodes &nd, const PlanParams &pp, hipStream_t s) {
+    const int d = pp.d;
+    int64_t ncells = 1;
+    for (int k = 0; k < d; ++k) ncells *= pp.nf_dims[k];
+    nd.nf_cell_start.alloc(ncells + 1);
+    nd.nf_order.alloc(nd.n + 1);
+    nd.nf_xs.alloc(nd.n * d + 1);
+    DevBuf<int> key(nd.n + 1), hist(ncells + 1), cursor(ncells + 1), chunkdummy(2 * (ncells + 1)),
+        totals(2);
+    fill_i32(hist.p, ncells + 1, 0, s);
+    fill_i32(cursor.p, ncells + 1, 0, s);
+    NearArgs na{};
+    na.d = d;
+    na.h_inv = (float)(1.0 / pp.nf_h);
+    for (int k = 0; k < 3; ++k) {
+        na.lo[k] = (float)pp.nf_lo[k];
+        na.dims[k] = pp.nf_dims[k];
+    }
+    if (nd.n > 0) {
+        hipLaunchKernelGGL(k_nf_keys, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256), 0,
+                           s, nd.xs.p, nd.n, na, key.p, hist.p);
+        FS_LAUNCHED();
+    }
+    // exclusive scan over ncells + 1 entries (last entry 0) gives start offsets and the total
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, hist.p, (int)(ncells + 1), 1 << 30,
+                       nd.nf_cell_start.p, chunkdummy.p, totals.p);
+    FS_LAUNCHED();
+    if (nd.n > 0) {
+        hipLaunchKernelGGL(k_nf_scatter, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256),
+                           0, s, nd.xs.p, nd.n, d, key.p, nd.nf_cell_start.p, cursor.p,
+                           nd.nf_order.p, nd.nf_xs.p);
+        FS_LAUNCHED();
+    }
+    FS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, int d,
+                const fs_params &p, hipStream_t s) {
+    PlanParams &pp = pl.pp;
+    pl.flags = p.flags;
+    pp.d = d;
+    pp.kind = p.kernel;
+    pp.lambda = p.lambda;
+    pp.G = p.grid;
+    pp.sigma = p.oversampling ? p.oversampling : 2;
+    pp.m = p.window ? p.window : 6;
+    pp.W = 2 * pp.m;
+    pp.p = p.smoothness ? p.smoothness : 8;
+    FS_REQUIRE(d >= 1 && d <= 3, FS_EDOMAIN, "NFFT fast summation supports d in 1..3 (got %d)", d);
+    FS_REQUIRE(pp.G >= 16 && pp.G <= 512 && (pp.G & (pp.G - 1)) == 0, FS_EINVAL,
+               "grid must be a power of two in 16..512 (got %d)", pp.G);
+    FS_REQUIRE(pp.sigma >= 2 && pp.G % pp.sigma == 0, FS_EINVAL,
+               "oversampling must be an integer >= 2 dividing the grid (got %d)", pp.sigma);
+    pp.N = pp.G / pp.sigma;
+    FS_REQUIRE(pp.N >= 4 && pp.N % 2 == 0, FS_EINVAL, "bandwidth grid/oversampling must be even >= 4");
+    FS_REQUIRE(pp.m >= 2 && pp.m <= 8, FS_EINVAL, "window cutoff must be in 2..8 (got %d)", pp.m);
+    FS_REQUIRE(pp.W <= pp.G, FS_EINVAL, "window support 2m=%d exceeds the grid %d", pp.W, pp.G);
+    FS_REQUIRE(pp.p >= 2 && pp.p <= 16, FS_EINVAL, "smoothness must be in 2..16 (got %d)", pp.p);
+    FS_REQUIRE(pp.kind == FS_GAUSS || pp.kind == FS_LAPLACE || pp.kind == FS_ENERGY, FS_EINVAL,
+               "unknown kernel %d", pp.kind);
+    FS_REQUIRE(pp.kind == FS_ENERGY || (pp.lambda > 0 && std::isfinite(pp.lambda)), FS_EINVAL,
+               "lambda must be positive");
+    pp.T = (d == 3) ? 8 : (d == 2 ? 32 : 256);
+    if (pp.T > pp.G) pp.T = pp.G;
+    const int64_t nmax = std::max(n, m);
+    int ch = 64;
+    while (ch < 2048 && ch * 1024 < nmax) ch *= 2;
+    pp.chunk = ch;
+
+    // ---- bounding box of both point sets (A1)
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    {
+        const int nb = 512;
+        DevBuf<float> part(nb * 6 * 2);
+        DevBuf<int> bad(1);
+        fill_i32(bad.p, 1, 0, s);
+        fill_f32(part.p, nb * 6 * 2, 0.0f, s);
+        if (n > 0) {
+            hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, x, n, d, part.p, bad.p);
+            FS_LAUNCHED();
+        }
+        if (m > 0 && y != x) {
+            hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, y, m, d, part.p + nb * 6, bad.p);
+            FS_LAUNCHED();
+        }
+        std::vector<float> h(nb * 12);
+        int hb = 0;
+        FS_HIP(hipMemcpyAsync(h.data(), part.p, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipStreamSynchronize(s));
+        FS_REQUIRE(hb == 0, FS_EDOMAIN, "non-finite point coordinates");
+        for (int set = 0; set < 2; ++set) {
+            if ((set == 0 && n == 0) || (set == 1 && (m == 0 || y == x))) continue;
+            for (int b = 0; b < nb; ++b)
+                for (int k = 0; k < d; ++k) {
+                    lo[k] = std::min(lo[k], (double)h[set * nb * 6 + b * 6 + k]);
+                    hi[k] = std::max(hi[k], (double)h[set * nb * 6 + b * 6 + 3 + k]);
+                }
+        }
+    }
+    double ext = 0.0, diag2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        if (!(lo[k] <= hi[k])) { lo[k] = hi[k] = 0.0; }
+        pp.center[k] = 0.5 * (lo[k] + hi[k]);
+        double e = hi[k] - lo[k];
+        ext = std::max(ext, e);
+        diag2 += e * e;
+    }
+    const double diag = std::sqrt(diag2);
+
+    // ---- period and regularisation (Section "approximation aspects": K is replaced by a smooth
+    //      periodic K_R; "heuristic stabilisation": the data are rescaled into the torus)
+    const double tolK = 1e-10, ltol = std::log(1.0 / tolK);
+    double Pcube = INFINITY;
+    if (pp.kind == FS_GAUSS) {
+        const double rk = std::sqrt(pp.lambda * ltol);
+        Pcube = std::max(ext + rk, 2.0 * rk);
+    } else if (pp.kind == FS_LAPLACE) {
+        const double rk = pp.lambda * ltol;
+        Pcube = std::max(ext + rk, 2.0 * rk);
+    }
+    // the boundary-regularised (ball) torus needs a boundary zone epsB = p/N narrower than the
+    // half period; the cube periodisation needs a kernel that decays within the padding
+    const double epsB_default = (double)pp.p / pp.N;
+    const bool ball_ok = epsB_default < 0.4;
+    const double Pball = ball_ok ? std::max(diag, 1e-6) / (0.5 - epsB_default) * (1.0 + 1e-6)
+                                 : INFINITY;
+    if (std::isfinite(Pcube) && Pcube <= Pball) {
+        pp.regime = REGIME_CUBE;
+        pp.P = Pcube;
+        pp.epsB = 0.0;
+    } else {
+        FS_REQUIRE(ball_ok, FS_EINVAL,
+                   "smoothness %d too large for bandwidth %d: the boundary regularisation needs "
+                   "p/N < 0.4 (raise grid or lower smoothness)", pp.p, pp.N);
+        pp.regime = REGIME_BALL;
+        pp.P = Pball;
+        pp.epsB = epsB_default;
+    }
+    pp.nearfield = (pp.kind != FS_GAUSS) && !(p.flags & FS_FLAG_NO_NEARFIELD);
+    if (pp.kind != FS_GAUSS) {
+        pp.epsI = (p.nearfield_radius > 0) ? p.nearfield_radius / pp.P : (double)pp.p / pp.N;
+        FS_REQUIRE(pp.epsI < 0.5 - pp.epsB - 1e-9 && pp.epsI > 0, FS_EINVAL,
+                   "near-field radius %g (torus %g) incompatible with the torus size",
+                   p.nearfield_radius, pp.epsI);
+        inner_poly(pp.kind, pp.lambda, pp.P, pp.epsI, pp.p, pp.ci);
+    } else {
+        pp.epsI = 0.0;
+    }
+    if (pp.regime == REGIME_BALL) boundary_poly(pp.kind, pp.lambda, pp.P, pp.epsB, pp.p, pp.cb);
+
+    // ---- window
+    const double b = M_PI * (2.0 - 1.0 / pp.sigma);
+    pp.kb.m = (float)pp.m;
+    pp.kb.b = (float)b;
+    pp.kb.inv_one_minus = (float)(1.0 / (-std::expm1(-2.0 * b * pp.m)));
+
+    // ---- bin the point sets (A2)
+    pl.same = (y == x && m == n);
+    bin_nodes(pl.X, x, n, pp, s);
+    if (!pl.same) bin_nodes(pl.Y, y, m, pp, s);
+
+    if (pp.nearfield) {
+        pp.nf_h = pp.epsI * pp.P * (1.0 + 1e-6);
+        for (int k = 0; k < 3; ++k) {
+            pp.nf_lo[k] = (k < d) ? lo[k] : 0.0;
+            pp.nf_dims[k] = 1;
+        }
+        int64_t ncells = 1;
+        for (int k = 0; k < d; ++k) {
+            int64_t dk = (int64_t)std::floor((hi[k] - lo[k]) / pp.nf_h) + 1;
+            dk = std::max<int64_t>(1, std::min<int64_t>(dk, 4096));
+            pp.nf_dims[k] = (int)dk;
+            ncells *= dk;
+        }
+        FS_REQUIRE(ncells < (int64_t(1) << 26), FS_EINVAL, "near-field cell grid too large");
+        build_nearfield_cells(pl.X, pp, s);
+        if (!pl.same) build_nearfield_cells(pl.Y, pp, s);
+    }
+
+    // ---- Fourier coefficients b_k of K_R and the multiplier M_k (A3)
+    {
+        const int N = pp.N, H = N / 2 + 1;
+        int64_t nsamp = 1, nh = 1;
+        for (int k = 0; k < d; ++k) { nsamp *= N; nh *= H; }
+        DevBuf<double> samp(nsamp), t1(nsamp), t2(nsamp), costab(N), dconv(H);
+        std::vector<double> hc(N), hd(H);
+        for (int q = 0; q < N; ++q) hc[q] = std::cos(2.0 * M_PI * q / N);
+        for (int k = 0; k < H; ++k) {
+            const double ph = kb_hat(pp.m, b, pp.G, k);
+            hd[k] = 1.0 / ((double)pp.G * pp.G * ph * ph);
+        }
+        FS_HIP(hipMemcpyAsync(costab.p, hc.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
+        FS_HIP(hipMemcpyAsync(dconv.p, hd.data(), H * sizeof(double), hipMemcpyHostToDevice, s));
+        RegArgs ra{};
+        ra.kind = pp.kind;
+        ra.regime = pp.regime;
+        ra.p = pp.p;
+        ra.lambda = pp.lambda;
+        ra.P = pp.P;
+        ra.epsI = pp.epsI;
+        ra.epsB = pp.epsB;
+        std::memcpy(ra.ci, pp.ci, sizeof(ra.ci));
+        std::memcpy(ra.cb, pp.cb, sizeof(ra.cb));
+        hipLaunchKernelGGL(k_sample_kr, dim3(blocks_for(nsamp, 256, 65536)), dim3(256), 0, s, ra,
+                           N, d, samp.p);
+        FS_LAUNCHED();
+        // axis 0 (fastest): A = N^{d-1}, B = 1 ; axis 1: A = N^{d-2}, B = H ; axis 2: A = 1, B = H^2
+        const double *in = samp.p;
+        double *outs[3] = {t1.p, t2.p, t1.p};
+        int64_t B = 1, A = nsamp / N;
+        for (int ax = 0; ax < d; ++ax) {
+            const int64_t work = A * H * B;
+            hipLaunchKernelGGL(k_cos_dft, dim3(blocks_for(work, 256, 65536)), dim3(256), 0, s, in, A,
+                               N, B, costab.p, outs[ax]);
+            FS_LAUNCHED();
+            in = outs[ax];
+            B *= H;
+            A /= N;
+        }
+        pl.Mk.alloc(nh);
+        const double scale = std::pow((double)N, -(double)d);
+        hipLaunchKernelGGL(k_build_mult, dim3(blocks_for(nh, 256, 65536)), dim3(256), 0, s, in, N,
+                           d, dconv.p, scale, pl.Mk.p);
+        FS_LAUNCHED();
+        FS_HIP(hipStreamSynchronize(s));
+    }
+
+    // ---- FFT buffers and twiddles
+    {
+        const int G = pp.G, N = pp.N, KX = N / 2 + 1;
+        int64_t gsz = 1;
+        for (int k = 0; k < d; ++k) gsz *= G;
+        pl.grid.alloc(gsz);
+        if (d >= 2) pl.specA.alloc((gsz / G) * KX);
+        if (d == 3) pl.specB.alloc((int64_t)G * (N + 1) * KX);
+        std::vector<float2> tw(G / 2);
+        for (int q = 0; q < G / 2; ++q) {
+            double a = -2.0 * M_PI * q / G;
+            tw[q] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+        pl.twiddle.alloc(G / 2);
+        FS_HIP(hipMemcpyAsync(pl.twiddle.p, tw.data(), tw.size() * sizeof(float2),
+                              hipMemcpyHostToDevice, s));
+        const int S = pp.T + pp.W - 1;
+        int64_t box = 1;
+        for (int k = 0; k < d; ++k) box *= S;
+        const int nch = std::max(pl.X.nchunks, pl.same ? 0 : pl.Y.nchunks);
+        pl.scratch.alloc((int64_t)std::max(nch, 1) * box);
+        pl.wbuf.alloc(std::max(n, m) + 1);
+        pl.tbuf.alloc(std::max(n, m) + 1);
+        FS_HIP(hipStreamSynchronize(s));
+    }
+}
+
+// ------------------------------------------------------------------ apply
+namespace {
+
+template <int D, int W>
+void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const float *w,
+                          float *t, float *grad, hipStream_t s) {
+    const PlanParams &pp = pl.pp;
+    SpreadArgs sa{pp.kb, pp.G, pp.T, pp.G / pp.T, pp.m};
+    // the tile side shrinks to the grid size for small grids
+    auto run = [&](auto tconst) {
+        constexpr int T = decltype(tconst)::value;
+        if (src.nchunks > 0) {
+            if constexpr (D == 1) {
+                hipLaunchKernelGGL((k_spread<D, W, T>), dim3(src.nchunks), dim3(256), 0, s,
+                                   src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
+            } else {
+                hipLaunchKernelGGL((k_spread_wave<D, W, T>), dim3(src.nchunks), dim3(256), 0, s,
+                                   src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
+            }
+            FS_LAUNCHED();
+            int box = 1;
+            for (int k = 0; k < D; ++k) box *= (T + W - 1);
+            int64_t ntiles = 1;
+            for (int k = 0; k < D; ++k) ntiles *= pp.G / T;
+            hipLaunchKernelGGL(k_reduce_chunks,
+                               dim3((box + 255) / 256, (unsigned)std::min<int64_t>(ntiles, 65535)),
+                               dim3(256), 0, s, pl.scratch.p, src.tile_chunk.p, (int)ntiles, box);
+            FS_LAUNCHED();
+        }
+        int64_t gsz = 1;
+        for (int k = 0; k < D; ++k) gsz *= pp.G;
+        if (src.nchunks > 0) {
+            hipLaunchKernelGGL(k_fold<D>, dim3(blocks_for(gsz, 256, 1 << 16)), dim3(256), 0, s,
+                               pl.scratch.p, src.tile_chunk.p, pp.G, T, pp.G / T, pp.m,
+                               T + W - 1, pl.grid.p);
+            FS_LAUNCHED();
+        } else {
+            fill_f32(pl.grid.p, gsz, 0.0f, s);
+        }
+        // FFT -> multiply -> inverse FFT
+        FftArgs fa{};
+        fa.G = pp.G;
+        fa.logG = 0;
+        while ((1 << fa.logG) < pp.G) ++fa.logG;
+        fa.N = pp.N;
+        fa.KX = pp.N / 2 + 1;
+        const int nbmax = FFT_ELEMS / pp.G;
+        const int nblk = (fa.KX + nbmax - 1) / nbmax;
+        fa.nbx = (fa.KX + nblk - 1) / nblk;
+        if (D == 1) {
+            hipLaunchKernelGGL(k_fft_1d_conv, dim3(1), dim3(FFT_THREADS), 0, s, pl.grid.p, fa,
+                               pl.twiddle.p, pl.Mk.p);
+            FS_LAUNCHED();
+        } else {
+            const int rows = (int)(gsz / pp.G);
+            const int pairs = rows / 2, nbp = FFT_ELEMS / pp.G;
+            const unsigned xblocks = (pairs + nbp - 1) / nbp;
+            hipLaunchKernelGGL(k_fft_x_r2c, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.grid.p, rows,
+                               fa, pl.twiddle.p, pl.specA.p);
+            FS_LAUNCHED();
+            const int nkb = (fa.KX + fa.nbx - 1) / fa.nbx;
+            if (D == 2) {
+                hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(FFT_THREADS), 0, s, pl.specA.p,
+                                   pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                FS_LAUNCHED();
+            } else {
+                hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
+                                   pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                FS_LAUNCHED();
+                hipLaunchKernelGGL(k_fft_z_conv, dim3((pp.N + 1) * nkb), dim3(FFT_THREADS), 0, s,
+                                   pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                FS_LAUNCHED();
+                hipLaunchKernelGGL(k_fft_y<2>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
+                                   pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                FS_LAUNCHED();
+            }
+            hipLaunchKernelGGL(k_fft_x_c2r, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.specA.p,
+                               rows, fa, pl.twiddle.p, pl.grid.p);
+            FS_LAUNCHED();
+        }
+        if (dst.n > 0) {
+            if (dst.nchunks > 0) {
+                const float gscale = (float)(pp.G / pp.P);
+                if (grad) {
+                    hipLaunchKernelGGL((k_gather<D, W, T, true>), dim3(dst.nchunks), dim3(256), 0,
+                                       s, dst.rec.p, dst.chunks.p, sa, pl.grid.p, t, grad, gscale);
+                } else {
+                    hipLaunchKernelGGL((k_gather<D, W, T, false>), dim3(dst.nchunks), dim3(256), 0,
+                                       s, dst.rec.p, dst.chunks.p, sa, pl.grid.p, t, grad, gscale);
+                }
+                FS_LAUNCHED();
+            }
+        }
+    };
+    if constexpr (D == 3) {
+        FS_REQUIRE(pp.T == 8, FS_EUNSUPPORTED, "unsupported tile size %d for d=3", pp.T);
+        run(std::integral_constant<int, 8>{});
+    } else if constexpr (D == 2) {
+        if (pp.T == 32) run(std::integral_constant<int, 32>{});
+        else if (pp.T == 16) run(std::integral_constant<int, 16>{});
+        else FS_REQUIRE(false, FS_EUNSUPPORTED, "unsupported tile size %d for d=2", pp.T);
+    } else {
+        switch (pp.T) {
+            case 256: run(std::integral_constant<int, 256>{}); break;
+            case 128: run(std::integral_constant<int, 128>{}); break;
+            case 64: run(std::integral_constant<int, 64>{}); break;
+            case 32: run(std::integral_constant<int, 32>{}); break;
+            case 16: run(std::integral_constant<int, 16>{}); break;
+            default: FS_REQUIRE(false, FS_EUNSUPPORTED, "unsupported tile size %d for d=1", pp.T);
+        }
+    }
+}
+
+template <int D>
+void dispatch_w(Plan &pl, const Nodes &src, const Nodes &dst, const float *w, float *t,
+                float *grad, hipStream_t s) {
+    switch (pl.pp.W) {
+        case 4: return launch_spread_gather<D, 4>(pl, src, dst, w, t, grad, s);
+        case 6: return launch_spread_gather<D, 6>(pl, src, dst, w, t, grad, s);
+        case 8: return launch_spread_gather<D, 8>(pl, src, dst, w, t, grad, s);
+        case 10: return launch_spread_gather<D, 10>(pl, src, dst, w, t, grad, s);
+        case 12: return launch_spread_gather<D, 12>(pl, src, dst, w, t, grad, s);
+        case 14: return launch_spread_gather<D, 14>(pl, src, dst, w, t, grad, s);
+        case 16: return launch_spread_gather<D, 16>(pl, src, dst, w, t, grad, s);
+        default: FS_REQUIRE(false, FS_EINVAL, "unsupported window %d", pl.pp.W);
+    }
+}
+
+}  // namespace
+
+void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *grad,
+                       int transpose, hipStream_t s) {
+    const Nodes &src = pl.src(transpose);
+    const Nodes &dst = pl.dst(transpose);
+    switch (pl.pp.d) {
+        case 1: dispatch_w<1>(pl, src, dst, w_sorted, t_sorted, grad, s); break;
+        case 2: dispatch_w<2>(pl, src, dst, w_sorted, t_sorted, grad, s); break;
+        default: dispatch_w<3>(pl, src, dst, w_sorted, t_sorted, grad, s); break;
+    }
+    if (pl.pp.nearfield && dst.n > 0 && src.n > 0) {
+        const PlanParams &pp = pl.pp;
+        NearArgs na{};
+        na.kind = pp.kind;
+        na.p = pp.p;
+        na.d = pp.d;
+        na.lambda_inv = (float)(pp.kind == FS_ENERGY ? 0.0 : 1.0 / pp.lambda);
+        na.rinv = (float)(1.0 / (pp.epsI * pp.P));
+        na.r2max = (float)((pp.epsI * pp.P) * (pp.epsI * pp.P));
+        for (int k = 0; k < 16; ++k) na.ci[k] = (float)pp.ci[k];
+        na.h_inv = (float)(1.0 / pp.nf_h);
+        for (int k = 0; k < 3; ++k) {
+            na.lo[k] = (float)pp.nf_lo[k];
+            na.dims[k] = pp.nf_dims[k];
+        }
+        dim3 g(blocks_for(dst.n, 256, int64_t(1) << 30)), b(256);
+#define FS_NF(DD, GG)                                                                        \
+    hipLaunchKernelGGL((k_nearfield<DD, GG>), g, b, 0, s, dst.xs.p, dst.n,                   \
+                       src.nf_cell_start.p, src.nf_order.p, src.nf_xs.p, w_sorted, na, t_sorted, \
+                       grad)
+        if (grad) {
+            if (pp.d == 1) FS_NF(1, true); else if (pp.d == 2) FS_NF(2, true); else FS_NF(3, true);
+        } else {
+            if (pp.d == 1) FS_NF(1, false); else if (pp.d == 2) FS_NF(2, false); else FS_NF(3, false);
+        }
+#undef FS_NF
+        FS_LAUNCHED();
+    }
+}
+
+}  // namespace fs

@@ -1,0 +1,113 @@
+// Error state, workspace cache and small utility kernels of libfastuot.
+#include <cstdarg>
+#include <map>
+#include <mutex>
+
+#include "internal.h"
+
+namespace fs {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+const char *last_error() { return g_err; }
+
+// ------------------------------------------------------------------ workspace cache
+namespace {
+struct Cache {
+    std::mutex mu;
+    std::map<void *, size_t> live;              // pointer -> size
+    std::multimap<size_t, void *> free_blocks;  // size -> pointer
+    size_t free_bytes = 0;
+};
+Cache &cache() {
+    static Cache *c = new Cache();  // never destroyed: blocks live until process exit
+    return *c;
+}
+}  // namespace
+
+void *ws_alloc(size_t bytes) {
+    // round to 256 B so that nearby sizes share blocks
+    size_t sz = (bytes + 255) & ~size_t(255);
+    Cache &c = cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        auto it = c.free_blocks.find(sz);
+        if (it != c.free_blocks.end()) {
+            void *p = it->second;
+            c.free_blocks.erase(it);
+            c.free_bytes -= sz;
+            c.live[p] = sz;
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // give cached blocks back and retry once
+        ws_release_all();
+        e = hipMalloc(&p, sz);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("device allocation of %zu bytes failed: %s", sz, hipGetErrorString(e));
+            throw Error{FS_ENOMEM};
+        }
+    }
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.live[p] = sz;
+    return p;
+}
+
+void ws_free(void *p) {
+    if (!p) return;
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    c.free_blocks.emplace(it->second, p);
+    c.free_bytes += it->second;
+    c.live.erase(it);
+}
+
+void ws_release_all() {
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    // the caller guarantees no queued work still uses cached blocks (they were freed by it)
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c.free_blocks) (void)hipFree(kv.second);
+    c.free_blocks.clear();
+    c.free_bytes = 0;
+}
+
+// ------------------------------------------------------------------ fills
+template <class T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_f32(float *p, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<float>, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    FS_LAUNCHED();
+}
+void fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    FS_LAUNCHED();
+}
+void fill_i32(int *p, int64_t n, int v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<int>, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+    FS_LAUNCHED();
+}
+
+}  // namespace fs

@@ -1,0 +1,72 @@
+// Operators (direct or NFFT) and the Sinkhorn / MMD drivers built on them.
+#pragma once
+#include <memory>
+
+#include "direct.h"
+#include "nfft.h"
+
+namespace fs {
+
+// A kernel-sum operator between a target set X (n) and a source set Y (m).  "Operator order" is
+// the order in which the operator wants its vectors: tile-sorted for the NFFT path, the caller's
+// order for the direct path.
+struct Op {
+    bool fast = false;
+    bool mfma = false;
+    int d = 0, kind = FS_GAUSS;
+    double lambda = 1.0;
+    unsigned flags = 0;
+    int64_t n = 0, m = 0;
+    const float *x = nullptr, *y = nullptr;  // caller order (direct path)
+    bool same = false;
+    std::unique_ptr<Plan> plan;
+    GramOperand gx, gy;
+    DevBuf<float> xcopy, ycopy;  // direct path keeps copies only when asked to
+
+    int64_t count(int side) const { return side == 0 ? n : m; }  // 0: X, 1: Y
+    // caller order -> operator order (side 0: X, 1: Y)
+    void to_op(int side, const float *v, float *vo, hipStream_t s) const;
+    void to_op64(int side, const double *v, double *vo, hipStream_t s) const;
+    void from_op(int side, const float *vo, float *v, hipStream_t s) const;
+    void from_op64(int side, const double *vo, double *v, hipStream_t s) const;
+    void rows_from_op(int side, const float *vo, float *v, hipStream_t s) const;
+    // coordinates of a side in operator order (n x d)
+    const float *coords(int side) const;
+    // transpose = 0: t (X, op order) = K w (Y, op order); 1: t (Y) = K^T w (X).
+    // grad (nullable): gradient of t with respect to the target positions (op order, x d).
+    void apply(const float *w, float *t, float *grad, int transpose, hipStream_t s);
+};
+
+std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m, int d,
+                            const fs_params &p, hipStream_t s);
+
+struct SinkhornResult {
+    double objective = 0.0;
+};
+
+// Sinkhorn in operator order.  a_o (n), b_o (m) float weights; f_o, g_o double potentials
+// (in/out; used as starting values when warm).
+void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, double rho, int iters,
+                    bool warm, double *f_o, double *g_o, double *objective_host, hipStream_t s);
+
+// Envelope gradients of the UOT dual at given potentials (caller order in and out); any output
+// may be NULL.  Scaled by `scale`.
+void uot_grad_core(Op &op, const float *a, const float *b, const double *f, const double *g,
+                   double eps, double rho, double scale, float *dx, float *da, float *dy,
+                   float *db, hipStream_t s);
+
+// MMD^2 on the union z = (x, y) with weights (a, -b); terms3 (nullable) gets the three sums.
+void mmd_core(const float *x, const float *a, int64_t n, const float *y, const float *b,
+              int64_t m, int d, const fs_params &p, double *mmd2, double *terms3, hipStream_t s);
+void mmd_grad_core(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                   int64_t m, int d, const fs_params &p, double scale, float *dx, float *da,
+                   float *dy, float *db, hipStream_t s);
+
+// Compensated FP64 sum / dot of float vectors on the device, returned to the host.
+double device_sum(const float *u, int64_t n, hipStream_t s);
+double device_dot(const float *u, const float *v, int64_t n, hipStream_t s);
+// out = s1 u + s2 v + cst  (v nullable)
+void combine(const float *u, const float *v, int64_t n, double s1, double s2, double cst,
+             float *out, hipStream_t s);
+
+}  // namespace fs

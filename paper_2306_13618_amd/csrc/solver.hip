@@ -1,0 +1,716 @@
+// Unbalanced Sinkhorn (Algorithm 2), MMD (eq. (1205)), Sinkhorn divergence (eq. (586)) and the
+// envelope gradients, on top of the kernel-sum operators.
+//
+// Precision split: the kernel sums (spread / FFT / gather, or the direct pair loop) run in FP32;
+// the potential updates, the weights' exponent shift and every final reduction run in FP64.
+//
+// Log-domain bookkeeping.  With k_ij = exp(-C_ij / eps) and kappa = rho / (rho + eps), the beta
+// half-step of eq. (Sinkhorn_uot_iteration) is
+//     f_i = -eps kappa log sum_j k_ij b_j e^{g_j/eps}.
+// The sum is formed with shifted weights  w_j = b_j e^{(g_j - gmax)/eps} in (0, b_j]  (so FP32
+// cannot overflow), and the shift is added back in FP64:
+//     f_i = -kappa (gmax + eps log t_i),   t_i = sum_j k_ij w_j.
+#include <cfloat>
+
+#include "solver.h"
+
+namespace fs {
+
+// =====================================================================================
+//                                        kernels
+// =====================================================================================
+namespace {
+
+constexpr int RT = 256;     // threads for reductions
+constexpr int RBLK = 1024;  // max blocks for reductions
+
+__device__ __forceinline__ void nadd(double &s, double &c, double v) {
+    double t = s + v;
+    if (fabs(s) >= fabs(v)) c += (s - t) + v; else c += (v - t) + s;
+    s = t;
+}
+
+// w_k = base_k exp((pot_k - *potmax) / eps)   (FP64 exponent, FP32 result)
+__global__ void k_weights(const float *__restrict__ base, const double *__restrict__ pot,
+                          const double *__restrict__ potmax, double inv_eps, int64_t n,
+                          float *__restrict__ w) {
+    const double pm = *potmax;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = (float)((double)base[i] * exp((pot[i] - pm) * inv_eps));
+}
+
+// pot_i = -kappa (*shift + eps log t_i) in FP64; *out_max = max_i pot_i (last-block reduction).
+// Non-positive sums are counted in *nbad and replaced by the smallest normal float.
+__global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int64_t n,
+                                               const double *__restrict__ shift, double kappa,
+                                               double eps, double *__restrict__ pot,
+                                               double *__restrict__ partial,
+                                               unsigned *__restrict__ counter,
+                                               double *__restrict__ out_max, int *__restrict__ nbad) {
+    __shared__ double sm[RT];
+    __shared__ bool last;
+    const double sh = *shift;
+    double mx = -INFINITY;
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v = t[i];
+        if (!(v > 0.0f)) { bad++; v = FLT_MIN; }
+        const double f = -kappa * (sh + eps * log((double)v));
+        pot[i] = f;
+        mx = fmax(mx, f);
+    }
+    if (bad) atomicAdd(nbad, bad);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = sm[0];
+        __threadfence();
+        unsigned ticket = atomicAdd(counter, 1u);
+        last = (ticket == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        double v = -INFINITY;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += RT) v = fmax(v, partial[b]);
+        sm[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = RT / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            *out_max = (n > 0) ? sm[0] : 0.0;
+            *counter = 0u;
+        }
+    }
+}
+
+// max of a double array (last-block pattern), used for warm starts.
+__global__ void __launch_bounds__(RT) k_max64(const double *__restrict__ v, int64_t n,
+                                              double *__restrict__ partial,
+                                              unsigned *__restrict__ counter,
+                                              double *__restrict__ out) {
+    __shared__ double sm[RT];
+    __shared__ bool last;
+    double mx = -INFINITY;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        mx = fmax(mx, v[i]);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = sm[0];
+        __threadfence();
+        last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        double w = -INFINITY;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += RT) w = fmax(w, partial[b]);
+        sm[threadIdx.x] = w;
+        __syncthreads();
+        for (int s = RT / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            *out = (n > 0) ? sm[0] : 0.0;
+            *counter = 0u;
+        }
+    }
+}
+
+// Compensated FP64 sums of per-element terms.  MODE 0 (objective pieces for one side):
+//   out[0] += sum base (1 - e^{-pot/rho}),  out[1] += sum base e^{-pot/rho},  out[2] += sum base
+// MODE 1 (dot products):  out[0] += sum u v,  with optional split by perm < split:
+//   out[1] += sum_{perm < split} u v, out[2] += sum_{perm >= split} u v.
+// Each block writes (sum, compensation) pairs; the last block folds them with Neumaier sums.
+template <int MODE>
+__global__ void __launch_bounds__(RT) k_csum(const float *__restrict__ u, const double *__restrict__ pot,
+                                             const float *__restrict__ v, const int *__restrict__ perm,
+                                             int64_t split, int64_t n, double rho,
+                                             double *__restrict__ partial,
+                                             unsigned *__restrict__ counter,
+                                             double *__restrict__ out) {
+    __shared__ double ss[3][RT], sc[3][RT];
+    __shared__ bool last;
+    double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (MODE == 0) {
+            const double bi = u[i], e = exp(-pot[i] / rho);
+            nadd(s[0], c[0], -bi * expm1(-pot[i] / rho));
+            nadd(s[1], c[1], bi * e);
+            nadd(s[2], c[2], bi);
+        } else if (MODE == 2) {
+            nadd(s[0], c[0], (double)u[i]);
+        } else {
+            const double pv = (double)u[i] * (double)v[i];
+            nadd(s[0], c[0], pv);
+            if (perm) {
+                if (perm[i] < split) nadd(s[1], c[1], pv); else nadd(s[2], c[2], pv);
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) { ss[k][threadIdx.x] = s[k]; sc[k][threadIdx.x] = c[k]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; ++k) {
+            double S = 0, C = 0;
+            for (int t = 0; t < RT; ++t) { nadd(S, C, ss[k][t]); nadd(S, C, sc[k][t]); }
+            partial[(blockIdx.x * 3 + k) * 2] = S;
+            partial[(blockIdx.x * 3 + k) * 2 + 1] = C;
+        }
+        __threadfence();
+        last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        for (int k = 0; k < 3; ++k) {
+            double S = 0, C = 0;
+            for (int b = 0; b < (int)gridDim.x; ++b) {
+                nadd(S, C, partial[(b * 3 + k) * 2]);
+                nadd(S, C, partial[(b * 3 + k) * 2 + 1]);
+            }
+            out[k] = S + C;
+        }
+        *counter = 0u;
+    }
+}
+
+// Direct gradient sum: g_i = sum_j grad K(x_i - y_j) w_j (and t_i), any d <= 128.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_direct_grad(const float *__restrict__ x, int64_t n,
+                                                     const float *__restrict__ y, int64_t m,
+                                                     int d, const float *__restrict__ w,
+                                                     float lam_inv, float *__restrict__ t,
+                                                     float *__restrict__ g) {
+    constexpr int GT = 32;
+    __shared__ float sy[GT * 128];
+    __shared__ float sw[GT];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float *xi = x + (i < n ? i : 0) * d;
+    double acc = 0.0;
+    double gacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int dd = d < 8 ? d : 8;
+    for (int64_t j0 = 0; j0 < m; j0 += GT) {
+        const int cnt = (int)((m - j0) < GT ? (m - j0) : GT);
+        __syncthreads();
+        for (int q = threadIdx.x; q < GT * d; q += blockDim.x) {
+            int jj = q / d;
+            sy[q] = (jj < cnt) ? y[(j0 + jj) * d + (q - jj * d)] : 0.0f;
+        }
+        for (int q = threadIdx.x; q < GT; q += blockDim.x) sw[q] = (q < cnt) ? w[j0 + q] : 0.0f;
+        __syncthreads();
+        float part = 0.0f, gp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int q = 0; q < cnt; ++q) {
+            float r2 = 0.0f;
+            for (int k = 0; k < d; ++k) {
+                float dv = xi[k] - sy[q * d + k];
+                r2 = fmaf(dv, dv, r2);
+            }
+            const float r = sqrtf(r2);
+            float kv, coef;  // K and (dK/dr)/r
+            if (KIND == FS_GAUSS) {
+                kv = __expf(-r2 * lam_inv);
+                coef = -2.0f * lam_inv * kv;
+            } else if (KIND == FS_LAPLACE) {
+                kv = __expf(-r * lam_inv);
+                coef = (r > 0.0f) ? -lam_inv * kv / r : 0.0f;
+            } else {
+                kv = -r;
+                coef = (r > 0.0f) ? -1.0f / r : 0.0f;
+            }
+            part = fmaf(kv, sw[q], part);
+            for (int k = 0; k < dd; ++k) gp[k] = fmaf(coef * sw[q], xi[k] - sy[q * d + k], gp[k]);
+        }
+        acc += (double)part;
+        for (int k = 0; k < dd; ++k) gacc[k] += (double)gp[k];
+    }
+    if (i < n) {
+        if (t) t[i] = (float)acc;
+        for (int k = 0; k < dd; ++k) g[i * d + k] = (float)gacc[k];
+    }
+}
+
+// dx_i = coef * a_i * exp((f_i + gmax)/eps) * grad_i  (grad: d per row) and
+// da_i = rho (1 - e^{-f_i/rho}) - eps (exp((f_i + gmax)/eps) t_i - Mb)
+__global__ void k_uot_grad_rows(const float *__restrict__ a, const double *__restrict__ f,
+                                const float *__restrict__ t, const float *__restrict__ grad,
+                                int d, int64_t n, const double *__restrict__ gmax, double eps,
+                                double rho, const double *__restrict__ Mb, double scale,
+                                float *__restrict__ dx, float *__restrict__ da) {
+    const double gm = *gmax, mb = *Mb;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double e = exp((f[i] + gm) / eps);
+        if (dx)
+            for (int k = 0; k < d; ++k)
+                dx[i * d + k] = (float)(-scale * eps * (double)a[i] * e * (double)grad[i * d + k]);
+        if (da) da[i] = (float)(scale * (-rho * expm1(-f[i] / rho) - eps * (e * (double)t[i] - mb)));
+    }
+}
+
+// out = s1 * u + s2 * v + s3 * c  (float outputs from float inputs; v may be NULL)
+__global__ void k_combine(const float *__restrict__ u, const float *__restrict__ v, int64_t n,
+                          double s1, double s2, double cst, float *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double r = s1 * (double)u[i] + cst;
+        if (v) r += s2 * (double)v[i];
+        out[i] = (float)r;
+    }
+}
+
+// MMD gradient rows on the union plan (operator order): with w_k the union weights,
+//   dz_k = 2 scale w_k grad s(z_k),   dw_k = 2 scale s(z_k) (sign folded for the b side).
+__global__ void k_mmd_grad_rows(const float *__restrict__ ws, const float *__restrict__ ts,
+                                const float *__restrict__ gs, const int *__restrict__ perm,
+                                int64_t ntot, int64_t n, int d, double scale,
+                                float *__restrict__ dx, float *__restrict__ da,
+                                float *__restrict__ dy, float *__restrict__ db) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ntot;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = perm ? perm[k] : k;
+        const double w = ws[k];
+        if (o < n) {
+            if (dx)
+                for (int c = 0; c < d; ++c) dx[o * d + c] = (float)(2.0 * scale * w * gs[k * d + c]);
+            if (da) da[o] = (float)(2.0 * scale * ts[k]);
+        } else {
+            const int64_t j = o - n;
+            if (dy)
+                for (int c = 0; c < d; ++c) dy[j * d + c] = (float)(2.0 * scale * w * gs[k * d + c]);
+            if (db) db[j] = (float)(-2.0 * scale * ts[k]);
+        }
+    }
+}
+
+__global__ void k_concat_weights(const float *__restrict__ a, int64_t n,
+                                 const float *__restrict__ b, int64_t m, float sa, float sb,
+                                 float *__restrict__ w) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n + m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = (i < n) ? sa * a[i] : sb * b[i - n];
+}
+
+}  // namespace
+
+// =====================================================================================
+//                                     operators
+// =====================================================================================
+std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m, int d,
+                            const fs_params &p, hipStream_t s) {
+    auto op = std::make_unique<Op>();
+    op->d = d;
+    op->kind = p.kernel;
+    op->lambda = p.lambda;
+    op->flags = p.flags;
+    op->n = n;
+    op->m = m;
+    op->x = x;
+    op->y = y;
+    op->same = (x == y && n == m);
+    FS_REQUIRE(p.kernel == FS_GAUSS || p.kernel == FS_LAPLACE || p.kernel == FS_ENERGY, FS_EINVAL,
+               "unknown kernel %d", p.kernel);
+    FS_REQUIRE(p.kernel == FS_ENERGY || (p.lambda > 0 && std::isfinite(p.lambda)), FS_EINVAL,
+               "lambda must be positive and finite");
+    if (p.grid > 0) {
+        op->fast = true;
+        op->plan = std::make_unique<Plan>();
+        plan_build(*op->plan, x, n, y, m, d, p, s);
+    } else {
+        FS_REQUIRE(d >= 1 && d <= 128, FS_EINVAL, "direct summation supports d in 1..128 (got %d)", d);
+        op->mfma = mfma_supported(p.kernel, d) && !(p.flags & FS_FLAG_FORCE_VALU);
+        if (op->mfma) {
+            gram_prepare(x, n, d, op->gx, s);
+            if (!op->same) gram_prepare(y, m, d, op->gy, s);
+        }
+    }
+    return op;
+}
+
+void Op::to_op(int side, const float *v, float *vo, hipStream_t s) const {
+    const int64_t c = count(side);
+    if (fast) gather_to_sorted(side == 0 ? plan->X : (plan->same ? plan->X : plan->Y), v, vo, s);
+    else if (c > 0 && v != vo) FS_HIP(hipMemcpyAsync(vo, v, c * sizeof(float), hipMemcpyDeviceToDevice, s));
+}
+void Op::to_op64(int side, const double *v, double *vo, hipStream_t s) const {
+    const int64_t c = count(side);
+    if (fast) gather_to_sorted64(side == 0 ? plan->X : (plan->same ? plan->X : plan->Y), v, vo, s);
+    else if (c > 0 && v != vo) FS_HIP(hipMemcpyAsync(vo, v, c * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+void Op::from_op(int side, const float *vo, float *v, hipStream_t s) const {
+    const int64_t c = count(side);
+    if (fast) scatter_from_sorted(side == 0 ? plan->X : (plan->same ? plan->X : plan->Y), vo, v, s);
+    else if (c > 0 && v != vo) FS_HIP(hipMemcpyAsync(v, vo, c * sizeof(float), hipMemcpyDeviceToDevice, s));
+}
+void Op::from_op64(int side, const double *vo, double *v, hipStream_t s) const {
+    const int64_t c = count(side);
+    if (fast) scatter_from_sorted64(side == 0 ? plan->X : (plan->same ? plan->X : plan->Y), vo, v, s);
+    else if (c > 0 && v != vo) FS_HIP(hipMemcpyAsync(v, vo, c * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+void Op::rows_from_op(int side, const float *vo, float *v, hipStream_t s) const {
+    const int64_t c = count(side);
+    if (fast) scatter_rows_from_sorted(side == 0 ? plan->X : (plan->same ? plan->X : plan->Y), vo, d, v, s);
+    else if (c > 0 && v != vo) FS_HIP(hipMemcpyAsync(v, vo, c * d * sizeof(float), hipMemcpyDeviceToDevice, s));
+}
+const float *Op::coords(int side) const {
+    if (fast) return (side == 0 ? plan->X : (plan->same ? plan->X : plan->Y)).xs.p;
+    return side == 0 ? x : y;
+}
+
+void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t s) {
+    const int64_t nt = transpose ? m : n, ns = transpose ? n : m;
+    if (nt == 0) return;
+    if (ns == 0) {
+        fill_f32(t, nt, 0.0f, s);
+        if (grad) fill_f32(grad, nt * d, 0.0f, s);
+        return;
+    }
+    if (fast) {
+        plan_apply_sorted(*plan, w, t, grad, transpose, s);
+        return;
+    }
+    const float *xt = transpose ? y : x, *ys = transpose ? x : y;
+    if (grad) {
+        FS_REQUIRE(d <= 8, FS_EUNSUPPORTED, "direct gradients support d <= 8 (got %d)", d);
+        const float li = (kind == FS_ENERGY) ? 0.0f : (float)(1.0 / lambda);
+        dim3 g(blocks_for(nt, 256, int64_t(1) << 30)), b(256);
+        if (kind == FS_GAUSS)
+            hipLaunchKernelGGL(k_direct_grad<FS_GAUSS>, g, b, 0, s, xt, nt, ys, ns, d, w, li, t, grad);
+        else if (kind == FS_LAPLACE)
+            hipLaunchKernelGGL(k_direct_grad<FS_LAPLACE>, g, b, 0, s, xt, nt, ys, ns, d, w, li, t, grad);
+        else
+            hipLaunchKernelGGL(k_direct_grad<FS_ENERGY>, g, b, 0, s, xt, nt, ys, ns, d, w, li, t, grad);
+        FS_LAUNCHED();
+        return;
+    }
+    if (mfma) {
+        const GramOperand &gt = transpose ? (same ? gx : gy) : gx;
+        const GramOperand &gs = transpose ? gx : (same ? gx : gy);
+        direct_mfma_gauss(lambda, gt, gs, w, t, nullptr, s);
+    } else {
+        direct_valu(kind, lambda, xt, nt, ys, ns, d, w, t, nullptr, s);
+    }
+}
+
+// =====================================================================================
+//                                       Sinkhorn
+// =====================================================================================
+namespace {
+
+struct Scalars {
+    // device scalars: [0] gmax, [1] fmax, [2] Mb, [3] Ma ; sums at [8..)
+    DevBuf<double> v;
+    DevBuf<double> partial;
+    DevBuf<unsigned> counter;
+    DevBuf<int> nbad;
+    Scalars() : v(32), partial(RBLK * 6), counter(1), nbad(1) {}
+    void reset(hipStream_t s) {
+        fill_f64(v.p, 32, 0.0, s);
+        fill_i32(reinterpret_cast<int *>(counter.p), 1, 0, s);
+        fill_i32(nbad.p, 1, 0, s);
+    }
+};
+
+unsigned red_blocks(int64_t n) { return blocks_for(n, RT, RBLK); }
+
+void launch_update(const float *t, int64_t n, const double *shift, double kappa, double eps,
+                   double *pot, Scalars &sc, double *out_max, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(red_blocks(n)), dim3(RT), 0, s, t, n, shift, kappa, eps,
+                       pot, sc.partial.p, sc.counter.p, out_max, sc.nbad.p);
+    FS_LAUNCHED();
+}
+
+void launch_weights(const float *base, const double *pot, const double *pmax, double eps,
+                    int64_t n, float *w, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_weights, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, base, pot,
+                       pmax, 1.0 / eps, n, w);
+    FS_LAUNCHED();
+}
+
+void launch_csum0(const float *base, const double *pot, int64_t n, double rho, Scalars &sc,
+                  double *out3, hipStream_t s) {
+    hipLaunchKernelGGL(k_csum<0>, dim3(red_blocks(n)), dim3(RT), 0, s, base, pot, nullptr,
+                       nullptr, (int64_t)0, n, rho, sc.partial.p, sc.counter.p, out3);
+    FS_LAUNCHED();
+}
+
+}  // namespace
+
+void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, double rho, int iters,
+                    bool warm, double *f_o, double *g_o, double *objective_host, hipStream_t s) {
+    const int64_t n = op.n, m = op.m;
+    const double kappa = rho / (rho + eps);
+    Scalars sc;
+    sc.reset(s);
+    double *gmax = sc.v.p + 0, *fmax = sc.v.p + 1;
+    DevBuf<float> wX(n + 1), wY(m + 1), tX(n + 1), tY(m + 1);
+    if (warm) {
+        hipLaunchKernelGGL(k_max64, dim3(red_blocks(m)), dim3(RT), 0, s, g_o, m, sc.partial.p,
+                           sc.counter.p, gmax);
+        FS_LAUNCHED();
+    } else {
+        fill_f64(g_o, m, 0.0, s);
+        fill_f64(f_o, n, 0.0, s);
+    }
+    for (int it = 0; it < iters; ++it) {
+        // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}
+        launch_weights(b_o, g_o, gmax, eps, m, wY.p, s);
+        op.apply(wY.p, tX.p, nullptr, 0, s);
+        if (n > 0) launch_update(tX.p, n, gmax, kappa, eps, f_o, sc, fmax, s);
+        // gamma half-step (Delta even): t~_j = sum_i k_ij a_i e^{f_i/eps}
+        launch_weights(a_o, f_o, fmax, eps, n, wX.p, s);
+        op.apply(wX.p, tY.p, nullptr, 1, s);
+        if (m > 0) launch_update(tY.p, m, fmax, kappa, eps, g_o, sc, gmax, s);
+    }
+    int nbad = 0;
+    if (objective_host) {
+        // Dual value of Theorem "dualization" at (f, g).  After a gamma half-step the double sum
+        // sum_ij a_i b_j e^{(f_i + g_j - C_ij)/eps} = sum_j b_j e^{g_j/eps} t~_j equals
+        // sum_j b_j e^{-g_j/rho} (the update makes e^{g_j/eps} t~_j = e^{-g_j/rho}), so no extra
+        // kernel sum is needed:  D = rho sum a (1 - e^{-f/rho}) + rho sum b (1 - e^{-g/rho})
+        //                            - eps (sum b e^{-g/rho} - Ma Mb).
+        // With no sweep done (f = g = 0 or the warm start) the double sum is formed explicitly.
+        double *sx = sc.v.p + 8, *sy = sc.v.p + 12, *sd = sc.v.p + 16;
+        launch_csum0(a_o, f_o, n, rho, sc, sx, s);
+        launch_csum0(b_o, g_o, m, rho, sc, sy, s);
+        if (iters == 0) {
+            // sum_i a_i e^{f_i/eps} sum_j k_ij b_j e^{g_j/eps}, shifted by fmax and gmax
+            if (n > 0) {
+                hipLaunchKernelGGL(k_max64, dim3(red_blocks(n)), dim3(RT), 0, s, f_o, n,
+                                   sc.partial.p, sc.counter.p, fmax);
+                FS_LAUNCHED();
+            }
+            launch_weights(b_o, g_o, gmax, eps, m, wY.p, s);
+            op.apply(wY.p, tX.p, nullptr, 0, s);
+            launch_weights(a_o, f_o, fmax, eps, n, wX.p, s);
+            hipLaunchKernelGGL(k_csum<1>, dim3(red_blocks(n)), dim3(RT), 0, s, wX.p, nullptr,
+                               tX.p, nullptr, (int64_t)0, n, rho, sc.partial.p, sc.counter.p, sd);
+            FS_LAUNCHED();
+        }
+        double h[20];
+        FS_HIP(hipMemcpyAsync(h, sc.v.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipMemcpyAsync(&nbad, sc.nbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipStreamSynchronize(s));
+        const double Ma = h[10], Mb = h[14];
+        double dsum = h[13];
+        if (iters == 0) {
+            double fm = 0.0, gm = 0.0;
+            FS_HIP(hipMemcpy(&fm, fmax, sizeof(double), hipMemcpyDeviceToHost));
+            FS_HIP(hipMemcpy(&gm, gmax, sizeof(double), hipMemcpyDeviceToHost));
+            dsum = h[16] * std::exp((fm + gm) / eps);
+        }
+        *objective_host = rho * h[8] + rho * h[12] - eps * (dsum - Ma * Mb);
+    } else {
+        FS_HIP(hipMemcpyAsync(&nbad, sc.nbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipStreamSynchronize(s));
+    }
+    FS_REQUIRE(nbad == 0, FS_ENUMERIC,
+               "%d kernel sums were not positive (points too far apart for lambda, or the fast "
+               "summation is not accurate enough for them)", nbad);
+}
+
+// =====================================================================================
+//                           reductions, gradients and MMD drivers
+// =====================================================================================
+namespace {
+
+void csum(const float *u, const float *v, const int *perm, int64_t split, int64_t n, int mode,
+          Scalars &sc, double *out3, hipStream_t s) {
+    if (mode == 2)
+        hipLaunchKernelGGL(k_csum<2>, dim3(red_blocks(n)), dim3(RT), 0, s, u, nullptr, v, perm,
+                           split, n, 0.0, sc.partial.p, sc.counter.p, out3);
+    else
+        hipLaunchKernelGGL(k_csum<1>, dim3(red_blocks(n)), dim3(RT), 0, s, u, nullptr, v, perm,
+                           split, n, 0.0, sc.partial.p, sc.counter.p, out3);
+    FS_LAUNCHED();
+}
+
+}  // namespace
+
+double device_sum(const float *u, int64_t n, hipStream_t s) {
+    if (n <= 0) return 0.0;
+    Scalars sc;
+    sc.reset(s);
+    csum(u, nullptr, nullptr, 0, n, 2, sc, sc.v.p, s);
+    double h = 0.0;
+    FS_HIP(hipMemcpyAsync(&h, sc.v.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+double device_dot(const float *u, const float *v, int64_t n, hipStream_t s) {
+    if (n <= 0) return 0.0;
+    Scalars sc;
+    sc.reset(s);
+    csum(u, v, nullptr, 0, n, 1, sc, sc.v.p, s);
+    double h = 0.0;
+    FS_HIP(hipMemcpyAsync(&h, sc.v.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+void combine(const float *u, const float *v, int64_t n, double s1, double s2, double cst,
+             float *out, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_combine, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, u, v, n, s1, s2,
+                       cst, out);
+    FS_LAUNCHED();
+}
+
+void uot_grad_core(Op &op, const float *a, const float *b, const double *f, const double *g,
+                   double eps, double rho, double scale, float *dx, float *da, float *dy,
+                   float *db, hipStream_t s) {
+    const int64_t n = op.n, m = op.m;
+    const int d = op.d;
+    Scalars sc;
+    sc.reset(s);
+    double *gmax = sc.v.p + 0, *fmax = sc.v.p + 1, *Mb = sc.v.p + 2, *Ma = sc.v.p + 3;
+    DevBuf<float> ao(n + 1), bo(m + 1), w(std::max(n, m) + 1), t(std::max(n, m) + 1),
+        gr((std::max(n, m) + 1) * d), ox((std::max(n, m) + 1) * d), o1(std::max(n, m) + 1);
+    DevBuf<double> fo(n + 1), go(m + 1);
+    op.to_op(0, a, ao.p, s);
+    op.to_op(1, b, bo.p, s);
+    op.to_op64(0, f, fo.p, s);
+    op.to_op64(1, g, go.p, s);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_max64, dim3(red_blocks(m)), dim3(RT), 0, s, go.p, m, sc.partial.p,
+                           sc.counter.p, gmax);
+        FS_LAUNCHED();
+    }
+    if (n > 0) {
+        hipLaunchKernelGGL(k_max64, dim3(red_blocks(n)), dim3(RT), 0, s, fo.p, n, sc.partial.p,
+                           sc.counter.p, fmax);
+        FS_LAUNCHED();
+    }
+    {
+        double *tmp = sc.v.p + 8;
+        csum(bo.p, nullptr, nullptr, 0, m, 2, sc, tmp, s);
+        FS_HIP(hipMemcpyAsync(Mb, tmp, sizeof(double), hipMemcpyDeviceToDevice, s));
+        csum(ao.p, nullptr, nullptr, 0, n, 2, sc, tmp, s);
+        FS_HIP(hipMemcpyAsync(Ma, tmp, sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if ((dx || da) && n > 0) {
+        launch_weights(bo.p, go.p, gmax, eps, m, w.p, s);
+        op.apply(w.p, t.p, gr.p, 0, s);
+        hipLaunchKernelGGL(k_uot_grad_rows, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, ao.p,
+                           fo.p, t.p, gr.p, d, n, gmax, eps, rho, Mb, scale,
+                           dx ? ox.p : nullptr, da ? o1.p : nullptr);
+        FS_LAUNCHED();
+        if (dx) op.rows_from_op(0, ox.p, dx, s);
+        if (da) op.from_op(0, o1.p, da, s);
+    }
+    if ((dy || db) && m > 0) {
+        launch_weights(ao.p, fo.p, fmax, eps, n, w.p, s);
+        op.apply(w.p, t.p, gr.p, 1, s);
+        hipLaunchKernelGGL(k_uot_grad_rows, dim3(blocks_for(m, 256, 8192)), dim3(256), 0, s, bo.p,
+                           go.p, t.p, gr.p, d, m, fmax, eps, rho, Ma, scale,
+                           dy ? ox.p : nullptr, db ? o1.p : nullptr);
+        FS_LAUNCHED();
+        if (dy) op.rows_from_op(1, ox.p, dy, s);
+        if (db) op.from_op(1, o1.p, db, s);
+    }
+    FS_HIP(hipStreamSynchronize(s));
+}
+
+namespace {
+
+// union point set z = (x, y) in caller order
+void make_union(const float *x, int64_t n, const float *y, int64_t m, int d, DevBuf<float> &z,
+                hipStream_t s) {
+    z.alloc((n + m) * d + 1);
+    if (n > 0) FS_HIP(hipMemcpyAsync(z.p, x, n * d * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (m > 0)
+        FS_HIP(hipMemcpyAsync(z.p + n * d, y, m * d * sizeof(float), hipMemcpyDeviceToDevice, s));
+}
+
+void concat_weights(const float *a, int64_t n, const float *b, int64_t m, float sa, float sb,
+                    float *w, hipStream_t s) {
+    if (n + m == 0) return;
+    hipLaunchKernelGGL(k_concat_weights, dim3(blocks_for(n + m, 256, 8192)), dim3(256), 0, s, a, n,
+                       b, m, sa, sb, w);
+    FS_LAUNCHED();
+}
+
+}  // namespace
+
+void mmd_core(const float *x, const float *a, int64_t n, const float *y, const float *b,
+              int64_t m, int d, const fs_params &p, double *mmd2, double *terms3, hipStream_t s) {
+    const int64_t nz = n + m;
+    if (nz == 0) {
+        if (mmd2) *mmd2 = 0.0;
+        if (terms3) terms3[0] = terms3[1] = terms3[2] = 0.0;
+        return;
+    }
+    DevBuf<float> z, wz(nz + 1), wo(nz + 1), to(nz + 1);
+    make_union(x, n, y, m, d, z, s);
+    auto op = make_op(z.p, nz, z.p, nz, d, p, s);
+    Scalars sc;
+    sc.reset(s);
+    double h[8] = {0};
+    if (!terms3) {
+        // one kernel sum with the signed weights w = (a, -b):  MMD^2 = w . K w
+        concat_weights(a, n, b, m, 1.0f, -1.0f, wz.p, s);
+        op->to_op(0, wz.p, wo.p, s);
+        op->apply(wo.p, to.p, nullptr, 0, s);
+        csum(wo.p, to.p, nullptr, 0, nz, 1, sc, sc.v.p, s);
+        FS_HIP(hipMemcpyAsync(h, sc.v.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipStreamSynchronize(s));
+        if (mmd2) *mmd2 = h[0];
+        return;
+    }
+    // two kernel sums, K (a, 0) and K (0, b), give the three double sums of eq. (1205)
+    DevBuf<float> w2(nz + 1), t2(nz + 1);
+    concat_weights(a, n, b, m, 1.0f, 0.0f, wz.p, s);
+    op->to_op(0, wz.p, wo.p, s);
+    op->apply(wo.p, to.p, nullptr, 0, s);
+    concat_weights(a, n, b, m, 0.0f, 1.0f, wz.p, s);
+    op->to_op(0, wz.p, w2.p, s);
+    op->apply(w2.p, t2.p, nullptr, 0, s);
+    csum(wo.p, to.p, nullptr, 0, nz, 1, sc, sc.v.p + 8, s);   // a K a
+    csum(wo.p, t2.p, nullptr, 0, nz, 1, sc, sc.v.p + 12, s);  // a K b
+    csum(w2.p, t2.p, nullptr, 0, nz, 1, sc, sc.v.p + 16, s);  // b K b
+    double hv[20];
+    FS_HIP(hipMemcpyAsync(hv, sc.v.p, sizeof(hv), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    terms3[0] = hv[8];
+    terms3[1] = hv[12];
+    terms3[2] = hv[16];
+    if (mmd2) *mmd2 = hv[8] - 2.0 * hv[12] + hv[16];
+}
+
+void mmd_grad_core(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                   int64_t m, int d, const fs_params &p, double scale, float *dx, float *da,
+                   float *dy, float *db, hipStream_t s) {
+    const int64_t nz = n + m;
+    if (nz == 0) return;
+    DevBuf<float> z, wz(nz + 1), wo(nz + 1), to(nz + 1), go(nz * d + 1);
+    make_union(x, n, y, m, d, z, s);
+    auto op = make_op(z.p, nz, z.p, nz, d, p, s);
+    concat_weights(a, n, b, m, 1.0f, -1.0f, wz.p, s);
+    op->to_op(0, wz.p, wo.p, s);
+    op->apply(wo.p, to.p, go.p, 0, s);
+    const int *perm = op->fast ? op->plan->X.perm.p : nullptr;
+    hipLaunchKernelGGL(k_mmd_grad_rows, dim3(blocks_for(nz, 256, 8192)), dim3(256), 0, s, wo.p,
+                       to.p, go.p, perm, nz, n, d, scale, dx, da, dy, db);
+    FS_LAUNCHED();
+    FS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace fs

@@ -1,0 +1,56 @@
+"""The C-ABI library loads and exports every symbol include/fastuot.h declares (CPU only: no
+compute calls), and the binding rejects bad arguments before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fastuot.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src)
+    skip = {"if", "sizeof"}
+    return sorted({n for n in names if n not in skip})
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for n in ("fastsum_apply", "uot_sinkhorn", "mmd", "fs_plan_create", "fs_plan_apply",
+              "fs_plan_destroy", "uot_sinkhorn_grad", "mmd_grad", "sinkhorn_divergence",
+              "sinkhorn_divergence_grad", "fs_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2306_13618_amd as fu
+    lib = ctypes.CDLL(fu.library_path())
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_symbols()) == set(fu.EXPORTED)
+
+
+def test_version_and_error_string_without_gpu():
+    import paper_2306_13618_amd as fu
+    assert fu._lib.fs_version() >= (1 << 16)
+    assert isinstance(fu._lib.fs_last_error(), bytes)
+
+
+def test_null_arguments_are_rejected_without_device_work():
+    import paper_2306_13618_amd as fu
+    p = fu._params("gauss", 0.1, 64, 6)
+    st = fu._lib.fastsum_apply(None, 10, None, 10, 3, None, None, ctypes.byref(p), None)
+    assert st == -1 and b"NULL" in fu._lib.fs_last_error()
+    st = fu._lib.uot_sinkhorn(None, None, 0, None, None, 0, 2, ctypes.byref(p), -1.0, 5, None,
+                              None, None, None)
+    assert st == -1 and b"rho" in fu._lib.fs_last_error()
+
+
+def test_binding_requires_device_tensors():
+    import torch
+    import paper_2306_13618_amd as fu
+    with pytest.raises(TypeError):
+        fu.fastsum_apply(torch.zeros(4, 2), torch.zeros(3, 2), torch.zeros(3))

@@ -1,0 +1,310 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle on the same seeded
+inputs.  Tolerance: relative error <= 1e-5 for every FP32 kernel sum and for the Sinkhorn
+potentials and objective (the stated accuracy of the FP32 fast summation); sizes span several
+tiles and end in ragged tails."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2306_13618_amd as fu  # noqa: E402
+
+DEV = torch.device("cuda:0")
+TOL = 1e-5
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def relinf(got, ref):
+    got, ref = np.asarray(got, float), np.asarray(ref, float)
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def rel2(got, ref):
+    got, ref = np.asarray(got, float), np.asarray(ref, float)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def clouds(d, n, m, seed, spread=0.03):
+    rng = np.random.default_rng([4242, d, n, m, seed])
+    x = rng.uniform(-0.25, 0.25, (n, d)).astype(np.float32)
+    base = x[rng.integers(0, n, m)]
+    y = np.clip(base + rng.normal(0, spread, (m, d)), -0.25, synth.HI).astype(np.float32)
+    v = rng.uniform(0.5, 1.5, m).astype(np.float32)
+    return x, y, v
+
+
+# --------------------------------------------------------------------------- direct sums
+
+@pytest.mark.parametrize("kind,lam", [("gauss", 0.02), ("laplace", 0.05), ("energy", 1.0)])
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_direct_sum(kind, lam, d):
+    x, y, v = clouds(d, 1537, 1201, 1)
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel=kind, lam=lam, grid=0).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, kind, lam)
+    assert relinf(got, ref) < TOL
+
+
+# --------------------------------------------------------------------------- NFFT fast sums
+
+@pytest.mark.parametrize("d,grid,window,lam", [(1, 64, 6, 0.02), (2, 64, 6, 0.02),
+                                               (2, 128, 4, 0.02), (3, 128, 6, 0.02),
+                                               (3, 64, 6, 0.02), (3, 64, 4, 0.02),
+                                               (3, 128, 5, 0.005)])
+def test_fastsum_gauss(d, grid, window, lam):
+    x, y, v = clouds(d, 3001, 2777, 2)
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=lam, grid=grid,
+                           window=window).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, "gauss", lam)
+    assert relinf(got, ref) < TOL
+
+
+@pytest.mark.parametrize("kind,lam,d,grid", [("laplace", 0.01, 1, 256), ("laplace", 0.01, 2, 256),
+                                             ("laplace", 0.01, 3, 128), ("energy", 1.0, 1, 256),
+                                             ("energy", 1.0, 2, 256), ("energy", 1.0, 3, 256)])
+def test_fastsum_nearfield_kernels(kind, lam, d, grid):
+    x, y, v = clouds(d, 2003, 1999, 3)
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel=kind, lam=lam, grid=grid,
+                           window=6).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, kind, lam)
+    assert relinf(got, ref) < TOL
+
+
+def test_fastsum_signed_weights_and_wide_gaussian():
+    # a Gaussian wider than the data: the plan switches to the boundary-regularised torus
+    x, y, v = clouds(2, 1500, 1300, 4)
+    v = v - 1.0
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=0.25, grid=128,
+                           window=6).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, "gauss", 0.25)
+    assert relinf(got, ref) < TOL
+
+
+def test_plan_adjoint_and_transpose():
+    x, y, v = clouds(3, 2500, 1800, 5)
+    u = np.random.default_rng(5).normal(size=2500).astype(np.float32)
+    pl = fu.Plan(T(x), T(y), kernel="gauss", lam=0.02, grid=64, window=6)
+    kv = pl.apply(T(v)).cpu().numpy().astype(float)
+    ktu = pl.apply(T(u), transpose=True).cpu().numpy().astype(float)
+    assert relinf(kv, oracle.direct_sum(x, y, v, "gauss", 0.02)) < TOL
+    assert relinf(ktu, oracle.direct_sum(y, x, u, "gauss", 0.02)) < TOL
+    lhs, rhs = u.astype(float) @ kv, ktu @ v.astype(float)
+    assert abs(lhs - rhs) < 1e-5 * (np.abs(u) @ np.abs(kv))
+
+
+def test_fastsum_edge_cases():
+    x, y, v = clouds(2, 40, 30, 6)
+    # no sources: zero output
+    out = fu.fastsum_apply(T(x), T(y[:0]), T(v[:0]), kernel="gauss", lam=0.05, grid=64)
+    assert float(out.abs().max()) == 0.0
+    # no targets
+    out = fu.fastsum_apply(T(x[:0]), T(y), T(v), kernel="gauss", lam=0.05, grid=64)
+    assert out.numel() == 0
+    # a single source and target
+    got = fu.fastsum_apply(T(x[:1]), T(y[:1]), T(v[:1]), kernel="gauss", lam=0.05, grid=64)
+    ref = oracle.direct_sum(x[:1], y[:1], v[:1], "gauss", 0.05)
+    assert relinf(got.cpu().numpy(), ref) < TOL
+    # all points at one location (degenerate bounding box)
+    xs = np.zeros((50, 3), np.float32) + 0.1
+    got = fu.fastsum_apply(T(xs), T(xs), T(np.ones(50, np.float32)), kernel="gauss", lam=0.05,
+                           grid=32).cpu().numpy()
+    assert np.allclose(got, 50.0, rtol=TOL)
+
+
+def test_bad_arguments_raise():
+    x, y, v = clouds(2, 40, 30, 7)
+    with pytest.raises(fu.FastsumError):
+        fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=0.05, grid=100)  # not 2^k
+    with pytest.raises(fu.FastsumError):
+        fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=-1.0, grid=64)
+    bad = x.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(fu.FastsumError):
+        fu.fastsum_apply(T(bad), T(y), T(v), kernel="gauss", lam=0.05, grid=64)
+    x4 = np.zeros((10, 4), np.float32)
+    with pytest.raises(fu.FastsumError):
+        fu.fastsum_apply(T(x4), T(x4), T(np.ones(10, np.float32)), kernel="gauss", lam=0.05,
+                         grid=64)
+
+
+# --------------------------------------------------------------------------- MFMA direct path
+
+@pytest.mark.parametrize("n,m", [(1000, 777), (64, 33)])
+def test_mfma_gram_gauss_d32(n, m):
+    w = synth.make("cfg4b", n=n, m=m)
+    v = w["b"] / w["b"].max()
+    got = fu.fastsum_apply(T(w["x"]), T(w["y"]), T(v), kernel="gauss", lam=1.0,
+                           grid=0).cpu().numpy()
+    ref = oracle.direct_sum(w["x"], w["y"], v, "gauss", 1.0)
+    assert relinf(got, ref) < TOL
+    valu = fu.fastsum_apply(T(w["x"]), T(w["y"]), T(v), kernel="gauss", lam=1.0, grid=0,
+                            flags=fu.FLAG_FORCE_VALU).cpu().numpy()
+    assert relinf(valu, ref) < TOL
+
+
+# --------------------------------------------------------------------------- Sinkhorn
+
+_cache = {}
+
+
+def oracle_uot(key, x, a, y, b, eps, rho, sweeps, r=2):
+    if key not in _cache:
+        beta, gamma = oracle.uot_sinkhorn(x, a, y, b, eps, rho, sweeps, r=r)
+        D = oracle.uot_dual(x, a, y, b, eps, rho, beta, gamma, r=r)
+        _cache[key] = (beta, gamma, D)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("grid", [0, 64])
+def test_uot_cfg0(grid):
+    """cfg0 in full: d=1, n=m=2000, 200 sweeps, eps=0.05, rho=1 (the paper's lambda=20, eta=1)."""
+    w = synth.make("cfg0")
+    beta, gamma, D = oracle_uot("cfg0", w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"],
+                                w["iters"])
+    f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                                w["iters"], kernel="gauss", grid=grid, window=6)
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    assert rel2(f, beta) < TOL and rel2(g, gamma) < TOL
+    assert abs(obj - D) < TOL * abs(D)
+
+
+@pytest.mark.parametrize("cfg,n,sweeps,grid,window", [("cfg1", 3000, 30, 128, 6),
+                                                      ("cfg2", 2500, 20, 64, 6),
+                                                      ("cfg2", 2500, 20, 64, 4)])
+def test_uot_reduced(cfg, n, sweeps, grid, window):
+    w = synth.make(cfg, n=n, m=n - 217)
+    beta, gamma, D = oracle_uot((cfg, n, sweeps), w["x"], w["a"], w["y"], w["b"], w["eps"],
+                                w["rho"], sweeps)
+    f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                                sweeps, kernel="gauss", grid=grid, window=window)
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    assert rel2(f, beta) < TOL and rel2(g, gamma) < TOL
+    assert abs(obj - D) < TOL * abs(D)
+
+
+def test_uot_laplace_gibbs_kernel():
+    """r = 1: Gibbs kernel exp(-|x-y|/eps) through the near-field-corrected fast sum."""
+    w = synth.make("cfg4a", n=2000, m=1800)
+    sweeps = 10
+    beta, gamma, D = oracle_uot("cfg4a-small", w["x"], w["a"], w["y"], w["b"], w["eps"],
+                                w["rho"], sweeps, r=1)
+    for grid in (0, 128):
+        f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"],
+                                    w["rho"], sweeps, kernel="laplace", grid=grid, window=6)
+        f, g = f.cpu().numpy(), g.cpu().numpy()
+        assert rel2(f, beta) < TOL and rel2(g, gamma) < TOL, grid
+        assert abs(obj - D) < TOL * abs(D), grid
+
+
+def test_uot_warm_start_continues_the_iteration():
+    w = synth.make("cfg0", n=700, m=650)
+    x, a, y, b = (T(w[k]) for k in ("x", "a", "y", "b"))
+    f1, g1, _ = fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 7, grid=64)
+    f2, g2, o2 = fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 5, grid=64, f0=f1, g0=g1)
+    beta, gamma = oracle.uot_sinkhorn(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], 12)
+    assert rel2(f2.cpu().numpy(), beta) < TOL and rel2(g2.cpu().numpy(), gamma) < TOL
+
+
+def test_uot_objective_without_sweeps():
+    w = synth.make("cfg0", n=300, m=280)
+    _, _, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"], 0)
+    D = oracle.uot_dual(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], np.zeros(300),
+                        np.zeros(280))
+    assert abs(obj - D) < TOL * abs(D)
+
+
+def test_sinkhorn_divergence():
+    w = synth.make("cfg3", n=900, m=800)
+    sweeps = 60
+    sd, terms = oracle.sinkhorn_divergence(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"],
+                                           sweeps)
+    for grid in (0, 128):
+        val, t3 = fu.sinkhorn_divergence(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"],
+                                         w["rho"], sweeps, grid=grid, window=6)
+        for k in range(3):
+            assert abs(t3[k] - terms[k]) < TOL * abs(terms[k])
+        assert abs(val - sd) < 1e-4 * abs(sd) + 1e-5 * max(abs(t) for t in terms)
+
+
+# --------------------------------------------------------------------------- MMD
+
+@pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.02, 0), ("gauss", 0.02, 64),
+                                           ("laplace", 0.05, 128), ("energy", 1.0, 256),
+                                           ("energy", 1.0, 0)])
+@pytest.mark.parametrize("d", [2, 3])
+def test_mmd(kind, lam, grid, d):
+    w = synth.make("cfg2" if d == 3 else "cfg1", n=1800, m=1500)
+    x, y = w["x"][:, :d], w["y"][:, :d]
+    ref, terms = oracle.mmd2(x, w["a"], y, w["b"], kind, lam)
+    val, t3 = fu.mmd(T(x), T(w["a"]), T(y), T(w["b"]), kernel=kind, lam=lam, grid=grid, window=6,
+                     terms=True)
+    for k in range(3):
+        assert abs(t3[k] - terms[k]) < TOL * abs(terms[k])
+    scale = max(abs(t) for t in terms)
+    assert abs(val - ref) < TOL * scale
+    val1 = fu.mmd(T(x), T(w["a"]), T(y), T(w["b"]), kernel=kind, lam=lam, grid=grid, window=6)
+    assert abs(val1 - ref) < TOL * scale
+
+
+def test_mmd_self_is_zero():
+    w = synth.make("cfg2", n=2000)
+    x, a = T(w["x"]), T(w["a"])
+    val, t3 = fu.mmd(x, a, x, a, kernel="gauss", lam=0.02, grid=64, terms=True)
+    assert abs(val) < 1e-6 * abs(t3[0])
+
+
+# --------------------------------------------------------------------------- gradients
+
+@pytest.mark.parametrize("kind,grid,tol", [("gauss", 0, 1e-4), ("gauss", 64, 1e-4),
+                                           ("laplace", 0, 1e-4), ("laplace", 256, 2e-3)])
+def test_uot_grad_against_oracle_envelope(kind, grid, tol):
+    """Backward kernels: the GPU envelope gradient at given potentials equals the oracle's direct
+    FP64 gradient at the same potentials.  For the r = 1 (Laplace Gibbs) kernel the fast sum's
+    FP32 absolute error floor (~1e-7 of the largest sum) is multiplied by exp((f_i + gmax)/eps),
+    which is large at points far from the transported mass; the max-normalised error there is
+    ~1e-3, so that case carries a wider tolerance (the Gaussian cases keep 1e-4)."""
+    w = synth.make("cfg3", n=1200, m=1000)
+    r = 2 if kind == "gauss" else 1
+    beta, gamma = oracle.uot_sinkhorn(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], 40, r=r)
+    ref = oracle.uot_grad(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], beta, gamma, r=r)
+    got = fu.uot_sinkhorn_grad(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                               T(beta), T(gamma), kernel=kind, grid=grid, window=6)
+    errs = [relinf(gv.cpu().numpy(), rv) for gv, rv in zip(got, ref)]
+    print("uot grad rel errors (dx, da, dy, db):", errs)
+    assert max(errs) < tol
+
+
+@pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.02, 0), ("gauss", 0.02, 64),
+                                           ("energy", 1.0, 256)])
+def test_mmd_grad_against_oracle(kind, lam, grid):
+    w = synth.make("cfg1", n=1100, m=900)
+    ref = oracle.mmd2_grad(w["x"], w["a"], w["y"], w["b"], kind, lam)
+    got = fu.mmd_grad(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), kernel=kind, lam=lam, grid=grid,
+                      window=6)
+    errs = [relinf(gv.cpu().numpy(), rv) for gv, rv in zip(got, ref)]
+    print("mmd grad rel errors (dx, da, dy, db):", errs)
+    assert max(errs) < 1e-4
+
+
+def test_autograd_functions():
+    w = synth.make("cfg3", n=500, m=450)
+    x = T(w["x"]).requires_grad_()
+    a = T(w["a"]).requires_grad_()
+    y, b = T(w["y"]), T(w["b"])
+    s = fu.SinkhornDivergence.apply(x, a, y, b, w["eps"], w["rho"], 300, {"grid": 64})
+    s.backward()
+    assert torch.isfinite(x.grad).all() and torch.isfinite(a.grad).all()
+    x2 = T(w["x"]).requires_grad_()
+    m2 = fu.MMD2.apply(x2, a.detach(), y, b, {"kernel": "gauss", "lam": 0.01, "grid": 64})
+    m2.backward()
+    ref = oracle.mmd2_grad(w["x"], w["a"], w["y"], w["b"], "gauss", 0.01)[0]
+    assert relinf(x2.grad.cpu().numpy(), ref) < 1e-4
