@@ -1,19 +1,24 @@
 """Benchmark: unbalanced Sinkhorn sweeps/s with NFFT fast summation on one MI355X.
 
-Workload (the headline configuration): d=3, n=m=1M, x ~ U[-1/4,1/4)^3, y = clip(x + N(0,0.03^2)),
-weights U(0.5,1.5) with masses 1.0 / 1.2, Gibbs kernel exp(-|x-y|^2/eps), eps=0.02, rho=1,
-50 sweeps per solve, FFT grid 64^3, Kaiser-Bessel window cutoff 6.  One timed step is one full
-uot_sinkhorn call: plan (scaling, binning, kernel coefficients) plus 50 sweeps plus the objective,
-with the inputs already resident in HBM.  value = sweeps per second.
+Headline workload: d=3, n=m=1M, x ~ U[-1/4,1/4)^3, y = clip(x + N(0,0.03^2)), weights U(0.5,1.5)
+with masses 1.0 / 1.2, Gibbs kernel exp(-|x-y|^2/eps), eps=0.02, rho=1, 50 sweeps per solve, FFT
+grid 64^3, Kaiser-Bessel window cutoff 6.  One timed step is one full uot_sinkhorn call (plan:
+scaling, binning, kernel coefficients; 50 sweeps; objective) with the inputs resident in HBM.
+value = sweeps per second.
 
-Also reported: GPU direct-summation sweeps/s on the same inputs (the O(n m) baseline), the sampled
-full-size error against the FP64 oracle, the dominant kernel's roofline and the oracle's rate on
-the host cores.
+Also reported (extra keys of the same JSON line):
+  * GPU direct-summation sweeps/s on the same inputs and the speedup of the fast path;
+  * the sampled full-size error of the last half-step against the FP64 oracle;
+  * per-pass average durations from HIP events recorded on the launch stream during the timed
+    steps, the dominant kernel's roofline, and HBM GB/s of spread, FFT and gather;
+  * the secondary metric: forward and forward+backward ms of the Sinkhorn divergence on the
+    d=2, n=m=200k Gaussian-mixture workload;
+  * the FP64 oracle's rate on the host cores (a bounded sample scaled to sweeps/s).
 """
 import argparse
+import hashlib
 import json
 import os
-import subprocess
 import sys
 import time
 
@@ -22,25 +27,48 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0          # MI355X published HBM3E bandwidth
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=None, help="override point count (testing only)")
+    ap.add_argument("--n", type=int, default=None, help="override the point count (testing only)")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--grid", type=int, default=64)
     ap.add_argument("--window", type=int, default=6)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def traffic_from_profile(kernel_src):
+    """HBM bytes per launch of the spread kernel from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "spread_pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    digest = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != digest:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the fast-summation path is built and timed on a "
-              "single MI355X (multi-GPU sharding is described in DESIGN.md, not implemented).",
+              "single MI355X (sharding across GPUs is described in DESIGN.md, not implemented).",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -48,44 +76,76 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
-    cfg = "cfg2"
-    w = synth.make(cfg, n=args.n)
+    w = synth.make("cfg2", n=args.n)
     n, m, d = w["n"], w["m"], w["d"]
     eps, rho, sweeps = w["eps"], w["rho"], w["iters"]
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
     torch.cuda.synchronize()
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(grid, iters):
         return fu.uot_sinkhorn(x, a, y, b, eps, rho, iters, kernel="gauss", grid=grid,
                                window=args.window)
 
-    print("bench: warmup %d steps (n=m=%d, d=%d, %d sweeps, grid %d, window %d)"
-          % (args.warmup, n, d, sweeps, args.grid, args.window), file=sys.stderr, flush=True)
+    log("warmup %d steps (n=m=%d, d=%d, %d sweeps/step, grid %d, window %d)"
+        % (args.warmup, n, d, sweeps, args.grid, args.window))
     for _ in range(args.warmup):
         step(args.grid, sweeps)
     torch.cuda.synchronize()
+    fu.fs_profile_reset()
+    fu.fs_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         f, g, obj = step(args.grid, sweeps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    fu.fs_profile_enable(False)
+    passes = {}
+    for name in ("spread", "fold", "fft", "gather", "update"):
+        ms, cnt = fu.fs_profile_query(name)
+        passes[name] = {"avg_ms": ms / cnt if cnt else None, "launches": cnt}
     ms_per_step = 1e3 * elapsed / args.steps
     value = sweeps * args.steps / elapsed
-    print("bench: fast %.3f ms/step, %.1f sweeps/s, objective %.9g" % (ms_per_step, value, obj),
-          file=sys.stderr, flush=True)
+    log("fast %.3f ms/step, %.1f sweeps/s, objective %.9g" % (ms_per_step, value, obj))
+    log("passes (avg ms): " + ", ".join("%s %.4f" % (k, v["avg_ms"] or 0) for k, v in passes.items()))
 
-    # ---- sampled full-size parity: the last (gamma) half-step recomputed in FP64 by the oracle
-    #      from the GPU's final beta, for sampled rows, against the GPU's final gamma
+    # ---- roofline of the dominant kernel (spread): algorithmic work per launch
+    W = 2 * args.window
+    sp = passes["spread"]["avg_ms"]
+    flops_per_launch = n * 2.0 * W ** d          # one multiply and one add per window point
+    achieved_tflops = flops_per_launch / (sp * 1e-3) / 1e12
+    bytes_per_launch = n * (16 + 4) + 4 * args.grid ** d  # node record + weight, grid written
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2306_13618_amd", "csrc", "nfft.hip"))
+    roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
+                "traffic": traffic, "kernel": "k_spread_wave (spreading, adjoint NFFT)",
+                "work_per_launch": "%d nodes x 2 x %d^%d flops" % (n, W, d)}
+    lds_ops = n * float(W ** d)
+    hbm = {}
+    G = args.grid
+    for name, nbytes in (("spread", bytes_per_launch),
+                         ("gather", n * (16 + 4) + 4 * G ** d),
+                         ("fft", 2 * 4 * G ** d)):
+        t = passes[name]["avg_ms"]
+        hbm[name] = {"algorithmic_bytes": nbytes,
+                     "GBs": nbytes / (t * 1e-3) / 1e9 if t else None,
+                     "frac_of_8TBs": (nbytes / (t * 1e-3) / 1e9) / PEAK_HBM_GBS if t else None}
+
+    # ---- sampled full-size parity: the last (gamma) half-step recomputed by the FP64 oracle
+    #      from the GPU's final beta for sampled rows, against the GPU's final gamma
     import oracle
     rows = synth.sample_rows(m, 128, seed=1)
     fh = f.cpu().numpy()
-    t1 = time.perf_counter()
     gamma_rows = oracle.uot_beta_rows(w["y"], rows, w["x"], w["a"], fh, eps, rho)
-    t_rows = time.perf_counter() - t1
     gh = g.cpu().numpy()[rows]
     err_sampled = float(np.max(np.abs(gh - gamma_rows)) / np.max(np.abs(gamma_rows)))
-    print("bench: sampled last-half-step error %.2e (%d rows, %.1f s on CPU)"
-          % (err_sampled, len(rows), t_rows), file=sys.stderr, flush=True)
+    log("sampled last-half-step error %.2e (%d rows)" % (err_sampled, len(rows)))
 
     # ---- GPU direct summation on the same inputs (one sweep)
     direct = None
@@ -94,44 +154,74 @@ def main():
         t0 = time.perf_counter()
         step(0, 1)
         torch.cuda.synchronize()
-        td = time.perf_counter() - t0
-        direct = 1.0 / td
-        print("bench: direct %.3f s/sweep" % td, file=sys.stderr, flush=True)
+        direct = 1.0 / (time.perf_counter() - t0)
+        log("direct %.3f s/sweep" % (1.0 / direct))
 
-    # ---- oracle on the host cores: f half-step for a bounded sample of rows, scaled to sweeps/s
+    # ---- secondary: Sinkhorn divergence forward and forward+backward (d=2, n=m=200k)
+    secondary = None
+    if not args.no_secondary:
+        w3 = synth.make("cfg3")
+        x3, a3, y3, b3 = (torch.from_numpy(w3[k]).to(dev) for k in ("x", "a", "y", "b"))
+        it3 = 300
+        opts = {"grid": w3["grid"], "window": w3["window"]}
+        for rep in range(2):  # first repetition warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.no_grad():
+                fu.sinkhorn_divergence(x3, a3, y3, b3, w3["eps"], w3["rho"], it3, **opts)
+            torch.cuda.synchronize()
+            fwd_ms = 1e3 * (time.perf_counter() - t0)
+            xg = x3.clone().requires_grad_()
+            ag = a3.clone().requires_grad_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = fu.SinkhornDivergence.apply(xg, ag, y3, b3, w3["eps"], w3["rho"], it3, opts)
+            s.backward()
+            torch.cuda.synchronize()
+            fb_ms = 1e3 * (time.perf_counter() - t0)
+        secondary = {"workload": "Sinkhorn divergence, d=2 n=m=200k Gaussian mixtures, eps=0.01 "
+                                 "rho=0.5, %d sweeps per UOT term, grid 128^2, window 6" % it3,
+                     "fwd_ms": fwd_ms, "fwd_bwd_ms": fb_ms, "bwd_over_fwd": (fb_ms - fwd_ms) / fwd_ms,
+                     "value": float(s.item())}
+        log("divergence fwd %.1f ms, fwd+bwd %.1f ms" % (fwd_ms, fb_ms))
+
+    # ---- oracle on the host cores: beta and gamma half-steps for a bounded sample of rows
     cpu = None
     if not args.no_cpu:
-        R = 1024
+        R = 8192
         rows = synth.sample_rows(n, R, seed=2)
         t1 = time.perf_counter()
         oracle.uot_beta_rows(w["x"], rows, w["y"], w["b"], np.zeros(m), eps, rho)
-        tf = time.perf_counter() - t1
-        t1 = time.perf_counter()
         oracle.uot_beta_rows(w["y"], rows, w["x"], w["a"], np.zeros(n), eps, rho)
-        tg = time.perf_counter() - t1
-        sweep_s = (tf + tg) * (n / R)
+        tcpu = time.perf_counter() - t1
+        sweep_s = tcpu * (n / R)
         cpu = {"value": 1.0 / sweep_s, "unit": "sweeps/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": "FP64 beta and gamma half-steps for %d of %d rows each against all "
-                         "%d sources (%.1f s), scaled to one full sweep" % (R, n, m, tf + tg)}
-        print("bench: oracle %.3g sweeps/s on %d threads" % (cpu["value"], cpu["cores"]),
-              file=sys.stderr, flush=True)
+               "sample": "FP64 beta and gamma half-steps (Algorithm 1, log-sum-exp) for %d of %d "
+                         "rows each against all %d sources, %.1f s, scaled to one full sweep"
+                         % (R, n, m, tcpu)}
+        log("oracle %.3g sweeps/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     line = {
         "metric": "UOT Sinkhorn iters/sec fast-sum vs direct, n=1M d=3 at rel err<=1e-5; fwd+bwd ms",
         "value": value, "unit": "sweeps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "cfg2 UOT Sinkhorn: d=3 n=m=%d uniform/perturbed, Gauss eps=%g "
-                               "rho=%g, %d sweeps/step, grid %d^3, window %d"
+        "config": {"workload": "UOT Sinkhorn, d=3 n=m=%d uniform / perturbed clouds, Gauss eps=%g "
+                               "rho=%g, %d sweeps per step, grid %d^3, window %d"
                                % (n, eps, rho, sweeps, args.grid, args.window),
                    "n": n, "m": m, "d": d, "sweeps_per_step": sweeps, "grid": args.grid,
                    "window": args.window, "update_dtype": "f64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
         "direct_sweeps_per_s": direct,
         "speedup_vs_direct": (value / direct) if direct else None,
         "err_sampled_last_halfstep": err_sampled,
         "objective": obj,
-        "cpu_baseline": cpu,
+        "passes_avg_ms": {k: v["avg_ms"] for k, v in passes.items()},
+        "lds_atomic_ops_per_s_spread": lds_ops / (sp * 1e-3),
+        "hbm": hbm,
+        "secondary": secondary,
     }
     print(json.dumps(line), flush=True)
 

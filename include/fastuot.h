@@ -88,6 +88,16 @@ int fs_version(void);
 /* Release the cached workspace blocks (device memory) of the calling process. */
 void fs_release_cache(void);
 
+/* Pass timing (instrumentation, not part of the method).  fs_profile_enable(1) makes every
+ * subsequent launch of the named passes ("spread", "fold", "fft", "gather", "nearfield",
+ * "update", "direct") record a pair of HIP events on the stream the pass is launched on;
+ * fs_profile_query waits for the recorded events and returns the summed duration in
+ * milliseconds and the launch count for one pass name (0 and 0 if none); fs_profile_reset
+ * discards the records.  Returns FS_OK or FS_EINVAL (NULL argument). */
+int fs_profile_enable(int enable);
+int fs_profile_query(const char *pass, double *total_ms, int64_t *count);
+void fs_profile_reset(void);
+
 /* Kernel sum, eq. (fast_sum):  out_i = sum_j K(x_i - y_j) v_j,  i < n, j < m.
  *   x (n x d), y (m x d), v (m), out (n): device, float32.  d in 1..3 for the fast path
  *   (Section "Curse of dimensionality": the method is restricted to d <= 3); any d in 1..128 for

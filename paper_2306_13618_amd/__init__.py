@@ -17,7 +17,8 @@ import torch
 __all__ = [
     "fastsum_apply", "Plan", "uot_sinkhorn", "uot_sinkhorn_grad", "sinkhorn_divergence",
     "sinkhorn_divergence_grad", "mmd", "mmd_grad", "SinkhornDivergence", "MMD2",
-    "FastsumError", "KERNELS", "library_path", "EXPORTED",
+    "FastsumError", "KERNELS", "library_path", "EXPORTED", "fs_profile_enable",
+    "fs_profile_query", "fs_profile_reset",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +27,8 @@ KERNELS = {"gauss": 0, "laplace": 1, "energy": 2}
 FLAG_WARM_START = 0x1
 FLAG_FORCE_VALU = 0x2
 FLAG_NO_NEARFIELD = 0x4
-EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fastsum_apply", "fs_plan_create",
+EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fs_profile_enable",
+            "fs_profile_query", "fs_profile_reset", "fastsum_apply", "fs_plan_create",
             "fs_plan_apply", "fs_plan_destroy", "uot_sinkhorn", "uot_sinkhorn_grad",
             "sinkhorn_divergence", "sinkhorn_divergence_grad", "mmd", "mmd_grad")
 
@@ -58,6 +60,9 @@ def _load():
         "fs_last_error": (ctypes.c_char_p, []),
         "fs_version": (I, []),
         "fs_release_cache": (None, []),
+        "fs_profile_enable": (I, [I]),
+        "fs_profile_query": (I, [ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]),
+        "fs_profile_reset": (None, []),
         "fastsum_apply": (I, [P, I64, P, I64, I, P, P, PP, P]),
         "fs_plan_create": (I, [P, I64, P, I64, I, PP, P, ctypes.POINTER(P)]),
         "fs_plan_apply": (I, [P, P, P, I, P]),
@@ -126,6 +131,22 @@ def _stream(device):
 
 def _opt(out):
     return _ptr(out) if out is not None else ctypes.c_void_p(0)
+
+
+def fs_profile_enable(enable=True):
+    """Record HIP events around the library's passes (spread, fold, fft, gather, ...)."""
+    _check(_lib.fs_profile_enable(int(bool(enable))))
+
+
+def fs_profile_query(name):
+    """(total milliseconds, launch count) of one pass since the last reset."""
+    ms, cnt = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(_lib.fs_profile_query(name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def fs_profile_reset():
+    _lib.fs_profile_reset()
 
 
 def fastsum_apply(x, y, v, kernel="gauss", lam=1.0, grid=0, window=0, oversampling=0,

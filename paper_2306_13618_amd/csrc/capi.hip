@@ -7,6 +7,9 @@
 
 namespace fs {
 const char *last_error();
+int profile_enable(int on);
+int profile_query(const char *pass, double *total_ms, int64_t *count);
+void profile_reset();
 
 namespace {
 
@@ -85,6 +88,14 @@ const char *fs_last_error(void) { return fs::last_error(); }
 int fs_version(void) { return (1 << 16) | 0; }
 
 void fs_release_cache(void) { ws_release_all(); }
+
+int fs_profile_enable(int enable) { return fs::profile_enable(enable); }
+
+int fs_profile_query(const char *pass, double *total_ms, int64_t *count) {
+    return fs::profile_query(pass, total_ms, count);
+}
+
+void fs_profile_reset(void) { fs::profile_reset(); }
 
 int fastsum_apply(const float *x, int64_t n, const float *y, int64_t m, int d, const float *v,
                   float *out, const fs_params *p, void *stream) {

@@ -90,6 +90,17 @@ void fill_f32(float *p, int64_t n, float v, hipStream_t s);
 void fill_f64(double *p, int64_t n, double v, hipStream_t s);
 void fill_i32(int *p, int64_t n, int v, hipStream_t s);
 
+// ------------------------------------------------------------------ pass timing
+// When enabled (fs_profile_enable), a ProfScope records HIP events on the launch stream around
+// the kernels of one pass; the events are folded into per-name totals on query.
+bool prof_enabled();
+struct ProfScope {
+    int slot = -1;
+    hipStream_t s = nullptr;
+    ProfScope(const char *name, hipStream_t stream);
+    ~ProfScope();
+};
+
 // ------------------------------------------------------------------ Kaiser-Bessel window
 // Window in grid units (s = distance to the grid point times the grid size), cutoff m, shape b,
 // normalised to phi(0) = 1:

@@ -1384,6 +1384,7 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
     auto run = [&](auto tconst) {
         constexpr int T = decltype(tconst)::value;
         if (src.nchunks > 0) {
+            ProfScope ps("spread", s);
             if constexpr (D == 1) {
                 hipLaunchKernelGGL((k_spread<D, W, T>), dim3(src.nchunks), dim3(256), 0, s,
                                    src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
@@ -1392,6 +1393,9 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                                    src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
             }
             FS_LAUNCHED();
+        }
+        if (src.nchunks > 0) {
+            ProfScope ps("fold", s);
             int box = 1;
             for (int k = 0; k < D; ++k) box *= (T + W - 1);
             int64_t ntiles = 1;
@@ -1411,49 +1415,53 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
         } else {
             fill_f32(pl.grid.p, gsz, 0.0f, s);
         }
+        {
         // FFT -> multiply -> inverse FFT
-        FftArgs fa{};
-        fa.G = pp.G;
-        fa.logG = 0;
-        while ((1 << fa.logG) < pp.G) ++fa.logG;
-        fa.N = pp.N;
-        fa.KX = pp.N / 2 + 1;
-        const int nbmax = FFT_ELEMS / pp.G;
-        const int nblk = (fa.KX + nbmax - 1) / nbmax;
-        fa.nbx = (fa.KX + nblk - 1) / nblk;
-        if (D == 1) {
-            hipLaunchKernelGGL(k_fft_1d_conv, dim3(1), dim3(FFT_THREADS), 0, s, pl.grid.p, fa,
-                               pl.twiddle.p, pl.Mk.p);
-            FS_LAUNCHED();
-        } else {
-            const int rows = (int)(gsz / pp.G);
-            const int pairs = rows / 2, nbp = FFT_ELEMS / pp.G;
-            const unsigned xblocks = (pairs + nbp - 1) / nbp;
-            hipLaunchKernelGGL(k_fft_x_r2c, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.grid.p, rows,
-                               fa, pl.twiddle.p, pl.specA.p);
-            FS_LAUNCHED();
-            const int nkb = (fa.KX + fa.nbx - 1) / fa.nbx;
-            if (D == 2) {
-                hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(FFT_THREADS), 0, s, pl.specA.p,
-                                   pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+            ProfScope pf("fft", s);
+            FftArgs fa{};
+            fa.G = pp.G;
+            fa.logG = 0;
+            while ((1 << fa.logG) < pp.G) ++fa.logG;
+            fa.N = pp.N;
+            fa.KX = pp.N / 2 + 1;
+            const int nbmax = FFT_ELEMS / pp.G;
+            const int nblk = (fa.KX + nbmax - 1) / nbmax;
+            fa.nbx = (fa.KX + nblk - 1) / nblk;
+            if (D == 1) {
+                hipLaunchKernelGGL(k_fft_1d_conv, dim3(1), dim3(FFT_THREADS), 0, s, pl.grid.p, fa,
+                                   pl.twiddle.p, pl.Mk.p);
                 FS_LAUNCHED();
             } else {
-                hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
-                                   pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                const int rows = (int)(gsz / pp.G);
+                const int pairs = rows / 2, nbp = FFT_ELEMS / pp.G;
+                const unsigned xblocks = (pairs + nbp - 1) / nbp;
+                hipLaunchKernelGGL(k_fft_x_r2c, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.grid.p, rows,
+                                   fa, pl.twiddle.p, pl.specA.p);
                 FS_LAUNCHED();
-                hipLaunchKernelGGL(k_fft_z_conv, dim3((pp.N + 1) * nkb), dim3(FFT_THREADS), 0, s,
-                                   pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
-                FS_LAUNCHED();
-                hipLaunchKernelGGL(k_fft_y<2>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
-                                   pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                const int nkb = (fa.KX + fa.nbx - 1) / fa.nbx;
+                if (D == 2) {
+                    hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(FFT_THREADS), 0, s, pl.specA.p,
+                                       pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    FS_LAUNCHED();
+                } else {
+                    hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
+                                       pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    FS_LAUNCHED();
+                    hipLaunchKernelGGL(k_fft_z_conv, dim3((pp.N + 1) * nkb), dim3(FFT_THREADS), 0, s,
+                                       pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    FS_LAUNCHED();
+                    hipLaunchKernelGGL(k_fft_y<2>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
+                                       pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    FS_LAUNCHED();
+                }
+                hipLaunchKernelGGL(k_fft_x_c2r, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.specA.p,
+                                   rows, fa, pl.twiddle.p, pl.grid.p);
                 FS_LAUNCHED();
             }
-            hipLaunchKernelGGL(k_fft_x_c2r, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.specA.p,
-                               rows, fa, pl.twiddle.p, pl.grid.p);
-            FS_LAUNCHED();
         }
         if (dst.n > 0) {
             if (dst.nchunks > 0) {
+                ProfScope pg("gather", s);
                 const float gscale = (float)(pp.G / pp.P);
                 if (grad) {
                     hipLaunchKernelGGL((k_gather<D, W, T, true>), dim3(dst.nchunks), dim3(256), 0,
@@ -1527,6 +1535,7 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
             na.dims[k] = pp.nf_dims[k];
         }
         dim3 g(blocks_for(dst.n, 256, int64_t(1) << 30)), b(256);
+        ProfScope pn("nearfield", s);
 #define FS_NF(DD, GG)                                                                        \
     hipLaunchKernelGGL((k_nearfield<DD, GG>), g, b, 0, s, dst.xs.p, dst.n,                   \
                        src.nf_cell_start.p, src.nf_order.p, src.nf_xs.p, w_sorted, na, t_sorted, \

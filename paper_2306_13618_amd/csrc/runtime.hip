@@ -86,6 +86,102 @@ void ws_release_all() {
     c.free_bytes = 0;
 }
 
+// ------------------------------------------------------------------ pass timing
+namespace {
+struct ProfRec {
+    std::string name;
+    hipEvent_t e0, e1;
+};
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+};
+Prof &prof() {
+    static Prof *p = new Prof();
+    return *p;
+}
+hipEvent_t take_event(Prof &p) {
+    if (!p.pool.empty()) {
+        hipEvent_t e = p.pool.back();
+        p.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    FS_HIP(hipEventCreate(&e));
+    return e;
+}
+void fold_records(Prof &p) {
+    for (auto &r : p.recs) {
+        FS_HIP(hipEventSynchronize(r.e1));
+        float ms = 0.0f;
+        FS_HIP(hipEventElapsedTime(&ms, r.e0, r.e1));
+        auto &t = p.totals[r.name];
+        t.first += ms;
+        t.second += 1;
+        p.pool.push_back(r.e0);
+        p.pool.push_back(r.e1);
+    }
+    p.recs.clear();
+}
+}  // namespace
+
+bool prof_enabled() { return prof().on; }
+
+ProfScope::ProfScope(const char *name, hipStream_t stream) : s(stream) {
+    Prof &p = prof();
+    if (!p.on) return;
+    std::lock_guard<std::mutex> lk(p.mu);
+    ProfRec r{name, take_event(p), take_event(p)};
+    FS_HIP(hipEventRecord(r.e0, s));
+    p.recs.push_back(r);
+    slot = (int)p.recs.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+    if (slot < 0) return;
+    Prof &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (slot < (int)p.recs.size()) (void)hipEventRecord(p.recs[slot].e1, s);
+}
+
+int profile_enable(int on) {
+    prof().on = (on != 0);
+    return FS_OK;
+}
+
+int profile_query(const char *pass, double *total_ms, int64_t *count) {
+    if (!pass || !total_ms || !count) {
+        set_error("fs_profile_query: NULL argument");
+        return FS_EINVAL;
+    }
+    Prof &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    try {
+        fold_records(p);
+    } catch (const Error &e) {
+        return e.code;
+    }
+    auto it = p.totals.find(pass);
+    *total_ms = (it == p.totals.end()) ? 0.0 : it->second.first;
+    *count = (it == p.totals.end()) ? 0 : it->second.second;
+    return FS_OK;
+}
+
+void profile_reset() {
+    Prof &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    for (auto &r : p.recs) {
+        (void)hipEventSynchronize(r.e1);
+        p.pool.push_back(r.e0);
+        p.pool.push_back(r.e1);
+    }
+    p.recs.clear();
+    p.totals.clear();
+}
+
 // ------------------------------------------------------------------ fills
 template <class T>
 __global__ void k_fill(T *p, int64_t n, T v) {

@@ -399,6 +399,7 @@ void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t
         FS_LAUNCHED();
         return;
     }
+    ProfScope ps("direct", s);
     if (mfma) {
         const GramOperand &gt = transpose ? (same ? gx : gy) : gx;
         const GramOperand &gs = transpose ? gx : (same ? gx : gy);
@@ -431,6 +432,7 @@ unsigned red_blocks(int64_t n) { return blocks_for(n, RT, RBLK); }
 
 void launch_update(const float *t, int64_t n, const double *shift, double kappa, double eps,
                    double *pot, Scalars &sc, double *out_max, hipStream_t s) {
+    ProfScope ps("update", s);
     hipLaunchKernelGGL(k_update, dim3(red_blocks(n)), dim3(RT), 0, s, t, n, shift, kappa, eps,
                        pot, sc.partial.p, sc.counter.p, out_max, sc.nbad.p);
     FS_LAUNCHED();
