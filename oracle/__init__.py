@@ -58,6 +58,8 @@ def lib():
             "orc_uot_grad": (None, [P, P, I64, P, P, I64, I, I, D, D, P, P, P, P, P, P]),
             "orc_mmd2": (D, [P, P, I64, P, P, I64, I, I, D, P]),
             "orc_mmd2_grad": (None, [P, P, I64, P, P, I64, I, I, D, P, P, P, P]),
+            "orc_uot_grad_rows": (None, [P, P, P, I64, P, P, I64, I, I, D, D, P, P, P, P]),
+            "orc_mmd2_grad_rows": (None, [P, P, I64, P, I64, P, P, I64, I, I, D, P, P]),
             "orc_num_threads": (I, []),
         }
         for name, (res, args) in sig.items():
@@ -220,6 +222,30 @@ def uot_grad(x, mu, y, nu, eps, eta, beta, gamma, r=2):
     lib().orc_uot_grad(_p(x), _p(mu), n, _p(y), _p(nu), m, d, int(r), float(eps), float(eta),
                        _p(beta), _p(gamma), _p(dx), _p(dmu), _p(dy), _p(dnu))
     return dx, dmu, dy, dnu
+
+
+def uot_grad_rows(x, mu, rows, y, nu, eps, eta, beta, gamma, r=2):
+    """Envelope gradient (dx, dmu) of the dual for selected rows of x (first slot)."""
+    x, n, d = _pts(x)
+    y, m, _ = _pts(y)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    mu, nu, beta, gamma = _f64(mu), _f64(nu), _f64(beta), _f64(gamma)
+    dx, dmu = np.empty((len(rows), d)), np.empty(len(rows))
+    lib().orc_uot_grad_rows(_p(x), _p(mu), _p(rows), len(rows), _p(y), _p(nu), m, d, int(r),
+                            float(eps), float(eta), _p(beta), _p(gamma), _p(dx), _p(dmu))
+    return dx, dmu
+
+
+def mmd2_grad_rows(x, mu, rows, y, nu, kind, lam_k):
+    """Gradient rows (dx, dmu) of eq. (1205) for selected rows of x."""
+    x, n, d = _pts(x)
+    y, m, _ = _pts(y)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    mu, nu = _f64(mu), _f64(nu)
+    dx, dmu = np.empty((len(rows), d)), np.empty(len(rows))
+    lib().orc_mmd2_grad_rows(_p(x), _p(mu), n, _p(rows), len(rows), _p(y), _p(nu), m, d,
+                             _kind(kind), float(lam_k), _p(dx), _p(dmu))
+    return dx, dmu
 
 
 def mmd2(x, mu, y, nu, kind, lam_k):

@@ -381,6 +381,34 @@ void orc_uot_grad(const double *x, const double *mu, int64_t n, const double *y,
     }
 }
 
+/* Envelope gradient rows (as orc_uot_grad, first slot only) for selected rows of x. */
+void orc_uot_grad_rows(const double *x, const double *mu, const int64_t *rows, int64_t nrows,
+                       const double *y, const double *nu, int64_t m, int d, int r, double eps,
+                       double eta, const double *beta, const double *gamma, double *dx,
+                       double *dmu) {
+    const double lam = 1.0 / eps;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        nsum g[64], s = {0, 0};
+        for (int k = 0; k < d; ++k) g[k].s = g[k].c = 0;
+        for (int64_t j = 0; j < m; ++j) {
+            double dij = dist(x + i * d, y + j * d, d);
+            double c = (r == 2) ? dij * dij : dij;
+            double e = exp(lam * (beta[i] + gamma[j] - c));
+            double pij = mu[i] * nu[j] * e;
+            for (int k = 0; k < d; ++k) {
+                double diff = x[i * d + k] - y[j * d + k];
+                double gc = (r == 2) ? 2.0 * diff : (dij > 0 ? diff / dij : 0.0);
+                nadd(&g[k], pij * gc);
+            }
+            nadd(&s, (e - 1.0) * nu[j]);
+        }
+        for (int k = 0; k < d; ++k) dx[t * d + k] = nval(&g[k]);
+        dmu[t] = eta * (1.0 - exp(-beta[i] / eta)) - nval(&s) / lam;
+    }
+}
+
 /* ---------------------------------------------------------------- MMD
  * eq. (1205): MMD^2 = sum_ij mu_i mu_j k(x_i,x_j) - 2 sum_ij mu_i nu_j k(x_i,xt_j)
  *                     + sum_ij nu_i nu_j k(xt_i,xt_j)   (diagonal included; signed for the
@@ -430,6 +458,33 @@ void orc_mmd2_grad(const double *x, const double *mu, int64_t n, const double *y
         dnu[j] = 2.0 * (s1[j] - s2[j]);
     }
     free(g1); free(g2); free(s1); free(s2);
+}
+
+/* Gradient rows of eq. (1205) for selected rows of x (first measure):
+ *   dx_i = 2 mu_i [sum_j mu_j gradK(x_i - x_j) - sum_j nu_j gradK(x_i - xt_j)],
+ *   dmu_i = 2 [sum_j mu_j K(x_i - x_j) - sum_j nu_j K(x_i - xt_j)]. */
+void orc_mmd2_grad_rows(const double *x, const double *mu, int64_t n, const int64_t *rows,
+                        int64_t nrows, const double *y, const double *nu, int64_t m, int d,
+                        int kind, double lam_k, double *dx, double *dmu) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nrows; ++t) {
+        const int64_t i = rows[t];
+        nsum g[64], s = {0, 0};
+        double gk[64];
+        for (int k = 0; k < d; ++k) g[k].s = g[k].c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            kernel_grad(kind, lam_k, x + i * d, x + j * d, d, gk);
+            for (int k = 0; k < d; ++k) nadd(&g[k], gk[k] * mu[j]);
+            nadd(&s, orc_kernel(kind, lam_k, dist(x + i * d, x + j * d, d)) * mu[j]);
+        }
+        for (int64_t j = 0; j < m; ++j) {
+            kernel_grad(kind, lam_k, x + i * d, y + j * d, d, gk);
+            for (int k = 0; k < d; ++k) nadd(&g[k], -gk[k] * nu[j]);
+            nadd(&s, -orc_kernel(kind, lam_k, dist(x + i * d, y + j * d, d)) * nu[j]);
+        }
+        for (int k = 0; k < d; ++k) dx[t * d + k] = 2.0 * mu[i] * nval(&g[k]);
+        dmu[t] = 2.0 * nval(&s);
+    }
 }
 
 int orc_num_threads(void) {

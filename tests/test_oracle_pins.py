@@ -437,3 +437,20 @@ def test_generators_are_seeded_and_in_domain():
         assert w["x"].dtype == np.float32 and w["x"].min() >= -0.25 and w["x"].max() < 0.25
         assert w["y"].min() >= -0.25 and w["y"].max() < 0.25
         assert abs(w["a"].sum() - w["mass_a"]) < 1e-4 and abs(w["b"].sum() - w["mass_b"]) < 1e-4
+
+
+def test_row_gradients_match_full_gradients():
+    """The sampled-row gradient functions agree with the full ones (same definitions, row subset)."""
+    x, mu, y, nu = _small_problem(n=15, m=11, d=2)
+    rows = np.array([0, 4, 14])
+    for r in (1, 2):
+        b, g = oracle.uot_sinkhorn(x, mu, y, nu, 0.05, 1.0, 50, r=r)
+        dx, dmu, _, _ = oracle.uot_grad(x, mu, y, nu, 0.05, 1.0, b, g, r=r)
+        rx, rm = oracle.uot_grad_rows(x, mu, rows, y, nu, 0.05, 1.0, b, g, r=r)
+        assert np.allclose(rx, dx[rows], rtol=1e-12, atol=1e-15)
+        assert np.allclose(rm, dmu[rows], rtol=1e-12, atol=1e-15)
+    for kind in ("gauss", "energy"):
+        dx, dmu, _, _ = oracle.mmd2_grad(x, mu, y, nu, kind, 0.1)
+        rx, rm = oracle.mmd2_grad_rows(x, mu, rows, y, nu, kind, 0.1)
+        assert np.allclose(rx, dx[rows], rtol=1e-12, atol=1e-15)
+        assert np.allclose(rm, dmu[rows], rtol=1e-12, atol=1e-15)
