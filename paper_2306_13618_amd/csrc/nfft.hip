@@ -232,8 +232,10 @@ struct ScaleArgs {
     int G, T, ntd, d;
 };
 
-__global__ void k_keys(const float *__restrict__ p, int64_t n, ScaleArgs sa, int *__restrict__ key,
-                       float4 *__restrict__ tmp, int *__restrict__ hist) {
+// Sort key of a node: its tile, and (when the key space is small enough) its cell inside the
+// tile, so that nodes are ordered by tile and, within a tile, by grid cell.
+__global__ void k_keys(const float *__restrict__ p, int64_t n, ScaleArgs sa, int cell_keys,
+                       int *__restrict__ key, float4 *__restrict__ tmp, int *__restrict__ hist) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     int cell[3] = {0, 0, 0};
@@ -249,13 +251,80 @@ __global__ void k_keys(const float *__restrict__ p, int64_t n, ScaleArgs sa, int
         fr[k] = (float)f;
         if (fr[k] >= 1.0f) fr[k] = 0.99999994f;
     }
-    int tk = 0;
-    for (int k = sa.d - 1; k >= 0; --k) tk = tk * sa.ntd + cell[k] / sa.T;
+    int tk = 0, loc = 0;
+    for (int k = sa.d - 1; k >= 0; --k) {
+        tk = tk * sa.ntd + cell[k] / sa.T;
+        loc = loc * sa.T + cell[k] % sa.T;
+    }
     int packed = 0;
     for (int k = sa.d - 1; k >= 0; --k) packed = packed * sa.G + cell[k];
-    key[i] = tk;
+    int cells_per_tile = 1;
+    for (int k = 0; k < sa.d; ++k) cells_per_tile *= sa.T;
+    const int kk = cell_keys ? tk * cells_per_tile + loc : tk;
+    key[i] = kk;
     tmp[i] = make_float4(fr[0], fr[1], fr[2], __int_as_float(packed));
-    atomicAdd(&hist[tk], 1);
+    atomicAdd(&hist[kk], 1);
+}
+
+// Multi-block exclusive scan of an int array (up to 2^31 elements): block sums, a scan of the
+// block sums (k_scan_tiles with chunk = 1 as a plain scan), then each block rescans its part.
+constexpr int SCAN_PER_BLOCK = 4096;
+__global__ void __launch_bounds__(256) k_block_sums(const int *__restrict__ in, int64_t n,
+                                                    int *__restrict__ bsum) {
+    __shared__ int sm[256];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_PER_BLOCK;
+    int s = 0;
+    for (int q = threadIdx.x; q < SCAN_PER_BLOCK; q += 256) {
+        const int64_t i = base + q;
+        if (i < n) s += in[i];
+    }
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sm[0];
+}
+
+__global__ void __launch_bounds__(256) k_block_scan(const int *__restrict__ in, int64_t n,
+                                                    const int *__restrict__ boff,
+                                                    int *__restrict__ out) {
+    __shared__ int sm[256];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_PER_BLOCK;
+    constexpr int PER = SCAN_PER_BLOCK / 256;  // 16 consecutive elements per thread
+    int v[PER];
+    int s = 0;
+    for (int q = 0; q < PER; ++q) {
+        const int64_t i = base + threadIdx.x * PER + q;
+        v[q] = (i < n) ? in[i] : 0;
+        s += v[q];
+    }
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        int t = ((int)threadIdx.x >= o) ? sm[threadIdx.x - o] : 0;
+        __syncthreads();
+        sm[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = boff[blockIdx.x] + sm[threadIdx.x] - s;
+    for (int q = 0; q < PER; ++q) {
+        const int64_t i = base + threadIdx.x * PER + q;
+        if (i < n) out[i] = run;
+        run += v[q];
+    }
+}
+
+// Node count of every tile from the cell-level offsets.
+__global__ void k_tile_counts(const int *__restrict__ key_start, int ntiles, int cells_per_tile,
+                              int total, int *__restrict__ tile_count) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    const int64_t k0 = (int64_t)t * cells_per_tile, k1 = k0 + cells_per_tile;
+    const int s0 = key_start[k0];
+    const int s1 = (t + 1 < ntiles) ? key_start[k1] : total;
+    tile_count[t] = s1 - s0;
 }
 
 // Exclusive scans of node counts and chunk counts per tile (single workgroup).
@@ -476,10 +545,13 @@ __global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
 }
 
-// Wave-cooperative spreading (d = 2, 3).  A wave takes one node at a time; lane l < d W
-// evaluates the window value of dimension l / W at offset l % W, then the lanes cover the W^2
-// (y, x) pairs of the node's window in ceil(W^2 / 64) passes and walk the z offsets together, so
-// every LDS atomic of one instruction hits a distinct address of one contiguous patch.
+// Wave-cooperative spreading (d = 2, 3).  Nodes are sorted by grid cell inside each tile; every
+// wave takes a contiguous run of its chunk's nodes, one node at a time: lane l < d W evaluates the
+// window value of dimension l / W at offset l % W, the lanes own the W^2 (y, x) pairs of the
+// window (ceil(W^2 / 64) passes) and accumulate alpha phi_x phi_y phi_z for all W z offsets in
+// registers while consecutive nodes share a cell.  When the cell changes the registers are added
+// to the chunk's LDS box with integer atomics (fixed point, see chunk_scale); the 64 addresses of
+// every such atomic instruction are distinct and contiguous.
 template <int D, int W, int T>
 __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ rec,
                                                      const float *__restrict__ w,
@@ -488,6 +560,7 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     constexpr int S = T + W - 1;
     constexpr int BOX = (D == 2) ? S * S : S * S * S;
     constexpr int NP = (W * W + 63) / 64;  // passes over the (y, x) pairs
+    constexpr int NZ = (D == 3) ? W : 1;
     __shared__ int box[BOX];
     __shared__ float red[4];
     const int4 ch = chunks[blockIdx.x];
@@ -497,52 +570,75 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     const float scale = chunk_scale(w, ch.y, ch.z, red);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const float mm1 = (float)(sa.m - 1);
-    // this lane's (y, x) pairs: offsets inside the box row structure
     int poff[NP];
     int pa[NP], pb[NP];
+    bool pv[NP];
 #pragma unroll
     for (int P = 0; P < NP; ++P) {
         const int q = P * 64 + lane;
-        pb[P] = (q < W * W) ? q / W : 0;
-        pa[P] = (q < W * W) ? q % W : 0;
+        pv[P] = q < W * W;
+        pb[P] = pv[P] ? q / W : 0;
+        pa[P] = pv[P] ? q % W : 0;
         poff[P] = pb[P] * S + pa[P];
     }
     const int wdim = (lane < D * W) ? lane / W : 0;
     const int woff = lane % W;
-    for (int k = ch.y + wave; k < ch.y + ch.z; k += nwaves) {
-        const float4 r = rec[k];
+    // contiguous node range of this wave
+    const int per = (ch.z + nwaves - 1) / nwaves;
+    const int k0 = ch.y + wave * per, k1 = min(ch.y + ch.z, k0 + per);
+    float acc[NP][NZ];
+#pragma unroll
+    for (int P = 0; P < NP; ++P)
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) acc[P][l] = 0.0f;
+    int cur = -1;
+    auto flush = [&](int packed) {
         int c[3] = {0, 0, 0};
-        unpack_cell<D>(__float_as_int(r.w), sa.G, c);
+        unpack_cell<D>(packed, sa.G, c);
+        const int ox = c[0] - tc[0] * T, oy = c[1] - tc[1] * T;
+        const int oz = (D == 3) ? c[2] - tc[2] * T : 0;
+        const int base = oy * S + ox;
+#pragma unroll
+        for (int l = 0; l < NZ; ++l) {
+            const int zb = (D == 3 ? (oz + l) * S * S : 0) + base;
+#pragma unroll
+            for (int P = 0; P < NP; ++P) {
+                if (pv[P]) atomicAdd(&box[zb + poff[P]], __float2int_rn(acc[P][l]));
+                acc[P][l] = 0.0f;
+            }
+        }
+    };
+    for (int k = k0; k < k1; ++k) {
+        const float4 r = rec[k];
+        const int packed = __float_as_int(r.w);
+        if (packed != cur) {
+            if (cur >= 0) flush(cur);
+            cur = packed;
+        }
         const float alpha = w[k] * scale;
         const float fr = (wdim == 0) ? r.x : (wdim == 1 ? r.y : r.z);
         const float val = (lane < D * W) ? kb_phi(sa.kb, fr + mm1 - (float)woff) : 0.0f;
-        const int ox = c[0] - tc[0] * T, oy = c[1] - tc[1] * T;
-        const int base = oy * S + ox;
         float wxy[NP];
 #pragma unroll
         for (int P = 0; P < NP; ++P) {
             const float vx = __shfl(val, pa[P], 64);
             const float vy = __shfl(val, W + pb[P], 64);
-            wxy[P] = (P * 64 + lane < W * W) ? alpha * vx * vy : 0.0f;
+            wxy[P] = pv[P] ? alpha * vx * vy : 0.0f;
         }
         if (D == 2) {
 #pragma unroll
-            for (int P = 0; P < NP; ++P)
-                if (P * 64 + lane < W * W) atomicAdd(&box[base + poff[P]], __float2int_rn(wxy[P]));
+            for (int P = 0; P < NP; ++P) acc[P][0] += wxy[P];
         } else {
-            const int oz = c[2] - tc[2] * T;
 #pragma unroll
-            for (int l = 0; l < W; ++l) {
+            for (int l = 0; l < NZ; ++l) {
                 const float wz = __int_as_float(
                     __builtin_amdgcn_readlane(__float_as_int(val), 2 * W + l));
-                const int zb = (oz + l) * S * S + base;
 #pragma unroll
-                for (int P = 0; P < NP; ++P)
-                    if (P * 64 + lane < W * W)
-                        atomicAdd(&box[zb + poff[P]], __float2int_rn(wz * wxy[P]));
+                for (int P = 0; P < NP; ++P) acc[P][l] = fmaf(wz, wxy[P], acc[P][l]);
             }
         }
     }
+    if (cur >= 0) flush(cur);
     __syncthreads();
     const float inv = 1.0f / scale;
     float *dst = scratch + (int64_t)blockIdx.x * BOX;
@@ -966,67 +1062,96 @@ __global__ void k_nf_scatter(const float *__restrict__ xs, int64_t n, int d,
     for (int c = 0; c < d; ++c) cxs[(int64_t)pos * d + c] = xs[i * d + c];
 }
 
+// One workgroup per target cell: the targets of the cell (up to 256 at a time) against the
+// sources of the (2R+1)^d neighbouring cells (cell side = radius / R), staged through LDS so that
+// every source is loaded once per workgroup and read by all lanes as a broadcast.
+constexpr int NF_R = 2;
 template <int D, bool GRAD>
-__global__ void __launch_bounds__(256) k_nearfield(const float *__restrict__ txs, int64_t nt,
-                                                   const int *__restrict__ cell_start,
-                                                   const int *__restrict__ order,
-                                                   const float *__restrict__ sxs,
+__global__ void __launch_bounds__(256) k_nearfield(const int *__restrict__ t_start,
+                                                   const int *__restrict__ t_order,
+                                                   const float *__restrict__ t_xs,
+                                                   const int *__restrict__ s_start,
+                                                   const int *__restrict__ s_order,
+                                                   const float *__restrict__ s_xs,
                                                    const float *__restrict__ w, NearArgs na,
-                                                   float *__restrict__ out,
+                                                   int ncells, float *__restrict__ out,
                                                    float *__restrict__ gout) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= nt) return;
-    float xi[3] = {0, 0, 0};
-    int ci[3] = {0, 0, 0};
-    for (int c = 0; c < D; ++c) {
-        xi[c] = txs[i * D + c];
-        ci[c] = max(0, min(na.dims[c] - 1, (int)floorf((xi[c] - na.lo[c]) * na.h_inv)));
-    }
-    float acc = 0.0f, g[3] = {0, 0, 0};
-    const int z0 = (D > 2) ? max(ci[2] - 1, 0) : 0, z1 = (D > 2) ? min(ci[2] + 1, na.dims[2] - 1) : 0;
-    const int y0 = (D > 1) ? max(ci[1] - 1, 0) : 0, y1 = (D > 1) ? min(ci[1] + 1, na.dims[1] - 1) : 0;
-    const int x0 = max(ci[0] - 1, 0), x1 = min(ci[0] + 1, na.dims[0] - 1);
-    for (int cz = z0; cz <= z1; ++cz)
-        for (int cy = y0; cy <= y1; ++cy) {
-            const int rowc = (cz * na.dims[1] + cy) * na.dims[0];
-            const int s0 = cell_start[rowc + x0], s1 = cell_start[rowc + x1 + 1];
-            for (int k = s0; k < s1; ++k) {
-                float dv[3], r2 = 0.0f;
-                for (int c = 0; c < D; ++c) {
-                    dv[c] = xi[c] - sxs[(int64_t)k * D + c];
-                    r2 = fmaf(dv[c], dv[c], r2);
+    __shared__ float sx[256 * D];
+    __shared__ float sw[256];
+    for (int cell = blockIdx.x; cell < ncells; cell += gridDim.x) {
+        const int tcs = t_start[cell], tce = t_start[cell + 1];
+        if (tcs >= tce) continue;
+        int cc[3] = {cell % na.dims[0], (cell / na.dims[0]) % na.dims[1],
+                     cell / (na.dims[0] * na.dims[1])};
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = (k < D) ? max(cc[k] - NF_R, 0) : 0;
+            hi[k] = (k < D) ? min(cc[k] + NF_R, na.dims[k] - 1) : 0;
+        }
+        for (int tb = tcs; tb < tce; tb += blockDim.x) {
+            const int t = tb + threadIdx.x;
+            const bool active = t < tce;
+            float xi[3] = {0, 0, 0};
+            if (active)
+                for (int c = 0; c < D; ++c) xi[c] = t_xs[(int64_t)t * D + c];
+            float acc = 0.0f, g[3] = {0, 0, 0};
+            for (int cz = lo[2]; cz <= hi[2]; ++cz)
+                for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+                    const int row = (cz * na.dims[1] + cy) * na.dims[0];
+                    const int s0 = s_start[row + lo[0]], s1 = s_start[row + hi[0] + 1];
+                    for (int sb = s0; sb < s1; sb += blockDim.x) {
+                        const int cnt = min((int)blockDim.x, s1 - sb);
+                        __syncthreads();
+                        if ((int)threadIdx.x < cnt) {
+                            const int k = sb + threadIdx.x;
+                            for (int c = 0; c < D; ++c) sx[threadIdx.x * D + c] = s_xs[(int64_t)k * D + c];
+                            sw[threadIdx.x] = w[s_order[k]];
+                        }
+                        __syncthreads();
+                        for (int j = 0; j < cnt; ++j) {
+                            float dv[3], r2 = 0.0f;
+                            for (int c = 0; c < D; ++c) {
+                                dv[c] = xi[c] - sx[j * D + c];
+                                r2 = fmaf(dv[c], dv[c], r2);
+                            }
+                            if (r2 >= na.r2max) continue;
+                            const float wj = sw[j];
+                            const float r = sqrtf(r2);
+                            // inner polynomial in rho^2, rho = r / (epsI P)
+                            const float rho2 = r2 * na.rinv * na.rinv;
+                            float q = 0.0f, dq = 0.0f;
+                            for (int kk = na.p - 1; kk >= 0; --kk) q = fmaf(q, rho2, na.ci[kk]);
+                            float kv, dk = 0.0f;  // K(r) and dK/dr
+                            if (na.kind == FS_LAPLACE) {
+                                kv = __expf(-r * na.lambda_inv);
+                                dk = -na.lambda_inv * kv;
+                            } else if (na.kind == FS_ENERGY) {
+                                kv = -r;
+                                dk = -1.0f;
+                            } else {
+                                kv = __expf(-r2 * na.lambda_inv);
+                                dk = -2.0f * r * na.lambda_inv * kv;
+                            }
+                            acc = fmaf(kv - q, wj, acc);
+                            if (GRAD) {
+                                // dq/dr = rinv^2 r sum_{k>=1} 2k c_k rho^{2(k-1)}
+                                for (int kk = na.p - 1; kk >= 1; --kk)
+                                    dq = fmaf(dq, rho2, 2.0f * kk * na.ci[kk]);
+                                const float dqdr = dq * r * na.rinv * na.rinv;
+                                const float coef = (r > 0.0f) ? (dk - dqdr) * wj / r : 0.0f;
+                                for (int c = 0; c < D; ++c) g[c] = fmaf(coef, dv[c], g[c]);
+                            }
+                        }
+                    }
                 }
-                if (r2 >= na.r2max) continue;
-                const float wj = w[order[k]];
-                const float r = sqrtf(r2);
-                // inner polynomial in rho^2, rho = r / (epsI P)
-                const float rho2 = r2 * na.rinv * na.rinv;
-                float q = 0.0f, dq = 0.0f;
-                for (int kk = na.p - 1; kk >= 0; --kk) q = fmaf(q, rho2, na.ci[kk]);
-                float kv, dk = 0.0f;  // K(r) and dK/dr
-                if (na.kind == FS_LAPLACE) {
-                    kv = __expf(-r * na.lambda_inv);
-                    dk = -na.lambda_inv * kv;
-                } else if (na.kind == FS_ENERGY) {
-                    kv = -r;
-                    dk = -1.0f;
-                } else {
-                    kv = __expf(-r2 * na.lambda_inv);
-                    dk = -2.0f * r * na.lambda_inv * kv;
-                }
-                acc = fmaf(kv - q, wj, acc);
-                if (GRAD) {
-                    // dq/dr = rinv^2 r sum_{k>=1} 2k c_k rho^{2(k-1)}
-                    for (int kk = na.p - 1; kk >= 1; --kk) dq = fmaf(dq, rho2, 2.0f * kk * na.ci[kk]);
-                    const float dqdr = dq * r * na.rinv * na.rinv;
-                    const float coef = (r > 0.0f) ? (dk - dqdr) * wj / r : 0.0f;
-                    for (int c = 0; c < D; ++c) g[c] = fmaf(coef, dv[c], g[c]);
-                }
+            if (active) {
+                const int o = t_order[t];
+                out[o] += acc;
+                if (GRAD)
+                    for (int c = 0; c < D; ++c) gout[(int64_t)o * D + c] += g[c];
             }
         }
-    out[i] += acc;
-    if (GRAD)
-        for (int c = 0; c < D; ++c) gout[i * D + c] += g[c];
+    }
 }
 
 }  // namespace
@@ -1068,19 +1193,42 @@ void scatter_rows_from_sorted(const Nodes &nd, const float *vs, int d, float *v,
 
 namespace {
 
+// Exclusive scan of n ints (device), result in out; returns nothing (stream-ordered).
+void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s) {
+    const int64_t nb = (n + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK;
+    FS_REQUIRE(nb <= 1024 * 1024, FS_EINVAL, "scan too large");
+    DevBuf<int> bsum(nb + 1), boff(nb + 1), tmp1(2 * (nb + 1)), tot(2);
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)nb), dim3(256), 0, s, in, n, bsum.p);
+    FS_LAUNCHED();
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bsum.p, (int)nb, 1 << 30, boff.p,
+                       tmp1.p, tot.p);
+    FS_LAUNCHED();
+    hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nb), dim3(256), 0, s, in, n, boff.p, out);
+    FS_LAUNCHED();
+    FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+}
+
 void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s) {
     nd.n = n;
     const int d = pp.d, G = pp.G, T = pp.T, ntd = G / T;
-    int64_t ntiles = 1;
-    for (int k = 0; k < d; ++k) ntiles *= ntd;
+    int64_t ntiles = 1, cells_per_tile = 1;
+    for (int k = 0; k < d; ++k) {
+        ntiles *= ntd;
+        cells_per_tile *= T;
+    }
+    // order nodes by (tile, cell) when the cell key space is at most 2^24 (64 MB of counters)
+    const int64_t ncellkeys = ntiles * cells_per_tile;
+    const bool cell_keys = ncellkeys <= (int64_t(1) << 24);
+    const int64_t nkeys = cell_keys ? ncellkeys : ntiles;
     nd.rec.alloc(n + 1);
     nd.perm.alloc(n + 1);
     nd.xs.alloc(n * d + 1);
     nd.tile_chunk.alloc(2 * ntiles);
-    DevBuf<int> key(n + 1), hist(ntiles), cursor(ntiles), tstart(ntiles), totals(2);
+    DevBuf<int> key(n + 1), hist(nkeys), cursor(nkeys), kstart(nkeys), tcount(ntiles),
+        tstart(ntiles), totals(2);
     DevBuf<float4> tmp(n + 1);
-    fill_i32(hist.p, ntiles, 0, s);
-    fill_i32(cursor.p, ntiles, 0, s);
+    fill_i32(hist.p, nkeys, 0, s);
+    fill_i32(cursor.p, nkeys, 0, s);
     ScaleArgs sa{};
     for (int k = 0; k < 3; ++k) sa.c[k] = pp.center[k];
     sa.inv_P = 1.0 / pp.P;
@@ -1090,15 +1238,23 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     sa.d = d;
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256), 0, s,
-                           pts, n, sa, key.p, tmp.p, hist.p);
+                           pts, n, sa, (int)cell_keys, key.p, tmp.p, hist.p);
         FS_LAUNCHED();
     }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, hist.p, (int)ntiles, pp.chunk,
+    exclusive_scan(hist.p, nkeys, kstart.p, s);
+    const int *tile_hist = hist.p;
+    if (cell_keys) {
+        hipLaunchKernelGGL(k_tile_counts, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, kstart.p,
+                           (int)ntiles, (int)cells_per_tile, (int)n, tcount.p);
+        FS_LAUNCHED();
+        tile_hist = tcount.p;
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, tile_hist, (int)ntiles, pp.chunk,
                        tstart.p, nd.tile_chunk.p, totals.p);
     FS_LAUNCHED();
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter_nodes, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256),
-                           0, s, pts, n, d, key.p, tmp.p, tstart.p, cursor.p, nd.rec.p,
+                           0, s, pts, n, d, key.p, tmp.p, kstart.p, cursor.p, nd.rec.p,
                            nd.perm.p, nd.xs.p);
         FS_LAUNCHED();
     }
@@ -1109,7 +1265,8 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     nd.chunks.alloc(nd.nchunks + 1);
     if (nd.nchunks > 0) {
         hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
-                           (int)ntiles, tstart.p, hist.p, nd.tile_chunk.p, pp.chunk, nd.chunks.p);
+                           (int)ntiles, tstart.p, tile_hist, nd.tile_chunk.p, pp.chunk,
+                           nd.chunks.p);
         FS_LAUNCHED();
     }
     FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
@@ -1280,7 +1437,7 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     if (!pl.same) bin_nodes(pl.Y, y, m, pp, s);
 
     if (pp.nearfield) {
-        pp.nf_h = pp.epsI * pp.P * (1.0 + 1e-6);
+        pp.nf_h = pp.epsI * pp.P * (1.0 + 1e-6) / NF_R;
         for (int k = 0; k < 3; ++k) {
             pp.nf_lo[k] = (k < d) ? lo[k] : 0.0;
             pp.nf_dims[k] = 1;
@@ -1534,12 +1691,14 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
             na.lo[k] = (float)pp.nf_lo[k];
             na.dims[k] = pp.nf_dims[k];
         }
-        dim3 g(blocks_for(dst.n, 256, int64_t(1) << 30)), b(256);
+        int ncells = 1;
+        for (int k = 0; k < pp.d; ++k) ncells *= pp.nf_dims[k];
+        dim3 g((unsigned)std::min(ncells, 1 << 20)), b(256);
         ProfScope pn("nearfield", s);
 #define FS_NF(DD, GG)                                                                        \
-    hipLaunchKernelGGL((k_nearfield<DD, GG>), g, b, 0, s, dst.xs.p, dst.n,                   \
-                       src.nf_cell_start.p, src.nf_order.p, src.nf_xs.p, w_sorted, na, t_sorted, \
-                       grad)
+    hipLaunchKernelGGL((k_nearfield<DD, GG>), g, b, 0, s, dst.nf_cell_start.p, dst.nf_order.p, \
+                       dst.nf_xs.p, src.nf_cell_start.p, src.nf_order.p, src.nf_xs.p, w_sorted,  \
+                       na, ncells, t_sorted, grad)
         if (grad) {
             if (pp.d == 1) FS_NF(1, true); else if (pp.d == 2) FS_NF(2, true); else FS_NF(3, true);
         } else {
