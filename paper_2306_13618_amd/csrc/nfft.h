@@ -22,6 +22,11 @@ struct Nodes {
 
 enum Regime { REGIME_CUBE = 0, REGIME_BALL = 1 };
 
+// Window segment polynomials: on the unit cell of a node (fractional offset t in [0, 1)), the
+// window value at grid offset a is phi(t + m - 1 - a), written as a degree-(WPOLY-1)
+// polynomial in u = 2t - 1 (fitted in FP64 per plan).
+constexpr int WPOLY = 10;
+
 struct PlanParams {
     int d = 0, kind = FS_GAUSS;
     double lambda = 1.0;
@@ -52,6 +57,7 @@ struct Plan {
     DevBuf<float> grid;  // G^d real
     DevBuf<float2> specA, specB;
     DevBuf<float2> twiddle;  // exp(-2 pi i q / G), q < G/2
+    DevBuf<float> wpoly;     // window segments as polynomials: value (W x WPOLY) then derivative
     DevBuf<float> scratch;   // per-chunk spread boxes
     DevBuf<float> wbuf;      // sorted weights
     DevBuf<float> tbuf;      // sorted sums

@@ -147,6 +147,39 @@ double kb_hat(double m, double b, int G, int k) {
     return bessel_i0(arg) / G / phi0;
 }
 
+// Kaiser-Bessel window (normalised, phi(0) = 1) and its derivative in FP64, grid units.
+double kb_value(double m, double b, double s) {
+    const double q2 = m * m - s * s;
+    if (q2 <= 0.0) return (q2 == 0.0) ? b * m / (-std::expm1(-2.0 * b * m)) * 2.0 * std::exp(-b * m) : 0.0;
+    const double q = std::sqrt(q2);
+    return std::exp(b * (q - m)) * (-std::expm1(-2.0 * b * q)) / q * m / (-std::expm1(-2.0 * b * m));
+}
+double kb_deriv(double m, double b, double s) {
+    const double h = 1e-6;
+    // complex-step-free central difference in FP64 is accurate to ~1e-10 here (smooth segment)
+    return (kb_value(m, b, s + h) - kb_value(m, b, s - h)) / (2.0 * h);
+}
+
+// Least-squares fit of f on [-1, 1] by sum_{k<K} c_k u^k at 4K Chebyshev points (normal equations
+// in FP64; the Vandermonde basis is well conditioned at this degree on these points).
+template <class F>
+void fit_poly(F f, int K, double *c) {
+    const int M = 4 * K;
+    std::vector<double> A(K * K, 0.0), rhs(K, 0.0);
+    for (int i = 0; i < M; ++i) {
+        const double u = std::cos(M_PI * (i + 0.5) / M);
+        const double fv = f(u);
+        double pu[32];
+        pu[0] = 1.0;
+        for (int k = 1; k < K; ++k) pu[k] = pu[k - 1] * u;
+        for (int r = 0; r < K; ++r) {
+            rhs[r] += pu[r] * fv;
+            for (int k = 0; k < K; ++k) A[r * K + k] += pu[r] * pu[k];
+        }
+    }
+    solve_dense(K, A, rhs, c);
+}
+
 }  // namespace
 
 // =====================================================================================
@@ -185,6 +218,14 @@ __device__ float2 *lds_fft(float2 *a, float2 *b, int logL, int NB, const float2 
         b = tmp;
     }
     return a;
+}
+
+// Horner evaluation of one window segment polynomial at u = 2t - 1.
+__device__ __forceinline__ float wpoly_eval(const float *__restrict__ c, float u) {
+    float v = c[WPOLY - 1];
+#pragma unroll
+    for (int k = WPOLY - 2; k >= 0; --k) v = fmaf(v, u, c[k]);
+    return v;
 }
 
 constexpr int FFT_THREADS = 256;
@@ -477,6 +518,7 @@ __global__ void k_build_mult(const double *__restrict__ bk, int N, int d,
 struct SpreadArgs {
     KB kb;
     int G, T, ntd, m;
+    const float *wp;  // window polynomials: value (W x WPOLY) then derivative (W x WPOLY)
 };
 
 template <int D>
@@ -535,7 +577,7 @@ __global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
         for (int i = 0; i < W; ++i) {
             int a = i + ra;
             a = (a >= W) ? a - W : a;
-            const float v = alpha * kb_phi(sa.kb, r.x + mm1 - (float)a);
+            const float v = alpha * wpoly_eval(sa.wp + a * WPOLY, 2.0f * r.x - 1.0f);
             atomicAdd(&box[c[0] - tc[0] * T + a], __float2int_rn(v));
         }
     }
@@ -562,7 +604,7 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     constexpr int NP = (W * W + 63) / 64;  // passes over the (y, x) pairs
     constexpr int NZ = (D == 3) ? W : 1;
     __shared__ int box[BOX];
-    __shared__ float red[4];
+    __shared__ float red[16];
     const int4 ch = chunks[blockIdx.x];
     int tc[3] = {0, 0, 0};
     tile_coords<D>(ch.x, sa.ntd, tc);
@@ -583,6 +625,9 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     }
     const int wdim = (lane < D * W) ? lane / W : 0;
     const int woff = lane % W;
+    float wc[WPOLY];
+#pragma unroll
+    for (int k = 0; k < WPOLY; ++k) wc[k] = sa.wp[woff * WPOLY + k];
     // contiguous node range of this wave
     const int per = (ch.z + nwaves - 1) / nwaves;
     const int k0 = ch.y + wave * per, k1 = min(ch.y + ch.z, k0 + per);
@@ -617,7 +662,7 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
         }
         const float alpha = w[k] * scale;
         const float fr = (wdim == 0) ? r.x : (wdim == 1 ? r.y : r.z);
-        const float val = (lane < D * W) ? kb_phi(sa.kb, fr + mm1 - (float)woff) : 0.0f;
+        const float val = (lane < D * W) ? wpoly_eval(wc, 2.0f * fr - 1.0f) : 0.0f;
         float wxy[NP];
 #pragma unroll
         for (int P = 0; P < NP; ++P) {
@@ -656,6 +701,71 @@ __global__ void k_reduce_chunks(float *__restrict__ scratch, const int *__restri
             for (int c = 1; c < nc; ++c) acc += scratch[(int64_t)(c0 + c) * box + e];
             scratch[(int64_t)c0 * box + e] = acc;
         }
+    }
+}
+
+// Fold for the common case (at least 3 tiles per dimension, boxes narrower than the grid,
+// m <= T), after k_reduce_chunks: one workgroup per tile; the reduced box offsets of the 3^d
+// neighbouring tiles sit in LDS and every grid point of the tile sums the boxes that cover it, in
+// a fixed neighbour order.
+template <int D>
+__global__ void __launch_bounds__(256) k_fold_tiles(const float *__restrict__ scratch,
+                                                    const int *__restrict__ tile_chunk, int G,
+                                                    int T, int ntd, int m, int S,
+                                                    float *__restrict__ grid) {
+    constexpr int NN = (D == 1) ? 3 : (D == 2 ? 9 : 27);
+    __shared__ int nc0[NN], nnc[NN], norg[NN][3];
+    const int t = blockIdx.x;
+    int tc[3] = {0, 0, 0};
+    tile_coords<D>(t, ntd, tc);
+    if ((int)threadIdx.x < NN) {
+        int rem = threadIdx.x, tid = 0, mul = 1;
+        for (int k = 0; k < D; ++k) {
+            const int dk = rem % 3 - 1;
+            rem /= 3;
+            const int tk = (tc[k] + dk + ntd) % ntd;
+            tid += tk * mul;
+            mul *= ntd;
+            norg[threadIdx.x][k] = tk * T - (m - 1);
+        }
+        nc0[threadIdx.x] = tile_chunk[2 * tid];
+        nnc[threadIdx.x] = tile_chunk[2 * tid + 1];
+    }
+    __syncthreads();
+    int box = S;
+    if (D > 1) box *= S;
+    if (D > 2) box *= S;
+    int npts = T;
+    if (D > 1) npts *= T;
+    if (D > 2) npts *= T;
+    for (int q = threadIdx.x; q < npts; q += blockDim.x) {
+        int p[3] = {0, 0, 0};
+        {
+            int rem = q;
+            for (int k = 0; k < D; ++k) {
+                p[k] = tc[k] * T + rem % T;
+                rem /= T;
+            }
+        }
+        float acc = 0.0f;
+        for (int j = 0; j < NN; ++j) {
+            const int nc = nnc[j];
+            if (nc == 0) continue;
+            int l = 0, mul = 1;
+            bool inside = true;
+            for (int k = 0; k < D; ++k) {
+                const int loc = (p[k] - norg[j][k] + G) & (G - 1);
+                inside &= loc < S;
+                l += loc * mul;
+                mul *= S;
+            }
+            if (!inside) continue;
+            acc += scratch[(int64_t)nc0[j] * box + l];
+        }
+        int64_t gi = p[0];
+        if (D > 1) gi += (int64_t)G * p[1];
+        if (D > 2) gi += (int64_t)G * G * p[2];
+        grid[gi] = acc;
     }
 }
 
@@ -712,15 +822,18 @@ __global__ void k_fold(const float *__restrict__ scratch, const int *__restrict_
 
 // ------------------------------------------------------------------ FFT passes
 struct FftArgs {
-    int G, logG, N, KX, nbx;  // nbx: columns per block in the strided passes
+    int G, logG, N, KX;
+    int nb;   // row pairs per block in the first-axis passes
+    int nbx;  // columns per block in the strided passes
 };
 
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_r2c(const float *__restrict__ grid,
                                                             int rows, FftArgs fa,
                                                             const float2 *__restrict__ tw,
                                                             float2 *__restrict__ specA) {
-    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
-    const int G = fa.G, NB = FFT_ELEMS / G;
+    extern __shared__ float2 fft_lds[];
+    const int G = fa.G, NB = fa.nb;
+    float2 *bufa = fft_lds, *bufb = fft_lds + NB * G;
     const int pairs = rows / 2;
     const int p0 = blockIdx.x * NB;
     const int nb = min(NB, pairs - p0);
@@ -751,8 +864,9 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restr
                                                             int rows, FftArgs fa,
                                                             const float2 *__restrict__ tw,
                                                             float *__restrict__ grid) {
-    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
-    const int G = fa.G, NB = FFT_ELEMS / G, h = fa.N / 2;
+    extern __shared__ float2 fft_lds[];
+    const int G = fa.G, NB = fa.nb, h = fa.N / 2;
+    float2 *bufa = fft_lds, *bufb = fft_lds + NB * G;
     const int pairs = rows / 2;
     const int p0 = blockIdx.x * NB;
     const int nb = min(NB, pairs - p0);
@@ -789,8 +903,9 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restr
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_1d_conv(float *__restrict__ grid, FftArgs fa,
                                                               const float2 *__restrict__ tw,
                                                               const float *__restrict__ M) {
-    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    extern __shared__ float2 fft_lds[];
     const int G = fa.G, h = fa.N / 2;
+    float2 *bufa = fft_lds, *bufb = fft_lds + G;
     for (int q = threadIdx.x; q < G; q += blockDim.x) bufa[q] = make_float2(grid[q], 0.f);
     __syncthreads();
     float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, 1, tw);
@@ -814,8 +929,9 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_y(float2 *__restrict__ spec
                                                         float2 *__restrict__ specB, FftArgs fa,
                                                         const float2 *__restrict__ tw,
                                                         const float *__restrict__ M) {
-    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    extern __shared__ float2 fft_lds[];
     const int G = fa.G, KX = fa.KX, NBX = fa.nbx, h = fa.N / 2, NB1 = fa.N + 1;
+    float2 *bufa = fft_lds, *bufb = fft_lds + NBX * G;
     const int nkb = (KX + NBX - 1) / NBX;
     const int z = blockIdx.x / nkb, kb = blockIdx.x - z * nkb;
     const int kx0 = kb * NBX, nbx = min(NBX, KX - kx0);
@@ -872,8 +988,9 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_z_conv(float2 *__restrict__
                                                              FftArgs fa,
                                                              const float2 *__restrict__ tw,
                                                              const float *__restrict__ M) {
-    __shared__ float2 bufa[FFT_ELEMS], bufb[FFT_ELEMS];
+    extern __shared__ float2 fft_lds[];
     const int G = fa.G, KX = fa.KX, NBX = fa.nbx, h = fa.N / 2, NB1 = fa.N + 1, H = h + 1;
+    float2 *bufa = fft_lds, *bufb = fft_lds + NBX * G;
     const int nkb = (KX + NBX - 1) / NBX;
     const int kyb = blockIdx.x / nkb, kb = blockIdx.x - kyb * nkb;
     const int kx0 = kb * NBX, nbx = min(NBX, KX - kx0);
@@ -925,8 +1042,10 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
         box[q] = grid[gi];
     }
     __syncthreads();
-    const float mm1 = (float)(sa.m - 1);
-    for (int k = ch.y + threadIdx.x; k < ch.y + ch.z; k += blockDim.x) {
+    // this workgroup's share of the chunk (gridDim.y workgroups per chunk)
+    const int per = (ch.z + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int kb = ch.y + (int)blockIdx.y * per, ke = min(ch.y + ch.z, kb + per);
+    for (int k = kb + threadIdx.x; k < ke; k += blockDim.x) {
         const float4 r = rec[k];
         int c[3] = {0, 0, 0};
         unpack_cell<D>(__float_as_int(r.w), sa.G, c);
@@ -934,10 +1053,11 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
         int o[3];
         for (int kk = 0; kk < D; ++kk) o[kk] = c[kk] - tc[kk] * T;
         float wx[W], dwx[W];
+        const float ux = 2.0f * fr[0] - 1.0f;
 #pragma unroll
         for (int a = 0; a < W; ++a) {
-            wx[a] = kb_phi(sa.kb, fr[0] + mm1 - (float)a);
-            if (GRAD) dwx[a] = kb_dphi(sa.kb, fr[0] + mm1 - (float)a);
+            wx[a] = wpoly_eval(sa.wp + a * WPOLY, ux);
+            if (GRAD) dwx[a] = wpoly_eval(sa.wp + (W + a) * WPOLY, ux);
         }
         float val = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
         if (D == 1) {
@@ -948,18 +1068,20 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
             }
         } else {
             float wy[W], dwy[W];
+            const float uy = 2.0f * fr[1] - 1.0f;
 #pragma unroll
             for (int b = 0; b < W; ++b) {
-                wy[b] = kb_phi(sa.kb, fr[1] + mm1 - (float)b);
-                if (GRAD) dwy[b] = kb_dphi(sa.kb, fr[1] + mm1 - (float)b);
+                wy[b] = wpoly_eval(sa.wp + b * WPOLY, uy);
+                if (GRAD) dwy[b] = wpoly_eval(sa.wp + (W + b) * WPOLY, uy);
             }
             const int nz = (D == 3) ? W : 1;
             for (int l = 0; l < nz; ++l) {
                 float wz = 1.0f, dwz = 0.0f;
                 int zb = 0;
                 if (D == 3) {
-                    wz = kb_phi(sa.kb, fr[2] + mm1 - (float)l);
-                    if (GRAD) dwz = kb_dphi(sa.kb, fr[2] + mm1 - (float)l);
+                    const float uz = 2.0f * fr[2] - 1.0f;
+                    wz = wpoly_eval(sa.wp + l * WPOLY, uz);
+                    if (GRAD) dwz = wpoly_eval(sa.wp + (W + l) * WPOLY, uz);
                     zb = (o[2] + l) * S * S;
                 }
                 float pv = 0.0f, pgx = 0.0f, pgy = 0.0f;
@@ -1339,6 +1461,7 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     pp.T = (d == 3) ? 8 : (d == 2 ? 32 : 256);
     if (pp.T > pp.G) pp.T = pp.G;
     const int64_t nmax = std::max(n, m);
+    // chunk size: about 1000 chunks over the point set (four per CU), 64..2048 nodes
     int ch = 64;
     while (ch < 2048 && ch * 1024 < nmax) ch *= 2;
     pp.chunk = ch;
@@ -1430,6 +1553,21 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     pp.kb.m = (float)pp.m;
     pp.kb.b = (float)b;
     pp.kb.inv_one_minus = (float)(1.0 / (-std::expm1(-2.0 * b * pp.m)));
+    {
+        // window value phi(t + m - 1 - a) and derivative d phi/ds on t in [0, 1), u = 2t - 1
+        std::vector<float> hp(2 * pp.W * WPOLY);
+        double c[WPOLY];
+        for (int a = 0; a < pp.W; ++a) {
+            const double off = pp.m - 1 - a;
+            fit_poly([&](double u) { return kb_value(pp.m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
+            for (int k = 0; k < WPOLY; ++k) hp[a * WPOLY + k] = (float)c[k];
+            fit_poly([&](double u) { return kb_deriv(pp.m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
+            for (int k = 0; k < WPOLY; ++k) hp[(pp.W + a) * WPOLY + k] = (float)c[k];
+        }
+        pl.wpoly.alloc(hp.size());
+        FS_HIP(hipMemcpyAsync(pl.wpoly.p, hp.data(), hp.size() * sizeof(float),
+                              hipMemcpyHostToDevice, s));
+    }
 
     // ---- bin the point sets (A2)
     pl.same = (y == x && m == n);
@@ -1536,7 +1674,7 @@ template <int D, int W>
 void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const float *w,
                           float *t, float *grad, hipStream_t s) {
     const PlanParams &pp = pl.pp;
-    SpreadArgs sa{pp.kb, pp.G, pp.T, pp.G / pp.T, pp.m};
+    SpreadArgs sa{pp.kb, pp.G, pp.T, pp.G / pp.T, pp.m, pl.wpoly.p};
     // the tile side shrinks to the grid size for small grids
     auto run = [&](auto tconst) {
         constexpr int T = decltype(tconst)::value;
@@ -1551,23 +1689,28 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
             }
             FS_LAUNCHED();
         }
+        int64_t gsz = 1;
+        for (int k = 0; k < D; ++k) gsz *= pp.G;
         if (src.nchunks > 0) {
             ProfScope ps("fold", s);
-            int box = 1;
-            for (int k = 0; k < D; ++k) box *= (T + W - 1);
+            const int S = T + W - 1, ntd = pp.G / T;
             int64_t ntiles = 1;
-            for (int k = 0; k < D; ++k) ntiles *= pp.G / T;
+            for (int k = 0; k < D; ++k) ntiles *= ntd;
+            int box = 1;
+            for (int k = 0; k < D; ++k) box *= S;
             hipLaunchKernelGGL(k_reduce_chunks,
                                dim3((box + 255) / 256, (unsigned)std::min<int64_t>(ntiles, 65535)),
                                dim3(256), 0, s, pl.scratch.p, src.tile_chunk.p, (int)ntiles, box);
             FS_LAUNCHED();
-        }
-        int64_t gsz = 1;
-        for (int k = 0; k < D; ++k) gsz *= pp.G;
-        if (src.nchunks > 0) {
-            hipLaunchKernelGGL(k_fold<D>, dim3(blocks_for(gsz, 256, 1 << 16)), dim3(256), 0, s,
-                               pl.scratch.p, src.tile_chunk.p, pp.G, T, pp.G / T, pp.m,
-                               T + W - 1, pl.grid.p);
+            if (ntd >= 3 && S <= pp.G && pp.m <= T) {
+                hipLaunchKernelGGL(k_fold_tiles<D>, dim3((unsigned)ntiles), dim3(256), 0, s,
+                                   pl.scratch.p, src.tile_chunk.p, pp.G, T, ntd, pp.m, S,
+                                   pl.grid.p);
+            } else {
+                hipLaunchKernelGGL(k_fold<D>, dim3(blocks_for(gsz, 256, 1 << 16)), dim3(256), 0, s,
+                                   pl.scratch.p, src.tile_chunk.p, pp.G, T, ntd, pp.m, S,
+                                   pl.grid.p);
+            }
             FS_LAUNCHED();
         } else {
             fill_f32(pl.grid.p, gsz, 0.0f, s);
@@ -1581,38 +1724,51 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
             while ((1 << fa.logG) < pp.G) ++fa.logG;
             fa.N = pp.N;
             fa.KX = pp.N / 2 + 1;
-            const int nbmax = FFT_ELEMS / pp.G;
-            const int nblk = (fa.KX + nbmax - 1) / nbmax;
-            fa.nbx = (fa.KX + nblk - 1) / nblk;
+            // launch shapes: enough workgroups to cover the chip (about 512), at most FFT_ELEMS
+            // complex elements per LDS buffer, threads = butterflies per stage (64..256)
+            const int maxcols = FFT_ELEMS / pp.G;
+            auto threads_for = [&](int transforms) {
+                int t = transforms * pp.G / 2;
+                t = std::max(64, std::min(256, (t + 63) / 64 * 64));
+                return t;
+            };
             if (D == 1) {
-                hipLaunchKernelGGL(k_fft_1d_conv, dim3(1), dim3(FFT_THREADS), 0, s, pl.grid.p, fa,
-                                   pl.twiddle.p, pl.Mk.p);
+                fa.nb = 1;
+                hipLaunchKernelGGL(k_fft_1d_conv, dim3(1), dim3(threads_for(1)),
+                                   2 * pp.G * sizeof(float2), s, pl.grid.p, fa, pl.twiddle.p, pl.Mk.p);
                 FS_LAUNCHED();
             } else {
                 const int rows = (int)(gsz / pp.G);
-                const int pairs = rows / 2, nbp = FFT_ELEMS / pp.G;
-                const unsigned xblocks = (pairs + nbp - 1) / nbp;
-                hipLaunchKernelGGL(k_fft_x_r2c, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.grid.p, rows,
-                                   fa, pl.twiddle.p, pl.specA.p);
+                const int pairs = rows / 2;
+                fa.nb = std::max(1, std::min(maxcols, pairs / 512));
+                const unsigned xblocks = (pairs + fa.nb - 1) / fa.nb;
+                const int ylines = (D == 2) ? 1 : pp.G;  // strided pencils per column block
+                int nbx = std::max(1, std::min(maxcols, fa.KX * ylines / 512));
+                int nkb = (fa.KX + nbx - 1) / nbx;
+                fa.nbx = (fa.KX + nkb - 1) / nkb;  // balanced column blocks
+                nkb = (fa.KX + fa.nbx - 1) / fa.nbx;
+                const size_t lds_x = 2 * (size_t)fa.nb * pp.G * sizeof(float2);
+                const size_t lds_y = 2 * (size_t)fa.nbx * pp.G * sizeof(float2);
+                hipLaunchKernelGGL(k_fft_x_r2c, dim3(xblocks), dim3(threads_for(fa.nb)), lds_x, s,
+                                   pl.grid.p, rows, fa, pl.twiddle.p, pl.specA.p);
                 FS_LAUNCHED();
-                const int nkb = (fa.KX + fa.nbx - 1) / fa.nbx;
                 if (D == 2) {
-                    hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(FFT_THREADS), 0, s, pl.specA.p,
-                                       pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(threads_for(fa.nbx)), lds_y, s,
+                                       pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
                     FS_LAUNCHED();
                 } else {
-                    hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
-                                       pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(threads_for(fa.nbx)), lds_y,
+                                       s, pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
                     FS_LAUNCHED();
-                    hipLaunchKernelGGL(k_fft_z_conv, dim3((pp.N + 1) * nkb), dim3(FFT_THREADS), 0, s,
-                                       pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    hipLaunchKernelGGL(k_fft_z_conv, dim3((pp.N + 1) * nkb), dim3(threads_for(fa.nbx)),
+                                       lds_y, s, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
                     FS_LAUNCHED();
-                    hipLaunchKernelGGL(k_fft_y<2>, dim3(pp.G * nkb), dim3(FFT_THREADS), 0, s,
-                                       pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    hipLaunchKernelGGL(k_fft_y<2>, dim3(pp.G * nkb), dim3(threads_for(fa.nbx)), lds_y,
+                                       s, pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
                     FS_LAUNCHED();
                 }
-                hipLaunchKernelGGL(k_fft_x_c2r, dim3(xblocks), dim3(FFT_THREADS), 0, s, pl.specA.p,
-                                   rows, fa, pl.twiddle.p, pl.grid.p);
+                hipLaunchKernelGGL(k_fft_x_c2r, dim3(xblocks), dim3(threads_for(fa.nb)), lds_x, s,
+                                   pl.specA.p, rows, fa, pl.twiddle.p, pl.grid.p);
                 FS_LAUNCHED();
             }
         }
@@ -1620,12 +1776,14 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
             if (dst.nchunks > 0) {
                 ProfScope pg("gather", s);
                 const float gscale = (float)(pp.G / pp.P);
+                const unsigned split = (pp.chunk >= 512) ? 2 : 1;
                 if (grad) {
-                    hipLaunchKernelGGL((k_gather<D, W, T, true>), dim3(dst.nchunks), dim3(256), 0,
-                                       s, dst.rec.p, dst.chunks.p, sa, pl.grid.p, t, grad, gscale);
+                    hipLaunchKernelGGL((k_gather<D, W, T, true>), dim3(dst.nchunks, split), dim3(256),
+                                       0, s, dst.rec.p, dst.chunks.p, sa, pl.grid.p, t, grad, gscale);
                 } else {
-                    hipLaunchKernelGGL((k_gather<D, W, T, false>), dim3(dst.nchunks), dim3(256), 0,
-                                       s, dst.rec.p, dst.chunks.p, sa, pl.grid.p, t, grad, gscale);
+                    hipLaunchKernelGGL((k_gather<D, W, T, false>), dim3(dst.nchunks, split),
+                                       dim3(256), 0, s, dst.rec.p, dst.chunks.p, sa, pl.grid.p, t,
+                                       grad, gscale);
                 }
                 FS_LAUNCHED();
             }

@@ -30,27 +30,47 @@ __device__ __forceinline__ void nadd(double &s, double &c, double v) {
     s = t;
 }
 
-// w_k = base_k exp((pot_k - *potmax) / eps)   (FP64 exponent, FP32 result)
-__global__ void k_weights(const float *__restrict__ base, const double *__restrict__ pot,
-                          const double *__restrict__ potmax, double inv_eps, int64_t n,
-                          float *__restrict__ w) {
-    const double pm = *potmax;
+// w_k = base_k exp((pot_k - pmax) / eps)  (FP64 exponent, FP32 result), where pmax is the max
+// of the nparts per-block maxima written by the update kernel (or a single value, nparts = 1).
+__global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
+                                                 const double *__restrict__ pot,
+                                                 const double *__restrict__ parts, int nparts,
+                                                 double inv_eps, int64_t n, float *__restrict__ w) {
+    __shared__ double sm[256];
+    double mx = -INFINITY;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) mx = fmax(mx, parts[b]);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const double pm = (sm[0] == -INFINITY) ? 0.0 : sm[0];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         w[i] = (float)((double)base[i] * exp((pot[i] - pm) * inv_eps));
 }
 
-// pot_i = -kappa (*shift + eps log t_i) in FP64; *out_max = max_i pot_i (last-block reduction).
-// Non-positive sums are counted in *nbad and replaced by the smallest normal float.
+// pot_i = -kappa (shift + eps log t_i) in FP64, shift = max of the other potential (the max of
+// nshift per-block maxima); writes one block maximum of the new potential per block.  Non-positive
+// sums are counted in *nbad and replaced by the smallest normal float.
+constexpr int UPD_BLOCKS = 256;
 __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int64_t n,
-                                               const double *__restrict__ shift, double kappa,
-                                               double eps, double *__restrict__ pot,
-                                               double *__restrict__ partial,
-                                               unsigned *__restrict__ counter,
-                                               double *__restrict__ out_max, int *__restrict__ nbad) {
+                                               const double *__restrict__ shift_parts, int nshift,
+                                               double kappa, double eps, double *__restrict__ pot,
+                                               double *__restrict__ out_parts,
+                                               int *__restrict__ nbad) {
     __shared__ double sm[RT];
-    __shared__ bool last;
-    const double sh = *shift;
+    double sh = -INFINITY;
+    for (int b = threadIdx.x; b < nshift; b += RT) sh = fmax(sh, shift_parts[b]);
+    sm[threadIdx.x] = sh;
+    __syncthreads();
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    sh = (sm[0] == -INFINITY) ? 0.0 : sm[0];
+    __syncthreads();
     double mx = -INFINITY;
     int bad = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -68,37 +88,13 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
         if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = sm[0];
-        __threadfence();
-        unsigned ticket = atomicAdd(counter, 1u);
-        last = (ticket == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) {
-        __threadfence();
-        double v = -INFINITY;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += RT) v = fmax(v, partial[b]);
-        sm[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = RT / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            *out_max = (n > 0) ? sm[0] : 0.0;
-            *counter = 0u;
-        }
-    }
+    if (threadIdx.x == 0) out_parts[blockIdx.x] = sm[0];
 }
 
-// max of a double array (last-block pattern), used for warm starts.
-__global__ void __launch_bounds__(RT) k_max64(const double *__restrict__ v, int64_t n,
-                                              double *__restrict__ partial,
-                                              unsigned *__restrict__ counter,
-                                              double *__restrict__ out) {
+// Per-block maxima of a double array (warm starts, gradients); combined by the consumer.
+__global__ void __launch_bounds__(RT) k_max_parts(const double *__restrict__ v, int64_t n,
+                                                  double *__restrict__ parts) {
     __shared__ double sm[RT];
-    __shared__ bool last;
     double mx = -INFINITY;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -109,43 +105,33 @@ __global__ void __launch_bounds__(RT) k_max64(const double *__restrict__ v, int6
         if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partial[blockIdx.x] = sm[0];
-        __threadfence();
-        last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = sm[0];
+}
+
+// out = max of nparts maxima (0 if all are -inf), one block
+__global__ void __launch_bounds__(RT) k_max_final(const double *__restrict__ parts, int nparts,
+                                                  double *__restrict__ out) {
+    __shared__ double sm[RT];
+    double mx = -INFINITY;
+    for (int b = threadIdx.x; b < nparts; b += RT) mx = fmax(mx, parts[b]);
+    sm[threadIdx.x] = mx;
     __syncthreads();
-    if (last) {
-        __threadfence();
-        double w = -INFINITY;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += RT) w = fmax(w, partial[b]);
-        sm[threadIdx.x] = w;
+    for (int s = RT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
         __syncthreads();
-        for (int s = RT / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            *out = (n > 0) ? sm[0] : 0.0;
-            *counter = 0u;
-        }
     }
+    if (threadIdx.x == 0) *out = (sm[0] == -INFINITY) ? 0.0 : sm[0];
 }
 
 // Compensated FP64 sums of per-element terms.  MODE 0 (objective pieces for one side):
-//   out[0] += sum base (1 - e^{-pot/rho}),  out[1] += sum base e^{-pot/rho},  out[2] += sum base
-// MODE 1 (dot products):  out[0] += sum u v,  with optional split by perm < split:
-//   out[1] += sum_{perm < split} u v, out[2] += sum_{perm >= split} u v.
-// Each block writes (sum, compensation) pairs; the last block folds them with Neumaier sums.
+//   out[0] = sum base (1 - e^{-pot/rho}),  out[1] = sum base e^{-pot/rho},  out[2] = sum base
+// MODE 1 (dot products):  out[0] = sum u v.   MODE 2:  out[0] = sum u.
+// Each block writes (sum, compensation) pairs; k_csum_final folds them with Neumaier sums.
 template <int MODE>
 __global__ void __launch_bounds__(RT) k_csum(const float *__restrict__ u, const double *__restrict__ pot,
-                                             const float *__restrict__ v, const int *__restrict__ perm,
-                                             int64_t split, int64_t n, double rho,
-                                             double *__restrict__ partial,
-                                             unsigned *__restrict__ counter,
-                                             double *__restrict__ out) {
+                                             const float *__restrict__ v, int64_t n, double rho,
+                                             double *__restrict__ partial) {
     __shared__ double ss[3][RT], sc[3][RT];
-    __shared__ bool last;
     double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -157,38 +143,38 @@ __global__ void __launch_bounds__(RT) k_csum(const float *__restrict__ u, const 
         } else if (MODE == 2) {
             nadd(s[0], c[0], (double)u[i]);
         } else {
-            const double pv = (double)u[i] * (double)v[i];
-            nadd(s[0], c[0], pv);
-            if (perm) {
-                if (perm[i] < split) nadd(s[1], c[1], pv); else nadd(s[2], c[2], pv);
-            }
+            nadd(s[0], c[0], (double)u[i] * (double)v[i]);
         }
     }
     for (int k = 0; k < 3; ++k) { ss[k][threadIdx.x] = s[k]; sc[k][threadIdx.x] = c[k]; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < 3; ++k) {
-            double S = 0, C = 0;
-            for (int t = 0; t < RT; ++t) { nadd(S, C, ss[k][t]); nadd(S, C, sc[k][t]); }
-            partial[(blockIdx.x * 3 + k) * 2] = S;
-            partial[(blockIdx.x * 3 + k) * 2 + 1] = C;
-        }
-        __threadfence();
-        last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        for (int k = 0; k < 3; ++k) {
-            double S = 0, C = 0;
-            for (int b = 0; b < (int)gridDim.x; ++b) {
-                nadd(S, C, partial[(b * 3 + k) * 2]);
-                nadd(S, C, partial[(b * 3 + k) * 2 + 1]);
+    // tree: pairwise Neumaier combination of (sum, compensation) pairs
+    for (int o = RT / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) {
+                double S = ss[k][threadIdx.x], C = sc[k][threadIdx.x] + sc[k][threadIdx.x + o];
+                nadd(S, C, ss[k][threadIdx.x + o]);
+                ss[k][threadIdx.x] = S;
+                sc[k][threadIdx.x] = C;
             }
-            out[k] = S + C;
-        }
-        *counter = 0u;
+        __syncthreads();
     }
+    if (threadIdx.x < 3) {
+        partial[(blockIdx.x * 3 + threadIdx.x) * 2] = ss[threadIdx.x][0];
+        partial[(blockIdx.x * 3 + threadIdx.x) * 2 + 1] = sc[threadIdx.x][0];
+    }
+}
+
+__global__ void k_csum_final(const double *__restrict__ partial, int nblocks,
+                             double *__restrict__ out) {
+    if (threadIdx.x >= 3) return;
+    const int k = threadIdx.x;
+    double S = 0, C = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        nadd(S, C, partial[(b * 3 + k) * 2]);
+        C += partial[(b * 3 + k) * 2 + 1];
+    }
+    out[k] = S + C;
 }
 
 // Direct gradient sum: g_i = sum_j grad K(x_i - y_j) w_j (and t_i), any d <= 128.
@@ -414,42 +400,66 @@ void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t
 // =====================================================================================
 namespace {
 
+// Device scratch of one solve: per-block maxima of both potentials, compensated-sum partials,
+// scalar results and the count of non-positive kernel sums.
 struct Scalars {
-    // device scalars: [0] gmax, [1] fmax, [2] Mb, [3] Ma ; sums at [8..)
-    DevBuf<double> v;
-    DevBuf<double> partial;
-    DevBuf<unsigned> counter;
+    DevBuf<double> v;       // scalar results: [0] gmax, [1] fmax, [2] Mb, [3] Ma, sums at [8..)
+    DevBuf<double> fparts;  // per-block maxima of f
+    DevBuf<double> gparts;  // per-block maxima of g
+    DevBuf<double> partial;  // compensated-sum partials (RBLK x 3 x 2)
     DevBuf<int> nbad;
-    Scalars() : v(32), partial(RBLK * 6), counter(1), nbad(1) {}
+    int nf = 1, ng = 1;      // number of valid entries in fparts / gparts
+    Scalars() : v(32), fparts(UPD_BLOCKS), gparts(UPD_BLOCKS), partial(RBLK * 6), nbad(1) {}
     void reset(hipStream_t s) {
         fill_f64(v.p, 32, 0.0, s);
-        fill_i32(reinterpret_cast<int *>(counter.p), 1, 0, s);
+        fill_f64(fparts.p, UPD_BLOCKS, 0.0, s);
+        fill_f64(gparts.p, UPD_BLOCKS, 0.0, s);
         fill_i32(nbad.p, 1, 0, s);
+        nf = ng = 1;
     }
 };
 
 unsigned red_blocks(int64_t n) { return blocks_for(n, RT, RBLK); }
+int upd_blocks(int64_t n) { return (int)blocks_for(n, RT, UPD_BLOCKS); }
 
-void launch_update(const float *t, int64_t n, const double *shift, double kappa, double eps,
-                   double *pot, Scalars &sc, double *out_max, hipStream_t s) {
+// pot = update(t) with shift = max of (shift_parts, nshift); writes per-block maxima of pot
+int launch_update(const float *t, int64_t n, const double *shift_parts, int nshift, double kappa,
+                  double eps, double *pot, double *out_parts, int *nbad, hipStream_t s) {
     ProfScope ps("update", s);
-    hipLaunchKernelGGL(k_update, dim3(red_blocks(n)), dim3(RT), 0, s, t, n, shift, kappa, eps,
-                       pot, sc.partial.p, sc.counter.p, out_max, sc.nbad.p);
+    const int nb = upd_blocks(n);
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(RT), 0, s, t, n, shift_parts, nshift, kappa, eps,
+                       pot, out_parts, nbad);
     FS_LAUNCHED();
+    return nb;
 }
 
-void launch_weights(const float *base, const double *pot, const double *pmax, double eps,
-                    int64_t n, float *w, hipStream_t s) {
+void launch_weights(const float *base, const double *pot, const double *parts, int nparts,
+                    double eps, int64_t n, float *w, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(k_weights, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, base, pot,
-                       pmax, 1.0 / eps, n, w);
+                       parts, nparts, 1.0 / eps, n, w);
     FS_LAUNCHED();
 }
 
-void launch_csum0(const float *base, const double *pot, int64_t n, double rho, Scalars &sc,
-                  double *out3, hipStream_t s) {
-    hipLaunchKernelGGL(k_csum<0>, dim3(red_blocks(n)), dim3(RT), 0, s, base, pot, nullptr,
-                       nullptr, (int64_t)0, n, rho, sc.partial.p, sc.counter.p, out3);
+int launch_max_parts(const double *v, int64_t n, double *parts, hipStream_t s) {
+    const int nb = upd_blocks(n);
+    hipLaunchKernelGGL(k_max_parts, dim3(nb), dim3(RT), 0, s, v, n, parts);
+    FS_LAUNCHED();
+    return nb;
+}
+
+// compensated sums: MODE 0 objective pieces (3 values), 1 dot, 2 sum -> out[0..2]
+void csum(int mode, const float *u, const double *pot, const float *v, int64_t n, double rho,
+          Scalars &sc, double *out, hipStream_t s) {
+    const unsigned nb = red_blocks(n);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_csum<0>, dim3(nb), dim3(RT), 0, s, u, pot, v, n, rho, sc.partial.p);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_csum<1>, dim3(nb), dim3(RT), 0, s, u, pot, v, n, rho, sc.partial.p);
+    else
+        hipLaunchKernelGGL(k_csum<2>, dim3(nb), dim3(RT), 0, s, u, pot, v, n, rho, sc.partial.p);
+    FS_LAUNCHED();
+    hipLaunchKernelGGL(k_csum_final, dim3(1), dim3(64), 0, s, sc.partial.p, (int)nb, out);
     FS_LAUNCHED();
 }
 
@@ -461,25 +471,27 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     const double kappa = rho / (rho + eps);
     Scalars sc;
     sc.reset(s);
-    double *gmax = sc.v.p + 0, *fmax = sc.v.p + 1;
     DevBuf<float> wX(n + 1), wY(m + 1), tX(n + 1), tY(m + 1);
     if (warm) {
-        hipLaunchKernelGGL(k_max64, dim3(red_blocks(m)), dim3(RT), 0, s, g_o, m, sc.partial.p,
-                           sc.counter.p, gmax);
-        FS_LAUNCHED();
+        if (m > 0) sc.ng = launch_max_parts(g_o, m, sc.gparts.p, s);
+        if (n > 0) sc.nf = launch_max_parts(f_o, n, sc.fparts.p, s);
     } else {
         fill_f64(g_o, m, 0.0, s);
         fill_f64(f_o, n, 0.0, s);
     }
     for (int it = 0; it < iters; ++it) {
         // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}
-        launch_weights(b_o, g_o, gmax, eps, m, wY.p, s);
+        launch_weights(b_o, g_o, sc.gparts.p, sc.ng, eps, m, wY.p, s);
         op.apply(wY.p, tX.p, nullptr, 0, s);
-        if (n > 0) launch_update(tX.p, n, gmax, kappa, eps, f_o, sc, fmax, s);
+        if (n > 0)
+            sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
+                                  sc.nbad.p, s);
         // gamma half-step (Delta even): t~_j = sum_i k_ij a_i e^{f_i/eps}
-        launch_weights(a_o, f_o, fmax, eps, n, wX.p, s);
+        launch_weights(a_o, f_o, sc.fparts.p, sc.nf, eps, n, wX.p, s);
         op.apply(wX.p, tY.p, nullptr, 1, s);
-        if (m > 0) launch_update(tY.p, m, fmax, kappa, eps, g_o, sc, gmax, s);
+        if (m > 0)
+            sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
+                                  sc.nbad.p, s);
     }
     int nbad = 0;
     if (objective_host) {
@@ -490,21 +502,18 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
         //                            - eps (sum b e^{-g/rho} - Ma Mb).
         // With no sweep done (f = g = 0 or the warm start) the double sum is formed explicitly.
         double *sx = sc.v.p + 8, *sy = sc.v.p + 12, *sd = sc.v.p + 16;
-        launch_csum0(a_o, f_o, n, rho, sc, sx, s);
-        launch_csum0(b_o, g_o, m, rho, sc, sy, s);
+        double *gmax = sc.v.p + 0, *fmax = sc.v.p + 1;
+        csum(0, a_o, f_o, nullptr, n, rho, sc, sx, s);
+        csum(0, b_o, g_o, nullptr, m, rho, sc, sy, s);
         if (iters == 0) {
             // sum_i a_i e^{f_i/eps} sum_j k_ij b_j e^{g_j/eps}, shifted by fmax and gmax
-            if (n > 0) {
-                hipLaunchKernelGGL(k_max64, dim3(red_blocks(n)), dim3(RT), 0, s, f_o, n,
-                                   sc.partial.p, sc.counter.p, fmax);
-                FS_LAUNCHED();
-            }
-            launch_weights(b_o, g_o, gmax, eps, m, wY.p, s);
-            op.apply(wY.p, tX.p, nullptr, 0, s);
-            launch_weights(a_o, f_o, fmax, eps, n, wX.p, s);
-            hipLaunchKernelGGL(k_csum<1>, dim3(red_blocks(n)), dim3(RT), 0, s, wX.p, nullptr,
-                               tX.p, nullptr, (int64_t)0, n, rho, sc.partial.p, sc.counter.p, sd);
+            hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.gparts.p, sc.ng, gmax);
+            hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.fparts.p, sc.nf, fmax);
             FS_LAUNCHED();
+            launch_weights(b_o, g_o, sc.gparts.p, sc.ng, eps, m, wY.p, s);
+            op.apply(wY.p, tX.p, nullptr, 0, s);
+            launch_weights(a_o, f_o, sc.fparts.p, sc.nf, eps, n, wX.p, s);
+            csum(1, wX.p, nullptr, tX.p, n, rho, sc, sd, s);
         }
         double h[20];
         FS_HIP(hipMemcpyAsync(h, sc.v.p, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -512,12 +521,7 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
         FS_HIP(hipStreamSynchronize(s));
         const double Ma = h[10], Mb = h[14];
         double dsum = h[13];
-        if (iters == 0) {
-            double fm = 0.0, gm = 0.0;
-            FS_HIP(hipMemcpy(&fm, fmax, sizeof(double), hipMemcpyDeviceToHost));
-            FS_HIP(hipMemcpy(&gm, gmax, sizeof(double), hipMemcpyDeviceToHost));
-            dsum = h[16] * std::exp((fm + gm) / eps);
-        }
+        if (iters == 0) dsum = h[16] * std::exp((h[1] + h[0]) / eps);
         *objective_host = rho * h[8] + rho * h[12] - eps * (dsum - Ma * Mb);
     } else {
         FS_HIP(hipMemcpyAsync(&nbad, sc.nbad.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -531,26 +535,11 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
 // =====================================================================================
 //                           reductions, gradients and MMD drivers
 // =====================================================================================
-namespace {
-
-void csum(const float *u, const float *v, const int *perm, int64_t split, int64_t n, int mode,
-          Scalars &sc, double *out3, hipStream_t s) {
-    if (mode == 2)
-        hipLaunchKernelGGL(k_csum<2>, dim3(red_blocks(n)), dim3(RT), 0, s, u, nullptr, v, perm,
-                           split, n, 0.0, sc.partial.p, sc.counter.p, out3);
-    else
-        hipLaunchKernelGGL(k_csum<1>, dim3(red_blocks(n)), dim3(RT), 0, s, u, nullptr, v, perm,
-                           split, n, 0.0, sc.partial.p, sc.counter.p, out3);
-    FS_LAUNCHED();
-}
-
-}  // namespace
-
 double device_sum(const float *u, int64_t n, hipStream_t s) {
     if (n <= 0) return 0.0;
     Scalars sc;
     sc.reset(s);
-    csum(u, nullptr, nullptr, 0, n, 2, sc, sc.v.p, s);
+    csum(2, u, nullptr, nullptr, n, 0.0, sc, sc.v.p, s);
     double h = 0.0;
     FS_HIP(hipMemcpyAsync(&h, sc.v.p, sizeof(double), hipMemcpyDeviceToHost, s));
     FS_HIP(hipStreamSynchronize(s));
@@ -561,7 +550,7 @@ double device_dot(const float *u, const float *v, int64_t n, hipStream_t s) {
     if (n <= 0) return 0.0;
     Scalars sc;
     sc.reset(s);
-    csum(u, v, nullptr, 0, n, 1, sc, sc.v.p, s);
+    csum(1, u, nullptr, v, n, 0.0, sc, sc.v.p, s);
     double h = 0.0;
     FS_HIP(hipMemcpyAsync(&h, sc.v.p, sizeof(double), hipMemcpyDeviceToHost, s));
     FS_HIP(hipStreamSynchronize(s));
@@ -591,25 +580,20 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
     op.to_op(1, b, bo.p, s);
     op.to_op64(0, f, fo.p, s);
     op.to_op64(1, g, go.p, s);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_max64, dim3(red_blocks(m)), dim3(RT), 0, s, go.p, m, sc.partial.p,
-                           sc.counter.p, gmax);
-        FS_LAUNCHED();
-    }
-    if (n > 0) {
-        hipLaunchKernelGGL(k_max64, dim3(red_blocks(n)), dim3(RT), 0, s, fo.p, n, sc.partial.p,
-                           sc.counter.p, fmax);
-        FS_LAUNCHED();
-    }
+    if (m > 0) sc.ng = launch_max_parts(go.p, m, sc.gparts.p, s);
+    if (n > 0) sc.nf = launch_max_parts(fo.p, n, sc.fparts.p, s);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.gparts.p, sc.ng, gmax);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.fparts.p, sc.nf, fmax);
+    FS_LAUNCHED();
     {
         double *tmp = sc.v.p + 8;
-        csum(bo.p, nullptr, nullptr, 0, m, 2, sc, tmp, s);
+        csum(2, bo.p, nullptr, nullptr, m, 0.0, sc, tmp, s);
         FS_HIP(hipMemcpyAsync(Mb, tmp, sizeof(double), hipMemcpyDeviceToDevice, s));
-        csum(ao.p, nullptr, nullptr, 0, n, 2, sc, tmp, s);
+        csum(2, ao.p, nullptr, nullptr, n, 0.0, sc, tmp, s);
         FS_HIP(hipMemcpyAsync(Ma, tmp, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     if ((dx || da) && n > 0) {
-        launch_weights(bo.p, go.p, gmax, eps, m, w.p, s);
+        launch_weights(bo.p, go.p, gmax, 1, eps, m, w.p, s);
         op.apply(w.p, t.p, gr.p, 0, s);
         hipLaunchKernelGGL(k_uot_grad_rows, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, ao.p,
                            fo.p, t.p, gr.p, d, n, gmax, eps, rho, Mb, scale,
@@ -619,7 +603,7 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
         if (da) op.from_op(0, o1.p, da, s);
     }
     if ((dy || db) && m > 0) {
-        launch_weights(ao.p, fo.p, fmax, eps, n, w.p, s);
+        launch_weights(ao.p, fo.p, fmax, 1, eps, n, w.p, s);
         op.apply(w.p, t.p, gr.p, 1, s);
         hipLaunchKernelGGL(k_uot_grad_rows, dim3(blocks_for(m, 256, 8192)), dim3(256), 0, s, bo.p,
                            go.p, t.p, gr.p, d, m, fmax, eps, rho, Ma, scale,
@@ -671,7 +655,7 @@ void mmd_core(const float *x, const float *a, int64_t n, const float *y, const f
         concat_weights(a, n, b, m, 1.0f, -1.0f, wz.p, s);
         op->to_op(0, wz.p, wo.p, s);
         op->apply(wo.p, to.p, nullptr, 0, s);
-        csum(wo.p, to.p, nullptr, 0, nz, 1, sc, sc.v.p, s);
+        csum(1, wo.p, nullptr, to.p, nz, 0.0, sc, sc.v.p, s);
         FS_HIP(hipMemcpyAsync(h, sc.v.p, sizeof(double), hipMemcpyDeviceToHost, s));
         FS_HIP(hipStreamSynchronize(s));
         if (mmd2) *mmd2 = h[0];
@@ -685,9 +669,9 @@ void mmd_core(const float *x, const float *a, int64_t n, const float *y, const f
     concat_weights(a, n, b, m, 0.0f, 1.0f, wz.p, s);
     op->to_op(0, wz.p, w2.p, s);
     op->apply(w2.p, t2.p, nullptr, 0, s);
-    csum(wo.p, to.p, nullptr, 0, nz, 1, sc, sc.v.p + 8, s);   // a K a
-    csum(wo.p, t2.p, nullptr, 0, nz, 1, sc, sc.v.p + 12, s);  // a K b
-    csum(w2.p, t2.p, nullptr, 0, nz, 1, sc, sc.v.p + 16, s);  // b K b
+    csum(1, wo.p, nullptr, to.p, nz, 0.0, sc, sc.v.p + 8, s);   // a K a
+    csum(1, wo.p, nullptr, t2.p, nz, 0.0, sc, sc.v.p + 12, s);  // a K b
+    csum(1, w2.p, nullptr, t2.p, nz, 0.0, sc, sc.v.p + 16, s);  // b K b
     double hv[20];
     FS_HIP(hipMemcpyAsync(hv, sc.v.p, sizeof(hv), hipMemcpyDeviceToHost, s));
     FS_HIP(hipStreamSynchronize(s));

@@ -308,3 +308,4 @@ def test_autograd_functions():
     m2.backward()
     ref = oracle.mmd2_grad(w["x"], w["a"], w["y"], w["b"], "gauss", 0.01)[0]
     assert relinf(x2.grad.cpu().numpy(), ref) < 1e-4
+
