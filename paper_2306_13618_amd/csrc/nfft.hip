@@ -589,8 +589,9 @@ __global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
 
 // Wave-cooperative spreading (d = 2, 3).  Nodes are sorted by grid cell inside each tile; every
 // wave takes a contiguous run of its chunk's nodes, one node at a time: lane l < d W evaluates the
-// window value of dimension l / W at offset l % W, the lanes own the W^2 (y, x) pairs of the
-// window (ceil(W^2 / 64) passes) and accumulate alpha phi_x phi_y phi_z for all W z offsets in
+// window value of dimension l / W at offset l % W and stores it in the wave's LDS slot; the lanes
+// own the W^2 (y, x) pairs of the window (ceil(W^2 / 64) passes), read their x and y values and the
+// W z values (broadcast) back, and accumulate alpha phi_x phi_y phi_z for all W z offsets in
 // registers while consecutive nodes share a cell.  When the cell changes the registers are added
 // to the chunk's LDS box with integer atomics (fixed point, see chunk_scale); the 64 addresses of
 // every such atomic instruction are distinct and contiguous.
@@ -605,6 +606,7 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     constexpr int NZ = (D == 3) ? W : 1;
     __shared__ int box[BOX];
     __shared__ float red[16];
+    __shared__ __align__(16) float wslot[4][3 * 16 + 4];  // per wave: window values of one node
     const int4 ch = chunks[blockIdx.x];
     int tc[3] = {0, 0, 0};
     tile_coords<D>(ch.x, sa.ntd, tc);
@@ -662,26 +664,30 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
         }
         const float alpha = w[k] * scale;
         const float fr = (wdim == 0) ? r.x : (wdim == 1 ? r.y : r.z);
-        const float val = (lane < D * W) ? wpoly_eval(wc, 2.0f * fr - 1.0f) : 0.0f;
+        float *slot = wslot[wave];
+        if (lane < D * W) slot[lane] = wpoly_eval(wc, 2.0f * fr - 1.0f);
+        // the wave's LDS accesses complete in order; the fence keeps the compiler from reordering
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float wxy[NP];
 #pragma unroll
-        for (int P = 0; P < NP; ++P) {
-            const float vx = __shfl(val, pa[P], 64);
-            const float vy = __shfl(val, W + pb[P], 64);
-            wxy[P] = pv[P] ? alpha * vx * vy : 0.0f;
-        }
+        for (int P = 0; P < NP; ++P) wxy[P] = pv[P] ? alpha * slot[pa[P]] * slot[W + pb[P]] : 0.0f;
         if (D == 2) {
 #pragma unroll
             for (int P = 0; P < NP; ++P) acc[P][0] += wxy[P];
         } else {
+            float wz[NZ];
 #pragma unroll
-            for (int l = 0; l < NZ; ++l) {
-                const float wz = __int_as_float(
-                    __builtin_amdgcn_readlane(__float_as_int(val), 2 * W + l));
+            for (int l = 0; l < NZ; ++l) wz[l] = slot[2 * W + l];
 #pragma unroll
-                for (int P = 0; P < NP; ++P) acc[P][l] = fmaf(wz, wxy[P], acc[P][l]);
-            }
+            for (int l = 0; l < NZ; ++l)
+#pragma unroll
+                for (int P = 0; P < NP; ++P) acc[P][l] = fmaf(wz[l], wxy[P], acc[P][l]);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (cur >= 0) flush(cur);
     __syncthreads();
