@@ -67,12 +67,15 @@ typedef struct fs_params {
                                 0 selects direct summation                                         */
     int window;              /* Kaiser-Bessel window cutoff m: support 2m grid points per dim,
                                 2..8 (0 -> 6)                                                      */
-    int oversampling;        /* sigma = grid / bandwidth N, integer >= 2 (0 -> 2)                 */
+    int oversampling;        /* sigma = grid / bandwidth N, integer >= 2 (0 -> 2); see bandwidth  */
     int smoothness;          /* p: derivatives matched by the regularisation polynomials (0 -> 8) */
     unsigned flags;          /* FS_FLAG_*                                                         */
     double lambda;           /* kernel width (see the kernel list); > 0 for Gauss and Laplace     */
     double nearfield_radius; /* Laplace/energy: radius (data units) inside which the kernel is
                                 summed directly; 0 -> smoothness / bandwidth in torus units        */
+    int bandwidth;           /* N, the trigonometric polynomial's bandwidth (even, <= grid - 2);
+                                0 -> grid / oversampling.  Overrides oversampling when set; the
+                                window shape follows the effective ratio grid / N.                 */
 } fs_params;
 
 /* Opaque plan: two point sets mapped to the torus, binned by grid tile, and the kernel's

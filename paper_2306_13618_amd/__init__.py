@@ -41,7 +41,7 @@ class fs_params(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("grid", ctypes.c_int), ("window", ctypes.c_int),
                 ("oversampling", ctypes.c_int), ("smoothness", ctypes.c_int),
                 ("flags", ctypes.c_uint), ("lambda_", ctypes.c_double),
-                ("nearfield_radius", ctypes.c_double)]
+                ("nearfield_radius", ctypes.c_double), ("bandwidth", ctypes.c_int)]
 
 
 def library_path():
@@ -91,8 +91,9 @@ def _check(status):
 
 
 def _params(kernel="gauss", lam=1.0, grid=0, window=0, oversampling=0, smoothness=0,
-            nearfield_radius=0.0, flags=0):
+            nearfield_radius=0.0, flags=0, bandwidth=0):
     p = fs_params()
+    p.bandwidth = int(bandwidth)
     p.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     p.grid = int(grid)
     p.window = int(window)
@@ -150,12 +151,13 @@ def fs_profile_reset():
 
 
 def fastsum_apply(x, y, v, kernel="gauss", lam=1.0, grid=0, window=0, oversampling=0,
-                  smoothness=0, nearfield_radius=0.0, flags=0):
+                  smoothness=0, nearfield_radius=0.0, flags=0, bandwidth=0):
     """out_i = sum_j K(x_i - y_j) v_j (eq. fast_sum); grid=0 selects direct summation."""
     x, y = _pts(x, "x"), _pts(y, "y")
     v = _dev(v, name="v").reshape(-1)
     out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
-    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
     _check(_lib.fastsum_apply(_ptr(x), x.shape[0], _ptr(y), y.shape[0], x.shape[1], _ptr(v),
                               _ptr(out), ctypes.byref(p), _stream(x.device)))
     return out
@@ -165,10 +167,11 @@ class Plan:
     """fs_plan_create / fs_plan_apply / fs_plan_destroy."""
 
     def __init__(self, x, y, kernel="gauss", lam=1.0, grid=0, window=0, oversampling=0,
-                 smoothness=0, nearfield_radius=0.0, flags=0):
+                 smoothness=0, nearfield_radius=0.0, flags=0, bandwidth=0):
         x, y = _pts(x, "x"), _pts(y, "y")
         self.n, self.m, self.d, self.device = x.shape[0], y.shape[0], x.shape[1], x.device
-        p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+        p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
         h = ctypes.c_void_p(0)
         _check(_lib.fs_plan_create(_ptr(x), self.n, _ptr(y), self.m, self.d, ctypes.byref(p),
                                    _stream(x.device), ctypes.byref(h)))
@@ -191,7 +194,7 @@ class Plan:
 
 
 def uot_sinkhorn(x, a, y, b, lam, rho, iters, kernel="gauss", grid=0, window=0, oversampling=0,
-                 smoothness=0, nearfield_radius=0.0, flags=0, f0=None, g0=None):
+                 smoothness=0, nearfield_radius=0.0, flags=0, bandwidth=0, f0=None, g0=None):
     """Algorithm 2: `iters` sweeps; returns (f, g, dual objective).  f0/g0 warm-start."""
     x, y = _pts(x, "x"), _pts(y, "y")
     a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
@@ -202,7 +205,8 @@ def uot_sinkhorn(x, a, y, b, lam, rho, iters, kernel="gauss", grid=0, window=0, 
         f.copy_(f0 if f0 is not None else torch.zeros_like(f))
         g.copy_(g0 if g0 is not None else torch.zeros_like(g))
         flags |= FLAG_WARM_START
-    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
     obj = ctypes.c_double(0.0)
     _check(_lib.uot_sinkhorn(_ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, x.shape[1],
                              ctypes.byref(p), float(rho), int(iters), _ptr(f), _ptr(g),
@@ -211,14 +215,16 @@ def uot_sinkhorn(x, a, y, b, lam, rho, iters, kernel="gauss", grid=0, window=0, 
 
 
 def uot_sinkhorn_grad(x, a, y, b, lam, rho, f, g, kernel="gauss", grid=0, window=0,
-                      oversampling=0, smoothness=0, nearfield_radius=0.0, flags=0, scale=1.0):
+                      oversampling=0, smoothness=0, nearfield_radius=0.0, flags=0, bandwidth=0,
+                      scale=1.0):
     """Envelope gradients (dx, da, dy, db) of the UOT value at the potentials (f, g)."""
     x, y = _pts(x, "x"), _pts(y, "y")
     a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
     f, g = _dev(f, torch.float64, "f"), _dev(g, torch.float64, "g")
     dx, dy = torch.empty_like(x), torch.empty_like(y)
     da, db = torch.empty_like(a), torch.empty_like(b)
-    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
     _check(_lib.uot_sinkhorn_grad(_ptr(x), _ptr(a), x.shape[0], _ptr(y), _ptr(b), y.shape[0],
                                   x.shape[1], ctypes.byref(p), float(rho), _ptr(f), _ptr(g),
                                   float(scale), _ptr(dx), _ptr(da), _ptr(dy), _ptr(db),
@@ -228,13 +234,14 @@ def uot_sinkhorn_grad(x, a, y, b, lam, rho, f, g, kernel="gauss", grid=0, window
 
 def sinkhorn_divergence(x, a, y, b, lam, rho, iters, kernel="gauss", grid=0, window=0,
                         oversampling=0, smoothness=0, nearfield_radius=0.0, flags=0,
-                        return_potentials=False):
+                        bandwidth=0, return_potentials=False):
     """eq. (586).  Returns the value (and the three UOT values), optionally the potentials."""
     x, y = _pts(x, "x"), _pts(y, "y")
     a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
     n, m = x.shape[0], y.shape[0]
     pots = [torch.empty(k, dtype=torch.float64, device=x.device) for k in (n, m, n, m)]
-    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
     val = ctypes.c_double(0.0)
     terms = (ctypes.c_double * 3)()
     _check(_lib.sinkhorn_divergence(_ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, x.shape[1],
@@ -247,13 +254,14 @@ def sinkhorn_divergence(x, a, y, b, lam, rho, iters, kernel="gauss", grid=0, win
 
 def sinkhorn_divergence_grad(x, a, y, b, lam, rho, pots, kernel="gauss", grid=0, window=0,
                              oversampling=0, smoothness=0, nearfield_radius=0.0, flags=0,
-                             scale=1.0):
+                             bandwidth=0, scale=1.0):
     x, y = _pts(x, "x"), _pts(y, "y")
     a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
     pots = [_dev(t, torch.float64, "potential") for t in pots]
     dx, dy = torch.empty_like(x), torch.empty_like(y)
     da, db = torch.empty_like(a), torch.empty_like(b)
-    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
     _check(_lib.sinkhorn_divergence_grad(_ptr(x), _ptr(a), x.shape[0], _ptr(y), _ptr(b),
                                          y.shape[0], x.shape[1], ctypes.byref(p), float(rho),
                                          _ptr(pots[0]), _ptr(pots[1]), _ptr(pots[2]),
@@ -263,11 +271,12 @@ def sinkhorn_divergence_grad(x, a, y, b, lam, rho, pots, kernel="gauss", grid=0,
 
 
 def mmd(x, a, y, b, kernel="gauss", lam=1.0, grid=0, window=0, oversampling=0, smoothness=0,
-        nearfield_radius=0.0, flags=0, terms=False):
+        nearfield_radius=0.0, flags=0, bandwidth=0, terms=False):
     """Signed MMD^2 of eq. (1205); with terms=True also (sum aaK, sum abK, sum bbK)."""
     x, y = _pts(x, "x"), _pts(y, "y")
     a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
-    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
     val = ctypes.c_double(0.0)
     t3 = (ctypes.c_double * 3)()
     _check(_lib.mmd(_ptr(x), _ptr(a), x.shape[0], _ptr(y), _ptr(b), y.shape[0], x.shape[1],
@@ -277,12 +286,13 @@ def mmd(x, a, y, b, kernel="gauss", lam=1.0, grid=0, window=0, oversampling=0, s
 
 
 def mmd_grad(x, a, y, b, kernel="gauss", lam=1.0, grid=0, window=0, oversampling=0,
-             smoothness=0, nearfield_radius=0.0, flags=0, scale=1.0):
+             smoothness=0, nearfield_radius=0.0, flags=0, bandwidth=0, scale=1.0):
     x, y = _pts(x, "x"), _pts(y, "y")
     a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
     dx, dy = torch.empty_like(x), torch.empty_like(y)
     da, db = torch.empty_like(a), torch.empty_like(b)
-    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, flags,
+                bandwidth)
     _check(_lib.mmd_grad(_ptr(x), _ptr(a), x.shape[0], _ptr(y), _ptr(b), y.shape[0], x.shape[1],
                          ctypes.byref(p), float(scale), _ptr(dx), _ptr(da), _ptr(dy), _ptr(db),
                          _stream(x.device)))

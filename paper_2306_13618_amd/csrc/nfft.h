@@ -43,6 +43,7 @@ struct PlanParams {
     bool nearfield = false;
     // near-field cell grid (data units)
     double nf_h = 0.0;
+    int nf_R = 2;  // near-field cells per radius (stencil of 2 nf_R + 1 cells per dimension)
     int nf_dims[3] = {1, 1, 1};
     double nf_lo[3] = {0, 0, 0};
     KB kb{};

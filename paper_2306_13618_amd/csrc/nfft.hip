@@ -1190,19 +1190,19 @@ __global__ void k_nf_scatter(const float *__restrict__ xs, int64_t n, int d,
     for (int c = 0; c < d; ++c) cxs[(int64_t)pos * d + c] = xs[i * d + c];
 }
 
-// One workgroup per target cell: the targets of the cell (up to 256 at a time) against the
-// sources of the (2R+1)^d neighbouring cells (cell side = radius / R), staged through LDS so that
-// every source is loaded once per workgroup and read by all lanes as a broadcast.
-constexpr int NF_R = 2;
+// One wave per target cell: the targets of the cell (up to 64 at a time) against the sources of
+// the (2R+1)^d neighbouring cells (cell side = radius / R, R chosen per plan so that a cell holds
+// about one wave of targets), staged through LDS so that every source is loaded once per wave and
+// read by all lanes as a broadcast.
 template <int D, bool GRAD>
-__global__ void __launch_bounds__(256) k_nearfield(const int *__restrict__ t_start,
+__global__ void __launch_bounds__(64) k_nearfield(const int *__restrict__ t_start,
                                                    const int *__restrict__ t_order,
                                                    const float *__restrict__ t_xs,
                                                    const int *__restrict__ s_start,
                                                    const int *__restrict__ s_order,
                                                    const float *__restrict__ s_xs,
                                                    const float *__restrict__ w, NearArgs na,
-                                                   int ncells, float *__restrict__ out,
+                                                   int ncells, int R, float *__restrict__ out,
                                                    float *__restrict__ gout) {
     __shared__ float sx[256 * D];
     __shared__ float sw[256];
@@ -1213,8 +1213,8 @@ __global__ void __launch_bounds__(256) k_nearfield(const int *__restrict__ t_sta
                      cell / (na.dims[0] * na.dims[1])};
         int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
         for (int k = 0; k < 3; ++k) {
-            lo[k] = (k < D) ? max(cc[k] - NF_R, 0) : 0;
-            hi[k] = (k < D) ? min(cc[k] + NF_R, na.dims[k] - 1) : 0;
+            lo[k] = (k < D) ? max(cc[k] - R, 0) : 0;
+            hi[k] = (k < D) ? min(cc[k] + R, na.dims[k] - 1) : 0;
         }
         for (int tb = tcs; tb < tce; tb += blockDim.x) {
             const int t = tb + threadIdx.x;
@@ -1453,10 +1453,16 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     FS_REQUIRE(d >= 1 && d <= 3, FS_EDOMAIN, "NFFT fast summation supports d in 1..3 (got %d)", d);
     FS_REQUIRE(pp.G >= 16 && pp.G <= 512 && (pp.G & (pp.G - 1)) == 0, FS_EINVAL,
                "grid must be a power of two in 16..512 (got %d)", pp.G);
-    FS_REQUIRE(pp.sigma >= 2 && pp.G % pp.sigma == 0, FS_EINVAL,
-               "oversampling must be an integer >= 2 dividing the grid (got %d)", pp.sigma);
-    pp.N = pp.G / pp.sigma;
-    FS_REQUIRE(pp.N >= 4 && pp.N % 2 == 0, FS_EINVAL, "bandwidth grid/oversampling must be even >= 4");
+    if (p.bandwidth > 0) {
+        pp.N = p.bandwidth;
+        FS_REQUIRE(pp.N % 2 == 0 && pp.N >= 4 && pp.N + 2 <= pp.G, FS_EINVAL,
+                   "bandwidth must be even, >= 4 and <= grid - 2 (got %d for grid %d)", pp.N, pp.G);
+    } else {
+        FS_REQUIRE(pp.sigma >= 2 && pp.G % pp.sigma == 0, FS_EINVAL,
+                   "oversampling must be an integer >= 2 dividing the grid (got %d)", pp.sigma);
+        pp.N = pp.G / pp.sigma;
+        FS_REQUIRE(pp.N >= 4 && pp.N % 2 == 0, FS_EINVAL, "bandwidth grid/oversampling must be even >= 4");
+    }
     FS_REQUIRE(pp.m >= 2 && pp.m <= 8, FS_EINVAL, "window cutoff must be in 2..8 (got %d)", pp.m);
     FS_REQUIRE(pp.W <= pp.G, FS_EINVAL, "window support 2m=%d exceeds the grid %d", pp.W, pp.G);
     FS_REQUIRE(pp.p >= 2 && pp.p <= 16, FS_EINVAL, "smoothness must be in 2..16 (got %d)", pp.p);
@@ -1555,7 +1561,8 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     if (pp.regime == REGIME_BALL) boundary_poly(pp.kind, pp.lambda, pp.P, pp.epsB, pp.p, pp.cb);
 
     // ---- window
-    const double b = M_PI * (2.0 - 1.0 / pp.sigma);
+    // window shape for the effective oversampling ratio G / N
+    const double b = M_PI * (2.0 - (double)pp.N / pp.G);
     pp.kb.m = (float)pp.m;
     pp.kb.b = (float)b;
     pp.kb.inv_one_minus = (float)(1.0 / (-std::expm1(-2.0 * b * pp.m)));
@@ -1581,7 +1588,16 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     if (!pl.same) bin_nodes(pl.Y, y, m, pp, s);
 
     if (pp.nearfield) {
-        pp.nf_h = pp.epsI * pp.P * (1.0 + 1e-6) / NF_R;
+        // cells of side radius / R with R chosen so that a cell holds about 64 targets
+        {
+            double vol = 1.0;
+            for (int k = 0; k < d; ++k) vol *= std::max(hi[k] - lo[k], 1e-12);
+            const double dens = (double)std::max<int64_t>(std::max(n, m), 1) / vol;
+            const double ht = std::pow(64.0 / dens, 1.0 / d);
+            const double r = pp.epsI * pp.P;
+            pp.nf_R = (int)std::max(1.0, std::min(4.0, std::round(r / ht)));
+            pp.nf_h = r * (1.0 + 1e-6) / pp.nf_R;
+        }
         for (int k = 0; k < 3; ++k) {
             pp.nf_lo[k] = (k < d) ? lo[k] : 0.0;
             pp.nf_dims[k] = 1;
@@ -1857,12 +1873,12 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
         }
         int ncells = 1;
         for (int k = 0; k < pp.d; ++k) ncells *= pp.nf_dims[k];
-        dim3 g((unsigned)std::min(ncells, 1 << 20)), b(256);
+        dim3 g((unsigned)std::min(ncells, 1 << 20)), b(64);
         ProfScope pn("nearfield", s);
 #define FS_NF(DD, GG)                                                                        \
     hipLaunchKernelGGL((k_nearfield<DD, GG>), g, b, 0, s, dst.nf_cell_start.p, dst.nf_order.p, \
                        dst.nf_xs.p, src.nf_cell_start.p, src.nf_order.p, src.nf_xs.p, w_sorted,  \
-                       na, ncells, t_sorted, grad)
+                       na, ncells, pp.nf_R, t_sorted, grad)
         if (grad) {
             if (pp.d == 1) FS_NF(1, true); else if (pp.d == 2) FS_NF(2, true); else FS_NF(3, true);
         } else {
