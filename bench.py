@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--grid", type=int, default=64)
     ap.add_argument("--window", type=int, default=6)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (2-D Sinkhorn, MMD, 4M Laplace, d=32 MFMA)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
@@ -62,6 +64,83 @@ def traffic_from_profile(kernel_src):
     if rec.get("source_sha256") != digest:
         return None
     return rec.get("bytes_per_launch")
+
+
+def extra_rows(fu, torch, dev, oracle, synth):
+    """The other workloads of the hot path, each timed on the GPU with its sampled error."""
+    rows = {}
+
+    def timed(fn, reps=1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / reps
+
+    def last_half_err(w, f, g, r=2):
+        idx = synth.sample_rows(w["m"], 64, seed=3)
+        ref = oracle.uot_beta_rows(w["y"], idx, w["x"], w["a"], f.cpu().numpy(), w["eps"], w["rho"],
+                                   r=r)
+        got = g.cpu().numpy()[idx]
+        return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+    # 2-D Gaussian-mixture Sinkhorn, n=m=100k, grid 128^2, 100 sweeps, fast vs direct
+    w = synth.make("cfg1")
+    x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
+    run = lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], w["iters"], grid=w["grid"],
+                                  window=w["window"])
+    timed(run)
+    (f, g, _), t = timed(run, 2)
+    _, td = timed(lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 2, grid=0))
+    rows["uot_d2_n100k"] = {"sweeps_per_s": w["iters"] / t, "direct_sweeps_per_s": 2 / td,
+                            "speedup_vs_direct": (w["iters"] / t) / (2 / td),
+                            "err_sampled_last_halfstep": last_half_err(w, f, g)}
+    log("2-D 100k: %.0f sweeps/s fast, %.1f direct" % (w["iters"] / t, 2 / td))
+
+    # MMD^2 at d=3, n=m=1M: energy kernel (near-field radius 1/16) and Gaussian lambda=0.02
+    w = synth.make("cfg2")
+    x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
+    mmd_rows = {}
+    for kind, opts in (("energy", {"grid": 256, "nearfield_radius": w["nearfield_radius"]}),
+                       ("gauss", {"lam": w["mmd_lambda"], "grid": 64})):
+        fu.mmd(x, a, y, b, kernel=kind, window=6, **opts)
+        v, t = timed(lambda: fu.mmd(x, a, y, b, kernel=kind, window=6, **opts), 2)
+        mmd_rows[kind] = {"ms": 1e3 * t, "mmd2": v}
+        log("MMD %s 1M: %.1f ms" % (kind, 1e3 * t))
+    rows["mmd_d3_n1M"] = mmd_rows
+
+    # 4M Laplace Gibbs-kernel Sinkhorn (r = 1) with near field, grid 256^3
+    w = synth.make("cfg4a")
+    x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
+    it = 5
+    opts = {"kernel": "laplace", "grid": w["grid"], "window": w["window"],
+            "bandwidth": w["bandwidth"], "smoothness": w["smoothness"]}
+    fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 1, **opts)
+    (f, g, _), t = timed(lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], it, **opts))
+    rows["uot_laplace_d3_n4M"] = {"sweeps_per_s": it / t, "sweeps_timed": it,
+                                  "grid": w["grid"], "bandwidth": w["bandwidth"],
+                                  "smoothness": w["smoothness"],
+                                  "err_sampled_last_halfstep": last_half_err(w, f, g, r=1)}
+    log("4M Laplace: %.1f sweeps/s (%d sweeps incl. plan)" % (it / t, it))
+
+    # d = 32 direct Gaussian sum on the MFMA path (BF16 hi/lo Gram tiles), n=m=200k
+    w = synth.make("cfg4b")
+    x, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "y", "b"))
+    fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0)
+    out, t = timed(lambda: fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0), 3)
+    idx = synth.sample_rows(w["n"], 64, seed=5)
+    ref = oracle.direct_sum_rows(w["x"], idx, w["y"], w["b"], "gauss", w["eps"])
+    err = float(np.max(np.abs(out.cpu().numpy()[idx] - ref)) / np.max(np.abs(ref)))
+    flops = 3 * 2.0 * w["d"] * w["n"] * w["m"]
+    rows["mfma_gauss_d32_n200k"] = {
+        "ms": 1e3 * t, "err_sampled": err,
+        "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": flops / t / 1e12 / 2500.0,
+                     "work": "3 BF16 products x 2 x d x n x m"},
+        "pairs_per_s": w["n"] * w["m"] / t}
+    log("d=32 MFMA: %.2f ms, err %.1e" % (1e3 * t, err))
+    return rows
 
 
 def main():
@@ -185,6 +264,8 @@ def main():
                      "value": float(s.item())}
         log("divergence fwd %.1f ms, fwd+bwd %.1f ms" % (fwd_ms, fb_ms))
 
+    extras = None if args.no_extras else extra_rows(fu, torch, dev, oracle, synth)
+
     # ---- oracle on the host cores: beta and gamma half-steps for a bounded sample of rows
     cpu = None
     if not args.no_cpu:
@@ -222,6 +303,7 @@ def main():
         "lds_atomic_ops_per_s_spread": lds_ops / (sp * 1e-3),
         "hbm": hbm,
         "secondary": secondary,
+        "rows": extras,
     }
     print(json.dumps(line), flush=True)
 

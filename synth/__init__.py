@@ -47,7 +47,8 @@ CONFIGS = {
                  iters=2000, grid=128, window=6, points="mixture", mmd_lambda=0.01,
                  fd_h=1e-3, fd_coords=64),
     "cfg4a": dict(d=3, n=4_000_000, mass_a=1.0, mass_b=1.2, kernel="laplace", eps=0.01,
-                  rho=1.0, iters=50, grid=256, window=6, points="perturbed"),
+                  rho=1.0, iters=50, grid=256, window=6, points="perturbed", bandwidth=192,
+                  smoothness=6),
     "cfg4b": dict(d=32, n=200_000, mass_a=1.0, mass_b=1.2, kernel="gauss", eps=1.0, rho=1.0,
                   iters=50, grid=0, window=0, points="gauss32"),
 }
