@@ -18,6 +18,8 @@ struct Nodes {
     DevBuf<int> nf_cell_start;  // ncells + 1
     DevBuf<int> nf_order;       // cell-sorted k -> tile-sorted position
     DevBuf<float> nf_xs;        // cell-sorted coordinates
+    DevBuf<int4> nf_blocks;     // target blocks (<= 64 targets inside one row of cells)
+    int nf_nblocks = 0;
 };
 
 enum Regime { REGIME_CUBE = 0, REGIME_BALL = 1 };
@@ -43,7 +45,7 @@ struct PlanParams {
     bool nearfield = false;
     // near-field cell grid (data units)
     double nf_h = 0.0;
-    int nf_R = 2;  // near-field cells per radius (stencil of 2 nf_R + 1 cells per dimension)
+    int nf_R = 2;  // stencil half-width in cells: nf_R * nf_h >= radius
     int nf_dims[3] = {1, 1, 1};
     double nf_lo[3] = {0, 0, 0};
     KB kb{};
@@ -62,6 +64,7 @@ struct Plan {
     DevBuf<float> scratch;   // per-chunk spread boxes
     DevBuf<float> wbuf;      // sorted weights
     DevBuf<float> tbuf;      // sorted sums
+    DevBuf<float4> nf_src;   // near-field source records (cell order) for the current weights
     const Nodes &src(int transpose) const { return transpose ? X : (same ? X : Y); }
     const Nodes &dst(int transpose) const { return transpose ? (same ? X : Y) : X; }
 };

@@ -1158,8 +1158,12 @@ __global__ void k_scatter_rows(const int *__restrict__ perm, int64_t n, int d,
 //   t_i += sum_{|x_i - y_j| < epsI P} (K(|x_i - y_j|) - q_I(|x_i - y_j| / P)) alpha_j
 struct NearArgs {
     int kind, p, d;
-    float lambda_inv, rinv, r2max;  // rinv = 1/(epsI P), r2max = (epsI P)^2
-    float ci[16];
+    // Laplace: exp(-r / lambda) = exp2(r * lambda_inv) with lambda_inv = -log2(e) / lambda, and
+    // K'(r) = lambda_lin K(r) with lambda_lin = -1 / lambda
+    float lambda_inv, lambda_lin;
+    float rinv, r2max;  // rinv = 1/(epsI P), r2max = (epsI P)^2
+    float ci[16];   // inner polynomial in s = (r / (epsI P))^2, zero-padded
+    float dci[16];  // its derivative in s: dci[k] = 2 (k + 1) ci[k + 1]
     float h_inv;
     float lo[3];
     int dims[3];
@@ -1190,95 +1194,146 @@ __global__ void k_nf_scatter(const float *__restrict__ xs, int64_t n, int d,
     for (int c = 0; c < d; ++c) cxs[(int64_t)pos * d + c] = xs[i * d + c];
 }
 
-// One wave per target cell: the targets of the cell (up to 64 at a time) against the sources of
-// the (2R+1)^d neighbouring cells (cell side = radius / R, R chosen per plan so that a cell holds
-// about one wave of targets), staged through LDS so that every source is loaded once per wave and
-// read by all lanes as a broadcast.
-template <int D, bool GRAD>
-__global__ void __launch_bounds__(64) k_nearfield(const int *__restrict__ t_start,
-                                                   const int *__restrict__ t_order,
+// Target blocks: runs of at most 64 consecutive targets (cell order) inside one row of cells,
+// {first target, end, first cell x | last cell x << 16, row}.
+__global__ void k_nf_row_counts(const int *__restrict__ cell_start, int nrows, int dims0,
+                                int *__restrict__ cnt) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r <= nrows) cnt[r] = (r < nrows) ? cell_start[(r + 1) * dims0] - cell_start[r * dims0] : 0;
+}
+
+__global__ void k_nf_fill_blocks(const int *__restrict__ cell_start, int nrows, int dims0,
+                                 const int *__restrict__ row_blk, int4 *__restrict__ blocks) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const int base = r * dims0, end = cell_start[base + dims0];
+    int o = row_blk[2 * r], cx = 0;
+    for (int t0 = cell_start[base]; t0 < end; t0 += 64, ++o) {
+        const int t1 = min(t0 + 64, end);
+        while (cell_start[base + cx + 1] <= t0) ++cx;
+        int cx1 = cx;
+        while (cell_start[base + cx1 + 1] < t1) ++cx1;
+        blocks[o] = make_int4(t0, t1, cx | (cx1 << 16), r);
+    }
+}
+
+// Sources in cell order as (x, y, z, weight) records for the current weights; four zero records
+// follow the last one so that the kernel may read whole groups of four.
+__global__ void k_nf_pack(const float *__restrict__ xs, const int *__restrict__ order,
+                          const float *__restrict__ w, int64_t m, int d, float4 *__restrict__ rec) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k < m) {
+        float c[3] = {0.0f, 0.0f, 0.0f};
+        for (int i = 0; i < d; ++i) c[i] = xs[k * d + i];
+        rec[k] = make_float4(c[0], c[1], c[2], w[order[k]]);
+    } else if (k < m + 4) {
+        rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+struct Rec4 {
+    float4 r[4];
+};
+
+// One wave per target block: each lane holds one target; the sources of the stencil rows around
+// the block (cell side h >= radius / R, rows and cells whose distance to the block's cells is at
+// least the radius are skipped) are read as wave-uniform records, so they arrive through scalar
+// loads and feed every lane without LDS traffic.  NP = number of inner polynomial coefficients
+// (zero-padded), KIND = Laplace or energy.
+template <int D, int KIND, int NP, bool GRAD>
+__global__ void __launch_bounds__(64) k_nearfield(const int4 *__restrict__ blocks,
                                                    const float *__restrict__ t_xs,
+                                                   const int *__restrict__ t_order,
                                                    const int *__restrict__ s_start,
-                                                   const int *__restrict__ s_order,
-                                                   const float *__restrict__ s_xs,
-                                                   const float *__restrict__ w, NearArgs na,
-                                                   int ncells, int R, float *__restrict__ out,
+                                                   const float4 *__restrict__ src,
+                                                   NearArgs na, int R, float rr,
+                                                   float *__restrict__ out,
                                                    float *__restrict__ gout) {
-    __shared__ float sx[256 * D];
-    __shared__ float sw[256];
-    for (int cell = blockIdx.x; cell < ncells; cell += gridDim.x) {
-        const int tcs = t_start[cell], tce = t_start[cell + 1];
-        if (tcs >= tce) continue;
-        int cc[3] = {cell % na.dims[0], (cell / na.dims[0]) % na.dims[1],
-                     cell / (na.dims[0] * na.dims[1])};
-        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = (k < D) ? max(cc[k] - R, 0) : 0;
-            hi[k] = (k < D) ? min(cc[k] + R, na.dims[k] - 1) : 0;
-        }
-        for (int tb = tcs; tb < tce; tb += blockDim.x) {
-            const int t = tb + threadIdx.x;
-            const bool active = t < tce;
-            float xi[3] = {0, 0, 0};
-            if (active)
-                for (int c = 0; c < D; ++c) xi[c] = t_xs[(int64_t)t * D + c];
-            float acc = 0.0f, g[3] = {0, 0, 0};
-            for (int cz = lo[2]; cz <= hi[2]; ++cz)
-                for (int cy = lo[1]; cy <= hi[1]; ++cy) {
-                    const int row = (cz * na.dims[1] + cy) * na.dims[0];
-                    const int s0 = s_start[row + lo[0]], s1 = s_start[row + hi[0] + 1];
-                    for (int sb = s0; sb < s1; sb += blockDim.x) {
-                        const int cnt = min((int)blockDim.x, s1 - sb);
-                        __syncthreads();
-                        if ((int)threadIdx.x < cnt) {
-                            const int k = sb + threadIdx.x;
-                            for (int c = 0; c < D; ++c) sx[threadIdx.x * D + c] = s_xs[(int64_t)k * D + c];
-                            sw[threadIdx.x] = w[s_order[k]];
-                        }
-                        __syncthreads();
-                        for (int j = 0; j < cnt; ++j) {
-                            float dv[3], r2 = 0.0f;
-                            for (int c = 0; c < D; ++c) {
-                                dv[c] = xi[c] - sx[j * D + c];
-                                r2 = fmaf(dv[c], dv[c], r2);
-                            }
-                            if (r2 >= na.r2max) continue;
-                            const float wj = sw[j];
-                            const float r = sqrtf(r2);
-                            // inner polynomial in rho^2, rho = r / (epsI P)
-                            const float rho2 = r2 * na.rinv * na.rinv;
-                            float q = 0.0f, dq = 0.0f;
-                            for (int kk = na.p - 1; kk >= 0; --kk) q = fmaf(q, rho2, na.ci[kk]);
-                            float kv, dk = 0.0f;  // K(r) and dK/dr
-                            if (na.kind == FS_LAPLACE) {
-                                kv = __expf(-r * na.lambda_inv);
-                                dk = -na.lambda_inv * kv;
-                            } else if (na.kind == FS_ENERGY) {
-                                kv = -r;
-                                dk = -1.0f;
+    const int4 bk = blocks[blockIdx.x];
+    const int t = bk.x + (int)threadIdx.x;
+    const bool active = t < bk.y;
+    float xi[3] = {0.0f, 0.0f, 0.0f};
+    if (active)
+        for (int c = 0; c < D; ++c) xi[c] = t_xs[(int64_t)t * D + c];
+    const int cxl = bk.z & 0xffff, cxh = bk.z >> 16;
+    const int cy = (D >= 2) ? bk.w % na.dims[1] : 0;
+    const int cz = (D == 3) ? bk.w / na.dims[1] : 0;
+    const int Ry = (D >= 2) ? R : 0, Rz = (D == 3) ? R : 0;
+    const float rinv2 = na.rinv * na.rinv;
+    float acc = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
+    for (int dz = -Rz; dz <= Rz; ++dz) {
+        const int z = cz + dz;
+        if (z < 0 || z >= na.dims[2]) continue;
+        const int ez = max(abs(dz) - 1, 0);
+        for (int dy = -Ry; dy <= Ry; ++dy) {
+            const int y = cy + dy;
+            if (y < 0 || y >= na.dims[1]) continue;
+            const int ey = max(abs(dy) - 1, 0);
+            const float M = rr - (float)(ey * ey + ez * ez);
+            if (M <= 0.0f) continue;
+            const int A = min(R, 1 + (int)sqrtf(M));
+            const int row = (z * na.dims[1] + y) * na.dims[0];
+            const int s0 = s_start[row + max(cxl - A, 0)];
+            const int s1 = s_start[row + min(cxh + A, na.dims[0] - 1) + 1];
+            // groups of four records (one 64-byte scalar load); the next group is requested
+            // as soon as the current one has arrived
+            Rec4 cur = *reinterpret_cast<const Rec4 *>(src + s0);
+            for (int k = s0; k < s1; k += 4) {
+                __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): cur has arrived
+                const Rec4 nxt = *reinterpret_cast<const Rec4 *>(src + min(k + 4, s1));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float4 sv = cur.r[u];
+                    const float wj = (k + u < s1) ? sv.w : 0.0f;
+                    float dv[3];
+                    dv[0] = xi[0] - sv.x;
+                    dv[1] = xi[1] - sv.y;
+                    dv[2] = xi[2] - sv.z;
+                    float r2 = dv[0] * dv[0];
+                    if (D >= 2) r2 = fmaf(dv[1], dv[1], r2);
+                    if (D == 3) r2 = fmaf(dv[2], dv[2], r2);
+                    if (r2 < na.r2max) {
+                        const float s = r2 * rinv2;
+                        float q = na.ci[NP - 1];
+#pragma unroll
+                        for (int kk = NP - 2; kk >= 0; --kk) q = fmaf(q, s, na.ci[kk]);
+                        if (!GRAD) {
+                            const float r = __builtin_amdgcn_sqrtf(r2);
+                            const float kv = (KIND == FS_LAPLACE)
+                                                 ? __builtin_amdgcn_exp2f(r * na.lambda_inv)
+                                                 : -r;
+                            acc = fmaf(kv - q, wj, acc);
+                        } else {
+                            const float r2c = fmaxf(r2, 1e-30f);
+                            const float ri = __builtin_amdgcn_rsqf(r2c);
+                            const float r = r2c * ri;
+                            float dq = na.dci[NP - 2];
+#pragma unroll
+                            for (int kk = NP - 3; kk >= 0; --kk) dq = fmaf(dq, s, na.dci[kk]);
+                            float kv, dkr;  // K(r) and K'(r) / r
+                            if (KIND == FS_LAPLACE) {
+                                kv = __builtin_amdgcn_exp2f(r * na.lambda_inv);
+                                dkr = na.lambda_lin * kv * ri;
                             } else {
-                                kv = __expf(-r2 * na.lambda_inv);
-                                dk = -2.0f * r * na.lambda_inv * kv;
+                                kv = -r;
+                                dkr = -ri;
                             }
                             acc = fmaf(kv - q, wj, acc);
-                            if (GRAD) {
-                                // dq/dr = rinv^2 r sum_{k>=1} 2k c_k rho^{2(k-1)}
-                                for (int kk = na.p - 1; kk >= 1; --kk)
-                                    dq = fmaf(dq, rho2, 2.0f * kk * na.ci[kk]);
-                                const float dqdr = dq * r * na.rinv * na.rinv;
-                                const float coef = (r > 0.0f) ? (dk - dqdr) * wj / r : 0.0f;
-                                for (int c = 0; c < D; ++c) g[c] = fmaf(coef, dv[c], g[c]);
-                            }
+                            // d/dr (K - q) / r = K'(r)/r - rinv2 * sum_k 2k c_k s^(k-1)
+                            const float coef = (dkr - rinv2 * dq) * wj;
+                            for (int c = 0; c < D; ++c) g[c] = fmaf(coef, dv[c], g[c]);
                         }
                     }
                 }
-            if (active) {
-                const int o = t_order[t];
-                out[o] += acc;
-                if (GRAD)
-                    for (int c = 0; c < D; ++c) gout[(int64_t)o * D + c] += g[c];
+                cur = nxt;
             }
         }
+    }
+    if (active) {
+        const int o = t_order[t];
+        out[o] += acc;
+        if (GRAD)
+            for (int c = 0; c < D; ++c) gout[(int64_t)o * D + c] += g[c];
     }
 }
 
@@ -1431,6 +1486,26 @@ void build_nearfield_cells(Nodes &nd, const PlanParams &pp, hipStream_t s) {
         hipLaunchKernelGGL(k_nf_scatter, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256),
                            0, s, nd.xs.p, nd.n, d, key.p, nd.nf_cell_start.p, cursor.p,
                            nd.nf_order.p, nd.nf_xs.p);
+        FS_LAUNCHED();
+    }
+    // target blocks per row of cells
+    const int dims0 = pp.nf_dims[0];
+    const int nrows = (int)(ncells / dims0);
+    DevBuf<int> rcnt(nrows + 1), rstart(nrows + 1), rblk(2 * (nrows + 1));
+    hipLaunchKernelGGL(k_nf_row_counts, dim3(blocks_for(nrows + 1, 256)), dim3(256), 0, s,
+                       nd.nf_cell_start.p, nrows, dims0, rcnt.p);
+    FS_LAUNCHED();
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, rcnt.p, nrows, 64, rstart.p,
+                       rblk.p, totals.p);
+    FS_LAUNCHED();
+    int tot[2] = {0, 0};
+    FS_HIP(hipMemcpyAsync(tot, totals.p, sizeof(tot), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    nd.nf_nblocks = tot[1];
+    nd.nf_blocks.alloc(std::max(tot[1], 1));
+    if (tot[1] > 0) {
+        hipLaunchKernelGGL(k_nf_fill_blocks, dim3(blocks_for(nrows, 64)), dim3(64), 0, s,
+                           nd.nf_cell_start.p, nrows, dims0, rblk.p, nd.nf_blocks.p);
         FS_LAUNCHED();
     }
     FS_HIP(hipStreamSynchronize(s));
@@ -1588,15 +1663,26 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     if (!pl.same) bin_nodes(pl.Y, y, m, pp, s);
 
     if (pp.nearfield) {
-        // cells of side radius / R with R chosen so that a cell holds about 64 targets
+        // cells of side about radius / R, R chosen so that a cell holds about 32 points: blocks of
+        // 64 targets then span a few cells of a row, and the distance pruning of the stencil
+        // keeps about 2.4 times the ball's volume in 3-D.  The side is raised where needed to
+        // keep the cell grid within 4000 per dimension and 2^24 cells; the stencil half-width is
+        // then ceil(radius / side), so the stencil always covers the radius.
         {
-            double vol = 1.0;
-            for (int k = 0; k < d; ++k) vol *= std::max(hi[k] - lo[k], 1e-12);
+            double vol = 1.0, ext = 0.0;
+            for (int k = 0; k < d; ++k) {
+                vol *= std::max(hi[k] - lo[k], 1e-12);
+                ext = std::max(ext, hi[k] - lo[k]);
+            }
             const double dens = (double)std::max<int64_t>(std::max(n, m), 1) / vol;
-            const double ht = std::pow(64.0 / dens, 1.0 / d);
+            const double ht = std::pow(32.0 / dens, 1.0 / d);
             const double r = pp.epsI * pp.P;
-            pp.nf_R = (int)std::max(1.0, std::min(4.0, std::round(r / ht)));
-            pp.nf_h = r * (1.0 + 1e-6) / pp.nf_R;
+            const int R0 = (int)std::max(1.0, std::min(6.0, std::round(r / ht)));
+            double h = r * (1.0 + 1e-6) / R0;
+            h = std::max(h, ext / 4000.0);
+            h = std::max(h, std::pow(vol / double(1 << 24), 1.0 / d));
+            pp.nf_h = h;
+            pp.nf_R = std::max(1, (int)std::ceil(r / h));
         }
         for (int k = 0; k < 3; ++k) {
             pp.nf_lo[k] = (k < d) ? lo[k] : 0.0;
@@ -1605,13 +1691,14 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
         int64_t ncells = 1;
         for (int k = 0; k < d; ++k) {
             int64_t dk = (int64_t)std::floor((hi[k] - lo[k]) / pp.nf_h) + 1;
-            dk = std::max<int64_t>(1, std::min<int64_t>(dk, 4096));
+            FS_REQUIRE(dk <= 8192, FS_EINVAL, "near-field cell grid too large");
             pp.nf_dims[k] = (int)dk;
             ncells *= dk;
         }
         FS_REQUIRE(ncells < (int64_t(1) << 26), FS_EINVAL, "near-field cell grid too large");
         build_nearfield_cells(pl.X, pp, s);
         if (!pl.same) build_nearfield_cells(pl.Y, pp, s);
+        pl.nf_src.alloc(std::max(pl.X.n, pl.same ? 0 : pl.Y.n) + 4);
     }
 
     // ---- Fourier coefficients b_k of K_R and the multiplier M_k (A3)
@@ -1856,34 +1943,55 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
         case 2: dispatch_w<2>(pl, src, dst, w_sorted, t_sorted, grad, s); break;
         default: dispatch_w<3>(pl, src, dst, w_sorted, t_sorted, grad, s); break;
     }
-    if (pl.pp.nearfield && dst.n > 0 && src.n > 0) {
+    if (pl.pp.nearfield && dst.n > 0 && src.n > 0 && dst.nf_nblocks > 0) {
         const PlanParams &pp = pl.pp;
         NearArgs na{};
         na.kind = pp.kind;
         na.p = pp.p;
         na.d = pp.d;
-        na.lambda_inv = (float)(pp.kind == FS_ENERGY ? 0.0 : 1.0 / pp.lambda);
-        na.rinv = (float)(1.0 / (pp.epsI * pp.P));
-        na.r2max = (float)((pp.epsI * pp.P) * (pp.epsI * pp.P));
-        for (int k = 0; k < 16; ++k) na.ci[k] = (float)pp.ci[k];
+        na.lambda_inv = (float)(pp.kind == FS_LAPLACE ? -M_LOG2E / pp.lambda : 0.0);
+        na.lambda_lin = (float)(pp.kind == FS_LAPLACE ? -1.0 / pp.lambda : 0.0);
+        const double r = pp.epsI * pp.P;
+        na.rinv = (float)(1.0 / r);
+        na.r2max = (float)(r * r);
+        for (int k = 0; k < 16; ++k) na.ci[k] = (k < pp.p) ? (float)pp.ci[k] : 0.0f;
+        for (int k = 0; k + 1 < 16; ++k)
+            na.dci[k] = (k + 1 < pp.p) ? (float)(2.0 * (k + 1) * pp.ci[k + 1]) : 0.0f;
         na.h_inv = (float)(1.0 / pp.nf_h);
         for (int k = 0; k < 3; ++k) {
             na.lo[k] = (float)pp.nf_lo[k];
             na.dims[k] = pp.nf_dims[k];
         }
-        int ncells = 1;
-        for (int k = 0; k < pp.d; ++k) ncells *= pp.nf_dims[k];
-        dim3 g((unsigned)std::min(ncells, 1 << 20)), b(64);
+        const float rr = (float)((r / pp.nf_h) * (r / pp.nf_h));
         ProfScope pn("nearfield", s);
-#define FS_NF(DD, GG)                                                                        \
-    hipLaunchKernelGGL((k_nearfield<DD, GG>), g, b, 0, s, dst.nf_cell_start.p, dst.nf_order.p, \
-                       dst.nf_xs.p, src.nf_cell_start.p, src.nf_order.p, src.nf_xs.p, w_sorted,  \
-                       na, ncells, pp.nf_R, t_sorted, grad)
+        hipLaunchKernelGGL(k_nf_pack, dim3(blocks_for(src.n + 4, 256, int64_t(1) << 30)),
+                           dim3(256), 0, s, src.nf_xs.p, src.nf_order.p, w_sorted, src.n, pp.d,
+                           pl.nf_src.p);
+        FS_LAUNCHED();
+        const int np = (pp.p <= 4) ? 4 : (pp.p <= 8) ? 8 : (pp.p <= 12) ? 12 : 16;
+        const dim3 g((unsigned)dst.nf_nblocks), b(64);
+#define FS_NF(DD, KK, NN, GG)                                                                    \
+    hipLaunchKernelGGL((k_nearfield<DD, KK, NN, GG>), g, b, 0, s, dst.nf_blocks.p, dst.nf_xs.p, \
+                       dst.nf_order.p, src.nf_cell_start.p, pl.nf_src.p, na, pp.nf_R, rr,     \
+                       t_sorted, grad)
+#define FS_NF_NP(DD, KK, GG)                                \
+    do {                                                    \
+        if (np == 4) FS_NF(DD, KK, 4, GG);                  \
+        else if (np == 8) FS_NF(DD, KK, 8, GG);             \
+        else if (np == 12) FS_NF(DD, KK, 12, GG);           \
+        else FS_NF(DD, KK, 16, GG);                         \
+    } while (0)
+#define FS_NF_K(DD, GG)                                                                       \
+    do {                                                                                      \
+        if (pp.kind == FS_LAPLACE) FS_NF_NP(DD, FS_LAPLACE, GG); else FS_NF_NP(DD, FS_ENERGY, GG); \
+    } while (0)
         if (grad) {
-            if (pp.d == 1) FS_NF(1, true); else if (pp.d == 2) FS_NF(2, true); else FS_NF(3, true);
+            if (pp.d == 1) FS_NF_K(1, true); else if (pp.d == 2) FS_NF_K(2, true); else FS_NF_K(3, true);
         } else {
-            if (pp.d == 1) FS_NF(1, false); else if (pp.d == 2) FS_NF(2, false); else FS_NF(3, false);
+            if (pp.d == 1) FS_NF_K(1, false); else if (pp.d == 2) FS_NF_K(2, false); else FS_NF_K(3, false);
         }
+#undef FS_NF_K
+#undef FS_NF_NP
 #undef FS_NF
         FS_LAUNCHED();
     }

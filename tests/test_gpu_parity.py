@@ -79,6 +79,34 @@ def test_fastsum_nearfield_kernels(kind, lam, d, grid):
     assert relinf(got, ref) < TOL
 
 
+@pytest.mark.parametrize("kind,d,smooth,radius", [("energy", 3, 4, 0.0), ("laplace", 3, 6, 0.0),
+                                                  ("energy", 3, 12, 0.0), ("energy", 3, 8, 1 / 16),
+                                                  ("laplace", 2, 12, 0.0), ("energy", 1, 6, 0.0)])
+def test_fastsum_nearfield_smoothness_and_radius(kind, d, smooth, radius):
+    """Inner polynomials of 4..12 coefficients and an explicit near-field radius."""
+    x, y, v = clouds(d, 2500, 2300, 8)
+    lam = 0.01 if kind == "laplace" else 1.0
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel=kind, lam=lam, grid=256, window=6,
+                           smoothness=smooth, nearfield_radius=radius).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, kind, lam)
+    assert relinf(got, ref) < TOL
+
+
+@pytest.mark.parametrize("cfg,kind,n,radius", [("cfg2", "energy", 200_000, 1 / 16),
+                                               ("cfg2", "laplace", 300_000, 0.0),
+                                               ("cfg1", "energy", 150_000, 0.02)])
+def test_fastsum_nearfield_dense_sampled(cfg, kind, n, radius):
+    """Dense clouds (several cells per radius, uniform and clustered): sampled rows against the
+    oracle's direct sums."""
+    w = synth.make(cfg, n=n, m=n - 1234)
+    lam = 0.01 if kind == "laplace" else 1.0
+    got = fu.fastsum_apply(T(w["x"]), T(w["y"]), T(w["b"]), kernel=kind, lam=lam, grid=256,
+                           window=6, nearfield_radius=radius).cpu().numpy()
+    rows = synth.sample_rows(n, 64, seed=9)
+    ref = oracle.direct_sum_rows(w["x"], rows, w["y"], w["b"], kind, lam)
+    assert relinf(got[rows], ref) < TOL
+
+
 def test_fastsum_signed_weights_and_wide_gaussian():
     # a Gaussian wider than the data: the plan switches to the boundary-regularised torus
     x, y, v = clouds(2, 1500, 1300, 4)
@@ -283,10 +311,12 @@ def test_uot_grad_against_oracle_envelope(kind, grid, tol):
     assert max(errs) < tol
 
 
-@pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.02, 0), ("gauss", 0.02, 64),
-                                           ("energy", 1.0, 256)])
-def test_mmd_grad_against_oracle(kind, lam, grid):
-    w = synth.make("cfg1", n=1100, m=900)
+@pytest.mark.parametrize("kind,lam,grid,cfg", [("gauss", 0.02, 0, "cfg1"), ("gauss", 0.02, 64, "cfg1"),
+                                               ("energy", 1.0, 256, "cfg1"),
+                                               ("energy", 1.0, 256, "cfg2"),
+                                               ("laplace", 0.05, 128, "cfg2")])
+def test_mmd_grad_against_oracle(kind, lam, grid, cfg):
+    w = synth.make(cfg, n=1100, m=900)
     ref = oracle.mmd2_grad(w["x"], w["a"], w["y"], w["b"], kind, lam)
     got = fu.mmd_grad(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), kernel=kind, lam=lam, grid=grid,
                       window=6)
