@@ -322,8 +322,8 @@ std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m
         FS_REQUIRE(d >= 1 && d <= 128, FS_EINVAL, "direct summation supports d in 1..128 (got %d)", d);
         op->mfma = mfma_supported(p.kernel, d) && !(p.flags & FS_FLAG_FORCE_VALU);
         if (op->mfma) {
-            gram_prepare(x, n, d, op->gx, s);
-            if (!op->same) gram_prepare(y, m, d, op->gy, s);
+            gram_prepare(x, n, d, p.lambda, op->gx, s);
+            if (!op->same) gram_prepare(y, m, d, p.lambda, op->gy, s);
         }
     }
     return op;
@@ -389,7 +389,7 @@ void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t
     if (mfma) {
         const GramOperand &gt = transpose ? (same ? gx : gy) : gx;
         const GramOperand &gs = transpose ? gx : (same ? gx : gy);
-        direct_mfma_gauss(lambda, gt, gs, w, t, nullptr, s);
+        direct_mfma_gauss(gt, gs, w, t, nullptr, s);
     } else {
         direct_valu(kind, lambda, xt, nt, ys, ns, d, w, t, nullptr, s);
     }

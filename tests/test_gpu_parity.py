@@ -179,6 +179,33 @@ def test_mfma_gram_gauss_d32(n, m):
     assert relinf(valu, ref) < TOL
 
 
+@pytest.mark.parametrize("d,n,m,lam", [(16, 2100, 1900, 0.5), (64, 1500, 3333, 2.0),
+                                       (128, 700, 650, 4.0), (32, 40, 5000, 1.0)])
+def test_mfma_gram_gauss_other_dims(d, n, m, lam):
+    rng = np.random.default_rng([77, d, n, m])
+    x = (rng.normal(size=(n, d)) / np.sqrt(d)).astype(np.float32)
+    y = (rng.normal(0.1, 1.0, size=(m, d)) / np.sqrt(d)).astype(np.float32)
+    v = rng.uniform(0.5, 1.5, m).astype(np.float32)
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=lam, grid=0).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, "gauss", lam)
+    assert relinf(got, ref) < TOL
+    # the transposed roles through a plan
+    u = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    pl = fu.Plan(T(x), T(y), kernel="gauss", lam=lam, grid=0)
+    assert relinf(pl.apply(T(u), transpose=True).cpu().numpy(),
+                  oracle.direct_sum(y, x, u, "gauss", lam)) < TOL
+
+
+def test_uot_mfma_d32():
+    """The d = 32 Sinkhorn on the MFMA path (Gibbs kernel exp(-|x-y|^2/eps)) against the oracle."""
+    w = synth.make("cfg4b", n=1500, m=1300)
+    f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                                10, kernel="gauss", grid=0)
+    beta, gamma = oracle.uot_sinkhorn(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], 10)
+    assert relinf(f.cpu().numpy(), beta) < TOL
+    assert relinf(g.cpu().numpy(), gamma) < TOL
+
+
 # --------------------------------------------------------------------------- Sinkhorn
 
 _cache = {}
