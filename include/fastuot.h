@@ -58,7 +58,6 @@ enum {
 /* flags */
 #define FS_FLAG_WARM_START 0x1u   /* uot_sinkhorn: f and g hold starting potentials on entry     */
 #define FS_FLAG_FORCE_VALU 0x2u   /* direct path: use the FP32 VALU kernel even where MFMA applies */
-#define FS_FLAG_NO_NEARFIELD 0x4u /* skip the near-field correction (diagnostics only)          */
 
 /* Parameters of one kernel sum.  Zero-initialise and set what you need; zeros mean defaults. */
 typedef struct fs_params {

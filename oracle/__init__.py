@@ -7,7 +7,7 @@ library.  Arrays are promoted to float64 before the call, so float32 inputs are 
 Notation follows the paper: ``eps`` is the temperature (the paper's 1/lambda), ``eta`` the marginal
 penalty, ``beta``/``gamma`` the dual potentials, r the cost exponent (r=2: Gibbs kernel
 exp(-|x-y|^2/eps); r=1: exp(-|x-y|/eps)).  Kernel kinds: 0 Gauss exp(-r^2/ell2), 1 Laplace
-exp(-r/ell), 2 energy -r.
+exp(-r/ell), 2 energy -r, 3 IMQ 1/sqrt(r^2 + c^2).
 """
 import ctypes
 import os
@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-KINDS = {"gauss": 0, "laplace": 1, "energy": 2}
+KINDS = {"gauss": 0, "laplace": 1, "energy": 2, "imq": 3}
 _lib = None
 
 

@@ -20,6 +20,7 @@
  *   kind 0  Gauss    exp(-r^2 / ell2)     (ell2 = ell^2, passed as `lam_k`)
  *   kind 1  Laplace  exp(-r / ell)        (ell passed as `lam_k`)
  *   kind 2  energy   -r                    (lam_k unused)
+ *   kind 3  IMQ      1 / sqrt(r^2 + c^2)  (c passed as `lam_k`)
  *
  * All sums use Neumaier (improved Kahan) compensated accumulation.
  * Parallelism is plain OpenMP over output rows; no blocking, fusion or reordering.
@@ -57,12 +58,14 @@ double orc_kernel(int kind, double lam_k, double r) {
         case 0: return exp(-r * r / lam_k);
         case 1: return exp(-r / lam_k);
         case 2: return -r;
+        case 3: return 1.0 / sqrt(r * r + lam_k * lam_k);
         default: return NAN;
     }
 }
 
 /* Gradient of the radial kernel K(y) with respect to y, at y = p - q.  Written out from the
- * kernel definitions: Gauss -2/ell2 y K, Laplace -(y/(ell |y|)) K, energy -y/|y| (0 at y = 0). */
+ * kernel definitions: Gauss -2/ell2 y K, Laplace -(y/(ell |y|)) K, energy -y/|y| (0 at y = 0),
+ * IMQ -y / (|y|^2 + c^2)^(3/2). */
 static void kernel_grad(int kind, double lam_k, const double *p, const double *q, int d,
                         double *out) {
     double r = dist(p, q, d);
@@ -72,6 +75,7 @@ static void kernel_grad(int kind, double lam_k, const double *p, const double *q
             case 0: out[k] = -2.0 / lam_k * y * exp(-r * r / lam_k); break;
             case 1: out[k] = (r > 0) ? -(y / (lam_k * r)) * exp(-r / lam_k) : 0.0; break;
             case 2: out[k] = (r > 0) ? -y / r : 0.0; break;
+            case 3: out[k] = -y / pow(r * r + lam_k * lam_k, 1.5); break;
             default: out[k] = NAN;
         }
     }

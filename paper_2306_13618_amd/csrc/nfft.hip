@@ -1623,7 +1623,7 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
         pp.P = Pball;
         pp.epsB = epsB_default;
     }
-    pp.nearfield = (pp.kind != FS_GAUSS) && !(p.flags & FS_FLAG_NO_NEARFIELD);
+    pp.nearfield = (pp.kind != FS_GAUSS);
     if (pp.kind != FS_GAUSS) {
         pp.epsI = (p.nearfield_radius > 0) ? p.nearfield_radius / pp.P : (double)pp.p / pp.N;
         FS_REQUIRE(pp.epsI < 0.5 - pp.epsB - 1e-9 && pp.epsI > 0, FS_EINVAL,

@@ -31,10 +31,13 @@ def _mp_kernel(kind, lam, r):
         return mp.e ** (-r * r / lam)
     if kind == "laplace":
         return mp.e ** (-r / lam)
+    if kind == "imq":
+        return 1 / mp.sqrt(r * r + lam * lam)
     return -r
 
 
-@pytest.mark.parametrize("kind,lam", [("gauss", 0.02), ("laplace", 0.05), ("energy", 0.0)])
+@pytest.mark.parametrize("kind,lam", [("gauss", 0.02), ("laplace", 0.05), ("energy", 0.0),
+                                      ("imq", 0.3), ("imq", 0.01)])
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_direct_sum_vs_mpmath_bruteforce(kind, lam, d):
     """eq. (fast_sum) evaluated in 40-digit arithmetic on n, m <= 24."""
@@ -52,6 +55,31 @@ def test_direct_sum_vs_mpmath_bruteforce(kind, lam, d):
             acc += _mp_kernel(kind, lam if lam else 1.0, r) * mp.mpf(float(v[j]))
         ref.append(float(acc))
     assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("c", [0.05, 0.5])
+def test_direct_sum_imq_as_gaussian_scale_mixture(c):
+    """IMQ through the Gaussian kernel: 1/sqrt(r^2 + c^2) = (2/sqrt(pi)) int_0^inf e^{-u^2 c^2}
+    e^{-u^2 r^2} du, so the IMQ sum is a quadrature over Gaussian sums (lambda = 1/u^2) that the
+    oracle evaluates through its independently pinned Gaussian kernel."""
+    from scipy.integrate import quad_vec
+    rng = np.random.default_rng([8, int(100 * c)])
+    x = rng.uniform(-0.25, 0.25, (15, 3))
+    y = rng.uniform(-0.25, 0.25, (21, 3))
+    v = rng.uniform(-1, 1, 21)
+
+    def f(t):  # u = t / (1 - t) maps [0, 1) onto [0, inf)
+        if t <= 0.0:
+            return np.zeros(len(x))
+        if t >= 1.0:
+            return np.zeros(len(x))
+        u = t / (1.0 - t)
+        return (2 / math.sqrt(math.pi)) * math.exp(-u * u * c * c) * \
+            oracle.direct_sum(x, y, v, "gauss", 1.0 / (u * u)) / (1.0 - t) ** 2
+
+    ref, _ = quad_vec(f, 0.0, 1.0, epsabs=1e-13, epsrel=1e-12)
+    got = oracle.direct_sum(x, y, v, "imq", c)
+    assert rel(got, ref) < 1e-9
 
 
 def _laplace_1d_two_sided(x, y, v, ell):
@@ -111,7 +139,7 @@ def test_direct_sum_1d_energy_vs_prefix_sums():
     assert rel(got, ref) < 1e-11
 
 
-@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy"])
+@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy", "imq"])
 def test_direct_sum_adjoint_symmetry(kind):
     """<u, K_xy v> = <K_yx u, v>: the kernel matrix of a radial kernel is symmetric."""
     rng = np.random.default_rng(13)
@@ -123,7 +151,7 @@ def test_direct_sum_adjoint_symmetry(kind):
     assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
 
 
-@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy"])
+@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy", "imq"])
 def test_direct_sum_grad_vs_central_differences(kind):
     rng = np.random.default_rng(14)
     x = rng.uniform(-0.25, 0.25, (6, 3))
@@ -354,20 +382,21 @@ def test_uot_envelope_gradient_vs_central_differences(r):
 
 # --------------------------------------------------------------------------- MMD
 
-@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy"])
+@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy", "imq"])
 def test_mmd_self_is_zero(kind):
     x, mu, _, _ = _small_problem()
     v, _ = oracle.mmd2(x, mu, x, mu, kind, 0.25)
     assert abs(v) < 1e-14
 
 
-@pytest.mark.parametrize("kind", ["gauss", "laplace"])
+@pytest.mark.parametrize("kind", ["gauss", "laplace", "imq"])
 def test_mmd_elementary_bound(kind):
     """0 <= MMD^2 <= sup|k| (mu(X)^2 + nu(X)^2) for nonnegative p.d. kernels (Remark on the
-    elementary bound; valid for Gauss and Laplace)."""
+    elementary bound; valid for Gauss, Laplace and IMQ, sup k = 1 resp. 1/c)."""
     x, mu, y, nu = _small_problem()
     v, _ = oracle.mmd2(x, mu, y, nu, kind, 0.25)
-    assert 0 <= v <= mu.sum() ** 2 + nu.sum() ** 2
+    sup = 1.0 / 0.25 if kind == "imq" else 1.0
+    assert 0 <= v <= sup * (mu.sum() ** 2 + nu.sum() ** 2)
 
 
 def test_mmd_energy_1d_cramer_identity():
@@ -389,7 +418,7 @@ def test_mmd_energy_1d_cramer_identity():
     assert abs(v - ref) < 1e-12 * max(1.0, abs(ref))
 
 
-@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy"])
+@pytest.mark.parametrize("kind", ["gauss", "laplace", "energy", "imq"])
 def test_mmd_grad_vs_central_differences(kind):
     x, mu, y, nu = _small_problem(n=12, m=9, d=3)
     dx, dmu, dy, dnu = oracle.mmd2_grad(x, mu, y, nu, kind, 0.1)
