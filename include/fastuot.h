@@ -52,7 +52,8 @@ typedef enum {
 enum {
     FS_GAUSS = 0,   /* exp(-r^2 / lambda)  (lambda = ell^2 of the table)      */
     FS_LAPLACE = 1, /* exp(-r / lambda)    (lambda = ell of the table)        */
-    FS_ENERGY = 2   /* -r                  (lambda unused)                    */
+    FS_ENERGY = 2,  /* -r                  (lambda unused)                    */
+    FS_IMQ = 3      /* 1 / sqrt(r^2 + c^2) (lambda = c of the table)          */
 };
 
 /* flags */
@@ -61,7 +62,7 @@ enum {
 
 /* Parameters of one kernel sum.  Zero-initialise and set what you need; zeros mean defaults. */
 typedef struct fs_params {
-    int kernel;              /* FS_GAUSS, FS_LAPLACE or FS_ENERGY                                 */
+    int kernel;              /* FS_GAUSS, FS_LAPLACE, FS_ENERGY or FS_IMQ                         */
     int grid;                /* oversampled FFT grid points per dimension (even, 16..512);
                                 0 selects direct summation                                         */
     int window;              /* Kaiser-Bessel window cutoff m: support 2m grid points per dim,
@@ -69,8 +70,8 @@ typedef struct fs_params {
     int oversampling;        /* sigma = grid / bandwidth N, integer >= 2 (0 -> 2); see bandwidth  */
     int smoothness;          /* p: derivatives matched by the regularisation polynomials (0 -> 8) */
     unsigned flags;          /* FS_FLAG_*                                                         */
-    double lambda;           /* kernel width (see the kernel list); > 0 for Gauss and Laplace     */
-    double nearfield_radius; /* Laplace/energy: radius (data units) inside which the kernel is
+    double lambda;           /* kernel width (see the kernel list); > 0 for Gauss, Laplace, IMQ   */
+    double nearfield_radius; /* Laplace/energy/IMQ: radius (data units) inside which the kernel is
                                 summed directly; 0 -> smoothness / bandwidth in torus units        */
     int bandwidth;           /* N, the trigonometric polynomial's bandwidth (even, <= grid - 2);
                                 0 -> grid / oversampling.  Overrides oversampling when set; the

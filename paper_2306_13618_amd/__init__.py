@@ -7,7 +7,8 @@ torch's current stream.  There is no CPU fallback: importing raises if the libra
 
 Parameter convention (temperature form): the Gibbs kernel of the cost |x-y|^r is
 exp(-|x-y|^r / lam), i.e. ``lam`` is the reciprocal of the paper's lambda; ``rho`` is the paper's
-marginal penalty eta.  Kernels: "gauss" exp(-r^2/lam), "laplace" exp(-r/lam), "energy" -r.
+marginal penalty eta.  Kernels: "gauss" exp(-r^2/lam), "laplace" exp(-r/lam), "energy" -r,
+"imq" 1/sqrt(r^2 + lam^2).
 """
 import ctypes
 import os
@@ -23,7 +24,7 @@ __all__ = [
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libfastuot.so")
-KERNELS = {"gauss": 0, "laplace": 1, "energy": 2}
+KERNELS = {"gauss": 0, "laplace": 1, "energy": 2, "imq": 3}
 FLAG_WARM_START = 0x1
 FLAG_FORCE_VALU = 0x2
 EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fs_profile_enable",

@@ -18,9 +18,10 @@ constexpr int DTILE = 256;
 
 template <int KIND>
 __device__ __forceinline__ float kval(float r2, float c) {
-    // c: Gauss -log2(e)/lambda ; Laplace -log2(e)/lambda
+    // c: Gauss -log2(e)/lambda ; Laplace -log2(e)/lambda ; IMQ lambda^2
     if (KIND == FS_GAUSS) return exp2f(r2 * c);
     if (KIND == FS_LAPLACE) return exp2f(sqrtf(r2) * c);
+    if (KIND == FS_IMQ) return rsqrtf(r2 + c);
     return -sqrtf(r2);
 }
 
@@ -136,6 +137,10 @@ void launch_small(int kind, const float *x, int64_t n, const float *y, int64_t m
             hipLaunchKernelGGL((k_direct_small<D, FS_LAPLACE>), grid, block, 0, s, x, n, y, m, w,
                                c, out, out64);
             break;
+        case FS_IMQ:
+            hipLaunchKernelGGL((k_direct_small<D, FS_IMQ>), grid, block, 0, s, x, n, y, m, w, c,
+                               out, out64);
+            break;
         default:
             hipLaunchKernelGGL((k_direct_small<D, FS_ENERGY>), grid, block, 0, s, x, n, y, m, w,
                                c, out, out64);
@@ -147,6 +152,7 @@ void launch_small(int kind, const float *x, int64_t n, const float *y, int64_t m
 
 float direct_coef(int kind, double lambda) {
     if (kind == FS_ENERGY) return 0.0f;
+    if (kind == FS_IMQ) return (float)(lambda * lambda);
     return (float)(-1.4426950408889634 / lambda);
 }
 
@@ -167,6 +173,10 @@ void direct_valu(int kind, double lambda, const float *x, int64_t n, const float
         case FS_LAPLACE:
             hipLaunchKernelGGL(k_direct_general<FS_LAPLACE>, grid, block, 0, s, x, n, y, m, d, w,
                                c, out, out64);
+            break;
+        case FS_IMQ:
+            hipLaunchKernelGGL(k_direct_general<FS_IMQ>, grid, block, 0, s, x, n, y, m, d, w, c,
+                               out, out64);
             break;
         default:
             hipLaunchKernelGGL(k_direct_general<FS_ENERGY>, grid, block, 0, s, x, n, y, m, d, w,

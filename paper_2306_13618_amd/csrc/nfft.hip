@@ -47,6 +47,20 @@ void kernel_derivs(int kind, double lambda, double s, int cnt, double *out) {
     } else if (kind == FS_LAPLACE) {
         const double e = std::exp(-s / lambda);
         for (int j = 0; j < cnt; ++j) out[j] = std::pow(-1.0 / lambda, j) * e;
+    } else if (kind == FS_IMQ) {
+        // K(s) = (s^2 + c^2)^(-1/2): expanding K(s + h) in h gives the Legendre generating
+        // function, K^{(j)}(s) = (-1)^j j! P_j(s / q) / q^(j+1) with q = sqrt(s^2 + c^2)
+        // ((j+1) P_{j+1} = (2j+1) x P_j - j P_{j-1})
+        const double q = std::sqrt(s * s + lambda * lambda), x = s / q;
+        double pprev = 0.0, pc = 1.0, fact = 1.0, qp = q;
+        for (int j = 0; j < cnt; ++j) {
+            out[j] = ((j & 1) ? -1.0 : 1.0) * fact * pc / qp;
+            const double pn = ((2.0 * j + 1.0) * x * pc - j * pprev) / (j + 1.0);
+            pprev = pc;
+            pc = pn;
+            fact *= (j + 1.0);
+            qp *= q;
+        }
     } else {
         for (int j = 0; j < cnt; ++j) out[j] = (j == 0) ? -s : (j == 1 ? -1.0 : 0.0);
     }
@@ -438,6 +452,9 @@ struct RegArgs {
     double ci[16], cb[32];
 };
 
+// The kernel kind is a template parameter: a runtime chain of kind tests in this FP64 kernel
+// gave wrong values for the last kind on this compiler.
+template <int KIND>
 __device__ double kr_eval(const RegArgs &ra, double r) {
     // regularised kernel K_R at torus distance r (data-unit kernel value K(P r))
     if (ra.epsI > 0.0 && r < ra.epsI) {
@@ -450,12 +467,14 @@ __device__ double kr_eval(const RegArgs &ra, double r) {
         for (int k = 2 * ra.p - 2; k >= 0; --k) v = v * z + ra.cb[k];
         return v;
     }
-    double s = ra.P * r;
-    if (ra.kind == FS_GAUSS) return exp(-s * s / ra.lambda);
-    if (ra.kind == FS_LAPLACE) return exp(-s / ra.lambda);
-    return -s;
+    const double s = ra.P * r;
+    if constexpr (KIND == FS_GAUSS) return exp(-s * s / ra.lambda);
+    if constexpr (KIND == FS_LAPLACE) return exp(-s / ra.lambda);
+    if constexpr (KIND == FS_IMQ) return 1.0 / sqrt(s * s + ra.lambda * ra.lambda);
+    if constexpr (KIND == FS_ENERGY) return -s;
 }
 
+template <int KIND>
 __global__ void k_sample_kr(RegArgs ra, int N, int d, double *__restrict__ out) {
     int64_t total = 1;
     for (int k = 0; k < d; ++k) total *= N;
@@ -469,7 +488,7 @@ __global__ void k_sample_kr(RegArgs ra, int N, int d, double *__restrict__ out) 
             double t = (double)(j - N / 2) / N;
             r2 += t * t;
         }
-        out[q] = kr_eval(ra, sqrt(r2));
+        out[q] = kr_eval<KIND>(ra, sqrt(r2));
     }
 }
 
@@ -1161,6 +1180,7 @@ struct NearArgs {
     // Laplace: exp(-r / lambda) = exp2(r * lambda_inv) with lambda_inv = -log2(e) / lambda, and
     // K'(r) = lambda_lin K(r) with lambda_lin = -1 / lambda
     float lambda_inv, lambda_lin;
+    float c2;           // IMQ: c^2
     float rinv, r2max;  // rinv = 1/(epsI P), r2max = (epsI P)^2
     float ci[16];   // inner polynomial in s = (r / (epsI P))^2, zero-padded
     float dci[16];  // its derivative in s: dci[k] = 2 (k + 1) ci[k + 1]
@@ -1239,7 +1259,7 @@ struct Rec4 {
 // the block (cell side h >= radius / R, rows and cells whose distance to the block's cells is at
 // least the radius are skipped) are read as wave-uniform records, so they arrive through scalar
 // loads and feed every lane without LDS traffic.  NP = number of inner polynomial coefficients
-// (zero-padded), KIND = Laplace or energy.
+// (zero-padded), KIND = Laplace, energy or IMQ.
 template <int D, int KIND, int NP, bool GRAD>
 __global__ void __launch_bounds__(64) k_nearfield(const int4 *__restrict__ blocks,
                                                    const float *__restrict__ t_xs,
@@ -1298,10 +1318,14 @@ __global__ void __launch_bounds__(64) k_nearfield(const int4 *__restrict__ block
 #pragma unroll
                         for (int kk = NP - 2; kk >= 0; --kk) q = fmaf(q, s, na.ci[kk]);
                         if (!GRAD) {
-                            const float r = __builtin_amdgcn_sqrtf(r2);
-                            const float kv = (KIND == FS_LAPLACE)
-                                                 ? __builtin_amdgcn_exp2f(r * na.lambda_inv)
-                                                 : -r;
+                            float kv;
+                            if (KIND == FS_IMQ) {
+                                kv = __builtin_amdgcn_rsqf(r2 + na.c2);
+                            } else {
+                                const float r = __builtin_amdgcn_sqrtf(r2);
+                                kv = (KIND == FS_LAPLACE) ? __builtin_amdgcn_exp2f(r * na.lambda_inv)
+                                                          : -r;
+                            }
                             acc = fmaf(kv - q, wj, acc);
                         } else {
                             const float r2c = fmaxf(r2, 1e-30f);
@@ -1314,6 +1338,9 @@ __global__ void __launch_bounds__(64) k_nearfield(const int4 *__restrict__ block
                             if (KIND == FS_LAPLACE) {
                                 kv = __builtin_amdgcn_exp2f(r * na.lambda_inv);
                                 dkr = na.lambda_lin * kv * ri;
+                            } else if (KIND == FS_IMQ) {
+                                kv = __builtin_amdgcn_rsqf(r2 + na.c2);
+                                dkr = -kv * kv * kv;
                             } else {
                                 kv = -r;
                                 dkr = -ri;
@@ -1541,8 +1568,8 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     FS_REQUIRE(pp.m >= 2 && pp.m <= 8, FS_EINVAL, "window cutoff must be in 2..8 (got %d)", pp.m);
     FS_REQUIRE(pp.W <= pp.G, FS_EINVAL, "window support 2m=%d exceeds the grid %d", pp.W, pp.G);
     FS_REQUIRE(pp.p >= 2 && pp.p <= 16, FS_EINVAL, "smoothness must be in 2..16 (got %d)", pp.p);
-    FS_REQUIRE(pp.kind == FS_GAUSS || pp.kind == FS_LAPLACE || pp.kind == FS_ENERGY, FS_EINVAL,
-               "unknown kernel %d", pp.kind);
+    FS_REQUIRE(pp.kind == FS_GAUSS || pp.kind == FS_LAPLACE || pp.kind == FS_ENERGY ||
+                   pp.kind == FS_IMQ, FS_EINVAL, "unknown kernel %d", pp.kind);
     FS_REQUIRE(pp.kind == FS_ENERGY || (pp.lambda > 0 && std::isfinite(pp.lambda)), FS_EINVAL,
                "lambda must be positive");
     pp.T = (d == 3) ? 8 : (d == 2 ? 32 : 256);
@@ -1725,8 +1752,15 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
         ra.epsB = pp.epsB;
         std::memcpy(ra.ci, pp.ci, sizeof(ra.ci));
         std::memcpy(ra.cb, pp.cb, sizeof(ra.cb));
-        hipLaunchKernelGGL(k_sample_kr, dim3(blocks_for(nsamp, 256, 65536)), dim3(256), 0, s, ra,
-                           N, d, samp.p);
+        {
+            const dim3 g(blocks_for(nsamp, 256, 65536)), b(256);
+            switch (pp.kind) {
+                case FS_GAUSS: hipLaunchKernelGGL(k_sample_kr<FS_GAUSS>, g, b, 0, s, ra, N, d, samp.p); break;
+                case FS_LAPLACE: hipLaunchKernelGGL(k_sample_kr<FS_LAPLACE>, g, b, 0, s, ra, N, d, samp.p); break;
+                case FS_IMQ: hipLaunchKernelGGL(k_sample_kr<FS_IMQ>, g, b, 0, s, ra, N, d, samp.p); break;
+                default: hipLaunchKernelGGL(k_sample_kr<FS_ENERGY>, g, b, 0, s, ra, N, d, samp.p); break;
+            }
+        }
         FS_LAUNCHED();
         // axis 0 (fastest): A = N^{d-1}, B = 1 ; axis 1: A = N^{d-2}, B = H ; axis 2: A = 1, B = H^2
         const double *in = samp.p;
@@ -1951,6 +1985,7 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
         na.d = pp.d;
         na.lambda_inv = (float)(pp.kind == FS_LAPLACE ? -M_LOG2E / pp.lambda : 0.0);
         na.lambda_lin = (float)(pp.kind == FS_LAPLACE ? -1.0 / pp.lambda : 0.0);
+        na.c2 = (float)(pp.kind == FS_IMQ ? pp.lambda * pp.lambda : 0.0);
         const double r = pp.epsI * pp.P;
         na.rinv = (float)(1.0 / r);
         na.r2max = (float)(r * r);
@@ -1983,7 +2018,9 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
     } while (0)
 #define FS_NF_K(DD, GG)                                                                       \
     do {                                                                                      \
-        if (pp.kind == FS_LAPLACE) FS_NF_NP(DD, FS_LAPLACE, GG); else FS_NF_NP(DD, FS_ENERGY, GG); \
+        if (pp.kind == FS_LAPLACE) FS_NF_NP(DD, FS_LAPLACE, GG);                               \
+        else if (pp.kind == FS_IMQ) FS_NF_NP(DD, FS_IMQ, GG);                                  \
+        else FS_NF_NP(DD, FS_ENERGY, GG);                                                      \
     } while (0)
         if (grad) {
             if (pp.d == 1) FS_NF_K(1, true); else if (pp.d == 2) FS_NF_K(2, true); else FS_NF_K(3, true);

@@ -216,6 +216,9 @@ __global__ void __launch_bounds__(256) k_direct_grad(const float *__restrict__ x
             } else if (KIND == FS_LAPLACE) {
                 kv = __expf(-r * lam_inv);
                 coef = (r > 0.0f) ? -lam_inv * kv / r : 0.0f;
+            } else if (KIND == FS_IMQ) {
+                kv = rsqrtf(r2 + lam_inv);  // lam_inv carries c^2 for this kernel
+                coef = -kv * kv * kv;
             } else {
                 kv = -r;
                 coef = (r > 0.0f) ? -1.0f / r : 0.0f;
@@ -310,7 +313,8 @@ std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m
     op->x = x;
     op->y = y;
     op->same = (x == y && n == m);
-    FS_REQUIRE(p.kernel == FS_GAUSS || p.kernel == FS_LAPLACE || p.kernel == FS_ENERGY, FS_EINVAL,
+    FS_REQUIRE(p.kernel == FS_GAUSS || p.kernel == FS_LAPLACE || p.kernel == FS_ENERGY ||
+                   p.kernel == FS_IMQ, FS_EINVAL,
                "unknown kernel %d", p.kernel);
     FS_REQUIRE(p.kernel == FS_ENERGY || (p.lambda > 0 && std::isfinite(p.lambda)), FS_EINVAL,
                "lambda must be positive and finite");
@@ -374,12 +378,15 @@ void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t
     const float *xt = transpose ? y : x, *ys = transpose ? x : y;
     if (grad) {
         FS_REQUIRE(d <= 8, FS_EUNSUPPORTED, "direct gradients support d <= 8 (got %d)", d);
-        const float li = (kind == FS_ENERGY) ? 0.0f : (float)(1.0 / lambda);
+        const float li = (kind == FS_ENERGY) ? 0.0f
+                         : (kind == FS_IMQ) ? (float)(lambda * lambda) : (float)(1.0 / lambda);
         dim3 g(blocks_for(nt, 256, int64_t(1) << 30)), b(256);
         if (kind == FS_GAUSS)
             hipLaunchKernelGGL(k_direct_grad<FS_GAUSS>, g, b, 0, s, xt, nt, ys, ns, d, w, li, t, grad);
         else if (kind == FS_LAPLACE)
             hipLaunchKernelGGL(k_direct_grad<FS_LAPLACE>, g, b, 0, s, xt, nt, ys, ns, d, w, li, t, grad);
+        else if (kind == FS_IMQ)
+            hipLaunchKernelGGL(k_direct_grad<FS_IMQ>, g, b, 0, s, xt, nt, ys, ns, d, w, li, t, grad);
         else
             hipLaunchKernelGGL(k_direct_grad<FS_ENERGY>, g, b, 0, s, xt, nt, ys, ns, d, w, li, t, grad);
         FS_LAUNCHED();

@@ -45,7 +45,8 @@ def clouds(d, n, m, seed, spread=0.03):
 
 # --------------------------------------------------------------------------- direct sums
 
-@pytest.mark.parametrize("kind,lam", [("gauss", 0.02), ("laplace", 0.05), ("energy", 1.0)])
+@pytest.mark.parametrize("kind,lam", [("gauss", 0.02), ("laplace", 0.05), ("energy", 1.0),
+                                      ("imq", 0.3)])
 @pytest.mark.parametrize("d", [1, 2, 3])
 def test_direct_sum(kind, lam, d):
     x, y, v = clouds(d, 1537, 1201, 1)
@@ -70,7 +71,9 @@ def test_fastsum_gauss(d, grid, window, lam):
 
 @pytest.mark.parametrize("kind,lam,d,grid", [("laplace", 0.01, 1, 256), ("laplace", 0.01, 2, 256),
                                              ("laplace", 0.01, 3, 128), ("energy", 1.0, 1, 256),
-                                             ("energy", 1.0, 2, 256), ("energy", 1.0, 3, 256)])
+                                             ("energy", 1.0, 2, 256), ("energy", 1.0, 3, 256),
+                                             ("imq", 1.0, 1, 128), ("imq", 0.5, 2, 128),
+                                             ("imq", 0.05, 2, 256), ("imq", 0.02, 3, 256)])
 def test_fastsum_nearfield_kernels(kind, lam, d, grid):
     x, y, v = clouds(d, 2003, 1999, 3)
     got = fu.fastsum_apply(T(x), T(y), T(v), kernel=kind, lam=lam, grid=grid,
@@ -294,7 +297,7 @@ def test_sinkhorn_divergence():
 
 @pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.02, 0), ("gauss", 0.02, 64),
                                            ("laplace", 0.05, 128), ("energy", 1.0, 256),
-                                           ("energy", 1.0, 0)])
+                                           ("energy", 1.0, 0), ("imq", 0.1, 128), ("imq", 0.1, 0)])
 @pytest.mark.parametrize("d", [2, 3])
 def test_mmd(kind, lam, grid, d):
     w = synth.make("cfg2" if d == 3 else "cfg1", n=1800, m=1500)
@@ -308,6 +311,32 @@ def test_mmd(kind, lam, grid, d):
     assert abs(val - ref) < TOL * scale
     val1 = fu.mmd(T(x), T(w["a"]), T(y), T(w["b"]), kernel=kind, lam=lam, grid=grid, window=6)
     assert abs(val1 - ref) < TOL * scale
+
+
+@pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.25, 64), ("laplace", 0.5, 128),
+                                           ("imq", 1.0, 128), ("energy", 1.0, 128)])
+@pytest.mark.parametrize("n", [100, 1000, 10000])
+def test_mmd_accuracy_experiment(kind, lam, grid, n):
+    """The MMD accuracy experiment (Table Accuracy_analysis3: d = 2, points and weights uniform on
+    [0, 1], l = 1/2, c = 1; probability vectors and unnormalised weights), GPU against the FP64
+    oracle.  The FP32 bar is relative to the largest of the three double sums; the paper's residual
+    relative to MMD^2 itself is printed (it grows where MMD^2 is small against the sums)."""
+    rng = np.random.default_rng([1365, n])
+    x = rng.uniform(0, 1, (n, 2)).astype(np.float32)
+    y = rng.uniform(0, 1, (n, 2)).astype(np.float32)
+    for norm in (True, False):
+        a = rng.uniform(0, 1, n)
+        b = rng.uniform(0, 1, n)
+        if norm:
+            a, b = a / a.sum(), b / b.sum()
+        a, b = a.astype(np.float32), b.astype(np.float32)
+        ref, terms = oracle.mmd2(x, a, y, b, kind, lam)
+        val = fu.mmd(T(x), T(a), T(y), T(b), kernel=kind, lam=lam, grid=grid, window=6)
+        scale = max(abs(t) for t in terms)
+        print("%s n=%d %s: residual %.2e (vs largest term %.2e)"
+              % (kind, n, "probability" if norm else "unbalanced", abs(val - ref) / abs(ref),
+                 abs(val - ref) / scale))
+        assert abs(val - ref) < TOL * scale
 
 
 def test_mmd_self_is_zero():
@@ -341,7 +370,8 @@ def test_uot_grad_against_oracle_envelope(kind, grid, tol):
 @pytest.mark.parametrize("kind,lam,grid,cfg", [("gauss", 0.02, 0, "cfg1"), ("gauss", 0.02, 64, "cfg1"),
                                                ("energy", 1.0, 256, "cfg1"),
                                                ("energy", 1.0, 256, "cfg2"),
-                                               ("laplace", 0.05, 128, "cfg2")])
+                                               ("laplace", 0.05, 128, "cfg2"),
+                                               ("imq", 0.1, 128, "cfg1"), ("imq", 0.05, 256, "cfg2")])
 def test_mmd_grad_against_oracle(kind, lam, grid, cfg):
     w = synth.make(cfg, n=1100, m=900)
     ref = oracle.mmd2_grad(w["x"], w["a"], w["y"], w["b"], kind, lam)
