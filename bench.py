@@ -8,11 +8,14 @@ value = sweeps per second.
 
 Also reported (extra keys of the same JSON line):
   * GPU direct-summation sweeps/s on the same inputs and the speedup of the fast path;
-  * the sampled full-size error of the last half-step against the FP64 oracle;
+  * the sampled full-size error of the last half-step against the FP64 oracle (and the sampled
+    errors of the other workloads), computed in the CPU-baseline leg together with its timing;
   * per-pass average durations from HIP events recorded on the launch stream during the timed
     steps, the dominant kernel's roofline, and HBM GB/s of spread, FFT and gather;
   * the secondary metric: forward and forward+backward ms of the Sinkhorn divergence on the
     d=2, n=m=200k Gaussian-mixture workload;
+  * the other workloads: 2-D 100k Sinkhorn, MMD at 1M (energy, Gauss, IMQ), the MMD accuracy
+    experiment at n=10k, the 4M Laplace Sinkhorn and the d=32 MFMA sum;
   * the FP64 oracle's rate on the host cores (a bounded sample scaled to sweeps/s).
 """
 import argparse
@@ -66,49 +69,68 @@ def traffic_from_profile(kernel_src):
     return rec.get("bytes_per_launch")
 
 
-def extra_rows(fu, torch, dev, oracle, synth):
-    """The other workloads of the hot path, each timed on the GPU with its sampled error."""
+def timed(torch, fn, reps=1):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t0) / reps
+
+
+def extra_rows(fu, torch, dev, synth, keep):
+    """The other workloads of the hot path, timed on the GPU.  Outputs needed for the sampled
+    error checks go to `keep`; the checks themselves run in the CPU-baseline leg."""
     rows = {}
-
-    def timed(fn, reps=1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            out = fn()
-        torch.cuda.synchronize()
-        return out, (time.perf_counter() - t0) / reps
-
-    def last_half_err(w, f, g, r=2):
-        idx = synth.sample_rows(w["m"], 64, seed=3)
-        ref = oracle.uot_beta_rows(w["y"], idx, w["x"], w["a"], f.cpu().numpy(), w["eps"], w["rho"],
-                                   r=r)
-        got = g.cpu().numpy()[idx]
-        return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
 
     # 2-D Gaussian-mixture Sinkhorn, n=m=100k, grid 128^2, 100 sweeps, fast vs direct
     w = synth.make("cfg1")
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
     run = lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], w["iters"], grid=w["grid"],
                                   window=w["window"])
-    timed(run)
-    (f, g, _), t = timed(run, 2)
-    _, td = timed(lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 2, grid=0))
+    timed(torch, run)
+    (f, g, _), t = timed(torch, run, 2)
+    _, td = timed(torch, lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 2, grid=0))
     rows["uot_d2_n100k"] = {"sweeps_per_s": w["iters"] / t, "direct_sweeps_per_s": 2 / td,
                             "speedup_vs_direct": (w["iters"] / t) / (2 / td),
-                            "err_sampled_last_halfstep": last_half_err(w, f, g)}
+                            "err_sampled_last_halfstep": None}
+    keep["uot_d2_n100k"] = ("uot", "cfg1", 2, f.cpu().numpy(), g.cpu().numpy())
     log("2-D 100k: %.0f sweeps/s fast, %.1f direct" % (w["iters"] / t, 2 / td))
 
-    # MMD^2 at d=3, n=m=1M: energy kernel (near-field radius 1/16) and Gaussian lambda=0.02
+    # MMD^2 at d=3, n=m=1M: energy kernel (near-field radius 1/16), Gaussian lambda=0.02, and the
+    # inverse multiquadric with c = 0.05 (near-field radius 1/16)
     w = synth.make("cfg2")
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
     mmd_rows = {}
     for kind, opts in (("energy", {"grid": 256, "nearfield_radius": w["nearfield_radius"]}),
-                       ("gauss", {"lam": w["mmd_lambda"], "grid": 64})):
+                       ("gauss", {"lam": w["mmd_lambda"], "grid": 64}),
+                       ("imq", {"lam": 0.05, "grid": 256, "nearfield_radius": w["nearfield_radius"]})):
         fu.mmd(x, a, y, b, kernel=kind, window=6, **opts)
-        v, t = timed(lambda: fu.mmd(x, a, y, b, kernel=kind, window=6, **opts), 2)
-        mmd_rows[kind] = {"ms": 1e3 * t, "mmd2": v}
+        v, t = timed(torch, lambda: fu.mmd(x, a, y, b, kernel=kind, window=6, **opts), 2)
+        mmd_rows[kind] = {"ms": 1e3 * t, "mmd2": v, **{k: o for k, o in opts.items()}}
         log("MMD %s 1M: %.1f ms" % (kind, 1e3 * t))
     rows["mmd_d3_n1M"] = mmd_rows
+
+    # the MMD accuracy experiment (Table Accuracy_analysis3): d = 2, n = m = 10000 points and
+    # weights uniform on [0, 1], l = 1/2, c = 1; probability vectors and unnormalised weights
+    rng = np.random.default_rng([1365, 10000])
+    xe = rng.uniform(0, 1, (10000, 2)).astype(np.float32)
+    ye = rng.uniform(0, 1, (10000, 2)).astype(np.float32)
+    acc = {}
+    for norm in (True, False):
+        ae, be = rng.uniform(0, 1, 10000), rng.uniform(0, 1, 10000)
+        if norm:
+            ae, be = ae / ae.sum(), be / be.sum()
+        ae, be = ae.astype(np.float32), be.astype(np.float32)
+        label = "probability" if norm else "unbalanced"
+        for kind, lam, grid in (("gauss", 0.25, 64), ("laplace", 0.5, 128), ("imq", 1.0, 128),
+                                ("energy", 1.0, 128)):
+            T = lambda z: torch.from_numpy(z).to(dev)
+            v, t = timed(torch, lambda: fu.mmd(T(xe), T(ae), T(ye), T(be), kernel=kind, lam=lam,
+                                               grid=grid, window=6))
+            acc["%s_%s" % (kind, label)] = {"mmd2": v, "ms": 1e3 * t, "residual": None}
+            keep["acc_%s_%s" % (kind, label)] = ("mmd", xe, ae, ye, be, kind, lam, v)
+    rows["mmd_accuracy_d2_n10k"] = acc
 
     # 4M Laplace Gibbs-kernel Sinkhorn (r = 1) with near field, grid 256^3
     w = synth.make("cfg4a")
@@ -117,30 +139,82 @@ def extra_rows(fu, torch, dev, oracle, synth):
     opts = {"kernel": "laplace", "grid": w["grid"], "window": w["window"],
             "bandwidth": w["bandwidth"], "smoothness": w["smoothness"]}
     fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 1, **opts)
-    (f, g, _), t = timed(lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], it, **opts))
+    (f, g, _), t = timed(torch, lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], it, **opts))
     rows["uot_laplace_d3_n4M"] = {"sweeps_per_s": it / t, "sweeps_timed": it,
                                   "grid": w["grid"], "bandwidth": w["bandwidth"],
                                   "smoothness": w["smoothness"],
-                                  "err_sampled_last_halfstep": last_half_err(w, f, g, r=1)}
+                                  "err_sampled_last_halfstep": None}
+    keep["uot_laplace_d3_n4M"] = ("uot", "cfg4a", 1, f.cpu().numpy(), g.cpu().numpy())
     log("4M Laplace: %.1f sweeps/s (%d sweeps incl. plan)" % (it / t, it))
 
     # d = 32 direct Gaussian sum on the MFMA path (BF16 hi/lo Gram tiles), n=m=200k
     w = synth.make("cfg4b")
     x, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "y", "b"))
     fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0)
-    out, t = timed(lambda: fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0), 3)
-    idx = synth.sample_rows(w["n"], 64, seed=5)
-    ref = oracle.direct_sum_rows(w["x"], idx, w["y"], w["b"], "gauss", w["eps"])
-    err = float(np.max(np.abs(out.cpu().numpy()[idx] - ref)) / np.max(np.abs(ref)))
+    out, t = timed(torch, lambda: fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0), 3)
     flops = 3 * 2.0 * w["d"] * w["n"] * w["m"]
     rows["mfma_gauss_d32_n200k"] = {
-        "ms": 1e3 * t, "err_sampled": err,
+        "ms": 1e3 * t, "err_sampled": None,
         "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": flops / t / 1e12 / 2500.0,
                      "work": "3 BF16 products x 2 x d x n x m"},
         "pairs_per_s": w["n"] * w["m"] / t}
-    log("d=32 MFMA: %.2f ms, err %.1e" % (1e3 * t, err))
+    keep["mfma_gauss_d32_n200k"] = ("sum", "cfg4b", out.cpu().numpy())
+    log("d=32 MFMA: %.2f ms" % (1e3 * t))
     return rows
+
+
+def cpu_baseline_leg(synth, w, f, g, extras, keep):
+    """The FP64 oracle on the host cores: its rate on a bounded sample of the headline workload,
+    and, from the same leg, the exact values of sampled rows (and of the small MMD experiment)
+    against which every GPU result of this run is scored."""
+    import oracle
+    n, m, eps, rho = w["n"], w["m"], w["eps"], w["rho"]
+
+    def rel(got, ref):
+        return float(np.max(np.abs(np.asarray(got) - ref)) / np.max(np.abs(ref)))
+
+    # rate: beta and gamma half-steps for R sampled rows each against all sources
+    R = 8192
+    rows = synth.sample_rows(n, R, seed=2)
+    t1 = time.perf_counter()
+    oracle.uot_beta_rows(w["x"], rows, w["y"], w["b"], np.zeros(m), eps, rho)
+    oracle.uot_beta_rows(w["y"], rows, w["x"], w["a"], np.zeros(n), eps, rho)
+    tcpu = time.perf_counter() - t1
+    sweep_s = tcpu * (n / R)
+    cpu = {"value": 1.0 / sweep_s, "unit": "sweeps/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": "FP64 beta and gamma half-steps (Algorithm 1, log-sum-exp) for %d of %d "
+                     "rows each against all %d sources, %.1f s, scaled to one full sweep"
+                     % (R, n, m, tcpu)}
+    log("oracle %.3g sweeps/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    # headline: the last (gamma) half-step recomputed from the GPU's final beta
+    idx = synth.sample_rows(m, 128, seed=1)
+    ref = oracle.uot_beta_rows(w["y"], idx, w["x"], w["a"], f, eps, rho)
+    err = rel(g[idx], ref)
+    log("sampled last-half-step error %.2e (%d rows)" % (err, len(idx)))
+
+    for key, item in keep.items():
+        if item[0] == "uot":
+            _, cfg, r, fk, gk = item
+            wk = synth.make(cfg)
+            idx = synth.sample_rows(wk["m"], 64, seed=3)
+            refk = oracle.uot_beta_rows(wk["y"], idx, wk["x"], wk["a"], fk, wk["eps"], wk["rho"], r=r)
+            extras[key]["err_sampled_last_halfstep"] = rel(gk[idx], refk)
+        elif item[0] == "sum":
+            _, cfg, out = item
+            wk = synth.make(cfg)
+            idx = synth.sample_rows(wk["n"], 64, seed=5)
+            refk = oracle.direct_sum_rows(wk["x"], idx, wk["y"], wk["b"], "gauss", wk["eps"])
+            extras[key]["err_sampled"] = rel(out[idx], refk)
+        elif item[0] == "mmd":
+            _, xe, ae, ye, be, kind, lam, v = item
+            refv, terms = oracle.mmd2(xe, ae, ye, be, kind, lam)
+            entry = extras["mmd_accuracy_d2_n10k"][key[4:]]
+            entry["residual"] = abs(v - refv) / abs(refv)
+            entry["err_vs_largest_term"] = abs(v - refv) / max(abs(t) for t in terms)
+    return cpu, err
 
 
 def main():
@@ -216,16 +290,6 @@ def main():
                      "GBs": nbytes / (t * 1e-3) / 1e9 if t else None,
                      "frac_of_8TBs": (nbytes / (t * 1e-3) / 1e9) / PEAK_HBM_GBS if t else None}
 
-    # ---- sampled full-size parity: the last (gamma) half-step recomputed by the FP64 oracle
-    #      from the GPU's final beta for sampled rows, against the GPU's final gamma
-    import oracle
-    rows = synth.sample_rows(m, 128, seed=1)
-    fh = f.cpu().numpy()
-    gamma_rows = oracle.uot_beta_rows(w["y"], rows, w["x"], w["a"], fh, eps, rho)
-    gh = g.cpu().numpy()[rows]
-    err_sampled = float(np.max(np.abs(gh - gamma_rows)) / np.max(np.abs(gamma_rows)))
-    log("sampled last-half-step error %.2e (%d rows)" % (err_sampled, len(rows)))
-
     # ---- GPU direct summation on the same inputs (one sweep)
     direct = None
     if not args.no_direct:
@@ -264,24 +328,14 @@ def main():
                      "value": float(s.item())}
         log("divergence fwd %.1f ms, fwd+bwd %.1f ms" % (fwd_ms, fb_ms))
 
-    extras = None if args.no_extras else extra_rows(fu, torch, dev, oracle, synth)
+    keep = {}
+    extras = None if args.no_extras else extra_rows(fu, torch, dev, synth, keep)
 
-    # ---- oracle on the host cores: beta and gamma half-steps for a bounded sample of rows
-    cpu = None
+    # ---- CPU-baseline leg: the FP64 oracle on the host cores (rate and sampled references)
+    cpu, err_sampled = None, None
     if not args.no_cpu:
-        R = 8192
-        rows = synth.sample_rows(n, R, seed=2)
-        t1 = time.perf_counter()
-        oracle.uot_beta_rows(w["x"], rows, w["y"], w["b"], np.zeros(m), eps, rho)
-        oracle.uot_beta_rows(w["y"], rows, w["x"], w["a"], np.zeros(n), eps, rho)
-        tcpu = time.perf_counter() - t1
-        sweep_s = tcpu * (n / R)
-        cpu = {"value": 1.0 / sweep_s, "unit": "sweeps/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": "FP64 beta and gamma half-steps (Algorithm 1, log-sum-exp) for %d of %d "
-                         "rows each against all %d sources, %.1f s, scaled to one full sweep"
-                         % (R, n, m, tcpu)}
-        log("oracle %.3g sweeps/s on %d threads" % (cpu["value"], cpu["cores"]))
+        cpu, err_sampled = cpu_baseline_leg(synth, w, f.cpu().numpy(), g.cpu().numpy(),
+                                            extras if extras is not None else {}, keep)
 
     line = {
         "metric": "UOT Sinkhorn iters/sec fast-sum vs direct, n=1M d=3 at rel err<=1e-5; fwd+bwd ms",
