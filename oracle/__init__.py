@@ -201,6 +201,37 @@ def uot_cstar(x, mu, y, nu, eps, eta, r=2):
     return c, ub.value
 
 
+def uot_sinkhorn_scaling(x, mu, y, nu, eps_stages, eta, max_sweeps, tol, init="zero", r=2,
+                         beta0=None, gamma0=None):
+    """lambda-scaling (Section "lambda-scaling"): Algorithm 1 solved for a sequence of
+    temperatures eps_stages (increasing lambda = 1/eps), each stage warm-started from the
+    potentials of the previous one.  A stage ends after the first full sweep (beta then gamma) that
+    changes no potential by more than `tol` (cost units), or after `max_sweeps` sweeps.
+    init: "zero" (gamma = 0), "cstar" (the remark on initialisation, read as e^{gamma/eps} = c*
+    with c* of eq. (561) at the first temperature: gamma = eps_0 log c*), or "warm" (beta0,
+    gamma0).  Returns (beta, gamma, sweeps per stage)."""
+    xs, n, _ = _pts(x)
+    ys, m, _ = _pts(y)
+    beta, gamma = np.zeros(n), np.zeros(m)
+    if init == "cstar":
+        c, _ = uot_cstar(x, mu, y, nu, eps_stages[0], eta, r=r)
+        gamma[:] = eps_stages[0] * np.log(c)
+    elif init == "warm":
+        beta, gamma = _f64(beta0).copy(), _f64(gamma0).copy()
+    counts = []
+    for eps in eps_stages:
+        k = 0
+        while k < max_sweeps:
+            nb, ng = uot_halfsteps(x, mu, y, nu, eps, eta, 2, beta, gamma, r=r)
+            k += 1
+            delta = max(np.max(np.abs(nb - beta), initial=0.0), np.max(np.abs(ng - gamma), initial=0.0))
+            beta, gamma = nb, ng
+            if delta <= tol:
+                break
+        counts.append(k)
+    return beta, gamma, counts
+
+
 def sinkhorn_divergence(x, mu, y, nu, eps, eta, sweeps, r=2):
     """eq. (586); returns (sd, (UOT(mu,nu), UOT(mu,mu), UOT(nu,nu)))."""
     x, n, d = _pts(x)

@@ -323,6 +323,42 @@ def test_uot_cstar_upper_bound():
         assert phi(c * 1.01) > phi(c) and phi(c * 0.99) > phi(c)
 
 
+def test_scaling_single_stage_is_plain_sinkhorn():
+    """One stage without a tolerance is Algorithm 1 itself."""
+    x, mu, y, nu = _small_problem()
+    b1, g1, cnt = oracle.uot_sinkhorn_scaling(x, mu, y, nu, [0.05], 1.0, 37, 0.0)
+    b2, g2 = oracle.uot_sinkhorn(x, mu, y, nu, 0.05, 1.0, 37)
+    assert cnt == [37]
+    assert np.array_equal(b1, b2) and np.array_equal(g1, g2)
+
+
+@pytest.mark.parametrize("init", ["zero", "cstar"])
+def test_scaling_reaches_the_fixed_point_of_the_last_temperature(init):
+    """The dual is strictly concave, so every start and every temperature path ends at the same
+    fixed point of the last temperature: the scaled solve agrees with a long plain solve, the
+    stopping rule holds at every stage end, and the marginal identity of the fixed point holds."""
+    x, mu, y, nu = _small_problem(n=70, m=60, d=2)
+    eta, tol = 1.0, 1e-12
+    stages = [1.0, 0.05, 0.01]
+    b, g, counts = oracle.uot_sinkhorn_scaling(x, mu, y, nu, stages, eta, 5000, tol, init=init)
+    assert all(c < 5000 for c in counts)
+    bref, gref = oracle.uot_sinkhorn(x, mu, y, nu, stages[-1], eta, 5000)
+    assert rel(b, bref) < 1e-8 and rel(g, gref) < 1e-8
+    # one more sweep moves nothing by more than the tolerance
+    b2, g2 = oracle.uot_halfsteps(x, mu, y, nu, stages[-1], eta, 2, b, g)
+    assert max(np.max(np.abs(b2 - b)), np.max(np.abs(g2 - g))) <= tol
+    P, Q = oracle.uot_marginals(x, mu, y, nu, stages[-1], b, g)
+    assert rel(P, mu * np.exp(-b / eta)) < 1e-8
+
+
+def test_scaling_cstar_start_is_the_log_of_eq_561():
+    """With zero sweeps the c* start leaves gamma = eps_0 log c* (eq. (561)) and beta = 0."""
+    x, mu, y, nu = _small_problem()
+    b, g, counts = oracle.uot_sinkhorn_scaling(x, mu, y, nu, [0.2], 1.5, 0, 0.0, init="cstar")
+    c, _ = oracle.uot_cstar(x, mu, y, nu, 0.2, 1.5)
+    assert counts == [0] and np.all(b == 0) and np.allclose(g, 0.2 * math.log(c), rtol=0, atol=1e-15)
+
+
 def test_sinkhorn_divergence_self_is_zero():
     x, mu, _, _ = _small_problem()
     sd, _ = oracle.sinkhorn_divergence(x, mu, x, mu, 0.05, 1.0, 200)
