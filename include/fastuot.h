@@ -134,6 +134,37 @@ int uot_sinkhorn(const float *x, const float *a, int64_t n, const float *y, cons
                  int64_t m, int d, const fs_params *p, double rho, int iters, double *f, double *g,
                  double *objective_host, void *stream);
 
+/* Upper bound of Proposition "Optimal independent measure" and the remark on upper bounds:
+ *   c* = exp(-<mu x nu, d^r> / (Ma Mb (2 rho + lambda))) Ma^(-rho/(2 rho + lambda))
+ *        Mb^(-rho/(2 rho + lambda))                          (eq. (561), eta_1 = eta_2 = rho)
+ *   bound = objective of eq. (W4) at pi = c* mu x nu  >=  UOT_lambda(mu, nu),
+ * with Ma, Mb the masses and r = 2 (FS_GAUSS) or 1 (FS_LAPLACE).  For r = 2, <mu x nu, d^2>
+ * comes from FP64 first and second moments; for r = 1 it is one energy-kernel sum with the grid,
+ * window and near-field settings of p (direct when grid = 0).  cstar_host and bound_host are
+ * host doubles (nullable).  Synchronises the stream. */
+int uot_upper_bound(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                    int64_t m, int d, const fs_params *p, double rho, double *cstar_host,
+                    double *bound_host, void *stream);
+
+/* Starting potentials of uot_sinkhorn_scaling */
+#define FS_INIT_ZERO 0  /* g = 0                                                           */
+#define FS_INIT_CSTAR 1 /* g = lambda_0 log c*, c* of eq. (561) at the first temperature,
+                           f = 0 (the remark on initialisation, read as e^{g/lambda} = c*) */
+#define FS_INIT_WARM 2  /* f and g hold the starting potentials on entry                  */
+
+/* lambda-scaling (Section "lambda-scaling"): the problem of uot_sinkhorn solved for the
+ * temperatures eps_stages[0..nstages) in turn (p->lambda is ignored), each stage warm-started
+ * from the potentials of the previous one.  A stage ends after the first sweep that changes no
+ * potential by more than tol * eps_stages[k] (the potentials enter the kernel sums as
+ * exp(f / eps); tol = 0 runs max_sweeps sweeps), or after max_sweeps sweeps.  The FP32 kernel
+ * sums leave a floor of about 1e-7 in this measure: use tol >= 1e-6.  Each stage builds its own plan (the torus period follows the temperature).
+ * sweeps_host (nullable, nstages ints) receives the sweeps run per stage; objective_host
+ * (nullable) the dual value at the last temperature.  f (n), g (m): device float64. */
+int uot_sinkhorn_scaling(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                         int64_t m, int d, const fs_params *p, const double *eps_stages,
+                         int nstages, double rho, int max_sweeps, double tol, int init, double *f,
+                         double *g, int *sweeps_host, double *objective_host, void *stream);
+
 /* Gradients of the UOT value at converged potentials (envelope theorem on the dual of Theorem
  * "dualization"), scaled by `scale`:
  *   dx_i = scale * sum_j pi_ij grad_x |x_i - y_j|^r,    pi_ij = a_i b_j exp((f_i + g_j - C_ij)/lambda)

@@ -206,7 +206,8 @@ def uot_sinkhorn_scaling(x, mu, y, nu, eps_stages, eta, max_sweeps, tol, init="z
     """lambda-scaling (Section "lambda-scaling"): Algorithm 1 solved for a sequence of
     temperatures eps_stages (increasing lambda = 1/eps), each stage warm-started from the
     potentials of the previous one.  A stage ends after the first full sweep (beta then gamma) that
-    changes no potential by more than `tol` (cost units), or after `max_sweeps` sweeps.
+    changes no potential by more than tol * eps (the potentials enter the kernel sums as
+    e^{potential/eps}), or after `max_sweeps` sweeps.
     init: "zero" (gamma = 0), "cstar" (the remark on initialisation, read as e^{gamma/eps} = c*
     with c* of eq. (561) at the first temperature: gamma = eps_0 log c*), or "warm" (beta0,
     gamma0).  Returns (beta, gamma, sweeps per stage)."""
@@ -226,7 +227,7 @@ def uot_sinkhorn_scaling(x, mu, y, nu, eps_stages, eta, max_sweeps, tol, init="z
             k += 1
             delta = max(np.max(np.abs(nb - beta), initial=0.0), np.max(np.abs(ng - gamma), initial=0.0))
             beta, gamma = nb, ng
-            if delta <= tol:
+            if delta <= tol * eps:
                 break
         counts.append(k)
     return beta, gamma, counts

@@ -16,7 +16,8 @@ import os
 import torch
 
 __all__ = [
-    "fastsum_apply", "Plan", "uot_sinkhorn", "uot_sinkhorn_grad", "sinkhorn_divergence",
+    "fastsum_apply", "Plan", "uot_sinkhorn", "uot_sinkhorn_grad", "uot_upper_bound",
+    "uot_sinkhorn_scaling", "sinkhorn_divergence",
     "sinkhorn_divergence_grad", "mmd", "mmd_grad", "SinkhornDivergence", "MMD2",
     "FastsumError", "KERNELS", "library_path", "EXPORTED", "fs_profile_enable",
     "fs_profile_query", "fs_profile_reset",
@@ -29,8 +30,10 @@ FLAG_WARM_START = 0x1
 FLAG_FORCE_VALU = 0x2
 EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fs_profile_enable",
             "fs_profile_query", "fs_profile_reset", "fastsum_apply", "fs_plan_create",
-            "fs_plan_apply", "fs_plan_destroy", "uot_sinkhorn", "uot_sinkhorn_grad",
-            "sinkhorn_divergence", "sinkhorn_divergence_grad", "mmd", "mmd_grad")
+            "fs_plan_apply", "fs_plan_destroy", "uot_sinkhorn", "uot_upper_bound",
+            "uot_sinkhorn_scaling", "uot_sinkhorn_grad", "sinkhorn_divergence",
+            "sinkhorn_divergence_grad", "mmd", "mmd_grad")
+INITS = {"zero": 0, "cstar": 1, "warm": 2}
 
 
 class FastsumError(RuntimeError):
@@ -68,6 +71,9 @@ def _load():
         "fs_plan_apply": (I, [P, P, P, I, P]),
         "fs_plan_destroy": (None, [P]),
         "uot_sinkhorn": (I, [P, P, I64, P, P, I64, I, PP, D, I, P, P, P, P]),
+        "uot_upper_bound": (I, [P, P, I64, P, P, I64, I, PP, D, P, P, P]),
+        "uot_sinkhorn_scaling": (I, [P, P, I64, P, P, I64, I, PP, P, I, D, I, D, I, P, P, P, P,
+                                     P]),
         "uot_sinkhorn_grad": (I, [P, P, I64, P, P, I64, I, PP, D, P, P, D, P, P, P, P, P]),
         "sinkhorn_divergence": (I, [P, P, I64, P, P, I64, I, PP, D, I, P, P, P, P, P, P, P]),
         "sinkhorn_divergence_grad": (I, [P, P, I64, P, P, I64, I, PP, D, P, P, P, P, D, P, P, P,
@@ -212,6 +218,48 @@ def uot_sinkhorn(x, a, y, b, lam, rho, iters, kernel="gauss", grid=0, window=0, 
                              ctypes.byref(p), float(rho), int(iters), _ptr(f), _ptr(g),
                              ctypes.byref(obj), _stream(x.device)))
     return f, g, obj.value
+
+
+def uot_upper_bound(x, a, y, b, lam, rho, kernel="gauss", grid=0, window=0, oversampling=0,
+                    smoothness=0, nearfield_radius=0.0, bandwidth=0):
+    """(c*, objective at c* mu x nu) of eq. (561); the objective bounds UOT from above.  For the
+    r = 1 cost ("laplace") the grid settings drive one energy-kernel sum."""
+    x, y = _pts(x, "x"), _pts(y, "y")
+    a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
+    p = _params(kernel, lam, grid, window, oversampling, smoothness, nearfield_radius, 0,
+                bandwidth)
+    c, ub = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(_lib.uot_upper_bound(_ptr(x), _ptr(a), x.shape[0], _ptr(y), _ptr(b), y.shape[0],
+                                x.shape[1], ctypes.byref(p), float(rho), ctypes.byref(c),
+                                ctypes.byref(ub), _stream(x.device)))
+    return c.value, ub.value
+
+
+def uot_sinkhorn_scaling(x, a, y, b, eps_stages, rho, max_sweeps, tol, init="zero", f0=None,
+                         g0=None, kernel="gauss", grid=0, window=0, oversampling=0, smoothness=0,
+                         nearfield_radius=0.0, flags=0, bandwidth=0):
+    """lambda-scaling over the temperatures eps_stages; returns (f, g, sweeps per stage,
+    objective).  init: "zero", "cstar" or "warm" (f0, g0)."""
+    x, y = _pts(x, "x"), _pts(y, "y")
+    a, b = _dev(a, name="a").reshape(-1), _dev(b, name="b").reshape(-1)
+    n, m = x.shape[0], y.shape[0]
+    f = torch.zeros(n, dtype=torch.float64, device=x.device)
+    g = torch.zeros(m, dtype=torch.float64, device=x.device)
+    if init == "warm":
+        f.copy_(f0 if f0 is not None else torch.zeros_like(f))
+        g.copy_(g0 if g0 is not None else torch.zeros_like(g))
+    stages = (ctypes.c_double * len(eps_stages))(*[float(e) for e in eps_stages])
+    counts = (ctypes.c_int * len(eps_stages))()
+    p = _params(kernel, eps_stages[0], grid, window, oversampling, smoothness, nearfield_radius,
+                flags, bandwidth)
+    obj = ctypes.c_double(0.0)
+    _check(_lib.uot_sinkhorn_scaling(_ptr(x), _ptr(a), n, _ptr(y), _ptr(b), m, x.shape[1],
+                                     ctypes.byref(p), ctypes.cast(stages, ctypes.c_void_p),
+                                     len(eps_stages), float(rho), int(max_sweeps), float(tol),
+                                     INITS[init], _ptr(f), _ptr(g),
+                                     ctypes.cast(counts, ctypes.c_void_p), ctypes.byref(obj),
+                                     _stream(x.device)))
+    return f, g, list(counts), obj.value
 
 
 def uot_sinkhorn_grad(x, a, y, b, lam, rho, f, g, kernel="gauss", grid=0, window=0,

@@ -57,7 +57,7 @@ int guarded(F &&f) {
 // Solve one UOT problem with a fresh operator; potentials returned in caller order.
 double solve_uot(const float *x, const float *a, int64_t n, const float *y, const float *b,
                  int64_t m, int d, const fs_params &p, double rho, int iters, bool warm,
-                 double *f, double *g, hipStream_t s) {
+                 double *f, double *g, hipStream_t s, double tol = 0.0, int *sweeps = nullptr) {
     auto op = make_op(x, n, y, m, d, p, s);
     DevBuf<float> ao(n + 1), bo(m + 1);
     DevBuf<double> fo(n + 1), go(m + 1);
@@ -68,11 +68,30 @@ double solve_uot(const float *x, const float *a, int64_t n, const float *y, cons
         op->to_op64(1, g, go.p, s);
     }
     double obj = 0.0;
-    sinkhorn_solve(*op, ao.p, bo.p, p.lambda, rho, iters, warm, fo.p, go.p, &obj, s);
+    sinkhorn_solve(*op, ao.p, bo.p, p.lambda, rho, iters, warm, fo.p, go.p, &obj, s, tol, sweeps);
     if (f) op->from_op64(0, fo.p, f, s);
     if (g) op->from_op64(1, go.p, g, s);
     FS_HIP(hipStreamSynchronize(s));
     return obj;
+}
+
+// c* of eq. (561) (Proposition "optimal independent measure", eta_1 = eta_2 = rho, 1/lambda_paper
+// = eps) and the objective of eq. (W4) at pi = c* mu x nu, which bounds UOT from above.
+void cstar_bound(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                 int64_t m, int d, const fs_params &p, double rho, double *cstar, double *bound,
+                 hipStream_t s) {
+    const int r = (p.kernel == FS_GAUSS) ? 2 : 1;
+    double Ma = 0.0, Mb = 0.0;
+    const double D = pair_cost_mean(x, a, n, y, b, m, d, r, p, &Ma, &Mb, s);
+    FS_REQUIRE(Ma > 0 && Mb > 0, FS_EINVAL, "both measures need positive mass");
+    const double eps = p.lambda, den = 2.0 * rho + eps;
+    const double c = std::exp(-D / (Ma * Mb * den)) * std::pow(Ma, -rho / den) *
+                     std::pow(Mb, -rho / den);
+    if (cstar) *cstar = c;
+    if (bound)
+        *bound = c * D + eps * Ma * Mb * (c * std::log(c) - c + 1.0) +
+                 rho * Ma * (c * Mb * std::log(c * Mb) - c * Mb + 1.0) +
+                 rho * Mb * (c * Ma * std::log(c * Ma) - c * Ma + 1.0);
 }
 
 }  // namespace
@@ -206,6 +225,66 @@ int uot_sinkhorn(const float *x, const float *a, int64_t n, const float *y, cons
         const bool warm = (p->flags & FS_FLAG_WARM_START) != 0;
         const double obj = solve_uot(x, a, n, y, b, m, d, *p, rho, iters, warm, f, g,
                                      as_stream(stream));
+        if (objective_host) *objective_host = obj;
+    });
+}
+
+int uot_upper_bound(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                    int64_t m, int d, const fs_params *p, double rho, double *cstar_host,
+                    double *bound_host, void *stream) {
+    return guarded([&] {
+        check_params(p);
+        check_transport(p, rho);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        cstar_bound(x, a, n, y, b, m, d, *p, rho, cstar_host, bound_host, as_stream(stream));
+    });
+}
+
+int uot_sinkhorn_scaling(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                         int64_t m, int d, const fs_params *p, const double *eps_stages,
+                         int nstages, double rho, int max_sweeps, double tol, int init, double *f,
+                         double *g, int *sweeps_host, double *objective_host, void *stream) {
+    return guarded([&] {
+        check_params(p);
+        FS_REQUIRE(nstages >= 1 && eps_stages != nullptr, FS_EINVAL, "need at least one stage");
+        for (int k = 0; k < nstages; ++k)
+            FS_REQUIRE(eps_stages[k] > 0 && std::isfinite(eps_stages[k]), FS_EINVAL,
+                       "stage %d: temperature must be > 0", k);
+        fs_params q = *p;
+        q.lambda = eps_stages[0];
+        check_transport(&q, rho);
+        check_points(x, n, "x");
+        check_points(a, n, "a");
+        check_points(y, m, "y");
+        check_points(b, m, "b");
+        check_points(f, n, "f");
+        check_points(g, m, "g");
+        FS_REQUIRE(d >= 1, FS_EINVAL, "d must be >= 1");
+        FS_REQUIRE(max_sweeps >= 0, FS_EINVAL, "max_sweeps must be >= 0");
+        FS_REQUIRE(tol >= 0 && std::isfinite(tol), FS_EINVAL, "tol must be finite and >= 0");
+        FS_REQUIRE(init == FS_INIT_ZERO || init == FS_INIT_CSTAR || init == FS_INIT_WARM,
+                   FS_EINVAL, "unknown init %d", init);
+        hipStream_t s = as_stream(stream);
+        bool warm = init == FS_INIT_WARM;
+        if (init == FS_INIT_CSTAR) {
+            double c = 0.0;
+            cstar_bound(x, a, n, y, b, m, d, q, rho, &c, nullptr, s);
+            fill_f64(f, n, 0.0, s);
+            fill_f64(g, m, eps_stages[0] * std::log(c), s);
+            warm = true;
+        }
+        double obj = 0.0;
+        for (int k = 0; k < nstages; ++k) {
+            q.lambda = eps_stages[k];
+            int done = 0;
+            obj = solve_uot(x, a, n, y, b, m, d, q, rho, max_sweeps, warm, f, g, s, tol, &done);
+            if (sweeps_host) sweeps_host[k] = done;
+            warm = true;
+        }
         if (objective_host) *objective_host = obj;
     });
 }

@@ -46,8 +46,11 @@ struct SinkhornResult {
 
 // Sinkhorn in operator order.  a_o (n), b_o (m) float weights; f_o, g_o double potentials
 // (in/out; used as starting values when warm).
+// tol > 0: stop after the first sweep that changes no potential by more than tol * eps;
+// sweeps_done (nullable) receives the number of sweeps run.
 void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, double rho, int iters,
-                    bool warm, double *f_o, double *g_o, double *objective_host, hipStream_t s);
+                    bool warm, double *f_o, double *g_o, double *objective_host, hipStream_t s,
+                    double tol = 0.0, int *sweeps_done = nullptr);
 
 // Envelope gradients of the UOT dual at given potentials (caller order in and out); any output
 // may be NULL.  Scaled by `scale`.
@@ -61,6 +64,12 @@ void mmd_core(const float *x, const float *a, int64_t n, const float *y, const f
 void mmd_grad_core(const float *x, const float *a, int64_t n, const float *y, const float *b,
                    int64_t m, int d, const fs_params &p, double scale, float *dx, float *da,
                    float *dy, float *db, hipStream_t s);
+
+// <mu x nu, d^r> = sum_ij a_i b_j |x_i - y_j|^r (eq. (561)): r = 2 from moments in FP64, r = 1
+// through one energy-kernel sum with the grid settings of p; also returns the two masses.
+double pair_cost_mean(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                      int64_t m, int d, int r, const fs_params &p, double *Ma, double *Mb,
+                      hipStream_t s);
 
 // Compensated FP64 sum / dot of float vectors on the device, returned to the host.
 double device_sum(const float *u, int64_t n, hipStream_t s);

@@ -14,6 +14,8 @@
 
 #include "solver.h"
 
+#include <vector>
+
 namespace fs {
 
 // =====================================================================================
@@ -55,11 +57,14 @@ __global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
 // nshift per-block maxima); writes one block maximum of the new potential per block.  Non-positive
 // sums are counted in *nbad and replaced by the smallest normal float.
 constexpr int UPD_BLOCKS = 256;
+// With DELTA the per-block maxima of |new - old| go to delta_parts (stopping rule).
+template <bool DELTA>
 __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int64_t n,
                                                const double *__restrict__ shift_parts, int nshift,
                                                double kappa, double eps, double *__restrict__ pot,
                                                double *__restrict__ out_parts,
-                                               int *__restrict__ nbad) {
+                                               int *__restrict__ nbad,
+                                               double *__restrict__ delta_parts) {
     __shared__ double sm[RT];
     double sh = -INFINITY;
     for (int b = threadIdx.x; b < nshift; b += RT) sh = fmax(sh, shift_parts[b]);
@@ -71,13 +76,14 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
     }
     sh = (sm[0] == -INFINITY) ? 0.0 : sm[0];
     __syncthreads();
-    double mx = -INFINITY;
+    double mx = -INFINITY, dmx = 0.0;
     int bad = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         float v = t[i];
         if (!(v > 0.0f)) { bad++; v = FLT_MIN; }
         const double f = -kappa * (sh + eps * log((double)v));
+        if (DELTA) dmx = fmax(dmx, fabs(f - pot[i]));
         pot[i] = f;
         mx = fmax(mx, f);
     }
@@ -89,6 +95,16 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
         __syncthreads();
     }
     if (threadIdx.x == 0) out_parts[blockIdx.x] = sm[0];
+    if (DELTA) {
+        __syncthreads();
+        sm[threadIdx.x] = dmx;
+        __syncthreads();
+        for (int s = RT / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) delta_parts[blockIdx.x] = sm[0];
+    }
 }
 
 // Per-block maxima of a double array (warm starts, gradients); combined by the consumer.
@@ -106,6 +122,51 @@ __global__ void __launch_bounds__(RT) k_max_parts(const double *__restrict__ v, 
         __syncthreads();
     }
     if (threadIdx.x == 0) parts[blockIdx.x] = sm[0];
+}
+
+// Weighted moments about the reference point ref (the first point of the set), per block:
+// parts[b][k] = sum w (p_k - ref_k) (k < d), parts[b][d] = sum w, parts[b][d+1] = sum w |p - ref|^2.
+__global__ void __launch_bounds__(RT) k_moments(const float *__restrict__ p, const float *__restrict__ w,
+                                                int64_t n, int d, const float *__restrict__ ref,
+                                                double *__restrict__ parts) {
+    __shared__ double sm[RT];
+    for (int k = 0; k < d + 2; ++k) {
+        double acc = 0.0;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const double wi = w[i];
+            if (k < d) {
+                acc += wi * ((double)p[i * d + k] - (double)ref[k]);
+            } else if (k == d) {
+                acc += wi;
+            } else {
+                double r2 = 0.0;
+                for (int c = 0; c < d; ++c) {
+                    const double t = (double)p[i * d + c] - (double)ref[c];
+                    r2 += t * t;
+                }
+                acc += wi * r2;
+            }
+        }
+        sm[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = RT / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) parts[(int64_t)blockIdx.x * (d + 2) + k] = sm[0];
+        __syncthreads();
+    }
+}
+
+// out[k] = sum over blocks of parts[b][k] (fixed order), one thread per component
+__global__ void k_moments_final(const double *__restrict__ parts, int nblocks, int ncomp,
+                                double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ncomp) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; ++b) acc += parts[(int64_t)b * ncomp + k];
+    out[k] = acc;
 }
 
 // out = max of nparts maxima (0 if all are -inf), one block
@@ -413,14 +474,18 @@ struct Scalars {
     DevBuf<double> v;       // scalar results: [0] gmax, [1] fmax, [2] Mb, [3] Ma, sums at [8..)
     DevBuf<double> fparts;  // per-block maxima of f
     DevBuf<double> gparts;  // per-block maxima of g
+    DevBuf<double> dparts;  // per-block maxima of |change| of f (first half) and g (second half)
     DevBuf<double> partial;  // compensated-sum partials (RBLK x 3 x 2)
     DevBuf<int> nbad;
     int nf = 1, ng = 1;      // number of valid entries in fparts / gparts
-    Scalars() : v(32), fparts(UPD_BLOCKS), gparts(UPD_BLOCKS), partial(RBLK * 6), nbad(1) {}
+    Scalars()
+        : v(32), fparts(UPD_BLOCKS), gparts(UPD_BLOCKS), dparts(2 * UPD_BLOCKS),
+          partial(RBLK * 6), nbad(1) {}
     void reset(hipStream_t s) {
         fill_f64(v.p, 32, 0.0, s);
         fill_f64(fparts.p, UPD_BLOCKS, 0.0, s);
         fill_f64(gparts.p, UPD_BLOCKS, 0.0, s);
+        fill_f64(dparts.p, 2 * UPD_BLOCKS, 0.0, s);
         fill_i32(nbad.p, 1, 0, s);
         nf = ng = 1;
     }
@@ -431,11 +496,16 @@ int upd_blocks(int64_t n) { return (int)blocks_for(n, RT, UPD_BLOCKS); }
 
 // pot = update(t) with shift = max of (shift_parts, nshift); writes per-block maxima of pot
 int launch_update(const float *t, int64_t n, const double *shift_parts, int nshift, double kappa,
-                  double eps, double *pot, double *out_parts, int *nbad, hipStream_t s) {
+                  double eps, double *pot, double *out_parts, int *nbad, double *delta_parts,
+                  hipStream_t s) {
     ProfScope ps("update", s);
     const int nb = upd_blocks(n);
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(RT), 0, s, t, n, shift_parts, nshift, kappa, eps,
-                       pot, out_parts, nbad);
+    if (delta_parts)
+        hipLaunchKernelGGL(k_update<true>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts, nshift,
+                           kappa, eps, pot, out_parts, nbad, delta_parts);
+    else
+        hipLaunchKernelGGL(k_update<false>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts, nshift,
+                           kappa, eps, pot, out_parts, nbad, delta_parts);
     FS_LAUNCHED();
     return nb;
 }
@@ -473,7 +543,8 @@ void csum(int mode, const float *u, const double *pot, const float *v, int64_t n
 }  // namespace
 
 void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, double rho, int iters,
-                    bool warm, double *f_o, double *g_o, double *objective_host, hipStream_t s) {
+                    bool warm, double *f_o, double *g_o, double *objective_host, hipStream_t s,
+                    double tol, int *sweeps_done) {
     const int64_t n = op.n, m = op.m;
     const double kappa = rho / (rho + eps);
     Scalars sc;
@@ -486,20 +557,35 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
         fill_f64(g_o, m, 0.0, s);
         fill_f64(f_o, n, 0.0, s);
     }
+    // with a tolerance, a sweep that changes no potential by more than tol * eps ends the solve
+    const bool track = tol > 0.0;
+    double *fd = track ? sc.dparts.p : nullptr, *gd = track ? sc.dparts.p + UPD_BLOCKS : nullptr;
+    int done = 0;
     for (int it = 0; it < iters; ++it) {
         // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}
         launch_weights(b_o, g_o, sc.gparts.p, sc.ng, eps, m, wY.p, s);
         op.apply(wY.p, tX.p, nullptr, 0, s);
         if (n > 0)
             sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
-                                  sc.nbad.p, s);
+                                  sc.nbad.p, fd, s);
         // gamma half-step (Delta even): t~_j = sum_i k_ij a_i e^{f_i/eps}
         launch_weights(a_o, f_o, sc.fparts.p, sc.nf, eps, n, wX.p, s);
         op.apply(wX.p, tY.p, nullptr, 1, s);
         if (m > 0)
             sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
-                                  sc.nbad.p, s);
+                                  sc.nbad.p, gd, s);
+        ++done;
+        if (track) {
+            hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.dparts.p, 2 * UPD_BLOCKS,
+                               sc.v.p + 24);
+            FS_LAUNCHED();
+            double change = 0.0;
+            FS_HIP(hipMemcpyAsync(&change, sc.v.p + 24, sizeof(double), hipMemcpyDeviceToHost, s));
+            FS_HIP(hipStreamSynchronize(s));
+            if (change <= tol * eps) break;
+        }
     }
+    if (sweeps_done) *sweeps_done = done;
     int nbad = 0;
     if (objective_host) {
         // Dual value of Theorem "dualization" at (f, g).  After a gamma half-step the double sum
@@ -570,6 +656,44 @@ void combine(const float *u, const float *v, int64_t n, double s1, double s2, do
     hipLaunchKernelGGL(k_combine, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, u, v, n, s1, s2,
                        cst, out);
     FS_LAUNCHED();
+}
+
+double pair_cost_mean(const float *x, const float *a, int64_t n, const float *y, const float *b,
+                      int64_t m, int d, int r, const fs_params &p, double *Ma, double *Mb,
+                      hipStream_t s) {
+    FS_REQUIRE(n > 0 && m > 0, FS_EINVAL, "both measures need at least one point");
+    // masses and, for r = 2, the first and second moments about x_0 (translation invariant)
+    const unsigned nbx = blocks_for(n, RT, RBLK), nby = blocks_for(m, RT, RBLK);
+    DevBuf<double> px((size_t)nbx * (d + 2)), py((size_t)nby * (d + 2)), mx(d + 2), my(d + 2);
+    hipLaunchKernelGGL(k_moments, dim3(nbx), dim3(RT), 0, s, x, a, n, d, x, px.p);
+    hipLaunchKernelGGL(k_moments, dim3(nby), dim3(RT), 0, s, y, b, m, d, x, py.p);
+    hipLaunchKernelGGL(k_moments_final, dim3(blocks_for(d + 2, 64)), dim3(64), 0, s, px.p,
+                       (int)nbx, d + 2, mx.p);
+    hipLaunchKernelGGL(k_moments_final, dim3(blocks_for(d + 2, 64)), dim3(64), 0, s, py.p,
+                       (int)nby, d + 2, my.p);
+    FS_LAUNCHED();
+    std::vector<double> hx(d + 2), hy(d + 2);
+    FS_HIP(hipMemcpyAsync(hx.data(), mx.p, (d + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(hy.data(), my.p, (d + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    *Ma = hx[d];
+    *Mb = hy[d];
+    if (r == 2) {
+        // sum_ij a_i b_j |x_i - y_j|^2 = Mb sum a |x|^2 + Ma sum b |y|^2 - 2 (sum a x).(sum b y)
+        double cross = 0.0;
+        for (int k = 0; k < d; ++k) cross += hx[k] * hy[k];
+        return *Mb * hx[d + 1] + *Ma * hy[d + 1] - 2.0 * cross;
+    }
+    // r = 1: sum_ij a_i b_j |x_i - y_j| = -<a, K_energy b>, one energy kernel sum
+    fs_params q = p;
+    q.kernel = FS_ENERGY;
+    q.lambda = 1.0;
+    auto op = make_op(x, n, y, m, d, q, s);
+    DevBuf<float> ao(n + 1), bo(m + 1), t(n + 1);
+    op->to_op(0, a, ao.p, s);
+    op->to_op(1, b, bo.p, s);
+    op->apply(bo.p, t.p, nullptr, 0, s);
+    return -device_dot(ao.p, t.p, n, s);
 }
 
 void uot_grad_core(Op &op, const float *a, const float *b, const double *f, const double *g,

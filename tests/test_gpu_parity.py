@@ -263,6 +263,59 @@ def test_uot_laplace_gibbs_kernel():
         assert abs(obj - D) < TOL * abs(D), grid
 
 
+@pytest.mark.parametrize("kind,grid", [("gauss", 0), ("laplace", 0), ("laplace", 256),
+                                       ("gauss", 128)])
+def test_uot_upper_bound(kind, grid):
+    """c* of eq. (561) and the objective at c* mu x nu against the oracle (r = 2 from moments,
+    r = 1 through an energy-kernel sum)."""
+    w = synth.make("cfg3", n=2000, m=1700)
+    r = 2 if kind == "gauss" else 1
+    c, ub = fu.uot_upper_bound(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                               kernel=kind, grid=grid, window=6)
+    cref, ubref = oracle.uot_cstar(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], r=r)
+    assert abs(c - cref) < 1e-6 * abs(cref)
+    assert abs(ub - ubref) < 1e-6 * abs(ubref)
+    # it bounds the solved problem's value from above
+    _, _, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                                200, kernel=kind, grid=0)
+    assert obj <= ub
+
+
+@pytest.mark.parametrize("grid,init", [(0, "zero"), (0, "cstar"), (128, "zero"), (128, "cstar")])
+def test_uot_scaling_against_oracle(grid, init):
+    """lambda-scaling: temperatures 1, 0.05, 0.01 with warm starts and the per-sweep stopping rule.
+    The sweep counts agree with the oracle's under the same rule (the FP32 kernel sums put a noise
+    floor under the measured change, so a stage may run a few sweeps longer); the potentials
+    agree with the oracle's iterate after the same number of sweeps per stage."""
+    w = synth.make("cfg3", n=900, m=800)
+    stages, rho, tol = [1.0, 0.05, 0.01], 1.0, 1e-6
+    f, g, counts, obj = fu.uot_sinkhorn_scaling(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), stages,
+                                                rho, 3000, tol, init=init, grid=grid, window=6)
+    _, _, cref = oracle.uot_sinkhorn_scaling(w["x"], w["a"], w["y"], w["b"], stages, rho, 3000,
+                                             tol, init=init)
+    print("sweeps per stage: GPU", counts, "oracle", cref)
+    assert all(abs(c1 - c2) <= max(2, c2 // 10) for c1, c2 in zip(counts, cref))
+    # the oracle's iterate after the GPU's sweep counts, stage by stage
+    bref, gref, _ = oracle.uot_sinkhorn_scaling(w["x"], w["a"], w["y"], w["b"], stages[:1], rho,
+                                                counts[0], 0.0, init=init)
+    for eps, c in zip(stages[1:], counts[1:]):
+        bref, gref, _ = oracle.uot_sinkhorn_scaling(w["x"], w["a"], w["y"], w["b"], [eps], rho, c,
+                                                    0.0, init="warm", beta0=bref, gamma0=gref)
+    assert relinf(f.cpu().numpy(), bref) < 1e-5 and relinf(g.cpu().numpy(), gref) < 1e-5
+    dref = oracle.uot_dual(w["x"], w["a"], w["y"], w["b"], stages[-1], rho, bref, gref)
+    assert abs(obj - dref) < 1e-6 * abs(dref)
+
+
+def test_uot_scaling_single_stage_is_uot_sinkhorn():
+    w = synth.make("cfg3", n=700, m=650)
+    args = (T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]))
+    f1, g1, c1, o1 = fu.uot_sinkhorn_scaling(*args, [0.05], 1.0, 25, 0.0, grid=0)
+    f2, g2, o2 = fu.uot_sinkhorn(*args, 0.05, 1.0, 25, grid=0)
+    assert c1 == [25]
+    assert relinf(f1.cpu().numpy(), f2.cpu().numpy()) < 1e-12
+    assert relinf(g1.cpu().numpy(), g2.cpu().numpy()) < 1e-12 and abs(o1 - o2) < 1e-12 * abs(o2)
+
+
 def test_uot_warm_start_continues_the_iteration():
     w = synth.make("cfg0", n=700, m=650)
     x, a, y, b = (T(w[k]) for k in ("x", "a", "y", "b"))

@@ -338,7 +338,7 @@ def test_scaling_reaches_the_fixed_point_of_the_last_temperature(init):
     fixed point of the last temperature: the scaled solve agrees with a long plain solve, the
     stopping rule holds at every stage end, and the marginal identity of the fixed point holds."""
     x, mu, y, nu = _small_problem(n=70, m=60, d=2)
-    eta, tol = 1.0, 1e-12
+    eta, tol = 1.0, 1e-10
     stages = [1.0, 0.05, 0.01]
     b, g, counts = oracle.uot_sinkhorn_scaling(x, mu, y, nu, stages, eta, 5000, tol, init=init)
     assert all(c < 5000 for c in counts)
@@ -346,7 +346,7 @@ def test_scaling_reaches_the_fixed_point_of_the_last_temperature(init):
     assert rel(b, bref) < 1e-8 and rel(g, gref) < 1e-8
     # one more sweep moves nothing by more than the tolerance
     b2, g2 = oracle.uot_halfsteps(x, mu, y, nu, stages[-1], eta, 2, b, g)
-    assert max(np.max(np.abs(b2 - b)), np.max(np.abs(g2 - g))) <= tol
+    assert max(np.max(np.abs(b2 - b)), np.max(np.abs(g2 - g))) <= tol * stages[-1]
     P, Q = oracle.uot_marginals(x, mu, y, nu, stages[-1], b, g)
     assert rel(P, mu * np.exp(-b / eta)) < 1e-8
 
