@@ -147,6 +147,38 @@ def extra_rows(fu, torch, dev, synth, keep):
     keep["uot_laplace_d3_n4M"] = ("uot", "cfg4a", 1, f.cpu().numpy(), g.cpu().numpy())
     log("4M Laplace: %.1f sweeps/s (%d sweeps incl. plan)" % (it / t, it))
 
+    # lambda-scaling (Section "lambda-scaling": Lambda = {1, 20, 100}, eta = 25, probability
+    # measures): the 2-D mixtures normalised to mass 1, temperatures 1, 0.05, 0.01 against a
+    # solve at 0.01 alone, both to the same stopping rule (largest change <= 1e-4 eps per sweep)
+    w = synth.make("cfg1")
+    a1, b1 = w["a"] / w["a"].sum(dtype=np.float64), w["b"] / w["b"].sum(dtype=np.float64)
+    x, a, y, b = (torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(dev)
+                  for v in (w["x"], a1, w["y"], b1))
+    sc = {}
+    for label, stages, init in (("scaled_zero_start", [1.0, 0.05, 0.01], "zero"),
+                                ("scaled_cstar_start", [1.0, 0.05, 0.01], "cstar"),
+                                ("single_temperature", [0.01], "zero")):
+        (f, g, counts, obj), t = timed(torch, lambda: fu.uot_sinkhorn_scaling(
+            x, a, y, b, stages, 25.0, 6000, 1e-4, init=init, grid=w["grid"], window=w["window"]))
+        sc[label] = {"stages": stages, "sweeps": counts, "total_sweeps": sum(counts),
+                     "ms": 1e3 * t, "objective": obj}
+        log("lambda-scaling %s: sweeps %s, %.1f ms" % (label, counts, 1e3 * t))
+    rows["lambda_scaling_d2_n100k"] = sc
+
+    # upper bound of eq. (561) at the headline workload: r = 2 from moments, r = 1 through one
+    # energy-kernel sum (grid 256, near-field radius 1/16)
+    w = synth.make("cfg2")
+    x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
+    ub = {}
+    for label, opts in (("r2", {"kernel": "gauss"}),
+                        ("r1", {"kernel": "laplace", "grid": 256, "window": 6,
+                                "nearfield_radius": w["nearfield_radius"]})):
+        (c, bound), t = timed(torch, lambda: fu.uot_upper_bound(x, a, y, b, w["eps"], w["rho"],
+                                                                **opts))
+        ub[label] = {"cstar": c, "bound": bound, "ms": 1e3 * t}
+        log("upper bound %s: c* %.6g, bound %.6g, %.2f ms" % (label, c, bound, 1e3 * t))
+    rows["upper_bound_d3_n1M"] = ub
+
     # d = 32 direct Gaussian sum on the MFMA path (BF16 hi/lo Gram tiles), n=m=200k
     w = synth.make("cfg4b")
     x, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "y", "b"))
