@@ -165,6 +165,28 @@ def extra_rows(fu, torch, dev, synth, keep):
         log("lambda-scaling %s: sweeps %s, %.1f ms" % (label, counts, 1e3 * t))
     rows["lambda_scaling_d2_n100k"] = sc
 
+    # Corollary 477 experiment: sd_{1;eta;lambda}(P, P~) of 1-D uniform probability measures
+    # (n = m = 10000) against half the energy MMD^2 of eq. (1205), for growing temperatures and
+    # marginal penalties (300 sweeps per UOT term, grid 256)
+    rng = np.random.default_rng([1450, 10000])
+    xe = torch.from_numpy(rng.uniform(0, 1, (10000, 1)).astype(np.float32)).to(dev)
+    ye = torch.from_numpy(rng.uniform(0, 1, (10000, 1)).astype(np.float32)).to(dev)
+    pe = torch.full((10000,), 1e-4, dtype=torch.float32, device=dev)
+    half = 0.5 * fu.mmd(xe, pe, ye, pe, kernel="energy", grid=256, window=6)
+    conv = {"half_energy_mmd2": half, "sd": {}}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for eps in (1.0, 10.0, 100.0):
+        for eta in (1.0, 100.0, 1e4):
+            sd, _ = fu.sinkhorn_divergence(xe, pe, ye, pe, eps, eta, 300, kernel="laplace",
+                                           grid=256, window=6)
+            conv["sd"]["eps=%g,eta=%g" % (eps, eta)] = {"sd": sd, "ratio_to_half_mmd2": sd / half}
+    torch.cuda.synchronize()
+    conv["ms_all"] = 1e3 * (time.perf_counter() - t0)
+    rows["divergence_to_energy_d1_n10k"] = conv
+    log("sd -> energy: half MMD^2 %.6g, sd(eps=100, eta=1e4) %.6g, %.0f ms for 9 divergences"
+        % (half, conv["sd"]["eps=100,eta=10000"]["sd"], conv["ms_all"]))
+
     # upper bound of eq. (561) at the headline workload: r = 2 from moments, r = 1 through one
     # energy-kernel sum (grid 256, near-field radius 1/16)
     w = synth.make("cfg2")

@@ -348,6 +348,28 @@ def test_sinkhorn_divergence():
 
 # --------------------------------------------------------------------------- MMD
 
+@pytest.mark.parametrize("eps,eta", [(1.0, 1.0), (1.0, 100.0), (10.0, 1e4)])
+def test_divergence_energy_limit_experiment(eps, eta):
+    """The setup of the Corollary 477 experiment (1-D uniform probability measures, r = 1 cost):
+    GPU sd_{1;eta;lambda} and energy MMD^2 against the oracle.  The FP32 kernel sums resolve the
+    UOT terms to ~1e-7 of their size, so sd (a difference of terms) is judged against the largest
+    term."""
+    rng = np.random.default_rng([1450, 7])
+    n = 1500
+    x = rng.uniform(0, 1, (n, 1)).astype(np.float32)
+    y = rng.uniform(0, 1, (n, 1)).astype(np.float32)
+    a = np.full(n, 1.0 / n, np.float32)
+    sd, terms = fu.sinkhorn_divergence(T(x), T(a), T(y), T(a), eps, eta, 300, kernel="laplace",
+                                       grid=256, window=6)
+    sdr, tr = oracle.sinkhorn_divergence(x, a, y, a, eps, eta, 300, r=1)
+    scale = max(abs(t) for t in tr)
+    print("sd GPU %.9g oracle %.9g (terms up to %.3g)" % (sd, sdr, scale))
+    assert abs(sd - sdr) < TOL * scale
+    m2 = fu.mmd(T(x), T(a), T(y), T(a), kernel="energy", grid=256, window=6)
+    m2r, mt = oracle.mmd2(x, a, y, a, "energy", 1.0)
+    assert abs(m2 - m2r) < TOL * max(abs(t) for t in mt)
+
+
 @pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.02, 0), ("gauss", 0.02, 64),
                                            ("laplace", 0.05, 128), ("energy", 1.0, 256),
                                            ("energy", 1.0, 0), ("imq", 0.1, 128), ("imq", 0.1, 0)])

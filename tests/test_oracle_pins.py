@@ -416,6 +416,23 @@ def test_uot_envelope_gradient_vs_central_differences(r):
     assert abs(fd - dnu[4]) < 1e-7 * (1 + abs(fd))
 
 
+def test_divergence_tends_to_half_energy_mmd():
+    """Corollary 477: for probability measures, sd_{1;eta;lambda} tends to the energy distance as
+    lambda -> 0 (eps -> inf) after eta -> inf.  With eq. (1205) for MMD^2 (signed, k = -|.|) the
+    limit is MMD^2 / 2: the plan tends to P x P~, so each UOT term tends to <P x P~, d>.  The ratio
+    approaches 1 as eps grows at large eta."""
+    rng = np.random.default_rng(1450)
+    n = 120
+    x, y = rng.uniform(0, 1, (n, 1)), rng.uniform(0, 1, (n, 1))
+    a = b = np.full(n, 1.0 / n)
+    half = 0.5 * oracle.mmd2(x, a, y, b, "energy", 1.0)[0]
+    errs = []
+    for eps in (10.0, 100.0, 1000.0):
+        sd, _ = oracle.sinkhorn_divergence(x, a, y, b, eps, 1e4, 300, r=1)
+        errs.append(abs(sd / half - 1.0))
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-3
+
+
 # --------------------------------------------------------------------------- MMD
 
 @pytest.mark.parametrize("kind", ["gauss", "laplace", "energy", "imq"])
