@@ -14,6 +14,7 @@ struct Nodes {
     DevBuf<int4> chunks;    // (tile, first node, node count, 0)
     int nchunks = 0;
     DevBuf<int> tile_chunk;  // per tile: [first chunk, chunk count]
+    int max_tile_chunks = 0;
     // near-field cell list (sources only): cell-sorted index -> tile-sorted position
     DevBuf<int> nf_cell_start;  // ncells + 1
     DevBuf<int> nf_order;       // cell-sorted k -> tile-sorted position

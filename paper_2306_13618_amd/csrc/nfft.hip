@@ -715,16 +715,40 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
 }
 
-// Sum the boxes of all chunks of a tile into the tile's first chunk box (fixed chunk order).
-__global__ void k_reduce_chunks(float *__restrict__ scratch, const int *__restrict__ tile_chunk,
-                                int ntiles, int box) {
+// Sum the boxes of all chunks of a tile into the tile's first chunk box (fixed order).  A block
+// takes 64 consecutive box elements of one tile; its blockDim.x / 64 waves split the tile's other
+// chunks (wave w sums chunks 1 + w, 1 + w + nw, ..., four loads in flight) and the wave sums are
+// added in wave order.
+__global__ void __launch_bounds__(256) k_reduce_chunks(float *__restrict__ scratch,
+                                                       const int *__restrict__ tile_chunk,
+                                                       int ntiles, int box) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int t = blockIdx.y; t < ntiles; t += gridDim.y) {
         const int c0 = tile_chunk[2 * t], nc = tile_chunk[2 * t + 1];
         if (nc <= 1) continue;
-        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < box; e += gridDim.x * blockDim.x) {
-            float acc = scratch[(int64_t)c0 * box + e];
-            for (int c = 1; c < nc; ++c) acc += scratch[(int64_t)(c0 + c) * box + e];
-            scratch[(int64_t)c0 * box + e] = acc;
+        for (int e0 = blockIdx.x * 64; e0 < box; e0 += gridDim.x * 64) {
+            const int e = e0 + lane;
+            float acc = 0.0f;
+            if (e < box) {
+                const float *base = scratch + (int64_t)c0 * box + e;
+                int c = 1 + wv;
+                for (; c + 3 * nw < nc; c += 4 * nw) {
+                    const float v0 = base[(int64_t)c * box], v1 = base[(int64_t)(c + nw) * box];
+                    const float v2 = base[(int64_t)(c + 2 * nw) * box];
+                    const float v3 = base[(int64_t)(c + 3 * nw) * box];
+                    acc += (v0 + v1) + (v2 + v3);
+                }
+                for (; c < nc; c += nw) acc += base[(int64_t)c * box];
+            }
+            part[wv][lane] = acc;
+            __syncthreads();
+            if (wv == 0 && e < box) {
+                float s = scratch[(int64_t)c0 * box + e];
+                for (int k = 0; k < nw; ++k) s += part[k][lane];
+                scratch[(int64_t)c0 * box + e] = s;
+            }
+            __syncthreads();
         }
     }
 }
@@ -1255,7 +1279,7 @@ struct Rec4 {
     float4 r[4];
 };
 
-// One wave per target block: each lane holds one target; the sources of the stencil rows around
+// One wave per target block (and source split): each lane holds one target; the sources of the stencil rows around
 // the block (cell side h >= radius / R, rows and cells whose distance to the block's cells is at
 // least the radius are skipped) are read as wave-uniform records, so they arrive through scalar
 // loads and feed every lane without LDS traffic.  NP = number of inner polynomial coefficients
@@ -1296,11 +1320,13 @@ __global__ void __launch_bounds__(64) k_nearfield(const int4 *__restrict__ block
             const int s0 = s_start[row + max(cxl - A, 0)];
             const int s1 = s_start[row + min(cxh + A, na.dims[0] - 1) + 1];
             // groups of four records (one 64-byte scalar load); the next group is requested
-            // as soon as the current one has arrived
-            Rec4 cur = *reinterpret_cast<const Rec4 *>(src + s0);
-            for (int k = s0; k < s1; k += 4) {
+            // as soon as the current one has arrived.  With a source split (gridDim.y > 1) this
+            // wave takes every gridDim.y-th group.
+            const int k0 = s0 + 4 * (int)blockIdx.y, kstep = 4 * (int)gridDim.y;
+            Rec4 cur = *reinterpret_cast<const Rec4 *>(src + min(k0, s1));
+            for (int k = k0; k < s1; k += kstep) {
                 __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): cur has arrived
-                const Rec4 nxt = *reinterpret_cast<const Rec4 *>(src + min(k + 4, s1));
+                const Rec4 nxt = *reinterpret_cast<const Rec4 *>(src + min(k + kstep, s1));
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const float4 sv = cur.r[u];
@@ -1358,9 +1384,15 @@ __global__ void __launch_bounds__(64) k_nearfield(const int4 *__restrict__ block
     }
     if (active) {
         const int o = t_order[t];
-        out[o] += acc;
-        if (GRAD)
-            for (int c = 0; c < D; ++c) gout[(int64_t)o * D + c] += g[c];
+        if (gridDim.y == 1) {
+            out[o] += acc;
+            if (GRAD)
+                for (int c = 0; c < D; ++c) gout[(int64_t)o * D + c] += g[c];
+        } else {
+            atomicAdd(&out[o], acc);
+            if (GRAD)
+                for (int c = 0; c < D; ++c) atomicAdd(&gout[(int64_t)o * D + c], g[c]);
+        }
     }
 }
 
@@ -1469,9 +1501,14 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
         FS_LAUNCHED();
     }
     int tot[2] = {0, 0};
+    std::vector<int> tch(2 * ntiles);
     FS_HIP(hipMemcpyAsync(tot, totals.p, sizeof(tot), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(tch.data(), nd.tile_chunk.p, 2 * ntiles * sizeof(int),
+                          hipMemcpyDeviceToHost, s));
     FS_HIP(hipStreamSynchronize(s));
     nd.nchunks = tot[1];
+    nd.max_tile_chunks = 0;
+    for (int64_t t = 0; t < ntiles; ++t) nd.max_tile_chunks = std::max(nd.max_tile_chunks, tch[2 * t + 1]);
     nd.chunks.alloc(nd.nchunks + 1);
     if (nd.nchunks > 0) {
         hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
@@ -1572,7 +1609,7 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
                    pp.kind == FS_IMQ, FS_EINVAL, "unknown kernel %d", pp.kind);
     FS_REQUIRE(pp.kind == FS_ENERGY || (pp.lambda > 0 && std::isfinite(pp.lambda)), FS_EINVAL,
                "lambda must be positive");
-    pp.T = (d == 3) ? 8 : (d == 2 ? 32 : 256);
+    pp.T = (d == 3) ? 8 : 32;
     if (pp.T > pp.G) pp.T = pp.G;
     const int64_t nmax = std::max(n, m);
     // chunk size: about 1000 chunks over the point set (four per CU), 64..2048 nodes
@@ -1841,10 +1878,14 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
             for (int k = 0; k < D; ++k) ntiles *= ntd;
             int box = 1;
             for (int k = 0; k < D; ++k) box *= S;
-            hipLaunchKernelGGL(k_reduce_chunks,
-                               dim3((box + 255) / 256, (unsigned)std::min<int64_t>(ntiles, 65535)),
-                               dim3(256), 0, s, pl.scratch.p, src.tile_chunk.p, (int)ntiles, box);
-            FS_LAUNCHED();
+            if (src.max_tile_chunks > 1) {
+                const int waves = std::min(4, src.max_tile_chunks - 1);
+                hipLaunchKernelGGL(k_reduce_chunks,
+                                   dim3((box + 63) / 64, (unsigned)std::min<int64_t>(ntiles, 65535)),
+                                   dim3(64 * waves), 0, s, pl.scratch.p, src.tile_chunk.p,
+                                   (int)ntiles, box);
+                FS_LAUNCHED();
+            }
             if (ntd >= 3 && S <= pp.G && pp.m <= T) {
                 hipLaunchKernelGGL(k_fold_tiles<D>, dim3((unsigned)ntiles), dim3(256), 0, s,
                                    pl.scratch.p, src.tile_chunk.p, pp.G, T, ntd, pp.m, S,
@@ -2004,7 +2045,10 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
                            pl.nf_src.p);
         FS_LAUNCHED();
         const int np = (pp.p <= 4) ? 4 : (pp.p <= 8) ? 8 : (pp.p <= 12) ? 12 : 16;
-        const dim3 g((unsigned)dst.nf_nblocks), b(64);
+        // few target blocks (small or low-dimensional sets): split every block's sources over
+        // several waves so that the launch still fills the chip
+        const int split = (int)std::min<int64_t>(64, std::max<int64_t>(1, (8192 + dst.nf_nblocks - 1) / dst.nf_nblocks));
+        const dim3 g((unsigned)dst.nf_nblocks, (unsigned)split), b(64);
 #define FS_NF(DD, KK, NN, GG)                                                                    \
     hipLaunchKernelGGL((k_nearfield<DD, KK, NN, GG>), g, b, 0, s, dst.nf_blocks.p, dst.nf_xs.p, \
                        dst.nf_order.p, src.nf_cell_start.p, pl.nf_src.p, na, pp.nf_R, rr,     \
