@@ -14,7 +14,10 @@ struct Nodes {
     DevBuf<int4> chunks;    // (tile, first node, node count, 0)
     int nchunks = 0;
     DevBuf<int> tile_chunk;  // per tile: [first chunk, chunk count]
-    int max_tile_chunks = 0;
+    DevBuf<int> multi_tiles;  // tiles holding more than one chunk
+    int n_multi = 0;
+    DevBuf<int> touched_tiles;  // tiles with a chunk in their 3^d neighbourhood
+    int n_touched = 0;
     // near-field cell list (sources only): cell-sorted index -> tile-sorted position
     DevBuf<int> nf_cell_start;  // ncells + 1
     DevBuf<int> nf_order;       // cell-sorted k -> tile-sorted position

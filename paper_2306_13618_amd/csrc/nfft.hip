@@ -715,56 +715,71 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
 }
 
-// Sum the boxes of all chunks of a tile into the tile's first chunk box (fixed order).  A block
-// takes 64 consecutive box elements of one tile; its blockDim.x / 64 waves split the tile's other
-// chunks (wave w sums chunks 1 + w, 1 + w + nw, ..., four loads in flight) and the wave sums are
-// added in wave order.
-__global__ void __launch_bounds__(256) k_reduce_chunks(float *__restrict__ scratch,
-                                                       const int *__restrict__ tile_chunk,
-                                                       int ntiles, int box) {
-    __shared__ float part[4][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int t = blockIdx.y; t < ntiles; t += gridDim.y) {
+// Sum the boxes of all chunks of a tile into the tile's first chunk box (fixed chunk order), one
+// thread per box element; `tiles` lists the ntiles tiles that hold more than one chunk.
+__global__ void k_reduce_chunks(float *__restrict__ scratch, const int *__restrict__ tile_chunk,
+                                const int *__restrict__ tiles, int ntiles, int box) {
+    for (int ti = blockIdx.y; ti < ntiles; ti += gridDim.y) {
+        const int t = tiles[ti];
         const int c0 = tile_chunk[2 * t], nc = tile_chunk[2 * t + 1];
-        if (nc <= 1) continue;
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < box; e += gridDim.x * blockDim.x) {
+            float acc = scratch[(int64_t)c0 * box + e];
+            for (int c = 1; c < nc; ++c) acc += scratch[(int64_t)(c0 + c) * box + e];
+            scratch[(int64_t)c0 * box + e] = acc;
+        }
+    }
+}
+
+// The same sum when few tiles hold many chunks (clustered or low-dimensional sets): a block of 256
+// threads takes 64 consecutive box elements of one tile; its 4 waves split the tile's chunks
+// (wave w sums chunks w, w + 4, ..., four loads in flight) and the wave sums are added in order.
+__global__ void __launch_bounds__(256) k_reduce_chunks_split(float *__restrict__ scratch,
+                                                             const int *__restrict__ tile_chunk,
+                                                             const int *__restrict__ tiles,
+                                                             int ntiles, int box) {
+    __shared__ float part[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int ti = blockIdx.y; ti < ntiles; ti += gridDim.y) {
+        const int t = tiles[ti];
+        const int c0 = tile_chunk[2 * t], nc = tile_chunk[2 * t + 1];
         for (int e0 = blockIdx.x * 64; e0 < box; e0 += gridDim.x * 64) {
             const int e = e0 + lane;
             float acc = 0.0f;
             if (e < box) {
                 const float *base = scratch + (int64_t)c0 * box + e;
-                int c = 1 + wv;
-                for (; c + 3 * nw < nc; c += 4 * nw) {
-                    const float v0 = base[(int64_t)c * box], v1 = base[(int64_t)(c + nw) * box];
-                    const float v2 = base[(int64_t)(c + 2 * nw) * box];
-                    const float v3 = base[(int64_t)(c + 3 * nw) * box];
+                int c = wv;
+                for (; c + 12 < nc; c += 16) {
+                    const float v0 = base[(int64_t)c * box], v1 = base[(int64_t)(c + 4) * box];
+                    const float v2 = base[(int64_t)(c + 8) * box];
+                    const float v3 = base[(int64_t)(c + 12) * box];
                     acc += (v0 + v1) + (v2 + v3);
                 }
-                for (; c < nc; c += nw) acc += base[(int64_t)c * box];
+                for (; c < nc; c += 4) acc += base[(int64_t)c * box];
             }
             part[wv][lane] = acc;
             __syncthreads();
-            if (wv == 0 && e < box) {
-                float s = scratch[(int64_t)c0 * box + e];
-                for (int k = 0; k < nw; ++k) s += part[k][lane];
-                scratch[(int64_t)c0 * box + e] = s;
-            }
+            if (wv == 0 && e < box)
+                scratch[(int64_t)c0 * box + e] = ((part[0][lane] + part[1][lane]) + part[2][lane]) +
+                                                 part[3][lane];
             __syncthreads();
         }
     }
 }
 
 // Fold for the common case (at least 3 tiles per dimension, boxes narrower than the grid,
-// m <= T), after k_reduce_chunks: one workgroup per tile; the reduced box offsets of the 3^d
+// m <= T), after k_reduce_chunks: blockIdx.x picks a tile of the list, blockIdx.y a group of its
+// points; the reduced box offsets of the 3^d
 // neighbouring tiles sit in LDS and every grid point of the tile sums the boxes that cover it, in
 // a fixed neighbour order.
 template <int D>
 __global__ void __launch_bounds__(256) k_fold_tiles(const float *__restrict__ scratch,
-                                                    const int *__restrict__ tile_chunk, int G,
+                                                    const int *__restrict__ tile_chunk,
+                                                    const int *__restrict__ tiles, int G,
                                                     int T, int ntd, int m, int S,
                                                     float *__restrict__ grid) {
     constexpr int NN = (D == 1) ? 3 : (D == 2 ? 9 : 27);
     __shared__ int nc0[NN], nnc[NN], norg[NN][3];
-    const int t = blockIdx.x;
+    const int t = tiles[blockIdx.x];
     int tc[3] = {0, 0, 0};
     tile_coords<D>(t, ntd, tc);
     if ((int)threadIdx.x < NN) {
@@ -787,7 +802,7 @@ __global__ void __launch_bounds__(256) k_fold_tiles(const float *__restrict__ sc
     int npts = T;
     if (D > 1) npts *= T;
     if (D > 2) npts *= T;
-    for (int q = threadIdx.x; q < npts; q += blockDim.x) {
+    for (int q = blockIdx.y * blockDim.x + threadIdx.x; q < npts; q += gridDim.y * blockDim.x) {
         int p[3] = {0, 0, 0};
         {
             int rem = q;
@@ -1507,8 +1522,39 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                           hipMemcpyDeviceToHost, s));
     FS_HIP(hipStreamSynchronize(s));
     nd.nchunks = tot[1];
-    nd.max_tile_chunks = 0;
-    for (int64_t t = 0; t < ntiles; ++t) nd.max_tile_chunks = std::max(nd.max_tile_chunks, tch[2 * t + 1]);
+    std::vector<int> multi;
+    for (int64_t t = 0; t < ntiles; ++t)
+        if (tch[2 * t + 1] > 1) multi.push_back((int)t);
+    nd.n_multi = (int)multi.size();
+    // tiles whose 3^d neighbourhood (periodic) holds a chunk: the only ones the fold must sum
+    std::vector<int> touched;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int tc[3] = {0, 0, 0};
+        int64_t rem = t;
+        for (int k = 0; k < d; ++k) { tc[k] = (int)(rem % ntd); rem /= ntd; }
+        bool any = false;
+        for (int q = 0; q < (d == 1 ? 3 : d == 2 ? 9 : 27) && !any; ++q) {
+            int r = q;
+            int64_t nb = 0, mul = 1;
+            for (int k = 0; k < d; ++k) {
+                const int tk = ((tc[k] + r % 3 - 1) % ntd + ntd) % ntd;
+                r /= 3;
+                nb += tk * mul;
+                mul *= ntd;
+            }
+            any = tch[2 * nb + 1] > 0;
+        }
+        if (any) touched.push_back((int)t);
+    }
+    nd.n_touched = (int)touched.size();
+    nd.touched_tiles.alloc(std::max<size_t>(touched.size(), 1));
+    if (!touched.empty())
+        FS_HIP(hipMemcpyAsync(nd.touched_tiles.p, touched.data(), touched.size() * sizeof(int),
+                              hipMemcpyHostToDevice, s));
+    nd.multi_tiles.alloc(std::max<size_t>(multi.size(), 1));
+    if (!multi.empty())
+        FS_HIP(hipMemcpyAsync(nd.multi_tiles.p, multi.data(), multi.size() * sizeof(int),
+                              hipMemcpyHostToDevice, s));
     nd.chunks.alloc(nd.nchunks + 1);
     if (nd.nchunks > 0) {
         hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
@@ -1878,18 +1924,31 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
             for (int k = 0; k < D; ++k) ntiles *= ntd;
             int box = 1;
             for (int k = 0; k < D; ++k) box *= S;
-            if (src.max_tile_chunks > 1) {
-                const int waves = std::min(4, src.max_tile_chunks - 1);
-                hipLaunchKernelGGL(k_reduce_chunks,
-                                   dim3((box + 63) / 64, (unsigned)std::min<int64_t>(ntiles, 65535)),
-                                   dim3(64 * waves), 0, s, pl.scratch.p, src.tile_chunk.p,
-                                   (int)ntiles, box);
+            // one thread per element of the boxes to reduce when that fills the chip, else the
+            // chunks are split over four waves per element
+            const unsigned nt = (unsigned)std::min(src.n_multi, 65535);
+            if (src.n_multi > 0 && (int64_t)src.n_multi * box >= 131072) {
+                hipLaunchKernelGGL(k_reduce_chunks, dim3((box + 255) / 256, nt), dim3(256), 0, s,
+                                   pl.scratch.p, src.tile_chunk.p, src.multi_tiles.p,
+                                   src.n_multi, box);
+                FS_LAUNCHED();
+            } else if (src.n_multi > 0) {
+                hipLaunchKernelGGL(k_reduce_chunks_split, dim3((box + 63) / 64, nt), dim3(256), 0,
+                                   s, pl.scratch.p, src.tile_chunk.p, src.multi_tiles.p,
+                                   src.n_multi, box);
                 FS_LAUNCHED();
             }
             if (ntd >= 3 && S <= pp.G && pp.m <= T) {
-                hipLaunchKernelGGL(k_fold_tiles<D>, dim3((unsigned)ntiles), dim3(256), 0, s,
-                                   pl.scratch.p, src.tile_chunk.p, pp.G, T, ntd, pp.m, S,
-                                   pl.grid.p);
+                // tiles with no chunk in their 3^d neighbourhood only need zeros
+                if (src.n_touched < ntiles) fill_f32(pl.grid.p, gsz, 0.0f, s);
+                // the T^d points of a tile are split over blocks of 64 threads
+                int npts = 1;
+                for (int k = 0; k < D; ++k) npts *= T;
+                if (src.n_touched > 0)
+                    hipLaunchKernelGGL(k_fold_tiles<D>,
+                                       dim3((unsigned)src.n_touched, (unsigned)((npts + 63) / 64)),
+                                       dim3(64), 0, s, pl.scratch.p, src.tile_chunk.p,
+                                       src.touched_tiles.p, pp.G, T, ntd, pp.m, S, pl.grid.p);
             } else {
                 hipLaunchKernelGGL(k_fold<D>, dim3(blocks_for(gsz, 256, 1 << 16)), dim3(256), 0, s,
                                    pl.scratch.p, src.tile_chunk.p, pp.G, T, ntd, pp.m, S,
