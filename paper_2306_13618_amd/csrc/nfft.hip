@@ -609,9 +609,9 @@ __global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
 // Wave-cooperative spreading (d = 2, 3).  Nodes are sorted by grid cell inside each tile; every
 // wave takes a contiguous run of its chunk's nodes, one node at a time: lane l < d W evaluates the
 // window value of dimension l / W at offset l % W and stores it in the wave's LDS slot; the lanes
-// own the W^2 (y, x) pairs of the window (ceil(W^2 / 64) passes), read their x and y values and the
-// W z values (broadcast) back, and accumulate alpha phi_x phi_y phi_z for all W z offsets in
-// registers while consecutive nodes share a cell.  When the cell changes the registers are added
+// own the W^2 (y, x) pairs of the window (ceil(W^2 / 64) passes, the last one split over z where
+// that fills it), read their x and y values and the z values back, and accumulate
+// alpha phi_x phi_y phi_z in registers while consecutive nodes share a cell.  When the cell changes the registers are added
 // to the chunk's LDS box with integer atomics (fixed point, see chunk_scale); the 64 addresses of
 // every such atomic instruction are distinct and contiguous.
 template <int D, int W, int T>
@@ -621,8 +621,15 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
                                                      SpreadArgs sa, float *__restrict__ scratch) {
     constexpr int S = T + W - 1;
     constexpr int BOX = (D == 2) ? S * S : S * S * S;
-    constexpr int NP = (W * W + 63) / 64;  // passes over the (y, x) pairs
     constexpr int NZ = (D == 3) ? W : 1;
+    // (y, x) pairs: NF full passes of 64 lanes and R pairs left over.  In 3-D the leftover pass
+    // splits the W z offsets over 64 / R lane groups when that divides evenly (W = 8, 12, 16), so
+    // every lane does W^3 / 64 multiply-adds per node; otherwise the leftover pass masks lanes.
+    constexpr int NF = (W * W) / 64;
+    constexpr int R = W * W - 64 * NF;
+    constexpr bool SPLITZ = (D == 3) && R > 0 && (64 % R == 0) && (W % (64 / R) == 0);
+    constexpr int ZL = SPLITZ ? W / (64 / R) : NZ;  // z offsets per lane in the leftover pass
+    constexpr int NP = NF + (R > 0 ? 1 : 0);        // passes
     __shared__ int box[BOX];
     __shared__ float red[16];
     __shared__ __align__(16) float wslot[4][3 * 16 + 4];  // per wave: window values of one node
@@ -632,18 +639,18 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const float scale = chunk_scale(w, ch.y, ch.z, red);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const float mm1 = (float)(sa.m - 1);
     int poff[NP];
     int pa[NP], pb[NP];
     bool pv[NP];
 #pragma unroll
     for (int P = 0; P < NP; ++P) {
-        const int q = P * 64 + lane;
+        const int q = (SPLITZ && P == NF) ? NF * 64 + lane % R : P * 64 + lane;
         pv[P] = q < W * W;
         pb[P] = pv[P] ? q / W : 0;
         pa[P] = pv[P] ? q % W : 0;
         poff[P] = pb[P] * S + pa[P];
     }
+    const int zoff = SPLITZ ? (lane / R) * ZL : 0;  // first z offset of this lane's leftover pass
     const int wdim = (lane < D * W) ? lane / W : 0;
     const int woff = lane % W;
     float wc[WPOLY];
@@ -665,10 +672,11 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
         const int oz = (D == 3) ? c[2] - tc[2] * T : 0;
         const int base = oy * S + ox;
 #pragma unroll
-        for (int l = 0; l < NZ; ++l) {
-            const int zb = (D == 3 ? (oz + l) * S * S : 0) + base;
+        for (int P = 0; P < NP; ++P) {
+            const bool part = SPLITZ && P == NF;
 #pragma unroll
-            for (int P = 0; P < NP; ++P) {
+            for (int l = 0; l < (part ? ZL : NZ); ++l) {
+                const int zb = (D == 3 ? (oz + (part ? zoff : 0) + l) * S * S : 0) + base;
                 if (pv[P]) atomicAdd(&box[zb + poff[P]], __float2int_rn(acc[P][l]));
                 acc[P][l] = 0.0f;
             }
@@ -700,9 +708,17 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
 #pragma unroll
             for (int l = 0; l < NZ; ++l) wz[l] = slot[2 * W + l];
 #pragma unroll
-            for (int l = 0; l < NZ; ++l)
+            for (int P = 0; P < NF; ++P)
 #pragma unroll
-                for (int P = 0; P < NP; ++P) acc[P][l] = fmaf(wz[l], wxy[P], acc[P][l]);
+                for (int l = 0; l < NZ; ++l) acc[P][l] = fmaf(wz[l], wxy[P], acc[P][l]);
+            if constexpr (SPLITZ) {
+#pragma unroll
+                for (int l = 0; l < ZL; ++l)
+                    acc[NF][l] = fmaf(slot[2 * W + zoff + l], wxy[NF], acc[NF][l]);
+            } else if constexpr (NP > NF) {
+#pragma unroll
+                for (int l = 0; l < NZ; ++l) acc[NF][l] = fmaf(wz[l], wxy[NF], acc[NF][l]);
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
