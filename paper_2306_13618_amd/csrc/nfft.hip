@@ -285,6 +285,7 @@ struct ScaleArgs {
     double c[3];
     double inv_P;
     int G, T, ntd, d;
+    int S;  // box side T + W - 1
 };
 
 // Sort key of a node: its tile, and (when the key space is small enough) its cell inside the
@@ -311,8 +312,9 @@ __global__ void k_keys(const float *__restrict__ p, int64_t n, ScaleArgs sa, int
         tk = tk * sa.ntd + cell[k] / sa.T;
         loc = loc * sa.T + cell[k] % sa.T;
     }
+    // the cell as a linear offset inside its tile's box: (oz S + oy) S + ox, o = cell - tile T
     int packed = 0;
-    for (int k = sa.d - 1; k >= 0; --k) packed = packed * sa.G + cell[k];
+    for (int k = sa.d - 1; k >= 0; --k) packed = packed * sa.S + cell[k] % sa.T;
     int cells_per_tile = 1;
     for (int k = 0; k < sa.d; ++k) cells_per_tile *= sa.T;
     const int kk = cell_keys ? tk * cells_per_tile + loc : tk;
@@ -541,13 +543,6 @@ struct SpreadArgs {
 };
 
 template <int D>
-__device__ __forceinline__ void unpack_cell(int packed, int G, int *c) {
-    c[0] = packed % G;
-    if (D > 1) c[1] = (packed / G) % G;
-    if (D > 2) c[2] = packed / (G * G);
-}
-
-template <int D>
 __device__ __forceinline__ void tile_coords(int tile, int ntd, int *t) {
     t[0] = tile % ntd;
     if (D > 1) t[1] = (tile / ntd) % ntd;
@@ -580,8 +575,6 @@ __global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
     __shared__ int box[BOX];
     __shared__ float red[4];
     const int4 ch = chunks[blockIdx.x];
-    int tc[3] = {0, 0, 0};
-    tile_coords<D>(ch.x, sa.ntd, tc);
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const float scale = chunk_scale(w, ch.y, ch.z, red);
     const int lane = threadIdx.x & 63;
@@ -589,15 +582,14 @@ __global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
     const float mm1 = (float)(sa.m - 1);
     for (int k = ch.y + threadIdx.x; k < ch.y + ch.z; k += blockDim.x) {
         const float4 r = rec[k];
-        int c[3] = {0, 0, 0};
-        unpack_cell<D>(__float_as_int(r.w), sa.G, c);
+        const int lb = __float_as_int(r.w);  // cell offset inside the tile's box
         const float alpha = w[k] * scale;
 #pragma unroll
         for (int i = 0; i < W; ++i) {
             int a = i + ra;
             a = (a >= W) ? a - W : a;
             const float v = alpha * wpoly_eval(sa.wp + a * WPOLY, 2.0f * r.x - 1.0f);
-            atomicAdd(&box[c[0] - tc[0] * T + a], __float2int_rn(v));
+            atomicAdd(&box[lb + a], __float2int_rn(v));
         }
     }
     __syncthreads();
@@ -634,8 +626,6 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     __shared__ float red[16];
     __shared__ __align__(16) float wslot[4][3 * 16 + 4];  // per wave: window values of one node
     const int4 ch = chunks[blockIdx.x];
-    int tc[3] = {0, 0, 0};
-    tile_coords<D>(ch.x, sa.ntd, tc);
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const float scale = chunk_scale(w, ch.y, ch.z, red);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
@@ -664,32 +654,40 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
     for (int P = 0; P < NP; ++P)
 #pragma unroll
         for (int l = 0; l < NZ; ++l) acc[P][l] = 0.0f;
+    // the record's .w is the cell's linear offset inside the tile's box
     int cur = -1;
-    auto flush = [&](int packed) {
-        int c[3] = {0, 0, 0};
-        unpack_cell<D>(packed, sa.G, c);
-        const int ox = c[0] - tc[0] * T, oy = c[1] - tc[1] * T;
-        const int oz = (D == 3) ? c[2] - tc[2] * T : 0;
-        const int base = oy * S + ox;
+    auto flush = [&](int lb) {
 #pragma unroll
         for (int P = 0; P < NP; ++P) {
             const bool part = SPLITZ && P == NF;
+            const int b0 = lb + poff[P] + (part ? zoff * S * S : 0);
 #pragma unroll
-            for (int l = 0; l < (part ? ZL : NZ); ++l) {
-                const int zb = (D == 3 ? (oz + (part ? zoff : 0) + l) * S * S : 0) + base;
-                if (pv[P]) atomicAdd(&box[zb + poff[P]], __float2int_rn(acc[P][l]));
-                acc[P][l] = 0.0f;
-            }
+            for (int l = 0; l < (part ? ZL : NZ); ++l)
+                if (pv[P]) atomicAdd(&box[b0 + (D == 3 ? l * S * S : 0)], __float2int_rn(acc[P][l]));
         }
     };
+    // the next node's record and weight are requested while this node is processed
+    float4 rn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float wn = 0.0f;
+    if (k0 < k1) {
+        rn = rec[k0];
+        wn = w[k0];
+    }
     for (int k = k0; k < k1; ++k) {
-        const float4 r = rec[k];
+        const float4 r = rn;
+        const float wk = wn;
+        if (k + 1 < k1) {
+            rn = rec[k + 1];
+            wn = w[k + 1];
+        }
         const int packed = __float_as_int(r.w);
-        if (packed != cur) {
+        // a new cell: the registers go to the box and restart from this node's products
+        const bool first = packed != cur;
+        if (first) {
             if (cur >= 0) flush(cur);
             cur = packed;
         }
-        const float alpha = w[k] * scale;
+        const float alpha = wk * scale;
         const float fr = (wdim == 0) ? r.x : (wdim == 1 ? r.y : r.z);
         float *slot = wslot[wave];
         if (lane < D * W) slot[lane] = wpoly_eval(wc, 2.0f * fr - 1.0f);
@@ -701,23 +699,38 @@ __global__ void __launch_bounds__(256) k_spread_wave(const float4 *__restrict__ 
 #pragma unroll
         for (int P = 0; P < NP; ++P) wxy[P] = pv[P] ? alpha * slot[pa[P]] * slot[W + pb[P]] : 0.0f;
         if (D == 2) {
+            if (first) {
 #pragma unroll
-            for (int P = 0; P < NP; ++P) acc[P][0] += wxy[P];
+                for (int P = 0; P < NP; ++P) acc[P][0] = wxy[P];
+            } else {
+#pragma unroll
+                for (int P = 0; P < NP; ++P) acc[P][0] += wxy[P];
+            }
         } else {
             float wz[NZ];
 #pragma unroll
             for (int l = 0; l < NZ; ++l) wz[l] = slot[2 * W + l];
+            float wzp[ZL];
 #pragma unroll
-            for (int P = 0; P < NF; ++P)
+            for (int l = 0; l < ZL; ++l) wzp[l] = SPLITZ ? slot[2 * W + zoff + l] : wz[l];
+            if (first) {
 #pragma unroll
-                for (int l = 0; l < NZ; ++l) acc[P][l] = fmaf(wz[l], wxy[P], acc[P][l]);
-            if constexpr (SPLITZ) {
+                for (int P = 0; P < NF; ++P)
 #pragma unroll
-                for (int l = 0; l < ZL; ++l)
-                    acc[NF][l] = fmaf(slot[2 * W + zoff + l], wxy[NF], acc[NF][l]);
-            } else if constexpr (NP > NF) {
+                    for (int l = 0; l < NZ; ++l) acc[P][l] = wz[l] * wxy[P];
+                if constexpr (NP > NF) {
 #pragma unroll
-                for (int l = 0; l < NZ; ++l) acc[NF][l] = fmaf(wz[l], wxy[NF], acc[NF][l]);
+                    for (int l = 0; l < ZL; ++l) acc[NF][l] = wzp[l] * wxy[NF];
+                }
+            } else {
+#pragma unroll
+                for (int P = 0; P < NF; ++P)
+#pragma unroll
+                    for (int l = 0; l < NZ; ++l) acc[P][l] = fmaf(wz[l], wxy[P], acc[P][l]);
+                if constexpr (NP > NF) {
+#pragma unroll
+                    for (int l = 0; l < ZL; ++l) acc[NF][l] = fmaf(wzp[l], wxy[NF], acc[NF][l]);
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1127,11 +1140,8 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
     const int kb = ch.y + (int)blockIdx.y * per, ke = min(ch.y + ch.z, kb + per);
     for (int k = kb + threadIdx.x; k < ke; k += blockDim.x) {
         const float4 r = rec[k];
-        int c[3] = {0, 0, 0};
-        unpack_cell<D>(__float_as_int(r.w), sa.G, c);
+        const int lb = __float_as_int(r.w);  // cell offset inside the tile's box
         const float fr[3] = {r.x, r.y, r.z};
-        int o[3];
-        for (int kk = 0; kk < D; ++kk) o[kk] = c[kk] - tc[kk] * T;
         float wx[W], dwx[W];
         const float ux = 2.0f * fr[0] - 1.0f;
 #pragma unroll
@@ -1143,8 +1153,8 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
         if (D == 1) {
 #pragma unroll
             for (int a = 0; a < W; ++a) {
-                val = fmaf(wx[a], box[o[0] + a], val);
-                if (GRAD) g0 = fmaf(dwx[a], box[o[0] + a], g0);
+                val = fmaf(wx[a], box[lb + a], val);
+                if (GRAD) g0 = fmaf(dwx[a], box[lb + a], g0);
             }
         } else {
             float wy[W], dwy[W];
@@ -1162,12 +1172,12 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
                     const float uz = 2.0f * fr[2] - 1.0f;
                     wz = wpoly_eval(sa.wp + l * WPOLY, uz);
                     if (GRAD) dwz = wpoly_eval(sa.wp + (W + l) * WPOLY, uz);
-                    zb = (o[2] + l) * S * S;
+                    zb = l * S * S;
                 }
                 float pv = 0.0f, pgx = 0.0f, pgy = 0.0f;
 #pragma unroll
                 for (int b = 0; b < W; ++b) {
-                    const float *row = box + zb + (o[1] + b) * S + o[0];
+                    const float *row = box + lb + zb + b * S;
                     float rv = 0.0f, rg = 0.0f;
 #pragma unroll
                     for (int a = 0; a < W; ++a) {
@@ -1509,6 +1519,7 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     sa.T = T;
     sa.ntd = ntd;
     sa.d = d;
+    sa.S = T + pp.W - 1;
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256), 0, s,
                            pts, n, sa, (int)cell_keys, key.p, tmp.p, hist.p);
