@@ -1554,25 +1554,22 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
         if (tch[2 * t + 1] > 1) multi.push_back((int)t);
     nd.n_multi = (int)multi.size();
     // tiles whose 3^d neighbourhood (periodic) holds a chunk: the only ones the fold must sum
-    std::vector<int> touched;
-    for (int64_t t = 0; t < ntiles; ++t) {
-        int tc[3] = {0, 0, 0};
-        int64_t rem = t;
-        for (int k = 0; k < d; ++k) { tc[k] = (int)(rem % ntd); rem /= ntd; }
-        bool any = false;
-        for (int q = 0; q < (d == 1 ? 3 : d == 2 ? 9 : 27) && !any; ++q) {
-            int r = q;
-            int64_t nb = 0, mul = 1;
-            for (int k = 0; k < d; ++k) {
-                const int tk = ((tc[k] + r % 3 - 1) % ntd + ntd) % ntd;
-                r /= 3;
-                nb += tk * mul;
-                mul *= ntd;
-            }
-            any = tch[2 * nb + 1] > 0;
+    // (occupied tiles dilated by one tile along each axis in turn)
+    std::vector<char> occ(ntiles), tmpo(ntiles);
+    for (int64_t t = 0; t < ntiles; ++t) occ[t] = tch[2 * t + 1] > 0;
+    int64_t stride = 1;
+    for (int k = 0; k < d; ++k, stride *= ntd) {
+        for (int64_t t = 0; t < ntiles; ++t) {
+            const int c = (int)((t / stride) % ntd);
+            const int64_t base = t - (int64_t)c * stride;
+            tmpo[t] = occ[t] || occ[base + (int64_t)((c + 1) % ntd) * stride] ||
+                      occ[base + (int64_t)((c + ntd - 1) % ntd) * stride];
         }
-        if (any) touched.push_back((int)t);
+        occ.swap(tmpo);
     }
+    std::vector<int> touched;
+    for (int64_t t = 0; t < ntiles; ++t)
+        if (occ[t]) touched.push_back((int)t);
     nd.n_touched = (int)touched.size();
     nd.touched_tiles.alloc(std::max<size_t>(touched.size(), 1));
     if (!touched.empty())
