@@ -58,7 +58,7 @@ enum {
 
 /* flags */
 #define FS_FLAG_WARM_START 0x1u   /* uot_sinkhorn: f and g hold starting potentials on entry     */
-#define FS_FLAG_FORCE_VALU 0x2u   /* direct path: use the FP32 VALU kernel even where MFMA applies */
+#define FS_FLAG_FORCE_VALU 0x2u   /* use the FP32 VALU kernels even where matrix-core ones apply */
 
 /* Parameters of one kernel sum.  Zero-initialise and set what you need; zeros mean defaults. */
 typedef struct fs_params {
@@ -105,7 +105,9 @@ void fs_profile_reset(void);
  *   x (n x d), y (m x d), v (m), out (n): device, float32.  d in 1..3 for the fast path
  *   (Section "Curse of dimensionality": the method is restricted to d <= 3); any d in 1..128 for
  *   direct summation (grid = 0), where a Gaussian kernel with d a multiple of 16 uses the MFMA
- *   Gram path (BF16 hi/lo split products accumulated in FP32) unless FS_FLAG_FORCE_VALU.
+ *   Gram path (BF16 hi/lo split products accumulated in FP32) unless FS_FLAG_FORCE_VALU.  In
+ *   3-D the fast path interpolates from the grid with FP32 matrix-core products where the nodes
+ *   fill groups of 16 (unless FS_FLAG_FORCE_VALU).
  *   n = 0 or m = 0 is valid (out is zero-filled when m = 0). */
 int fastsum_apply(const float *x, int64_t n, const float *y, int64_t m, int d, const float *v,
                   float *out, const fs_params *p, void *stream);

@@ -24,7 +24,18 @@ struct Nodes {
     DevBuf<float> nf_xs;        // cell-sorted coordinates
     DevBuf<int4> nf_blocks;     // target blocks (<= 64 targets inside one row of cells)
     int nf_nblocks = 0;
+    // matrix-core groups (d = 3): up to 16 consecutive nodes inside one brick of BRICK_X cells
+    // along x (same y and z cell); groups (first node, count, brick offset in the tile's box, 0)
+    // and blocks of groups inside one tile (tile, first group, group count, 0)
+    DevBuf<int4> mgroups, mblocks;
+    int n_mgroups = 0, n_mblocks = 0;
+    DevBuf<int> mtile_block;   // per tile: [first block, block count]
+    DevBuf<int> mmulti_tiles;  // tiles holding more than one block
+    int n_mmulti = 0;
 };
+
+constexpr int BRICK_X = 4;
+constexpr int MIN_GROUPS_PER_BLOCK = 4;  // one per wave
 
 enum Regime { REGIME_CUBE = 0, REGIME_BALL = 1 };
 

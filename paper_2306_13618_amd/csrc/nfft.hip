@@ -447,6 +447,43 @@ __global__ void k_fill_chunks(int ntiles, const int *__restrict__ tile_start,
     for (int c = 0; c < nc; ++c) chunks[c0 + c] = make_int4(t, s + c * chunk, min(chunk, cnt - c * chunk), 0);
 }
 
+// Matrix-core groups (d = 3, nodes ordered by tile and cell, x fastest): a brick is BRICK_X
+// consecutive cell keys (cells along x with the same y and z), so its nodes are contiguous; each
+// brick is cut into groups of up to 16 nodes.
+__global__ void k_brick_groups(const int *__restrict__ key_start, int64_t nbricks, int total,
+                               int *__restrict__ gcount) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nbricks) return;
+    const int s0 = key_start[b * BRICK_X];
+    const int s1 = (b + 1 < nbricks) ? key_start[(b + 1) * BRICK_X] : total;
+    gcount[b] = (s1 - s0 + 15) / 16;
+}
+
+// Sum of `per` consecutive entries per tile.
+__global__ void k_tile_sum(const int *__restrict__ in, int ntiles, int per, int *__restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int acc = 0;
+    for (int i = 0; i < per; ++i) acc += in[(int64_t)t * per + i];
+    out[t] = acc;
+}
+
+// groups[gstart[b] + j] = (first node, node count, brick offset inside the tile's box, 0)
+__global__ void k_fill_groups(const int *__restrict__ key_start, const int *__restrict__ gstart,
+                              int64_t nbricks, int total, int T, int S, int4 *__restrict__ groups) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= nbricks) return;
+    const int s0 = key_start[b * BRICK_X];
+    const int s1 = (b + 1 < nbricks) ? key_start[(b + 1) * BRICK_X] : total;
+    const int cnt = s1 - s0, g0 = gstart[b];
+    const int bpr = T / BRICK_X;  // bricks per tile row
+    const int lb = (int)(b % ((int64_t)bpr * T * T));
+    const int bx = lb % bpr, by = (lb / bpr) % T, bz = lb / (bpr * T);
+    const int off = (bz * S + by) * S + bx * BRICK_X;
+    for (int j = 0; 16 * j < cnt; ++j)
+        groups[g0 + j] = make_int4(s0 + 16 * j, min(16, cnt - 16 * j), off, 0);
+}
+
 // ------------------------------------------------------------------ kernel coefficients b_k
 struct RegArgs {
     int kind, regime, p;
@@ -1208,6 +1245,262 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
     }
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 3-D spreading on the matrix cores, the transpose of the gather below.  For the nodes of one
+// brick (BRICK_X cells along x with the same y and z cell), with alpha the weights and px, py, pz
+// the window values,
+//   H[x][(y, z)] += sum_n (alpha_n px_n[x - ox_n]) (py_n[y] pz_n[z]),
+// a 16 x (W x W) product over the nodes, 4 nodes per step of v_mfma_f32_16x16x4f32: lane l
+// supplies alpha px for box column l % 16 of node 4 s + l / 16 (operand A) and py pz of that node
+// at column l % 16 of each 4 x 4 block of (y, z) (operand B), and holds the sums for columns
+// 4 (l / 16) + r, r < 4, of that block.  The sums stay in registers while the brick stays the
+// same and then go to the chunk's LDS box with integer atomics (fixed point, see chunk_scale).
+template <int W>
+__global__ void __launch_bounds__(256) k_spread_mfma(const float4 *__restrict__ rec,
+                                                     const float *__restrict__ w,
+                                                     const int4 *__restrict__ mblocks,
+                                                     const int4 *__restrict__ mgroups,
+                                                     SpreadArgs sa, float *__restrict__ scratch) {
+    constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
+    constexpr int NZ = (W + 3) / 4;  // (y, z) offsets in blocks of 4
+    constexpr int NB = NZ * NZ;      // 4 x 4 blocks of (y, z)
+    constexpr int XR = W + BRICK_X - 1;  // box columns a brick reaches
+    constexpr int PX = W + 1;            // row stride of the x table (odd: no bank conflicts)
+    static_assert(XR <= 16, "brick and window exceed the 16 matrix rows");
+    __shared__ int box[BOX];
+    __shared__ float phx[4][16 * PX];     // per wave: alpha px, node-major
+    __shared__ float phyz[4][2][W][16];   // per wave: py and pz, offset-major
+    __shared__ int oxs[4][16];
+    __shared__ float red[16];
+    const int4 mb = mblocks[blockIdx.x];
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
+    const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
+    const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
+    const float scale = chunk_scale(w, k0, cnt, red);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = lane & 15, slot = lane >> 4;
+    const int iy = col >> 2, iz = col & 3;
+    float wc[NZ][WPOLY];
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) {
+        const int a = slot + 4 * e;
+#pragma unroll
+        for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
+    }
+    float *px = phx[wave];
+    float(*pyz)[W][16] = phyz[wave];
+    int *ox = oxs[wave];
+    const int per = (mb.z + 3) / 4;
+    const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
+    f32x4 acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    int cur = -1;
+    auto flush = [&]() {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int y = 4 * (j / NZ) + iy, z = 4 * (j % NZ) + iz;
+            if (W % 4 == 0 || (y < W && z < W)) {
+                const int b0 = cur + y * S + z * S * S;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int x = 4 * slot + r;
+                    if (x < XR) atomicAdd(&box[b0 + x], __float2int_rn(acc[j][r]));
+                }
+            }
+            acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    for (int g = gb; g < ge; ++g) {
+        const int4 gr = mgroups[g];
+        const int nn = min(col, gr.y - 1);
+        const float4 r = rec[gr.x + nn];
+        const float alpha = (col < gr.y) ? w[gr.x + nn] * scale : 0.0f;
+        // window values of node `col` at offsets slot + 4 e
+        const float fr[3] = {r.x, r.y, r.z};
+#pragma unroll
+        for (int e = 0; e < NZ; ++e) {
+            const int a = slot + 4 * e;
+            if (W % 4 == 0 || a < W) {
+                px[col * PX + a] = alpha * wpoly_eval(wc[e], 2.0f * fr[0] - 1.0f);
+                pyz[0][a][col] = wpoly_eval(wc[e], 2.0f * fr[1] - 1.0f);
+                pyz[1][a][col] = wpoly_eval(wc[e], 2.0f * fr[2] - 1.0f);
+            }
+        }
+        if (slot == 0) ox[col] = __float_as_int(r.w) % S - gr.z % S;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (gr.z != cur) {
+            if (cur >= 0) flush();
+            cur = gr.z;
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int n = 4 * s4 + slot;
+            const int a = col - ox[n];
+            const float av = (a >= 0 && a < W) ? px[n * PX + (a < 0 ? 0 : (a >= W ? W - 1 : a))] : 0.0f;
+            float py[NZ], pz[NZ];
+#pragma unroll
+            for (int j = 0; j < NZ; ++j) {
+                py[j] = (W % 4 == 0 || 4 * j + iy < W) ? pyz[0][4 * j + iy][n] : 0.0f;
+                pz[j] = (W % 4 == 0 || 4 * j + iz < W) ? pyz[1][4 * j + iz][n] : 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, py[j / NZ] * pz[j % NZ], acc[j], 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (cur >= 0) flush();
+    __syncthreads();
+    const float inv = 1.0f / scale;
+    float *dst = scratch + (int64_t)blockIdx.x * BOX;
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
+}
+
+// 3-D gather on the matrix cores.  A group holds up to 16 nodes of one brick (BRICK_X cells
+// along x with the same y and z cell).  With H the tile's box read from the brick's first cell,
+// px, py, pz a node's window values and ox its cell's x offset inside the brick,
+//   t_n = sum_x px_n[x - ox_n] D[x][n],   D[x][n] = sum_{y,z} H[x][y][z] py_n[y] pz_n[z],
+// x over 16 box columns (ox + W <= 16).  D is a 16 x 16 product over the index k = (y, z),
+// 4 values of k per step of v_mfma_f32_16x16x4f32: lane l supplies H[l % 16][k] (operand A, kept in
+// registers while the brick stays the same) and py_n[y] pz_n[z] for node l % 16 (operand B) at
+// the k of slot l / 16, and receives D[4 (l / 16) + r][l % 16] in register r.  The window values
+// of the group's nodes are evaluated once into the wave's LDS table (lane l takes offsets
+// l / 16 + 4 e of all three axes for node l % 16).
+template <int W>
+__global__ void __launch_bounds__(256) k_gather_mfma(const float4 *__restrict__ rec,
+                                                     const int4 *__restrict__ mblocks,
+                                                     const int4 *__restrict__ mgroups,
+                                                     SpreadArgs sa, const float *__restrict__ grid,
+                                                     float *__restrict__ out) {
+    constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
+    constexpr int NZ = (W + 3) / 4;  // z offsets in slots of 4
+    constexpr int KS = W * NZ;       // matrix steps
+    static_assert(W + BRICK_X - 1 <= 16, "brick and window exceed the 16 matrix rows");
+    // rows beyond the brick's reach read up to 19 - S floats past the box (zero padding)
+    __shared__ float box[BOX + 16];
+    __shared__ float phi[4][3][W][16];
+    const int4 mb = mblocks[blockIdx.x];
+    int tc[3];
+    tile_coords<3>(mb.x, sa.ntd, tc);
+    const int G = sa.G;
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) {
+        const int l0 = q % S, l1 = (q / S) % S, l2 = q / (S * S);
+        const int g0 = (tc[0] * T - (sa.m - 1) + l0 + G) & (G - 1);
+        const int g1 = (tc[1] * T - (sa.m - 1) + l1 + G) & (G - 1);
+        const int g2 = (tc[2] * T - (sa.m - 1) + l2 + G) & (G - 1);
+        box[q] = grid[((int64_t)g2 * G + g1) * G + g0];
+    }
+    if (threadIdx.x < 16) box[BOX + threadIdx.x] = 0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int node = lane & 15, slot = lane >> 4;
+    float wc[NZ][WPOLY];
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) {
+        const int a = slot + 4 * e;
+#pragma unroll
+        for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
+    }
+    float(*ph)[W][16] = phi[wave];
+    const int per = (mb.z + 3) / 4;
+    const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
+    if (gb >= ge) return;
+    // window values of one node into the wave's table (lane: offsets slot + 4 e, all axes)
+    auto eval_phi = [&](const float4 &r) {
+        const float fr[3] = {r.x, r.y, r.z};
+#pragma unroll
+        for (int dim = 0; dim < 3; ++dim) {
+            const float u = 2.0f * fr[dim] - 1.0f;
+#pragma unroll
+            for (int e = 0; e < NZ; ++e) {
+                const int a = slot + 4 * e;
+                if (W % 4 == 0 || a < W) ph[dim][a][node] = wpoly_eval(wc[e], u);
+            }
+        }
+    };
+    // Software pipeline: while the matrix products of group g run, the window values of group
+    // g + 1 are evaluated and the descriptor and records of group g + 2 are requested.  Columns
+    // of lanes beyond a group's count read its last node and are not stored (matrix columns are
+    // independent).
+    int4 gr = mgroups[gb];
+    const int4 gr1 = mgroups[min(gb + 1, ge - 1)];
+    float4 r = rec[gr.x + min(node, gr.y - 1)];
+    int4 grn = gr1;
+    float4 rn = rec[gr1.x + min(node, gr1.y - 1)];
+    eval_phi(r);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int cur = -1;
+    float A[KS];
+    for (int g = gb; g < ge; ++g) {
+        if (gr.z != cur) {
+            cur = gr.z;
+#pragma unroll
+            for (int y = 0; y < W; ++y)
+#pragma unroll
+                for (int j = 0; j < NZ; ++j) {
+                    const int z = 4 * j + slot;
+                    A[y * NZ + j] =
+                        (W % 4 == 0 || z < W) ? box[cur + node + y * S + z * S * S] : 0.0f;
+                }
+        }
+        // operands of group g from the table (read before the table is overwritten)
+        float pz[NZ];
+#pragma unroll
+        for (int j = 0; j < NZ; ++j)
+            pz[j] = (W % 4 == 0 || 4 * j + slot < W) ? ph[2][4 * j + slot][node] : 0.0f;
+        float B[KS];
+#pragma unroll
+        for (int y = 0; y < W; ++y) {
+            const float py = ph[1][y][node];
+#pragma unroll
+            for (int j = 0; j < NZ; ++j) B[y * NZ + j] = py * pz[j];
+        }
+        const int ox = __float_as_int(r.w) % S - cur % S;  // the node's x cell inside the brick
+        float pxs[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int a = 4 * slot + rr - ox;
+            pxs[rr] = (a >= 0 && a < W) ? ph[0][a < 0 ? 0 : (a >= W ? W - 1 : a)][node] : 0.0f;
+        }
+        const int gout = gr.x, gcnt = gr.y;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < KS; k += 2) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[k], B[k], acc0, 0, 0, 0);
+            if (k + 1 < KS) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[k + 1], B[k + 1], acc1, 0, 0, 0);
+        }
+        // group g + 1 into the table, group g + 2 requested
+        gr = grn;
+        r = rn;
+        eval_phi(r);
+        grn = mgroups[min(g + 2, ge - 1)];
+        rn = rec[grn.x + min(node, grn.y - 1)];
+        const f32x4 acc = acc0 + acc1;
+        float part = 0.0f;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) part = fmaf(pxs[rr], acc[rr], part);
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (slot == 0 && node < gcnt) out[gout + node] = part;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // ------------------------------------------------------------------ permutations
 __global__ void k_gather_perm(const int *__restrict__ perm, int64_t n, const float *__restrict__ v,
                               float *__restrict__ vs) {
@@ -1491,6 +1784,110 @@ void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s) {
     FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
 }
 
+// Workgroups of the matrix-core spread and gather that the current device holds at once (compute
+// units x resident workgroups per unit, the smaller of the two kernels), cached per device and
+// window.
+template <int W>
+int mfma_blocks_per_cu() {
+    int a = 0, b = 0;
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma<W>, 256, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma<W>, 256, 0));
+    return std::max(1, std::min(a, b));
+}
+
+int mfma_slots(int W) {
+    static int cache[16][17] = {};
+    int dev = 0;
+    FS_HIP(hipGetDevice(&dev));
+    if (dev < 16 && W <= 16 && cache[dev][W] > 0) return cache[dev][W];
+    int cus = 0, per = 1;
+    FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    switch (W) {
+        case 4: per = mfma_blocks_per_cu<4>(); break;
+        case 6: per = mfma_blocks_per_cu<6>(); break;
+        case 8: per = mfma_blocks_per_cu<8>(); break;
+        case 10: per = mfma_blocks_per_cu<10>(); break;
+        case 12: per = mfma_blocks_per_cu<12>(); break;
+        default: per = 1;
+    }
+    const int slots = std::max(1, cus * per);
+    if (dev < 16 && W <= 16) cache[dev][W] = slots;
+    return slots;
+}
+
+// Matrix-core groups and their blocks from the cell offsets of cell-sorted nodes (d = 3).  The
+// groups of a tile are cut into blocks of equal size, the smallest size for which all blocks fit
+// on the chip at once (`slots` resident workgroups): a second, partly filled round of workgroups
+// would nearly double the pass.
+void build_mgroups(Nodes &nd, const int *kstart, int64_t n, int64_t ntiles, int64_t cells_per_tile,
+                   const PlanParams &pp, int slots, hipStream_t s) {
+    const int64_t nbricks = ntiles * cells_per_tile / BRICK_X;
+    const int bpt = (int)(cells_per_tile / BRICK_X);
+    DevBuf<int> gcount(nbricks + 1), gstart(nbricks + 1), tgroups(ntiles), tgstart(ntiles),
+        totals(2);
+    nd.mtile_block.alloc(2 * ntiles);
+    int *tblock = nd.mtile_block.p;
+    hipLaunchKernelGGL(k_brick_groups, dim3(blocks_for(nbricks, 256)), dim3(256), 0, s, kstart,
+                       nbricks, (int)n, gcount.p);
+    FS_LAUNCHED();
+    exclusive_scan(gcount.p, nbricks, gstart.p, s);
+    hipLaunchKernelGGL(k_tile_sum, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, gcount.p,
+                       (int)ntiles, bpt, tgroups.p);
+    FS_LAUNCHED();
+    std::vector<int> tg(ntiles);
+    FS_HIP(hipMemcpyAsync(tg.data(), tgroups.p, ntiles * sizeof(int), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    int64_t total = 0;
+    int tmax = 0;
+    for (int v : tg) {
+        total += v;
+        tmax = std::max(tmax, v);
+    }
+    auto blocks_at = [&](int g) {
+        int64_t b = 0;
+        for (int v : tg) b += (v + g - 1) / g;
+        return b;
+    };
+    int lo = (int)std::max<int64_t>(MIN_GROUPS_PER_BLOCK, (total + slots - 1) / std::max(slots, 1));
+    int hi = std::max(lo, tmax);
+    while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (blocks_at(mid) <= slots) hi = mid;
+        else lo = mid + 1;
+    }
+    const int gpb = lo;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, tgroups.p, (int)ntiles, gpb,
+                       tgstart.p, tblock, totals.p);
+    FS_LAUNCHED();
+    // at most n / 16 full groups plus one partial group per non-empty brick
+    const int64_t cap = n / 16 + std::min<int64_t>(n, nbricks) + 1;
+    FS_REQUIRE(total <= cap, FS_EINVAL, "group count %lld above its bound", (long long)total);
+    nd.mgroups.alloc(cap);
+    hipLaunchKernelGGL(k_fill_groups, dim3(blocks_for(nbricks, 256)), dim3(256), 0, s, kstart,
+                       gstart.p, nbricks, (int)n, pp.T, pp.T + pp.W - 1, nd.mgroups.p);
+    FS_LAUNCHED();
+    int tot[2] = {0, 0};
+    FS_HIP(hipMemcpyAsync(tot, totals.p, sizeof(tot), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    nd.n_mgroups = tot[0];
+    nd.n_mblocks = tot[1];
+    nd.mblocks.alloc(nd.n_mblocks + 1);
+    if (nd.n_mblocks > 0) {
+        hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
+                           (int)ntiles, tgstart.p, tgroups.p, tblock, gpb, nd.mblocks.p);
+        FS_LAUNCHED();
+    }
+    std::vector<int> multi;
+    for (int64_t t = 0; t < ntiles; ++t)
+        if (tg[t] > gpb) multi.push_back((int)t);
+    nd.n_mmulti = (int)multi.size();
+    nd.mmulti_tiles.alloc(std::max<size_t>(multi.size(), 1));
+    if (!multi.empty())
+        FS_HIP(hipMemcpyAsync(nd.mmulti_tiles.p, multi.data(), multi.size() * sizeof(int),
+                              hipMemcpyHostToDevice, s));
+    FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+}
+
 void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s) {
     nd.n = n;
     const int d = pp.d, G = pp.G, T = pp.T, ntd = G / T;
@@ -1586,6 +1983,9 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                            nd.chunks.p);
         FS_LAUNCHED();
     }
+    nd.n_mgroups = nd.n_mblocks = 0;
+    if (d == 3 && cell_keys && T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 && n > 0)
+        build_mgroups(nd, kstart.p, n, ntiles, cells_per_tile, pp, mfma_slots(pp.W), s);
     FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
 }
 
@@ -1909,7 +2309,8 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
         const int S = pp.T + pp.W - 1;
         int64_t box = 1;
         for (int k = 0; k < d; ++k) box *= S;
-        const int nch = std::max(pl.X.nchunks, pl.same ? 0 : pl.Y.nchunks);
+        const int nch = std::max({pl.X.nchunks, pl.same ? 0 : pl.Y.nchunks, pl.X.n_mblocks,
+                                  pl.same ? 0 : pl.Y.n_mblocks});
         pl.scratch.alloc((int64_t)std::max(nch, 1) * box);
         pl.wbuf.alloc(std::max(n, m) + 1);
         pl.tbuf.alloc(std::max(n, m) + 1);
@@ -1920,6 +2321,14 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
 // ------------------------------------------------------------------ apply
 namespace {
 
+// The matrix-core spread and gather (d = 3) pay per group of up to 16 nodes; the lane-per-node
+// kernels pay per node.  The groups are used when they hold MIN_GROUP_FILL nodes on average.
+constexpr int MIN_GROUP_FILL = 4;
+bool use_mfma(const Plan &pl, const Nodes &nd) {
+    return !(pl.flags & FS_FLAG_FORCE_VALU) && nd.n_mblocks > 0 &&
+           nd.n >= (int64_t)MIN_GROUP_FILL * nd.n_mgroups;
+}
+
 template <int D, int W>
 void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const float *w,
                           float *t, float *grad, hipStream_t s) {
@@ -1928,14 +2337,30 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
     // the tile side shrinks to the grid size for small grids
     auto run = [&](auto tconst) {
         constexpr int T = decltype(tconst)::value;
+        // the spread writes one box per chunk (or per matrix-core block); tile_chunk maps a tile
+        // to its boxes and multi_tiles lists the tiles with several
+        bool mf = false;
+        const int *tile_boxes = src.tile_chunk.p, *multi = src.multi_tiles.p;
+        int n_multi = src.n_multi;
         if (src.nchunks > 0) {
             ProfScope ps("spread", s);
             if constexpr (D == 1) {
                 hipLaunchKernelGGL((k_spread<D, W, T>), dim3(src.nchunks), dim3(256), 0, s,
                                    src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
             } else {
-                hipLaunchKernelGGL((k_spread_wave<D, W, T>), dim3(src.nchunks), dim3(256), 0, s,
-                                   src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
+                if constexpr (D == 3 && W + BRICK_X - 1 <= 16) mf = use_mfma(pl, src);
+                if (mf) {
+                    if constexpr (D == 3 && W + BRICK_X - 1 <= 16)
+                        hipLaunchKernelGGL((k_spread_mfma<W>), dim3(src.n_mblocks), dim3(256), 0,
+                                           s, src.rec.p, w, src.mblocks.p, src.mgroups.p, sa,
+                                           pl.scratch.p);
+                    tile_boxes = src.mtile_block.p;
+                    multi = src.mmulti_tiles.p;
+                    n_multi = src.n_mmulti;
+                } else {
+                    hipLaunchKernelGGL((k_spread_wave<D, W, T>), dim3(src.nchunks), dim3(256), 0,
+                                       s, src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
+                }
             }
             FS_LAUNCHED();
         }
@@ -1950,16 +2375,14 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
             for (int k = 0; k < D; ++k) box *= S;
             // one thread per element of the boxes to reduce when that fills the chip, else the
             // chunks are split over four waves per element
-            const unsigned nt = (unsigned)std::min(src.n_multi, 65535);
-            if (src.n_multi > 0 && (int64_t)src.n_multi * box >= 131072) {
+            const unsigned nt = (unsigned)std::min(n_multi, 65535);
+            if (n_multi > 0 && (int64_t)n_multi * box >= 131072) {
                 hipLaunchKernelGGL(k_reduce_chunks, dim3((box + 255) / 256, nt), dim3(256), 0, s,
-                                   pl.scratch.p, src.tile_chunk.p, src.multi_tiles.p,
-                                   src.n_multi, box);
+                                   pl.scratch.p, tile_boxes, multi, n_multi, box);
                 FS_LAUNCHED();
-            } else if (src.n_multi > 0) {
+            } else if (n_multi > 0) {
                 hipLaunchKernelGGL(k_reduce_chunks_split, dim3((box + 63) / 64, nt), dim3(256), 0,
-                                   s, pl.scratch.p, src.tile_chunk.p, src.multi_tiles.p,
-                                   src.n_multi, box);
+                                   s, pl.scratch.p, tile_boxes, multi, n_multi, box);
                 FS_LAUNCHED();
             }
             if (ntd >= 3 && S <= pp.G && pp.m <= T) {
@@ -1971,12 +2394,11 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 if (src.n_touched > 0)
                     hipLaunchKernelGGL(k_fold_tiles<D>,
                                        dim3((unsigned)src.n_touched, (unsigned)((npts + 63) / 64)),
-                                       dim3(64), 0, s, pl.scratch.p, src.tile_chunk.p,
+                                       dim3(64), 0, s, pl.scratch.p, tile_boxes,
                                        src.touched_tiles.p, pp.G, T, ntd, pp.m, S, pl.grid.p);
             } else {
                 hipLaunchKernelGGL(k_fold<D>, dim3(blocks_for(gsz, 256, 1 << 16)), dim3(256), 0, s,
-                                   pl.scratch.p, src.tile_chunk.p, pp.G, T, ntd, pp.m, S,
-                                   pl.grid.p);
+                                   pl.scratch.p, tile_boxes, pp.G, T, ntd, pp.m, S, pl.grid.p);
             }
             FS_LAUNCHED();
         } else {
@@ -2044,7 +2466,16 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 ProfScope pg("gather", s);
                 const float gscale = (float)(pp.G / pp.P);
                 const unsigned split = (pp.chunk >= 512) ? 2 : 1;
-                if (grad) {
+                bool mf = false;
+                if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
+                    mf = !grad && use_mfma(pl, dst);
+                    if (mf)
+                        hipLaunchKernelGGL((k_gather_mfma<W>), dim3(dst.n_mblocks), dim3(256), 0, s,
+                                           dst.rec.p, dst.mblocks.p, dst.mgroups.p, sa, pl.grid.p, t);
+                }
+                if (mf) {
+                    // launched above
+                } else if (grad) {
                     hipLaunchKernelGGL((k_gather<D, W, T, true>), dim3(dst.nchunks, split), dim3(256),
                                        0, s, dst.rec.p, dst.chunks.p, sa, pl.grid.p, t, grad, gscale);
                 } else {

@@ -110,6 +110,33 @@ def test_fastsum_nearfield_dense_sampled(cfg, kind, n, radius):
     assert relinf(got[rows], ref) < TOL
 
 
+def dense_and_sparse(n, m, seed):
+    """80% of the points in a small cube (hundreds per grid cell), the rest spread over the whole
+    box (a few per brick): full, partial and single-node matrix-core groups."""
+    rng = np.random.default_rng([777, n, m, seed])
+
+    def pts(k):
+        kd = int(0.8 * k)
+        p = np.concatenate([rng.uniform(-0.05, 0.05, (kd, 3)),
+                            rng.uniform(-0.25, 0.25, (k - kd, 3))])
+        return rng.permutation(p).astype(np.float32)
+    return pts(n), pts(m), rng.uniform(0.5, 1.5, m).astype(np.float32)
+
+
+@pytest.mark.parametrize("window,lam", [(6, 0.02), (5, 0.02), (4, 0.02)])
+def test_fastsum_gauss_matrix_core_groups(window, lam):
+    """3-D gather on the matrix cores (groups of up to 16 nodes per brick of 4 cells) against the
+    oracle on sampled rows and against the lane-per-node kernels on every row."""
+    x, y, v = dense_and_sparse(50_000, 47_001, window)
+    args = dict(kernel="gauss", lam=lam, grid=64, window=window)
+    got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
+    valu = fu.fastsum_apply(T(x), T(y), T(v), flags=fu.FLAG_FORCE_VALU, **args).cpu().numpy()
+    rows = synth.sample_rows(len(x), 200, seed=window)
+    ref = oracle.direct_sum_rows(x, rows, y, v, "gauss", lam)
+    assert relinf(got[rows], ref) < TOL
+    assert relinf(got, valu) < 2e-6
+
+
 def test_fastsum_signed_weights_and_wide_gaussian():
     # a Gaussian wider than the data: the plan switches to the boundary-regularised torus
     x, y, v = clouds(2, 1500, 1300, 4)
