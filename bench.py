@@ -30,7 +30,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X published dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0          # MI355X published HBM3E bandwidth
 
 
@@ -329,11 +329,12 @@ def main():
     achieved_tflops = flops_per_launch / (sp * 1e-3) / 1e12
     bytes_per_launch = n * (16 + 4) + 4 * args.grid ** d  # node record + weight, grid written
     traffic = traffic_from_profile(os.path.join(ROOT, "paper_2306_13618_amd", "csrc", "nfft.hip"))
-    roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                "traffic": traffic, "kernel": "k_spread_wave (spreading, adjoint NFFT)",
+    roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS,
+                "traffic": traffic,
+                "kernel": "k_spread_mfma (spreading, adjoint NFFT, FP32 matrix cores)",
                 "work_per_launch": "%d nodes x 2 x %d^%d flops" % (n, W, d)}
-    lds_ops = n * float(W ** d)
+    window_terms = n * float(W ** d)
     hbm = {}
     G = args.grid
     for name, nbytes in (("spread", bytes_per_launch),
@@ -408,7 +409,7 @@ def main():
         "err_sampled_last_halfstep": err_sampled,
         "objective": obj,
         "passes_avg_ms": {k: v["avg_ms"] for k, v in passes.items()},
-        "lds_atomic_ops_per_s_spread": lds_ops / (sp * 1e-3),
+        "window_terms_per_s_spread": window_terms / (sp * 1e-3),
         "hbm": hbm,
         "secondary": secondary,
         "rows": extras,

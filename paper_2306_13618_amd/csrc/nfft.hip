@@ -1257,7 +1257,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // 4 (l / 16) + r, r < 4, of that block.  The sums stay in registers while the brick stays the
 // same and then go to the chunk's LDS box with integer atomics (fixed point, see chunk_scale).
 template <int W>
-__global__ void __launch_bounds__(256) k_spread_mfma(const float4 *__restrict__ rec,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spread_mfma(const float4 *__restrict__ rec,
                                                      const float *__restrict__ w,
                                                      const int4 *__restrict__ mblocks,
                                                      const int4 *__restrict__ mgroups,
