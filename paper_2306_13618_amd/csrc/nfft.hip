@@ -1501,6 +1501,168 @@ __global__ void __launch_bounds__(256) k_gather_mfma(const float4 *__restrict__ 
     }
 }
 
+// 3-D gather on the FP16 matrix cores with split operands.  For the nodes n of one brick
+// (BRICK_X cells along x with the same y and z cell), px, py, pz their window values and ox their
+// cell's x offset inside the brick,
+//   t_n = sum_{y,z} py_n[y] pz_n[z] E_y[z][n],   E_y[z][n] = sum_x H[x][y][z] px_n[x - ox_n],
+// x over 16 box columns from the brick's first cell.  Every factor of E is carried as a pair of
+// FP16 numbers, v = hi + lo (hi = v rounded to FP16, lo = the remainder rounded to FP16, about 22
+// significant bits together), and the four products hi hi, lo hi, hi lo, lo lo are summed in FP32
+// by two v_mfma_f32_16x16x32_f16 per y.  Lane l covers the columns x = 4 (l / 16) .. + 3: its
+// eight K elements are (hi, lo) of H at those columns against (hi, hi) of px in the first product
+// and (lo, lo) in the second.  The box is kept in LDS in the same order (per row of x: groups of
+// four columns, high parts then low parts, 16 bytes), scaled by a power of two so that its largest
+// value is about 2^14 (no FP16 overflow; the lost low bits are below 2^-39 of the largest value).
+// Lane l then holds E_y[4 (l / 16) + r][l % 16] and forms the y, z sums for node l % 16 over its
+// four rows.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int W>
+__global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict__ rec,
+                                                       const int4 *__restrict__ mblocks,
+                                                       const int4 *__restrict__ mgroups,
+                                                       SpreadArgs sa,
+                                                       const float *__restrict__ grid,
+                                                       float *__restrict__ out) {
+    constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
+    constexpr int NC = 5;  // groups of 4 columns per row: x < 20 covers 4 + 16 columns
+    constexpr int NZ = (W + 3) / 4;
+    constexpr int PER = (BOX + 255) / 256;
+    static_assert(W + BRICK_X - 1 <= 16 && S <= 4 * NC, "brick and window exceed the 16 columns");
+    __shared__ __align__(16) _Float16 bx[S * S][NC][8];
+    __shared__ float phi[4][3][W][16];
+    __shared__ float red[4];
+    const int4 mb = mblocks[blockIdx.x];
+    int tc[3];
+    tile_coords<3>(mb.x, sa.ntd, tc);
+    const int G = sa.G;
+    // the tile's box: values and their largest magnitude
+    float v[PER];
+    float mx = 0.0f;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        v[i] = 0.0f;
+        if (q < BOX) {
+            const int l0 = q % S, l1 = (q / S) % S, l2 = q / (S * S);
+            const int g0 = (tc[0] * T - (sa.m - 1) + l0 + G) & (G - 1);
+            const int g1 = (tc[1] * T - (sa.m - 1) + l1 + G) & (G - 1);
+            const int g2 = (tc[2] * T - (sa.m - 1) + l2 + G) & (G - 1);
+            v[i] = grid[((int64_t)g2 * G + g1) * G + g0];
+            mx = fmaxf(mx, fabsf(v[i]));
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    // columns x >= S of every row are zero
+    for (int q = threadIdx.x; q < S * S * (4 * NC - S); q += 256) {
+        const int row = q / (4 * NC - S), x = S + q % (4 * NC - S);
+        bx[row][x >> 2][x & 3] = (_Float16)0.0f;
+        bx[row][x >> 2][4 + (x & 3)] = (_Float16)0.0f;
+    }
+    __syncthreads();
+    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    // power-of-two scale: largest |value| in [2^13, 2^14)
+    int ex = 0;
+    frexpf(mx, &ex);
+    const float scale = (mx > 0.0f) ? ldexpf(1.0f, 14 - ex) : 1.0f;
+    const float unscale = (mx > 0.0f) ? ldexpf(1.0f, ex - 14) : 1.0f;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        if (q < BOX) {
+            const float u = v[i] * scale;
+            const _Float16 h = (_Float16)u;
+            const int row = q / S, x = q % S;
+            bx[row][x >> 2][x & 3] = h;
+            bx[row][x >> 2][4 + (x & 3)] = (_Float16)(u - (float)h);
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int node = lane & 15, slot = lane >> 4;
+    float wc[NZ][WPOLY];
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) {
+        const int a = slot + 4 * e;
+#pragma unroll
+        for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
+    }
+    float(*ph)[W][16] = phi[wave];
+    const int per = (mb.z + 3) / 4;
+    const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
+    if (gb >= ge) return;
+    int4 grn = mgroups[gb];
+    float4 rn = rec[grn.x + min(node, grn.y - 1)];
+    for (int g = gb; g < ge; ++g) {
+        const int4 gr = grn;
+        const float4 r = rn;
+        if (g + 1 < ge) {
+            grn = mgroups[g + 1];
+            rn = rec[grn.x + min(node, grn.y - 1)];
+        }
+        const float fr[3] = {r.x, r.y, r.z};
+#pragma unroll
+        for (int dim = 0; dim < 3; ++dim) {
+            const float u = 2.0f * fr[dim] - 1.0f;
+#pragma unroll
+            for (int e = 0; e < NZ; ++e) {
+                const int a = slot + 4 * e;
+                if (W % 4 == 0 || a < W) ph[dim][a][node] = wpoly_eval(wc[e], u);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cur = gr.z;
+        const int cx0 = cur % S, cy = (cur / S) % S, cz = cur / (S * S);
+        const int ox = __float_as_int(r.w) % S - cx0;  // the node's x cell inside the brick
+        // operand B: px of node `node` at x = 4 slot .. + 3 as (hi, hi) and (lo, lo)
+        f16x8 B1, B2;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int a = 4 * slot + e - ox;
+            const float pv = (a >= 0 && a < W) ? ph[0][a < 0 ? 0 : (a >= W ? W - 1 : a)][node] : 0.0f;
+            const _Float16 h = (_Float16)pv;
+            const _Float16 l = (_Float16)(pv - (float)h);
+            B1[e] = h;
+            B1[4 + e] = h;
+            B2[e] = l;
+            B2[4 + e] = l;
+        }
+        float pz[4], py[W];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int z = 4 * slot + rr;
+            pz[rr] = (z < W) ? ph[2][z < W ? z : W - 1][node] : 0.0f;
+        }
+#pragma unroll
+        for (int y = 0; y < W; ++y) py[y] = ph[1][y][node];
+        // operand A: row z = lane % 16 (rows at or beyond W read row W - 1; their pz is zero)
+        const int zr = node < W ? node : W - 1;
+        const uint4 *arow = reinterpret_cast<const uint4 *>(&bx[(cz + zr) * S + cy][(cx0 >> 2) + slot][0]);
+        float part = 0.0f;
+#pragma unroll
+        for (int y = 0; y < W; ++y) {
+            const f16x8 A = __builtin_bit_cast(f16x8, arow[y * NC]);
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B2, acc, 0, 0, 0);
+            float sy = 0.0f;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) sy = fmaf(pz[rr], acc[rr], sy);
+            part = fmaf(py[y], sy, part);
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (slot == 0 && node < gr.y) out[gr.x + node] = part * unscale;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // ------------------------------------------------------------------ permutations
 __global__ void k_gather_perm(const int *__restrict__ perm, int64_t n, const float *__restrict__ v,
                               float *__restrict__ vs) {
@@ -1790,7 +1952,7 @@ void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s) {
 template <int W>
 int mfma_blocks_per_cu() {
     int a = 0, b = 0;
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma<W>, 256, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W>, 256, 0));
     FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma<W>, 256, 0));
     return std::max(1, std::min(a, b));
 }
@@ -2470,7 +2632,7 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                     mf = !grad && use_mfma(pl, dst);
                     if (mf)
-                        hipLaunchKernelGGL((k_gather_mfma<W>), dim3(dst.n_mblocks), dim3(256), 0, s,
+                        hipLaunchKernelGGL((k_gather_mfma16<W>), dim3(dst.n_mblocks), dim3(256), 0, s,
                                            dst.rec.p, dst.mblocks.p, dst.mgroups.p, sa, pl.grid.p, t);
                 }
                 if (mf) {
