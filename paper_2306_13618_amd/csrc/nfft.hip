@@ -591,7 +591,8 @@ __device__ __forceinline__ void tile_coords(int tile, int ntd, int *t) {
 // scale = 2^30 / (count * max|alpha|) all int32 partial sums stay below 2^30 in magnitude.
 // LDS integer atomics are the fast path on gfx950 (LDS float atomics are far slower), and integer
 // addition makes the accumulation order-independent (bitwise reproducible).
-__device__ float chunk_scale(const float *__restrict__ w, int k0, int cnt, float *red) {
+__device__ float chunk_scale(const float *__restrict__ w, int k0, int cnt, float *red,
+                            float *wmax = nullptr) {
     float mx = 0.0f;
     for (int k = k0 + threadIdx.x; k < k0 + cnt; k += blockDim.x) mx = fmaxf(mx, fabsf(w[k]));
     for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
@@ -599,6 +600,7 @@ __device__ float chunk_scale(const float *__restrict__ w, int k0, int cnt, float
     __syncthreads();
     float m = 0.0f;
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmaxf(m, red[i]);
+    if (wmax) *wmax = m;
     return (m > 0.0f && cnt > 0) ? 1073741824.0f / ((float)cnt * m) : 1.0f;
 }
 
@@ -1246,25 +1248,37 @@ __global__ void __launch_bounds__(256) k_gather(const float4 *__restrict__ rec,
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-// 3-D spreading on the matrix cores, the transpose of the gather below.  For the nodes of one
-// brick (BRICK_X cells along x with the same y and z cell), with alpha the weights and px, py, pz
-// the window values,
+// Two FP32 values as FP16 pairs v = hi + lo: hi = v rounded to FP16, lo = the remainder rounded
+// to FP16 (about 22 significant bits together for values in FP16's normal range).
+__device__ __forceinline__ void split_f16(float a, float b, f16x2 &hi, f16x2 &lo) {
+    hi = __builtin_convertvector(f32x2{a, b}, f16x2);
+    const f32x2 back = __builtin_convertvector(hi, f32x2);
+    lo = __builtin_convertvector(f32x2{a - back.x, b - back.y}, f16x2);
+}
+
+// 3-D spreading on the FP16 matrix cores with split operands, the transpose of the gather
+// below.  For the nodes of one brick, with alpha the weights (divided by the chunk's largest
+// |weight|) and px, py, pz the window values,
 //   H[x][(y, z)] += sum_n (alpha_n px_n[x - ox_n]) (py_n[y] pz_n[z]),
-// a 16 x (W x W) product over the nodes, 4 nodes per step of v_mfma_f32_16x16x4f32: lane l
-// supplies alpha px for box column l % 16 of node 4 s + l / 16 (operand A) and py pz of that node
-// at column l % 16 of each 4 x 4 block of (y, z) (operand B), and holds the sums for columns
-// 4 (l / 16) + r, r < 4, of that block.  The sums stay in registers while the brick stays the
-// same and then go to the chunk's LDS box with integer atomics (fixed point, see chunk_scale).
+// a 16 x (W x W) product over the group's 16 nodes.  Both factors are carried as FP16 pairs
+// (hi + lo) and two v_mfma_f32_16x16x32_f16 per 4 x 4 block of (y, z) sum the four cross products
+// in FP32: lane l covers nodes 4 (l / 16) .. + 3, its K elements being (hi, lo) of alpha px for
+// box column l % 16 against (hi, hi) and then (lo, lo) of py pz at column l % 16 of the block.
+// Lane l holds the sums for columns 4 (l / 16) + r, r < 4; they stay in registers while the brick
+// stays the same and then go to the chunk's LDS box with integer atomics (fixed point, see
+// chunk_scale).
 template <int W>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) k_spread_mfma(const float4 *__restrict__ rec,
-                                                     const float *__restrict__ w,
-                                                     const int4 *__restrict__ mblocks,
-                                                     const int4 *__restrict__ mgroups,
-                                                     SpreadArgs sa, float *__restrict__ scratch) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
+                const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups, SpreadArgs sa,
+                float *__restrict__ scratch) {
     constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
-    constexpr int NZ = (W + 3) / 4;  // (y, z) offsets in blocks of 4
-    constexpr int NB = NZ * NZ;      // 4 x 4 blocks of (y, z)
+    constexpr int NZ = (W + 3) / 4;      // (y, z) offsets in blocks of 4
+    constexpr int NB = NZ * NZ;          // 4 x 4 blocks of (y, z)
     constexpr int XR = W + BRICK_X - 1;  // box columns a brick reaches
     constexpr int PX = W + 1;            // row stride of the x table (odd: no bank conflicts)
     static_assert(XR <= 16, "brick and window exceed the 16 matrix rows");
@@ -1277,7 +1291,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
     const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
-    const float scale = chunk_scale(w, k0, cnt, red);
+    // chunk_scale = 2^30 / (cnt max|w|): the weights enter the products as w / max|w| and the
+    // sums are converted with 2^30 / cnt
+    float wm = 0.0f;
+    const float scale = chunk_scale(w, k0, cnt, red, &wm);
+    const float wmax = (wm > 0.0f) ? wm : 1.0f;
+    const float inv_wmax = 1.0f / wmax, fscale = scale * wmax;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = lane & 15, slot = lane >> 4;
@@ -1307,7 +1326,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int x = 4 * slot + r;
-                    if (x < XR) atomicAdd(&box[b0 + x], __float2int_rn(acc[j][r]));
+                    if (x < XR) atomicAdd(&box[b0 + x], __float2int_rn(acc[j][r] * fscale));
                 }
             }
             acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -1317,7 +1336,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
         const int4 gr = mgroups[g];
         const int nn = min(col, gr.y - 1);
         const float4 r = rec[gr.x + nn];
-        const float alpha = (col < gr.y) ? w[gr.x + nn] * scale : 0.0f;
+        const float alpha = (col < gr.y) ? w[gr.x + nn] * inv_wmax : 0.0f;
         // window values of node `col` at offsets slot + 4 e
         const float fr[3] = {r.x, r.y, r.z};
 #pragma unroll
@@ -1337,20 +1356,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
             if (cur >= 0) flush();
             cur = gr.z;
         }
+        // operand A: alpha px of nodes 4 slot .. + 3 at box column `col`, (hi, lo)
+        float av[4];
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            const int n = 4 * s4 + slot;
+        for (int e = 0; e < 4; ++e) {
+            const int n = 4 * slot + e;
             const int a = col - ox[n];
-            const float av = (a >= 0 && a < W) ? px[n * PX + (a < 0 ? 0 : (a >= W ? W - 1 : a))] : 0.0f;
-            float py[NZ], pz[NZ];
+            av[e] = (a >= 0 && a < W) ? px[n * PX + (a < 0 ? 0 : (a >= W ? W - 1 : a))] : 0.0f;
+        }
+        f16x2 ah0, al0, ah1, al1;
+        split_f16(av[0], av[1], ah0, al0);
+        split_f16(av[2], av[3], ah1, al1);
+        const f16x8 A = {ah0[0], ah0[1], ah1[0], ah1[1], al0[0], al0[1], al1[0], al1[1]};
+        float py[NZ][4], pz[NZ][4];
 #pragma unroll
-            for (int j = 0; j < NZ; ++j) {
-                py[j] = (W % 4 == 0 || 4 * j + iy < W) ? pyz[0][4 * j + iy][n] : 0.0f;
-                pz[j] = (W % 4 == 0 || 4 * j + iz < W) ? pyz[1][4 * j + iz][n] : 0.0f;
+        for (int j = 0; j < NZ; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int n = 4 * slot + e;
+                py[j][e] = (W % 4 == 0 || 4 * j + iy < W) ? pyz[0][4 * j + iy][n] : 0.0f;
+                pz[j][e] = (W % 4 == 0 || 4 * j + iz < W) ? pyz[1][4 * j + iz][n] : 0.0f;
             }
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, py[j / NZ] * pz[j % NZ], acc[j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) {
+            const int jy = j / NZ, jz = j % NZ;
+            f16x2 bh0, bl0, bh1, bl1;
+            split_f16(py[jy][0] * pz[jz][0], py[jy][1] * pz[jz][1], bh0, bl0);
+            split_f16(py[jy][2] * pz[jz][2], py[jy][3] * pz[jz][3], bh1, bl1);
+            const f16x8 B1 = {bh0[0], bh0[1], bh1[0], bh1[1], bh0[0], bh0[1], bh1[0], bh1[1]};
+            const f16x8 B2 = {bl0[0], bl0[1], bl1[0], bl1[1], bl0[0], bl0[1], bl1[0], bl1[1]};
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B2, acc[j], 0, 0, 0);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1361,144 +1397,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))
     const float inv = 1.0f / scale;
     float *dst = scratch + (int64_t)blockIdx.x * BOX;
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
-}
-
-// 3-D gather on the matrix cores.  A group holds up to 16 nodes of one brick (BRICK_X cells
-// along x with the same y and z cell).  With H the tile's box read from the brick's first cell,
-// px, py, pz a node's window values and ox its cell's x offset inside the brick,
-//   t_n = sum_x px_n[x - ox_n] D[x][n],   D[x][n] = sum_{y,z} H[x][y][z] py_n[y] pz_n[z],
-// x over 16 box columns (ox + W <= 16).  D is a 16 x 16 product over the index k = (y, z),
-// 4 values of k per step of v_mfma_f32_16x16x4f32: lane l supplies H[l % 16][k] (operand A, kept in
-// registers while the brick stays the same) and py_n[y] pz_n[z] for node l % 16 (operand B) at
-// the k of slot l / 16, and receives D[4 (l / 16) + r][l % 16] in register r.  The window values
-// of the group's nodes are evaluated once into the wave's LDS table (lane l takes offsets
-// l / 16 + 4 e of all three axes for node l % 16).
-template <int W>
-__global__ void __launch_bounds__(256) k_gather_mfma(const float4 *__restrict__ rec,
-                                                     const int4 *__restrict__ mblocks,
-                                                     const int4 *__restrict__ mgroups,
-                                                     SpreadArgs sa, const float *__restrict__ grid,
-                                                     float *__restrict__ out) {
-    constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
-    constexpr int NZ = (W + 3) / 4;  // z offsets in slots of 4
-    constexpr int KS = W * NZ;       // matrix steps
-    static_assert(W + BRICK_X - 1 <= 16, "brick and window exceed the 16 matrix rows");
-    // rows beyond the brick's reach read up to 19 - S floats past the box (zero padding)
-    __shared__ float box[BOX + 16];
-    __shared__ float phi[4][3][W][16];
-    const int4 mb = mblocks[blockIdx.x];
-    int tc[3];
-    tile_coords<3>(mb.x, sa.ntd, tc);
-    const int G = sa.G;
-    for (int q = threadIdx.x; q < BOX; q += blockDim.x) {
-        const int l0 = q % S, l1 = (q / S) % S, l2 = q / (S * S);
-        const int g0 = (tc[0] * T - (sa.m - 1) + l0 + G) & (G - 1);
-        const int g1 = (tc[1] * T - (sa.m - 1) + l1 + G) & (G - 1);
-        const int g2 = (tc[2] * T - (sa.m - 1) + l2 + G) & (G - 1);
-        box[q] = grid[((int64_t)g2 * G + g1) * G + g0];
-    }
-    if (threadIdx.x < 16) box[BOX + threadIdx.x] = 0.0f;
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int node = lane & 15, slot = lane >> 4;
-    float wc[NZ][WPOLY];
-#pragma unroll
-    for (int e = 0; e < NZ; ++e) {
-        const int a = slot + 4 * e;
-#pragma unroll
-        for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
-    }
-    float(*ph)[W][16] = phi[wave];
-    const int per = (mb.z + 3) / 4;
-    const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
-    if (gb >= ge) return;
-    // window values of one node into the wave's table (lane: offsets slot + 4 e, all axes)
-    auto eval_phi = [&](const float4 &r) {
-        const float fr[3] = {r.x, r.y, r.z};
-#pragma unroll
-        for (int dim = 0; dim < 3; ++dim) {
-            const float u = 2.0f * fr[dim] - 1.0f;
-#pragma unroll
-            for (int e = 0; e < NZ; ++e) {
-                const int a = slot + 4 * e;
-                if (W % 4 == 0 || a < W) ph[dim][a][node] = wpoly_eval(wc[e], u);
-            }
-        }
-    };
-    // Software pipeline: while the matrix products of group g run, the window values of group
-    // g + 1 are evaluated and the descriptor and records of group g + 2 are requested.  Columns
-    // of lanes beyond a group's count read its last node and are not stored (matrix columns are
-    // independent).
-    int4 gr = mgroups[gb];
-    const int4 gr1 = mgroups[min(gb + 1, ge - 1)];
-    float4 r = rec[gr.x + min(node, gr.y - 1)];
-    int4 grn = gr1;
-    float4 rn = rec[gr1.x + min(node, gr1.y - 1)];
-    eval_phi(r);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    int cur = -1;
-    float A[KS];
-    for (int g = gb; g < ge; ++g) {
-        if (gr.z != cur) {
-            cur = gr.z;
-#pragma unroll
-            for (int y = 0; y < W; ++y)
-#pragma unroll
-                for (int j = 0; j < NZ; ++j) {
-                    const int z = 4 * j + slot;
-                    A[y * NZ + j] =
-                        (W % 4 == 0 || z < W) ? box[cur + node + y * S + z * S * S] : 0.0f;
-                }
-        }
-        // operands of group g from the table (read before the table is overwritten)
-        float pz[NZ];
-#pragma unroll
-        for (int j = 0; j < NZ; ++j)
-            pz[j] = (W % 4 == 0 || 4 * j + slot < W) ? ph[2][4 * j + slot][node] : 0.0f;
-        float B[KS];
-#pragma unroll
-        for (int y = 0; y < W; ++y) {
-            const float py = ph[1][y][node];
-#pragma unroll
-            for (int j = 0; j < NZ; ++j) B[y * NZ + j] = py * pz[j];
-        }
-        const int ox = __float_as_int(r.w) % S - cur % S;  // the node's x cell inside the brick
-        float pxs[4];
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int a = 4 * slot + rr - ox;
-            pxs[rr] = (a >= 0 && a < W) ? ph[0][a < 0 ? 0 : (a >= W ? W - 1 : a)][node] : 0.0f;
-        }
-        const int gout = gr.x, gcnt = gr.y;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int k = 0; k < KS; k += 2) {
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[k], B[k], acc0, 0, 0, 0);
-            if (k + 1 < KS) acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(A[k + 1], B[k + 1], acc1, 0, 0, 0);
-        }
-        // group g + 1 into the table, group g + 2 requested
-        gr = grn;
-        r = rn;
-        eval_phi(r);
-        grn = mgroups[min(g + 2, ge - 1)];
-        rn = rec[grn.x + min(node, grn.y - 1)];
-        const f32x4 acc = acc0 + acc1;
-        float part = 0.0f;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) part = fmaf(pxs[rr], acc[rr], part);
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (slot == 0 && node < gcnt) out[gout + node] = part;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
 }
 
 // 3-D gather on the FP16 matrix cores with split operands.  For the nodes n of one brick
@@ -1515,8 +1413,6 @@ __global__ void __launch_bounds__(256) k_gather_mfma(const float4 *__restrict__ 
 // value is about 2^14 (no FP16 overflow; the lost low bits are below 2^-39 of the largest value).
 // Lane l then holds E_y[4 (l / 16) + r][l % 16] and forms the y, z sums for node l % 16 over its
 // four rows.
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
 template <int W>
 __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict__ rec,
                                                        const int4 *__restrict__ mblocks,
@@ -1953,7 +1849,7 @@ template <int W>
 int mfma_blocks_per_cu() {
     int a = 0, b = 0;
     FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W>, 256, 0));
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma<W>, 256, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W>, 256, 0));
     return std::max(1, std::min(a, b));
 }
 
@@ -2513,7 +2409,7 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 if constexpr (D == 3 && W + BRICK_X - 1 <= 16) mf = use_mfma(pl, src);
                 if (mf) {
                     if constexpr (D == 3 && W + BRICK_X - 1 <= 16)
-                        hipLaunchKernelGGL((k_spread_mfma<W>), dim3(src.n_mblocks), dim3(256), 0,
+                        hipLaunchKernelGGL((k_spread_mfma16<W>), dim3(src.n_mblocks), dim3(256), 0,
                                            s, src.rec.p, w, src.mblocks.p, src.mgroups.p, sa,
                                            pl.scratch.p);
                     tile_boxes = src.mtile_block.p;
