@@ -19,9 +19,11 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 CFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Wno-unused-function", "-Wno-unused-variable",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-# MFMA accumulators in ordinary VGPRs: the exponentials read every accumulator element, and the
-# AGPR form would add one copy instruction per element.
-FILE_FLAGS = {"direct_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# MFMA accumulators in ordinary VGPRs: the consumers (the exponentials of the Gram kernel, the
+# window-weighted row sums of the 3-D gather) read every accumulator element, and the AGPR form
+# would add one copy instruction per element.
+FILE_FLAGS = {"direct_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+              "nfft.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src):

@@ -1266,8 +1266,8 @@ __device__ __forceinline__ void split_f16(float a, float b, f16x2 &hi, f16x2 &lo
 //   H[x][(y, z)] += sum_n (alpha_n px_n[x - ox_n]) (py_n[y] pz_n[z]),
 // a 16 x (W x W) product over the group's 16 nodes.  Both factors are carried as FP16 pairs
 // (hi + lo) and two v_mfma_f32_16x16x32_f16 per 4 x 4 block of (y, z) sum the four cross products
-// in FP32: lane l covers nodes 4 (l / 16) .. + 3, its K elements being (hi, lo) of alpha px for
-// box column l % 16 against (hi, hi) and then (lo, lo) of py pz at column l % 16 of the block.
+// in FP32: lane l covers nodes 4 (l / 16) .. + 3, its K elements being (hi, hi) and then (lo, lo)
+// of alpha px for box column l % 16 against (hi, lo) of py pz at column l % 16 of the block.
 // Lane l holds the sums for columns 4 (l / 16) + r, r < 4; they stay in registers while the brick
 // stays the same and then go to the chunk's LDS box with integer atomics (fixed point, see
 // chunk_scale).
@@ -1367,7 +1367,8 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
         f16x2 ah0, al0, ah1, al1;
         split_f16(av[0], av[1], ah0, al0);
         split_f16(av[2], av[3], ah1, al1);
-        const f16x8 A = {ah0[0], ah0[1], ah1[0], ah1[1], al0[0], al0[1], al1[0], al1[1]};
+        const f16x8 A1 = {ah0[0], ah0[1], ah1[0], ah1[1], ah0[0], ah0[1], ah1[0], ah1[1]};
+        const f16x8 A2 = {al0[0], al0[1], al1[0], al1[1], al0[0], al0[1], al1[0], al1[1]};
         float py[NZ][4], pz[NZ][4];
 #pragma unroll
         for (int j = 0; j < NZ; ++j)
@@ -1383,10 +1384,9 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
             f16x2 bh0, bl0, bh1, bl1;
             split_f16(py[jy][0] * pz[jz][0], py[jy][1] * pz[jz][1], bh0, bl0);
             split_f16(py[jy][2] * pz[jz][2], py[jy][3] * pz[jz][3], bh1, bl1);
-            const f16x8 B1 = {bh0[0], bh0[1], bh1[0], bh1[1], bh0[0], bh0[1], bh1[0], bh1[1]};
-            const f16x8 B2 = {bl0[0], bl0[1], bl1[0], bl1[1], bl0[0], bl0[1], bl1[0], bl1[1]};
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B2, acc[j], 0, 0, 0);
+            const f16x8 B = {bh0[0], bh0[1], bh1[0], bh1[1], bl0[0], bl0[1], bl1[0], bl1[1]};
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B, acc[j], 0, 0, 0);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1538,18 +1538,19 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
         // operand A: row z = lane % 16 (rows at or beyond W read row W - 1; their pz is zero)
         const int zr = node < W ? node : W - 1;
         const uint4 *arow = reinterpret_cast<const uint4 *>(&bx[(cz + zr) * S + cy][(cx0 >> 2) + slot][0]);
-        float part = 0.0f;
+        f32x4 ty = {0.0f, 0.0f, 0.0f, 0.0f};  // sum over y of py E_y, per row
 #pragma unroll
         for (int y = 0; y < W; ++y) {
             const f16x8 A = __builtin_bit_cast(f16x8, arow[y * NC]);
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B2, acc, 0, 0, 0);
-            float sy = 0.0f;
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) sy = fmaf(pz[rr], acc[rr], sy);
-            part = fmaf(py[y], sy, part);
+            for (int rr = 0; rr < 4; ++rr) ty[rr] = fmaf(py[y], acc[rr], ty[rr]);
         }
+        float part = 0.0f;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) part = fmaf(pz[rr], ty[rr], part);
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);
         if (slot == 0 && node < gr.y) out[gr.x + node] = part * unscale;
