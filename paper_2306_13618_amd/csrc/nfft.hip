@@ -791,8 +791,17 @@ __global__ void k_reduce_chunks(float *__restrict__ scratch, const int *__restri
         const int t = tiles[ti];
         const int c0 = tile_chunk[2 * t], nc = tile_chunk[2 * t + 1];
         for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < box; e += gridDim.x * blockDim.x) {
-            float acc = scratch[(int64_t)c0 * box + e];
-            for (int c = 1; c < nc; ++c) acc += scratch[(int64_t)(c0 + c) * box + e];
+            // eight loads in flight per step (fixed order)
+            const float *base = scratch + (int64_t)c0 * box + e;
+            float acc = base[0];
+            int c = 1;
+            for (; c + 8 <= nc; c += 8) {
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = base[(int64_t)(c + i) * box];
+                acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+            }
+            for (; c < nc; ++c) acc += base[(int64_t)c * box];
             scratch[(int64_t)c0 * box + e] = acc;
         }
     }
@@ -835,8 +844,8 @@ __global__ void __launch_bounds__(256) k_reduce_chunks_split(float *__restrict__
 }
 
 // Fold for the common case (at least 3 tiles per dimension, boxes narrower than the grid,
-// m <= T), after k_reduce_chunks: blockIdx.x picks a tile of the list, blockIdx.y a group of its
-// points; the reduced box offsets of the 3^d
+// m <= T), after k_reduce_chunks: blockIdx.x picks a tile of the list (or tile blockIdx.x when
+// there is no list), blockIdx.y a group of its points; the reduced box offsets of the 3^d
 // neighbouring tiles sit in LDS and every grid point of the tile sums the boxes that cover it, in
 // a fixed neighbour order.
 template <int D>
@@ -847,7 +856,7 @@ __global__ void __launch_bounds__(256) k_fold_tiles(const float *__restrict__ sc
                                                     float *__restrict__ grid) {
     constexpr int NN = (D == 1) ? 3 : (D == 2 ? 9 : 27);
     __shared__ int nc0[NN], nnc[NN], norg[NN][3];
-    const int t = tiles[blockIdx.x];
+    const int t = tiles ? tiles[blockIdx.x] : (int)blockIdx.x;
     int tc[3] = {0, 0, 0};
     tile_coords<D>(t, ntd, tc);
     if ((int)threadIdx.x < NN) {
@@ -879,21 +888,23 @@ __global__ void __launch_bounds__(256) k_fold_tiles(const float *__restrict__ sc
                 rem /= T;
             }
         }
-        float acc = 0.0f;
+        // the covering boxes are read together (all loads in flight), then summed in order
+        float v[NN];
+#pragma unroll
         for (int j = 0; j < NN; ++j) {
-            const int nc = nnc[j];
-            if (nc == 0) continue;
             int l = 0, mul = 1;
-            bool inside = true;
+            bool inside = nnc[j] > 0;
             for (int k = 0; k < D; ++k) {
                 const int loc = (p[k] - norg[j][k] + G) & (G - 1);
                 inside &= loc < S;
                 l += loc * mul;
                 mul *= S;
             }
-            if (!inside) continue;
-            acc += scratch[(int64_t)nc0[j] * box + l];
+            v[j] = inside ? scratch[(int64_t)nc0[j] * box + l] : 0.0f;
         }
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NN; ++j) acc += v[j];
         int64_t gi = p[0];
         if (D > 1) gi += (int64_t)G * p[1];
         if (D > 2) gi += (int64_t)G * G * p[2];
@@ -2383,6 +2394,9 @@ namespace {
 // The matrix-core spread and gather (d = 3) pay per group of up to 16 nodes; the lane-per-node
 // kernels pay per node.  The groups are used when they hold MIN_GROUP_FILL nodes on average.
 constexpr int MIN_GROUP_FILL = 4;
+// Grids of at most this many tiles are folded whole (untouched tiles write their zeros), which
+// saves the separate clearing pass.
+constexpr int64_t FOLD_ALL_TILES = 4096;
 bool use_mfma(const Plan &pl, const Nodes &nd) {
     return !(pl.flags & FS_FLAG_FORCE_VALU) && nd.n_mblocks > 0 &&
            nd.n >= (int64_t)MIN_GROUP_FILL * nd.n_mgroups;
@@ -2445,16 +2459,19 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 FS_LAUNCHED();
             }
             if (ntd >= 3 && S <= pp.G && pp.m <= T) {
-                // tiles with no chunk in their 3^d neighbourhood only need zeros
-                if (src.n_touched < ntiles) fill_f32(pl.grid.p, gsz, 0.0f, s);
-                // the T^d points of a tile are split over blocks of 64 threads
+                // the T^d points of a tile are split over blocks of 64 threads; on large grids
+                // only the tiles with a chunk in their 3^d neighbourhood are folded and the rest
+                // of the grid is cleared, on small ones every tile is folded (zeros included)
                 int npts = 1;
                 for (int k = 0; k < D; ++k) npts *= T;
-                if (src.n_touched > 0)
-                    hipLaunchKernelGGL(k_fold_tiles<D>,
-                                       dim3((unsigned)src.n_touched, (unsigned)((npts + 63) / 64)),
+                const bool all = src.n_touched == ntiles || ntiles <= FOLD_ALL_TILES;
+                if (!all) fill_f32(pl.grid.p, gsz, 0.0f, s);
+                const unsigned nfold = all ? (unsigned)ntiles : (unsigned)src.n_touched;
+                if (nfold > 0)
+                    hipLaunchKernelGGL(k_fold_tiles<D>, dim3(nfold, (unsigned)((npts + 63) / 64)),
                                        dim3(64), 0, s, pl.scratch.p, tile_boxes,
-                                       src.touched_tiles.p, pp.G, T, ntd, pp.m, S, pl.grid.p);
+                                       all ? nullptr : src.touched_tiles.p, pp.G, T, ntd, pp.m, S,
+                                       pl.grid.p);
             } else {
                 hipLaunchKernelGGL(k_fold<D>, dim3(blocks_for(gsz, 256, 1 << 16)), dim3(256), 0, s,
                                    pl.scratch.p, tile_boxes, pp.G, T, ntd, pp.m, S, pl.grid.p);
