@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
 // pot_i = -kappa (shift + eps log t_i) in FP64, shift = max of the other potential (the max of
 // nshift per-block maxima); writes one block maximum of the new potential per block.  Non-positive
 // sums are counted in *nbad and replaced by the smallest normal float.
-constexpr int UPD_BLOCKS = 256;
+constexpr int UPD_BLOCKS = 1024;
 // With DELTA the per-block maxima of |new - old| go to delta_parts (stopping rule).
 template <bool DELTA>
 __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int64_t n,
@@ -78,14 +78,29 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
     __syncthreads();
     double mx = -INFINITY, dmx = 0.0;
     int bad = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        float v = t[i];
-        if (!(v > 0.0f)) { bad++; v = FLT_MIN; }
-        const double f = -kappa * (sh + eps * log((double)v));
-        if (DELTA) dmx = fmax(dmx, fabs(f - pot[i]));
-        pot[i] = f;
-        mx = fmax(mx, f);
+    // four elements per thread and step, their loads issued together
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n; i0 += 4 * stride) {
+        float v[4];
+        double o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = i0 + k * stride;
+            v[k] = (i < n) ? t[i] : 1.0f;
+            o[k] = (DELTA && i < n) ? pot[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = i0 + k * stride;
+            if (i < n) {
+                float vk = v[k];
+                if (!(vk > 0.0f)) { bad++; vk = FLT_MIN; }
+                const double f = -kappa * (sh + eps * log((double)vk));
+                if (DELTA) dmx = fmax(dmx, fabs(f - o[k]));
+                pot[i] = f;
+                mx = fmax(mx, f);
+            }
+        }
     }
     if (bad) atomicAdd(nbad, bad);
     sm[threadIdx.x] = mx;
