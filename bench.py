@@ -10,8 +10,10 @@ Also reported (extra keys of the same JSON line):
   * GPU direct-summation sweeps/s on the same inputs and the speedup of the fast path;
   * the sampled full-size error of the last half-step against the FP64 oracle (and the sampled
     errors of the other workloads), computed in the CPU-baseline leg together with its timing;
-  * per-pass average durations from HIP events recorded on the launch stream during the timed
-    steps, the dominant kernel's roofline, and HBM GB/s of spread, FFT and gather;
+  * the dominant kernel's (the spread's) roofline, its average duration taken from HIP events
+    around every 5th of its launches during the timed steps, and per-pass average durations and
+    HBM GB/s of spread, FFT and gather from one further, untimed step with events around every
+    pass;
   * the secondary metric: forward and forward+backward ms of the Sinkhorn divergence on the
     d=2, n=m=200k Gaussian-mixture workload;
   * the other workloads: 2-D 100k Sinkhorn, MMD at 1M (energy, Gauss, IMQ), the MMD accuracy
@@ -30,8 +32,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X published dense FP32 matrix peak
+PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X published dense FP16 matrix peak
 PEAK_HBM_GBS = 8000.0          # MI355X published HBM3E bandwidth
+SPREAD_SAMPLE = 5              # time every 5th spread launch of the timed steps
 
 
 def parse():
@@ -305,7 +308,10 @@ def main():
     for _ in range(args.warmup):
         step(args.grid, sweeps)
     torch.cuda.synchronize()
+    # timed steps: HIP events around every SPREAD_SAMPLE-th launch of the dominant kernel (the
+    # spread) on its stream, few enough that their own cost stays out of the wall time
     fu.fs_profile_reset()
+    fu.fs_profile_select("spread", SPREAD_SAMPLE)
     fu.fs_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -313,10 +319,19 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     fu.fs_profile_enable(False)
+    sp_ms, sp_cnt = fu.fs_profile_query("spread")
+    # per-pass breakdown from one more (untimed) step with events around every pass
+    fu.fs_profile_reset()
+    fu.fs_profile_select(None, 1)
+    fu.fs_profile_enable(True)
+    step(args.grid, sweeps)
+    torch.cuda.synchronize()
+    fu.fs_profile_enable(False)
     passes = {}
     for name in ("spread", "fold", "fft", "gather", "update"):
         ms, cnt = fu.fs_profile_query(name)
         passes[name] = {"avg_ms": ms / cnt if cnt else None, "launches": cnt}
+    fu.fs_profile_reset()
     ms_per_step = 1e3 * elapsed / args.steps
     value = sweeps * args.steps / elapsed
     log("fast %.3f ms/step, %.1f sweeps/s, objective %.9g" % (ms_per_step, value, obj))
@@ -324,16 +339,19 @@ def main():
 
     # ---- roofline of the dominant kernel (spread): algorithmic work per launch
     W = 2 * args.window
-    sp = passes["spread"]["avg_ms"]
+    sp = sp_ms / sp_cnt  # sampled over the timed steps
     flops_per_launch = n * 2.0 * W ** d          # one multiply and one add per window point
     achieved_tflops = flops_per_launch / (sp * 1e-3) / 1e12
     bytes_per_launch = n * (16 + 4) + 4 * args.grid ** d  # node record + weight, grid written
     traffic = traffic_from_profile(os.path.join(ROOT, "paper_2306_13618_amd", "csrc", "nfft.hip"))
-    roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS,
+    roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP16_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP16_MFMA_TFLOPS,
                 "traffic": traffic,
-                "kernel": "k_spread_mfma (spreading, adjoint NFFT, FP32 matrix cores)",
-                "work_per_launch": "%d nodes x 2 x %d^%d flops" % (n, W, d)}
+                "kernel": "k_spread_mfma16 (spreading, adjoint NFFT, FP16 matrix cores with "
+                          "hi/lo split operands)",
+                "work_per_launch": "%d nodes x 2 x %d^%d flops (window products at FP32 accuracy; "
+                                   "four FP16 split products each, so frac <= 0.25)" % (n, W, d),
+                "timed_launches": sp_cnt}
     window_terms = n * float(W ** d)
     hbm = {}
     G = args.grid

@@ -96,8 +96,12 @@ void fs_release_cache(void);
  * "update", "direct") record a pair of HIP events on the stream the pass is launched on;
  * fs_profile_query waits for the recorded events and returns the summed duration in
  * milliseconds and the launch count for one pass name (0 and 0 if none); fs_profile_reset
- * discards the records.  Returns FS_OK or FS_EINVAL (NULL argument). */
+ * discards the records.  fs_profile_select(pass, period) restricts the recording to the passes
+ * named `pass` (NULL or "": all) and to every period-th of them (period >= 1; sampling keeps the
+ * events' own cost out of a timed run); it restarts the count.  Returns FS_OK or FS_EINVAL (NULL
+ * argument, period < 1). */
 int fs_profile_enable(int enable);
+int fs_profile_select(const char *pass, int period);
 int fs_profile_query(const char *pass, double *total_ms, int64_t *count);
 void fs_profile_reset(void);
 

@@ -20,7 +20,7 @@ __all__ = [
     "uot_sinkhorn_scaling", "sinkhorn_divergence",
     "sinkhorn_divergence_grad", "mmd", "mmd_grad", "SinkhornDivergence", "MMD2",
     "FastsumError", "KERNELS", "library_path", "EXPORTED", "fs_profile_enable",
-    "fs_profile_query", "fs_profile_reset",
+    "fs_profile_select", "fs_profile_query", "fs_profile_reset",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +29,7 @@ KERNELS = {"gauss": 0, "laplace": 1, "energy": 2, "imq": 3}
 FLAG_WARM_START = 0x1
 FLAG_FORCE_VALU = 0x2
 EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fs_profile_enable",
+            "fs_profile_select",
             "fs_profile_query", "fs_profile_reset", "fastsum_apply", "fs_plan_create",
             "fs_plan_apply", "fs_plan_destroy", "uot_sinkhorn", "uot_upper_bound",
             "uot_sinkhorn_scaling", "uot_sinkhorn_grad", "sinkhorn_divergence",
@@ -64,6 +65,7 @@ def _load():
         "fs_version": (I, []),
         "fs_release_cache": (None, []),
         "fs_profile_enable": (I, [I]),
+        "fs_profile_select": (I, [ctypes.c_char_p, I]),
         "fs_profile_query": (I, [ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I64)]),
         "fs_profile_reset": (None, []),
         "fastsum_apply": (I, [P, I64, P, I64, I, P, P, PP, P]),
@@ -143,6 +145,11 @@ def _opt(out):
 def fs_profile_enable(enable=True):
     """Record HIP events around the library's passes (spread, fold, fft, gather, ...)."""
     _check(_lib.fs_profile_enable(int(bool(enable))))
+
+
+def fs_profile_select(name=None, period=1):
+    """Record only the passes called `name` (None: all), every `period`-th of them."""
+    _check(_lib.fs_profile_select(name.encode() if name else None, int(period)))
 
 
 def fs_profile_query(name):

@@ -8,6 +8,7 @@
 namespace fs {
 const char *last_error();
 int profile_enable(int on);
+int profile_select(const char *pass, int period);
 int profile_query(const char *pass, double *total_ms, int64_t *count);
 void profile_reset();
 
@@ -109,6 +110,8 @@ int fs_version(void) { return (1 << 16) | 0; }
 void fs_release_cache(void) { ws_release_all(); }
 
 int fs_profile_enable(int enable) { return fs::profile_enable(enable); }
+
+int fs_profile_select(const char *pass, int period) { return fs::profile_select(pass, period); }
 
 int fs_profile_query(const char *pass, double *total_ms, int64_t *count) {
     return fs::profile_query(pass, total_ms, count);

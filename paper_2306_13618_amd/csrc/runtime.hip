@@ -95,6 +95,9 @@ struct ProfRec {
 struct Prof {
     std::mutex mu;
     bool on = false;
+    std::string only;    // record only scopes of this name (empty: all)
+    int period = 1;      // record every period-th eligible scope
+    int64_t seen = 0;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     std::map<std::string, std::pair<double, int64_t>> totals;
@@ -134,6 +137,8 @@ ProfScope::ProfScope(const char *name, hipStream_t stream) : s(stream) {
     Prof &p = prof();
     if (!p.on) return;
     std::lock_guard<std::mutex> lk(p.mu);
+    if (!p.only.empty() && p.only != name) return;
+    if (p.seen++ % p.period != 0) return;
     ProfRec r{name, take_event(p), take_event(p)};
     FS_HIP(hipEventRecord(r.e0, s));
     p.recs.push_back(r);
@@ -149,6 +154,19 @@ ProfScope::~ProfScope() {
 
 int profile_enable(int on) {
     prof().on = (on != 0);
+    return FS_OK;
+}
+
+int profile_select(const char *pass, int period) {
+    if (period < 1) {
+        set_error("fs_profile_select: period must be at least 1 (got %d)", period);
+        return FS_EINVAL;
+    }
+    Prof &p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    p.only = pass ? pass : "";
+    p.period = period;
+    p.seen = 0;
     return FS_OK;
 }
 
