@@ -175,13 +175,21 @@ __global__ void __launch_bounds__(RT) k_moments(const float *__restrict__ p, con
 }
 
 // out[k] = sum over blocks of parts[b][k] (fixed order), one thread per component
-__global__ void k_moments_final(const double *__restrict__ parts, int nblocks, int ncomp,
-                                double *__restrict__ out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ncomp) return;
+// One block per component: thread t sums blocks t, t + RT, ... in order, then a fixed tree.
+__global__ void __launch_bounds__(RT) k_moments_final(const double *__restrict__ parts,
+                                                      int nblocks, int ncomp,
+                                                      double *__restrict__ out) {
+    __shared__ double sm[RT];
+    const int k = blockIdx.x;
     double acc = 0.0;
-    for (int b = 0; b < nblocks; ++b) acc += parts[(int64_t)b * ncomp + k];
-    out[k] = acc;
+    for (int b = threadIdx.x; b < nblocks; b += RT) acc += parts[(int64_t)b * ncomp + k];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = RT / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sm[0];
 }
 
 // out = max of nparts maxima (0 if all are -inf), one block
@@ -241,16 +249,32 @@ __global__ void __launch_bounds__(RT) k_csum(const float *__restrict__ u, const 
     }
 }
 
-__global__ void k_csum_final(const double *__restrict__ partial, int nblocks,
-                             double *__restrict__ out) {
-    if (threadIdx.x >= 3) return;
-    const int k = threadIdx.x;
-    double S = 0, C = 0;
-    for (int b = 0; b < nblocks; ++b) {
-        nadd(S, C, partial[(b * 3 + k) * 2]);
-        C += partial[(b * 3 + k) * 2 + 1];
+// Combination of the per-block (sum, compensation) pairs: thread t takes blocks t, t + RT, ...
+// in order, then the same pairwise tree as above (a fixed order: reproducible).
+__global__ void __launch_bounds__(RT) k_csum_final(const double *__restrict__ partial, int nblocks,
+                                                   double *__restrict__ out) {
+    __shared__ double ss[3][RT], sc[3][RT];
+    for (int k = 0; k < 3; ++k) {
+        double S = 0, C = 0;
+        for (int b = threadIdx.x; b < nblocks; b += RT) {
+            nadd(S, C, partial[(b * 3 + k) * 2]);
+            C += partial[(b * 3 + k) * 2 + 1];
+        }
+        ss[k][threadIdx.x] = S;
+        sc[k][threadIdx.x] = C;
     }
-    out[k] = S + C;
+    __syncthreads();
+    for (int o = RT / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 3; ++k) {
+                double S = ss[k][threadIdx.x], C = sc[k][threadIdx.x] + sc[k][threadIdx.x + o];
+                nadd(S, C, ss[k][threadIdx.x + o]);
+                ss[k][threadIdx.x] = S;
+                sc[k][threadIdx.x] = C;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[threadIdx.x] = ss[threadIdx.x][0] + sc[threadIdx.x][0];
 }
 
 // Direct gradient sum: g_i = sum_j grad K(x_i - y_j) w_j (and t_i), any d <= 128.
@@ -551,7 +575,7 @@ void csum(int mode, const float *u, const double *pot, const float *v, int64_t n
     else
         hipLaunchKernelGGL(k_csum<2>, dim3(nb), dim3(RT), 0, s, u, pot, v, n, rho, sc.partial.p);
     FS_LAUNCHED();
-    hipLaunchKernelGGL(k_csum_final, dim3(1), dim3(64), 0, s, sc.partial.p, (int)nb, out);
+    hipLaunchKernelGGL(k_csum_final, dim3(1), dim3(RT), 0, s, sc.partial.p, (int)nb, out);
     FS_LAUNCHED();
 }
 
@@ -682,9 +706,9 @@ double pair_cost_mean(const float *x, const float *a, int64_t n, const float *y,
     DevBuf<double> px((size_t)nbx * (d + 2)), py((size_t)nby * (d + 2)), mx(d + 2), my(d + 2);
     hipLaunchKernelGGL(k_moments, dim3(nbx), dim3(RT), 0, s, x, a, n, d, x, px.p);
     hipLaunchKernelGGL(k_moments, dim3(nby), dim3(RT), 0, s, y, b, m, d, x, py.p);
-    hipLaunchKernelGGL(k_moments_final, dim3(blocks_for(d + 2, 64)), dim3(64), 0, s, px.p,
+    hipLaunchKernelGGL(k_moments_final, dim3(d + 2), dim3(RT), 0, s, px.p,
                        (int)nbx, d + 2, mx.p);
-    hipLaunchKernelGGL(k_moments_final, dim3(blocks_for(d + 2, 64)), dim3(64), 0, s, py.p,
+    hipLaunchKernelGGL(k_moments_final, dim3(d + 2), dim3(RT), 0, s, py.p,
                        (int)nby, d + 2, my.p);
     FS_LAUNCHED();
     std::vector<double> hx(d + 2), hy(d + 2);
