@@ -110,13 +110,13 @@ def test_fastsum_nearfield_dense_sampled(cfg, kind, n, radius):
     assert relinf(got[rows], ref) < TOL
 
 
-def dense_and_sparse(n, m, seed):
-    """80% of the points in a small cube (hundreds per grid cell), the rest spread over the whole
-    box (a few per brick): full, partial and single-node matrix-core groups."""
+def dense_and_sparse(n, m, seed, frac=0.8):
+    """A fraction `frac` of the points in a small cube (many per grid cell), the rest spread over
+    the whole box (a few per brick): full, partial and single-node matrix-core groups."""
     rng = np.random.default_rng([777, n, m, seed])
 
     def pts(k):
-        kd = int(0.8 * k)
+        kd = int(frac * k)
         p = np.concatenate([rng.uniform(-0.05, 0.05, (kd, 3)),
                             rng.uniform(-0.25, 0.25, (k - kd, 3))])
         return rng.permutation(p).astype(np.float32)
@@ -135,6 +135,62 @@ def test_fastsum_gauss_matrix_core_groups(window, lam):
     ref = oracle.direct_sum_rows(x, rows, y, v, "gauss", lam)
     assert relinf(got[rows], ref) < TOL
     assert relinf(got, valu) < 2e-6
+    assert np.any(got != valu)  # the two paths differ in rounding: the matrix cores ran
+
+
+@pytest.mark.parametrize("kind,lam", [("laplace", 0.01), ("energy", 1.0), ("imq", 0.05)])
+def test_fastsum_nearfield_matrix_core_groups(kind, lam):
+    """Near-field kernels with the 3-D matrix-core spread and gather (dense clusters) against the
+    oracle on sampled rows and against the lane-per-node kernels on every row."""
+    x, y, v = dense_and_sparse(40_000, 37_003, 11, frac=0.95)
+    args = dict(kernel=kind, lam=lam, grid=128, window=6)
+    got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
+    valu = fu.fastsum_apply(T(x), T(y), T(v), flags=fu.FLAG_FORCE_VALU, **args).cpu().numpy()
+    rows = synth.sample_rows(len(x), 200, seed=12)
+    ref = oracle.direct_sum_rows(x, rows, y, v, kind, lam)
+    assert relinf(got[rows], ref) < TOL
+    assert relinf(got, valu) < 2e-6
+    assert np.any(got != valu)  # the two paths differ in rounding: the matrix cores ran
+
+
+def test_uot_matrix_core_groups():
+    """A Sinkhorn solve whose kernel sums take the 3-D matrix-core spread and gather (dense
+    clusters, grid 64^3) against the oracle's iterates."""
+    x, y, _ = dense_and_sparse(8000, 7001, 21, frac=0.95)
+    rng = np.random.default_rng(22)
+    a = rng.uniform(0.5, 1.5, len(x)).astype(np.float32)
+    b = rng.uniform(0.5, 1.5, len(y)).astype(np.float32)
+    a, b = a / a.sum(), (1.2 * b / b.sum()).astype(np.float32)
+    eps, rho, sweeps = 0.02, 1.0, 10
+    f, g, obj = fu.uot_sinkhorn(T(x), T(a), T(y), T(b), eps, rho, sweeps, kernel="gauss",
+                                grid=64, window=6)
+    beta, gamma = oracle.uot_sinkhorn(x, a, y, b, eps, rho, sweeps)
+    D = oracle.uot_dual(x, a, y, b, eps, rho, beta, gamma)
+    assert relinf(f.cpu().numpy(), beta) < TOL
+    assert relinf(g.cpu().numpy(), gamma) < TOL
+    assert abs(obj - D) < TOL * abs(D)
+    fv, _, _ = fu.uot_sinkhorn(T(x), T(a), T(y), T(b), eps, rho, sweeps, kernel="gauss",
+                               grid=64, window=6, flags=fu.FLAG_FORCE_VALU)
+    assert np.any(fv.cpu().numpy() != f.cpu().numpy())  # the matrix cores ran
+
+
+@pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.02, 64), ("energy", 1.0, 128)])
+def test_mmd_matrix_core_groups(kind, lam, grid):
+    """MMD^2 of dense 3-D clouds (matrix-core spread and gather) against the oracle."""
+    x, y, _ = dense_and_sparse(9000, 8501, 31, frac=0.95)
+    rng = np.random.default_rng(32)
+    a = rng.uniform(0.5, 1.5, len(x)).astype(np.float32)
+    b = rng.uniform(0.5, 1.5, len(y)).astype(np.float32)
+    a, b = (a / a.sum()).astype(np.float32), (b / b.sum()).astype(np.float32)
+    ref, terms = oracle.mmd2(x, a, y, b, kind, lam)
+    val, t3 = fu.mmd(T(x), T(a), T(y), T(b), kernel=kind, lam=lam, grid=grid, window=6,
+                     terms=True)
+    for k in range(3):
+        assert abs(t3[k] - terms[k]) < TOL * abs(terms[k])
+    assert abs(val - ref) < TOL * max(abs(t) for t in terms)
+    _, tv = fu.mmd(T(x), T(a), T(y), T(b), kernel=kind, lam=lam, grid=grid, window=6,
+                   terms=True, flags=fu.FLAG_FORCE_VALU)
+    assert any(tv[k] != t3[k] for k in range(3))  # the matrix cores ran
 
 
 def test_fastsum_signed_weights_and_wide_gaussian():
