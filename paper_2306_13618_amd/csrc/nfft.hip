@@ -1839,8 +1839,11 @@ void scatter_rows_from_sorted(const Nodes &nd, const float *vs, int d, float *v,
 
 namespace {
 
-// Exclusive scan of n ints (device), result in out; returns nothing (stream-ordered).
-void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s) {
+// Exclusive scan of n ints (device), result in out (stream-ordered).  The temporaries are moved
+// into `keep` when given (the caller releases them after its own synchronisation), else the
+// stream is synchronised before they are released.
+void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s,
+                    std::vector<DevBuf<int>> *keep = nullptr) {
     const int64_t nb = (n + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK;
     FS_REQUIRE(nb <= 1024 * 1024, FS_EINVAL, "scan too large");
     DevBuf<int> bsum(nb + 1), boff(nb + 1), tmp1(2 * (nb + 1)), tot(2);
@@ -1851,7 +1854,14 @@ void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s) {
     FS_LAUNCHED();
     hipLaunchKernelGGL(k_block_scan, dim3((unsigned)nb), dim3(256), 0, s, in, n, boff.p, out);
     FS_LAUNCHED();
-    FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+    if (keep) {
+        keep->push_back(std::move(bsum));
+        keep->push_back(std::move(boff));
+        keep->push_back(std::move(tmp1));
+        keep->push_back(std::move(tot));
+    } else {
+        FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+    }
 }
 
 // Workgroups of the matrix-core spread and gather that the current device holds at once (compute
@@ -1885,28 +1895,40 @@ int mfma_slots(int W) {
     return slots;
 }
 
-// Matrix-core groups and their blocks from the cell offsets of cell-sorted nodes (d = 3).  The
-// groups of a tile are cut into blocks of equal size, the smallest size for which all blocks fit
-// on the chip at once (`slots` resident workgroups): a second, partly filled round of workgroups
-// would nearly double the pass.
-void build_mgroups(Nodes &nd, const int *kstart, int64_t n, int64_t ntiles, int64_t cells_per_tile,
-                   const PlanParams &pp, int slots, hipStream_t s) {
-    const int64_t nbricks = ntiles * cells_per_tile / BRICK_X;
-    const int bpt = (int)(cells_per_tile / BRICK_X);
-    DevBuf<int> gcount(nbricks + 1), gstart(nbricks + 1), tgroups(ntiles), tgstart(ntiles),
-        totals(2);
-    nd.mtile_block.alloc(2 * ntiles);
-    int *tblock = nd.mtile_block.p;
-    hipLaunchKernelGGL(k_brick_groups, dim3(blocks_for(nbricks, 256)), dim3(256), 0, s, kstart,
-                       nbricks, (int)n, gcount.p);
+// Matrix-core groups and their blocks from the cell offsets of cell-sorted nodes (d = 3), in two
+// stages around the binning's host synchronisation.  The groups of a tile are cut into blocks of
+// equal size, the smallest size for which all blocks fit on the chip at once (`slots` resident
+// workgroups): a second, partly filled round of workgroups would nearly double the pass.
+struct MGroupBuild {
+    int64_t nbricks = 0;
+    DevBuf<int> gcount, tgroups;
+    std::vector<int> tg;  // groups per tile (host)
+};
+
+// Stage 1 (before the synchronisation): groups per brick and per tile; the per-tile counts are
+// copied to mg.tg.
+void mgroups_count(MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles,
+                   int64_t cells_per_tile, hipStream_t s) {
+    mg.nbricks = ntiles * cells_per_tile / BRICK_X;
+    mg.gcount.alloc(mg.nbricks + 1);
+    mg.tgroups.alloc(ntiles);
+    mg.tg.assign(ntiles, 0);
+    hipLaunchKernelGGL(k_brick_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
+                       mg.nbricks, (int)n, mg.gcount.p);
     FS_LAUNCHED();
-    exclusive_scan(gcount.p, nbricks, gstart.p, s);
-    hipLaunchKernelGGL(k_tile_sum, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, gcount.p,
-                       (int)ntiles, bpt, tgroups.p);
+    hipLaunchKernelGGL(k_tile_sum, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, mg.gcount.p,
+                       (int)ntiles, (int)(cells_per_tile / BRICK_X), mg.tgroups.p);
     FS_LAUNCHED();
-    std::vector<int> tg(ntiles);
-    FS_HIP(hipMemcpyAsync(tg.data(), tgroups.p, ntiles * sizeof(int), hipMemcpyDeviceToHost, s));
-    FS_HIP(hipStreamSynchronize(s));
+    FS_HIP(hipMemcpyAsync(mg.tg.data(), mg.tgroups.p, ntiles * sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+}
+
+// Stage 2 (after it): block size from the per-tile counts, then the group and block tables.
+// Temporaries go to `keep`; host arrays whose copies may still be in flight go to `hkeep`.
+void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles,
+                  const PlanParams &pp, int slots, hipStream_t s,
+                  std::vector<DevBuf<int>> &keep, std::vector<std::vector<int>> &hkeep) {
+    const std::vector<int> &tg = mg.tg;
     int64_t total = 0;
     int tmax = 0;
     for (int v : tg) {
@@ -1926,36 +1948,53 @@ void build_mgroups(Nodes &nd, const int *kstart, int64_t n, int64_t ntiles, int6
         else lo = mid + 1;
     }
     const int gpb = lo;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, tgroups.p, (int)ntiles, gpb,
-                       tgstart.p, tblock, totals.p);
-    FS_LAUNCHED();
-    // at most n / 16 full groups plus one partial group per non-empty brick
-    const int64_t cap = n / 16 + std::min<int64_t>(n, nbricks) + 1;
-    FS_REQUIRE(total <= cap, FS_EINVAL, "group count %lld above its bound", (long long)total);
-    nd.mgroups.alloc(cap);
-    hipLaunchKernelGGL(k_fill_groups, dim3(blocks_for(nbricks, 256)), dim3(256), 0, s, kstart,
-                       gstart.p, nbricks, (int)n, pp.T, pp.T + pp.W - 1, nd.mgroups.p);
-    FS_LAUNCHED();
-    int tot[2] = {0, 0};
-    FS_HIP(hipMemcpyAsync(tot, totals.p, sizeof(tot), hipMemcpyDeviceToHost, s));
-    FS_HIP(hipStreamSynchronize(s));
-    nd.n_mgroups = tot[0];
-    nd.n_mblocks = tot[1];
-    nd.mblocks.alloc(nd.n_mblocks + 1);
-    if (nd.n_mblocks > 0) {
-        hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
-                           (int)ntiles, tgstart.p, tgroups.p, tblock, gpb, nd.mblocks.p);
-        FS_LAUNCHED();
+    // per tile: first group, [first block, block count]; tiles with several blocks
+    std::vector<int> tgstart(ntiles), tblock(2 * ntiles), multi;
+    int64_t g0 = 0, b0 = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int nb = (tg[t] + gpb - 1) / gpb;
+        tgstart[t] = (int)g0;
+        tblock[2 * t] = (int)b0;
+        tblock[2 * t + 1] = nb;
+        if (nb > 1) multi.push_back((int)t);
+        g0 += tg[t];
+        b0 += nb;
     }
-    std::vector<int> multi;
-    for (int64_t t = 0; t < ntiles; ++t)
-        if (tg[t] > gpb) multi.push_back((int)t);
+    // at most n / 16 full groups plus one partial group per non-empty brick
+    const int64_t cap = n / 16 + std::min<int64_t>(n, mg.nbricks) + 1;
+    FS_REQUIRE(total <= cap, FS_EINVAL, "group count %lld above its bound", (long long)total);
+    nd.n_mgroups = (int)total;
+    nd.n_mblocks = (int)b0;
     nd.n_mmulti = (int)multi.size();
+    DevBuf<int> gstart(mg.nbricks + 1), dtgstart(ntiles);
+    nd.mtile_block.alloc(2 * ntiles);
+    nd.mgroups.alloc(std::max<int64_t>(total, 1));
+    nd.mblocks.alloc(nd.n_mblocks + 1);
     nd.mmulti_tiles.alloc(std::max<size_t>(multi.size(), 1));
+    FS_HIP(hipMemcpyAsync(dtgstart.p, tgstart.data(), ntiles * sizeof(int), hipMemcpyHostToDevice,
+                          s));
+    FS_HIP(hipMemcpyAsync(nd.mtile_block.p, tblock.data(), 2 * ntiles * sizeof(int),
+                          hipMemcpyHostToDevice, s));
     if (!multi.empty())
         FS_HIP(hipMemcpyAsync(nd.mmulti_tiles.p, multi.data(), multi.size() * sizeof(int),
                               hipMemcpyHostToDevice, s));
-    FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+    exclusive_scan(mg.gcount.p, mg.nbricks, gstart.p, s, &keep);
+    hipLaunchKernelGGL(k_fill_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
+                       gstart.p, mg.nbricks, (int)n, pp.T, pp.T + pp.W - 1, nd.mgroups.p);
+    FS_LAUNCHED();
+    if (nd.n_mblocks > 0) {
+        hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
+                           (int)ntiles, dtgstart.p, mg.tgroups.p, nd.mtile_block.p, gpb,
+                           nd.mblocks.p);
+        FS_LAUNCHED();
+    }
+    keep.push_back(std::move(gstart));
+    keep.push_back(std::move(dtgstart));
+    keep.push_back(std::move(mg.gcount));
+    keep.push_back(std::move(mg.tgroups));
+    hkeep.push_back(std::move(tgstart));
+    hkeep.push_back(std::move(tblock));
+    hkeep.push_back(std::move(multi));
 }
 
 void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s) {
@@ -1992,7 +2031,10 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                            pts, n, sa, (int)cell_keys, key.p, tmp.p, hist.p);
         FS_LAUNCHED();
     }
-    exclusive_scan(hist.p, nkeys, kstart.p, s);
+    // device temporaries released, and host arrays kept alive, until the final synchronisation
+    std::vector<DevBuf<int>> keep;
+    std::vector<std::vector<int>> hkeep;
+    exclusive_scan(hist.p, nkeys, kstart.p, s, &keep);
     const int *tile_hist = hist.p;
     if (cell_keys) {
         hipLaunchKernelGGL(k_tile_counts, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, kstart.p,
@@ -2009,6 +2051,11 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                            nd.perm.p, nd.xs.p);
         FS_LAUNCHED();
     }
+    // matrix-core groups (d = 3): per-brick and per-tile counts, read back with the chunk table
+    const bool mgroups = d == 3 && cell_keys && T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 &&
+                         n > 0;
+    MGroupBuild mg;
+    if (mgroups) mgroups_count(mg, kstart.p, n, ntiles, cells_per_tile, s);
     int tot[2] = {0, 0};
     std::vector<int> tch(2 * ntiles);
     FS_HIP(hipMemcpyAsync(tot, totals.p, sizeof(tot), hipMemcpyDeviceToHost, s));
@@ -2053,9 +2100,8 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                            nd.chunks.p);
         FS_LAUNCHED();
     }
-    nd.n_mgroups = nd.n_mblocks = 0;
-    if (d == 3 && cell_keys && T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 && n > 0)
-        build_mgroups(nd, kstart.p, n, ntiles, cells_per_tile, pp, mfma_slots(pp.W), s);
+    nd.n_mgroups = nd.n_mblocks = nd.n_mmulti = 0;
+    if (mgroups) mgroups_fill(nd, mg, kstart.p, n, ntiles, pp, mfma_slots(pp.W), s, keep, hkeep);
     FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
 }
 
