@@ -42,7 +42,7 @@ enum Regime { REGIME_CUBE = 0, REGIME_BALL = 1 };
 // Window segment polynomials: on the unit cell of a node (fractional offset t in [0, 1)), the
 // window value at grid offset a is phi(t + m - 1 - a), written as a degree-(WPOLY-1)
 // polynomial in u = 2t - 1 (fitted in FP64 per plan).
-constexpr int WPOLY = 10;
+constexpr int WPOLY = 8;
 
 struct PlanParams {
     int d = 0, kind = FS_GAUSS;
