@@ -32,22 +32,29 @@ __device__ __forceinline__ void nadd(double &s, double &c, double v) {
     s = t;
 }
 
+// Largest v over the workgroup (wave shuffles, then one value per wave through `red`, which must
+// hold blockDim.x / 64 doubles); every thread gets the result.
+__device__ __forceinline__ double block_max(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();  // red may still be read by a previous call
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double m = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+    return m;
+}
+
 // w_k = base_k exp((pot_k - pmax) / eps)  (FP64 exponent, FP32 result), where pmax is the max
 // of the nparts per-block maxima written by the update kernel (or a single value, nparts = 1).
 __global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
                                                  const double *__restrict__ pot,
                                                  const double *__restrict__ parts, int nparts,
                                                  double inv_eps, int64_t n, float *__restrict__ w) {
-    __shared__ double sm[256];
+    __shared__ double red[4];
     double mx = -INFINITY;
     for (int b = threadIdx.x; b < nparts; b += blockDim.x) mx = fmax(mx, parts[b]);
-    sm[threadIdx.x] = mx;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
-        __syncthreads();
-    }
-    const double pm = (sm[0] == -INFINITY) ? 0.0 : sm[0];
+    mx = block_max(mx, red);
+    const double pm = (mx == -INFINITY) ? 0.0 : mx;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         w[i] = (float)((double)base[i] * exp((pot[i] - pm) * inv_eps));
@@ -65,17 +72,11 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
                                                double *__restrict__ out_parts,
                                                int *__restrict__ nbad,
                                                double *__restrict__ delta_parts) {
-    __shared__ double sm[RT];
+    __shared__ double red[RT / 64];
     double sh = -INFINITY;
     for (int b = threadIdx.x; b < nshift; b += RT) sh = fmax(sh, shift_parts[b]);
-    sm[threadIdx.x] = sh;
-    __syncthreads();
-    for (int s = RT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-        __syncthreads();
-    }
-    sh = (sm[0] == -INFINITY) ? 0.0 : sm[0];
-    __syncthreads();
+    sh = block_max(sh, red);
+    if (sh == -INFINITY) sh = 0.0;
     double mx = -INFINITY, dmx = 0.0;
     int bad = 0;
     // four elements per thread and step, their loads issued together
@@ -103,22 +104,11 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
         }
     }
     if (bad) atomicAdd(nbad, bad);
-    sm[threadIdx.x] = mx;
-    __syncthreads();
-    for (int s = RT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out_parts[blockIdx.x] = sm[0];
+    mx = block_max(mx, red);
+    if (threadIdx.x == 0) out_parts[blockIdx.x] = mx;
     if (DELTA) {
-        __syncthreads();
-        sm[threadIdx.x] = dmx;
-        __syncthreads();
-        for (int s = RT / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) delta_parts[blockIdx.x] = sm[0];
+        dmx = block_max(dmx, red);
+        if (threadIdx.x == 0) delta_parts[blockIdx.x] = dmx;
     }
 }
 
