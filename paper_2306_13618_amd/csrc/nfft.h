@@ -94,6 +94,21 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
 void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *grad,
                        int transpose, hipStream_t s);
 
+// Source weights given as w_k = base_k exp((pot_k - pmax) / eps), FP64 exponent, FP32 result
+// (a Sinkhorn half-step), pmax the largest of nparts per-block maxima (0 when all are -inf).
+struct PotWeights {
+    const float *base = nullptr;
+    const double *pot = nullptr, *parts = nullptr;
+    int nparts = 0;
+    double inv_eps = 1.0;
+};
+
+// True when the kernel sum of this direction evaluates such weights inside its spread (3-D
+// matrix-core spread, no near field); plan_apply_sorted_pot then needs no weight array.
+bool plan_fuses_weights(const Plan &pl, int transpose);
+void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
+                           hipStream_t s);
+
 // Permutations between caller order and a node set's sorted order.
 void gather_to_sorted(const Nodes &nd, const float *v, float *v_sorted, hipStream_t s);
 void scatter_from_sorted(const Nodes &nd, const float *v_sorted, float *v, hipStream_t s);

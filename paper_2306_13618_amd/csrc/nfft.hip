@@ -591,10 +591,10 @@ __device__ __forceinline__ void tile_coords(int tile, int ntd, int *t) {
 // scale = 2^30 / (count * max|alpha|) all int32 partial sums stay below 2^30 in magnitude.
 // LDS integer atomics are the fast path on gfx950 (LDS float atomics are far slower), and integer
 // addition makes the accumulation order-independent (bitwise reproducible).
-__device__ float chunk_scale(const float *__restrict__ w, int k0, int cnt, float *red,
-                            float *wmax = nullptr) {
+template <class WF>
+__device__ float chunk_scale_fn(WF wf, int k0, int cnt, float *red, float *wmax = nullptr) {
     float mx = 0.0f;
-    for (int k = k0 + threadIdx.x; k < k0 + cnt; k += blockDim.x) mx = fmaxf(mx, fabsf(w[k]));
+    for (int k = k0 + threadIdx.x; k < k0 + cnt; k += blockDim.x) mx = fmaxf(mx, fabsf(wf(k)));
     for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
@@ -602,6 +602,10 @@ __device__ float chunk_scale(const float *__restrict__ w, int k0, int cnt, float
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmaxf(m, red[i]);
     if (wmax) *wmax = m;
     return (m > 0.0f && cnt > 0) ? 1073741824.0f / ((float)cnt * m) : 1.0f;
+}
+__device__ float chunk_scale(const float *__restrict__ w, int k0, int cnt, float *red,
+                            float *wmax = nullptr) {
+    return chunk_scale_fn([&](int k) { return w[k]; }, k0, cnt, red, wmax);
 }
 
 template <int D, int W, int T>
@@ -1281,12 +1285,13 @@ __device__ __forceinline__ void split_f16(float a, float b, f16x2 &hi, f16x2 &lo
 // of alpha px for box column l % 16 against (hi, lo) of py pz at column l % 16 of the block.
 // Lane l holds the sums for columns 4 (l / 16) + r, r < 4; they stay in registers while the brick
 // stays the same and then go to the chunk's LDS box with integer atomics (fixed point, see
-// chunk_scale).
-template <int W>
+// chunk_scale).  With POT the weights are w_k = base_k exp((pot_k - pmax) / eps), evaluated here
+// (weight_exp: FP64 exponent, FP32 result) instead of read from w.
+template <int W, bool POT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
                 const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups, SpreadArgs sa,
-                float *__restrict__ scratch) {
+                float *__restrict__ scratch, PotWeights pw) {
     constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
     constexpr int NZ = (W + 3) / 4;      // (y, z) offsets in blocks of 4
     constexpr int NB = NZ * NZ;          // 4 x 4 blocks of (y, z)
@@ -1298,14 +1303,29 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
     __shared__ float phyz[4][2][W][16];   // per wave: py and pz, offset-major
     __shared__ int oxs[4][16];
     __shared__ float red[16];
+    __shared__ double pmx[4];
     const int4 mb = mblocks[blockIdx.x];
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
     const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
+    double pmax = 0.0;
+    if (POT) {
+        double mx = -INFINITY;
+        for (int b = threadIdx.x; b < pw.nparts; b += blockDim.x) mx = fmax(mx, pw.parts[b]);
+        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if ((threadIdx.x & 63) == 0) pmx[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        mx = fmax(fmax(pmx[0], pmx[1]), fmax(pmx[2], pmx[3]));
+        pmax = (mx == -INFINITY) ? 0.0 : mx;
+    }
+    auto weight = [&](int k) -> float {
+        if (POT) return weight_exp(pw.base[k], (pw.pot[k] - pmax) * pw.inv_eps);
+        return w[k];
+    };
     // chunk_scale = 2^30 / (cnt max|w|): the weights enter the products as w / max|w| and the
     // sums are converted with 2^30 / cnt
     float wm = 0.0f;
-    const float scale = chunk_scale(w, k0, cnt, red, &wm);
+    const float scale = chunk_scale_fn(weight, k0, cnt, red, &wm);
     const float wmax = (wm > 0.0f) ? wm : 1.0f;
     const float inv_wmax = 1.0f / wmax, fscale = scale * wmax;
     const int lane = threadIdx.x & 63;
@@ -1347,7 +1367,7 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
         const int4 gr = mgroups[g];
         const int nn = min(col, gr.y - 1);
         const float4 r = rec[gr.x + nn];
-        const float alpha = (col < gr.y) ? w[gr.x + nn] * inv_wmax : 0.0f;
+        const float alpha = (col < gr.y) ? weight(gr.x + nn) * inv_wmax : 0.0f;
         // window values of node `col` at offsets slot + 4 e
         const float fr[3] = {r.x, r.y, r.z};
 #pragma unroll
@@ -1871,7 +1891,7 @@ template <int W>
 int mfma_blocks_per_cu() {
     int a = 0, b = 0;
     FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W>, 256, 0));
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W>, 256, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W, true>, 256, 0));
     return std::max(1, std::min(a, b));
 }
 
@@ -2450,7 +2470,7 @@ bool use_mfma(const Plan &pl, const Nodes &nd) {
 
 template <int D, int W>
 void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const float *w,
-                          float *t, float *grad, hipStream_t s) {
+                          float *t, float *grad, hipStream_t s, const PotWeights *pw = nullptr) {
     const PlanParams &pp = pl.pp;
     SpreadArgs sa{pp.kb, pp.G, pp.T, pp.G / pp.T, pp.m, pl.wpoly.p};
     // the tile side shrinks to the grid size for small grids
@@ -2468,11 +2488,18 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                                    src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
             } else {
                 if constexpr (D == 3 && W + BRICK_X - 1 <= 16) mf = use_mfma(pl, src);
+                FS_REQUIRE(!pw || mf, FS_EINVAL, "weights from potentials need the matrix-core spread");
                 if (mf) {
-                    if constexpr (D == 3 && W + BRICK_X - 1 <= 16)
-                        hipLaunchKernelGGL((k_spread_mfma16<W>), dim3(src.n_mblocks), dim3(256), 0,
-                                           s, src.rec.p, w, src.mblocks.p, src.mgroups.p, sa,
-                                           pl.scratch.p);
+                    if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
+                        if (pw)
+                            hipLaunchKernelGGL((k_spread_mfma16<W, true>), dim3(src.n_mblocks),
+                                               dim3(256), 0, s, src.rec.p, w, src.mblocks.p,
+                                               src.mgroups.p, sa, pl.scratch.p, *pw);
+                        else
+                            hipLaunchKernelGGL((k_spread_mfma16<W, false>), dim3(src.n_mblocks),
+                                               dim3(256), 0, s, src.rec.p, w, src.mblocks.p,
+                                               src.mgroups.p, sa, pl.scratch.p, PotWeights{});
+                    }
                     tile_boxes = src.mtile_block.p;
                     multi = src.mmulti_tiles.p;
                     n_multi = src.n_mmulti;
@@ -2630,20 +2657,33 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
 
 template <int D>
 void dispatch_w(Plan &pl, const Nodes &src, const Nodes &dst, const float *w, float *t,
-                float *grad, hipStream_t s) {
+                float *grad, hipStream_t s, const PotWeights *pw = nullptr) {
     switch (pl.pp.W) {
-        case 4: return launch_spread_gather<D, 4>(pl, src, dst, w, t, grad, s);
-        case 6: return launch_spread_gather<D, 6>(pl, src, dst, w, t, grad, s);
-        case 8: return launch_spread_gather<D, 8>(pl, src, dst, w, t, grad, s);
-        case 10: return launch_spread_gather<D, 10>(pl, src, dst, w, t, grad, s);
-        case 12: return launch_spread_gather<D, 12>(pl, src, dst, w, t, grad, s);
-        case 14: return launch_spread_gather<D, 14>(pl, src, dst, w, t, grad, s);
-        case 16: return launch_spread_gather<D, 16>(pl, src, dst, w, t, grad, s);
+        case 4: return launch_spread_gather<D, 4>(pl, src, dst, w, t, grad, s, pw);
+        case 6: return launch_spread_gather<D, 6>(pl, src, dst, w, t, grad, s, pw);
+        case 8: return launch_spread_gather<D, 8>(pl, src, dst, w, t, grad, s, pw);
+        case 10: return launch_spread_gather<D, 10>(pl, src, dst, w, t, grad, s, pw);
+        case 12: return launch_spread_gather<D, 12>(pl, src, dst, w, t, grad, s, pw);
+        case 14: return launch_spread_gather<D, 14>(pl, src, dst, w, t, grad, s, pw);
+        case 16: return launch_spread_gather<D, 16>(pl, src, dst, w, t, grad, s, pw);
         default: FS_REQUIRE(false, FS_EINVAL, "unsupported window %d", pl.pp.W);
     }
 }
 
 }  // namespace
+
+bool plan_fuses_weights(const Plan &pl, int transpose) {
+    const Nodes &src = pl.src(transpose);
+    return pl.pp.d == 3 && !pl.pp.nearfield && pl.pp.W + BRICK_X - 1 <= 16 && use_mfma(pl, src) &&
+           src.nchunks > 0;
+}
+
+void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
+                           hipStream_t s) {
+    FS_REQUIRE(plan_fuses_weights(pl, transpose), FS_EINVAL,
+               "weights from potentials need the 3-D matrix-core spread without near field");
+    dispatch_w<3>(pl, pl.src(transpose), pl.dst(transpose), nullptr, t_sorted, nullptr, s, &pw);
+}
 
 void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *grad,
                        int transpose, hipStream_t s) {

@@ -35,6 +35,12 @@ struct Op {
     // transpose = 0: t (X, op order) = K w (Y, op order); 1: t (Y) = K^T w (X).
     // grad (nullable): gradient of t with respect to the target positions (op order, x d).
     void apply(const float *w, float *t, float *grad, int transpose, hipStream_t s);
+    // The same sum with source weights base_k exp((pot_k - max) / eps) (max: the largest of
+    // nparts per-block maxima), formed inside the spread where the plan supports it
+    // (fuses_weights), else through the weight array w.
+    bool fuses_weights(int transpose) const;
+    void apply_pot(const float *base, const double *pot, const double *parts, int nparts,
+                   double eps, float *w, float *t, int transpose, hipStream_t s);
 };
 
 std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m, int d,

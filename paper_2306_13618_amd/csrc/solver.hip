@@ -44,7 +44,7 @@ __device__ __forceinline__ double block_max(double v, double *red) {
     return m;
 }
 
-// w_k = base_k exp((pot_k - pmax) / eps)  (FP64 exponent, FP32 result), where pmax is the max
+// w_k = base_k exp((pot_k - pmax) / eps)  (weight_exp: FP64 exponent, FP32 result), pmax the max
 // of the nparts per-block maxima written by the update kernel (or a single value, nparts = 1).
 __global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
                                                  const double *__restrict__ pot,
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
     const double pm = (mx == -INFINITY) ? 0.0 : mx;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        w[i] = (float)((double)base[i] * exp((pot[i] - pm) * inv_eps));
+        w[i] = weight_exp(base[i], (pot[i] - pm) * inv_eps);
 }
 
 // pot_i = -kappa (shift + eps log t_i) in FP64, shift = max of the other potential (the max of
@@ -453,6 +453,32 @@ const float *Op::coords(int side) const {
     return side == 0 ? x : y;
 }
 
+namespace {
+void launch_weights(const float *base, const double *pot, const double *parts, int nparts,
+                    double eps, int64_t n, float *w, hipStream_t s);
+}  // namespace
+
+bool Op::fuses_weights(int transpose) const {
+    return fast && count(transpose ? 0 : 1) > 0 && count(transpose ? 1 : 0) > 0 &&
+           plan_fuses_weights(*plan, transpose);
+}
+
+void Op::apply_pot(const float *base, const double *pot, const double *parts, int nparts,
+                   double eps, float *w, float *t, int transpose, hipStream_t s) {
+    if (fuses_weights(transpose)) {
+        PotWeights pw;
+        pw.base = base;
+        pw.pot = pot;
+        pw.parts = parts;
+        pw.nparts = nparts;
+        pw.inv_eps = 1.0 / eps;
+        plan_apply_sorted_pot(*plan, pw, t, transpose, s);
+        return;
+    }
+    launch_weights(base, pot, parts, nparts, eps, count(transpose ? 0 : 1), w, s);
+    apply(w, t, nullptr, transpose, s);
+}
+
 void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t s) {
     const int64_t nt = transpose ? m : n, ns = transpose ? n : m;
     if (nt == 0) return;
@@ -592,14 +618,12 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     int done = 0;
     for (int it = 0; it < iters; ++it) {
         // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}
-        launch_weights(b_o, g_o, sc.gparts.p, sc.ng, eps, m, wY.p, s);
-        op.apply(wY.p, tX.p, nullptr, 0, s);
+        op.apply_pot(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, tX.p, 0, s);
         if (n > 0)
             sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
                                   sc.nbad.p, fd, s);
         // gamma half-step (Delta even): t~_j = sum_i k_ij a_i e^{f_i/eps}
-        launch_weights(a_o, f_o, sc.fparts.p, sc.nf, eps, n, wX.p, s);
-        op.apply(wX.p, tY.p, nullptr, 1, s);
+        op.apply_pot(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, tY.p, 1, s);
         if (m > 0)
             sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
                                   sc.nbad.p, gd, s);
