@@ -342,7 +342,9 @@ def main():
     sp = sp_ms / sp_cnt  # sampled over the timed steps
     flops_per_launch = n * 2.0 * W ** d          # one multiply and one add per window point
     achieved_tflops = flops_per_launch / (sp * 1e-3) / 1e12
-    bytes_per_launch = n * (16 + 4) + 4 * args.grid ** d  # node record + weight, grid written
+    # node record, FP32 base weight and FP64 potential (the weights are formed in the spread),
+    # grid written
+    bytes_per_launch = n * (16 + 4 + 8) + 4 * args.grid ** d
     traffic = traffic_from_profile(os.path.join(ROOT, "paper_2306_13618_amd", "csrc", "nfft.hip"))
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP16_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP16_MFMA_TFLOPS,
