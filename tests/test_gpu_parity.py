@@ -153,6 +153,32 @@ def test_fastsum_nearfield_matrix_core_groups(kind, lam):
     assert np.any(got != valu)  # the two paths differ in rounding: the matrix cores ran
 
 
+@pytest.mark.parametrize("window", [2, 3])
+def test_fastsum_matrix_core_small_windows(window):
+    """Windows of 4 and 6 points (two matrix rows of z offsets, partly empty operand columns): the
+    matrix-core spread and gather against the lane-per-node kernels on every row."""
+    x, y, v = dense_and_sparse(30_000, 28_001, 40 + window)
+    args = dict(kernel="gauss", lam=0.05, grid=64, window=window)
+    got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
+    valu = fu.fastsum_apply(T(x), T(y), T(v), flags=fu.FLAG_FORCE_VALU, **args).cpu().numpy()
+    assert relinf(got, valu) < 2e-6
+    assert np.any(got != valu)
+
+
+@pytest.mark.parametrize("n,m", [(64, 48), (17, 1), (1, 300)])
+def test_fastsum_matrix_core_tiny_clusters(n, m):
+    """A few points in one cluster (a handful of groups, one block per tile, blocks of the minimum
+    size) against the oracle."""
+    rng = np.random.default_rng([50, n, m])
+    x = rng.uniform(-0.002, 0.002, (n, 3)).astype(np.float32)
+    y = rng.uniform(-0.002, 0.002, (m, 3)).astype(np.float32)
+    v = rng.uniform(0.5, 1.5, m).astype(np.float32)
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=0.02, grid=64,
+                           window=6).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, "gauss", 0.02)
+    assert relinf(got, ref) < TOL
+
+
 def test_uot_matrix_core_groups():
     """A Sinkhorn solve whose kernel sums take the 3-D matrix-core spread and gather (dense
     clusters, grid 64^3) against the oracle's iterates."""
