@@ -112,6 +112,15 @@ __device__ __forceinline__ float weight_exp(float base, double x) {
     return ldexpf(base * expf(r), k);
 }
 
+// log v of a positive FP32 kernel sum, returned in FP64 to FP32 accuracy: v = f 2^e with f in
+// [0.5, 1) (frexp), log v = e ln 2 + log f with log f in FP32 (|log f| <= ln 2, so its error is
+// about 4e-8 absolute, below the relative error of the FP32 sum itself).
+__device__ __forceinline__ double sum_log(float v) {
+    int e = 0;
+    const float f = frexpf(v, &e);
+    return (double)e * 0.6931471805599453 + (double)logf(f);
+}
+
 // ------------------------------------------------------------------ Kaiser-Bessel window
 // Window in grid units (s = distance to the grid point times the grid size), cutoff m, shape b,
 // normalised to phi(0) = 1:

@@ -103,11 +103,29 @@ struct PotWeights {
     double inv_eps = 1.0;
 };
 
+// The potential update of a Sinkhorn half-step applied to the kernel sums t_k as they are
+// formed: pot_k = -kappa (shift + eps log t_k), shift the largest of nshift maxima (0 when all
+// are -inf); one maximum of the new potential per workgroup goes to out_parts (and of |new - old|
+// to delta_parts when it is not null); non-positive sums are counted in *nbad and replaced by the
+// smallest normal float.
+struct PotUpdate {
+    const double *shift_parts = nullptr;
+    int nshift = 0;
+    double kappa = 1.0, eps = 1.0;
+    double *pot = nullptr, *out_parts = nullptr, *delta_parts = nullptr;
+    int *nbad = nullptr;
+};
+
 // True when the kernel sum of this direction evaluates such weights inside its spread (3-D
 // matrix-core spread, no near field); plan_apply_sorted_pot then needs no weight array.
 bool plan_fuses_weights(const Plan &pl, int transpose);
+// True when, in addition, the gather forms the potential update itself (3-D matrix-core gather);
+// plan_update_parts is then the number of maxima it writes.
+bool plan_fuses_update(const Plan &pl, int transpose);
+int plan_update_parts(const Plan &pl, int transpose);
+// With pu the sums are not stored: the gather applies the update (t_sorted may be null).
 void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
-                           hipStream_t s);
+                           hipStream_t s, const PotUpdate *pu = nullptr);
 
 // Permutations between caller order and a node set's sorted order.
 void gather_to_sorted(const Nodes &nd, const float *v, float *v_sorted, hipStream_t s);

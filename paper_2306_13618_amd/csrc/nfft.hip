@@ -20,6 +20,7 @@
 //    first forward pass of each axis; the multiply by M_k is fused between the forward and inverse
 //    transform of the last axis.
 #include <algorithm>
+#include <cfloat>
 #include <cstring>
 
 #include "nfft.h"
@@ -240,6 +241,16 @@ __device__ __forceinline__ float wpoly_eval(const float *__restrict__ c, float u
 #pragma unroll
     for (int k = WPOLY - 2; k >= 0; --k) v = fmaf(v, u, c[k]);
     return v;
+}
+
+// Largest v over a workgroup of 256 threads (wave shuffles, then one value per wave through
+// red[4]); every thread gets the result.
+__device__ __forceinline__ double block_max_f64(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();  // red may still be read by a previous call
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 constexpr int FFT_THREADS = 256;
@@ -1443,14 +1454,15 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
 // four columns, high parts then low parts, 16 bytes), scaled by a power of two so that its largest
 // value is about 2^14 (no FP16 overflow; the lost low bits are below 2^-39 of the largest value).
 // Lane l then holds E_y[4 (l / 16) + r][l % 16] and forms the y, z sums for node l % 16 over its
-// four rows.
-template <int W>
+// four rows.  With UPD the sums are not stored; the potential update (PotUpdate) is applied to
+// them and each workgroup writes its maxima.
+template <int W, bool UPD>
 __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict__ rec,
                                                        const int4 *__restrict__ mblocks,
                                                        const int4 *__restrict__ mgroups,
                                                        SpreadArgs sa,
                                                        const float *__restrict__ grid,
-                                                       float *__restrict__ out) {
+                                                       float *__restrict__ out, PotUpdate pu) {
     constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
     constexpr int NC = 5;  // groups of 4 columns per row: x < 20 covers 4 + 16 columns
     constexpr int NZ = (W + 3) / 4;
@@ -1459,6 +1471,7 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
     __shared__ __align__(16) _Float16 bx[S * S][NC][8];
     __shared__ float phi[4][3][W][16];
     __shared__ float red[4];
+    __shared__ double dred[4];
     const int4 mb = mblocks[blockIdx.x];
     int tc[3];
     tile_coords<3>(mb.x, sa.ntd, tc);
@@ -1509,6 +1522,14 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int node = lane & 15, slot = lane >> 4;
+    double shift = 0.0, pmx = -INFINITY, dmx = 0.0;
+    int bad = 0;
+    if (UPD) {
+        double v = -INFINITY;
+        for (int b = threadIdx.x; b < pu.nshift; b += blockDim.x) v = fmax(v, pu.shift_parts[b]);
+        shift = block_max_f64(v, dred);
+        if (shift == -INFINITY) shift = 0.0;
+    }
     float wc[NZ][WPOLY];
 #pragma unroll
     for (int e = 0; e < NZ; ++e) {
@@ -1519,9 +1540,12 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
     float(*ph)[W][16] = phi[wave];
     const int per = (mb.z + 3) / 4;
     const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
-    if (gb >= ge) return;
-    int4 grn = mgroups[gb];
-    float4 rn = rec[grn.x + min(node, grn.y - 1)];
+    int4 grn = make_int4(0, 1, 0, 0);
+    float4 rn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (gb < ge) {
+        grn = mgroups[gb];
+        rn = rec[grn.x + min(node, grn.y - 1)];
+    }
     for (int g = gb; g < ge; ++g) {
         const int4 gr = grn;
         const float4 r = rn;
@@ -1584,10 +1608,34 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
         for (int rr = 0; rr < 4; ++rr) part = fmaf(pz[rr], ty[rr], part);
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);
-        if (slot == 0 && node < gr.y) out[gr.x + node] = part * unscale;
+        if (slot == 0 && node < gr.y) {
+            const int k = gr.x + node;
+            float t = part * unscale;
+            if (!UPD) {
+                out[k] = t;
+            } else {
+                if (!(t > 0.0f)) {
+                    ++bad;
+                    t = FLT_MIN;
+                }
+                const double f = -pu.kappa * (shift + pu.eps * sum_log(t));
+                if (pu.delta_parts) dmx = fmax(dmx, fabs(f - pu.pot[k]));
+                pu.pot[k] = f;
+                pmx = fmax(pmx, f);
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (UPD) {
+        if (bad) atomicAdd(pu.nbad, bad);
+        pmx = block_max_f64(pmx, dred);
+        if (threadIdx.x == 0) pu.out_parts[blockIdx.x] = pmx;
+        if (pu.delta_parts) {
+            dmx = block_max_f64(dmx, dred);
+            if (threadIdx.x == 0) pu.delta_parts[blockIdx.x] = dmx;
+        }
     }
 }
 
@@ -1890,7 +1938,7 @@ void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s,
 template <int W>
 int mfma_blocks_per_cu() {
     int a = 0, b = 0;
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W>, 256, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W, true>, 256, 0));
     FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W, true>, 256, 0));
     return std::max(1, std::min(a, b));
 }
@@ -2470,7 +2518,8 @@ bool use_mfma(const Plan &pl, const Nodes &nd) {
 
 template <int D, int W>
 void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const float *w,
-                          float *t, float *grad, hipStream_t s, const PotWeights *pw = nullptr) {
+                          float *t, float *grad, hipStream_t s, const PotWeights *pw = nullptr,
+                          const PotUpdate *pu = nullptr) {
     const PlanParams &pp = pl.pp;
     SpreadArgs sa{pp.kb, pp.G, pp.T, pp.G / pp.T, pp.m, pl.wpoly.p};
     // the tile side shrinks to the grid size for small grids
@@ -2618,9 +2667,15 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 bool mf = false;
                 if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                     mf = !grad && use_mfma(pl, dst);
-                    if (mf)
-                        hipLaunchKernelGGL((k_gather_mfma16<W>), dim3(dst.n_mblocks), dim3(256), 0, s,
-                                           dst.rec.p, dst.mblocks.p, dst.mgroups.p, sa, pl.grid.p, t);
+                    FS_REQUIRE(!pu || mf, FS_EINVAL, "the fused update needs the matrix-core gather");
+                    if (mf && pu)
+                        hipLaunchKernelGGL((k_gather_mfma16<W, true>), dim3(dst.n_mblocks),
+                                           dim3(256), 0, s, dst.rec.p, dst.mblocks.p,
+                                           dst.mgroups.p, sa, pl.grid.p, nullptr, *pu);
+                    else if (mf)
+                        hipLaunchKernelGGL((k_gather_mfma16<W, false>), dim3(dst.n_mblocks),
+                                           dim3(256), 0, s, dst.rec.p, dst.mblocks.p,
+                                           dst.mgroups.p, sa, pl.grid.p, t, PotUpdate{});
                 }
                 if (mf) {
                     // launched above
@@ -2657,15 +2712,16 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
 
 template <int D>
 void dispatch_w(Plan &pl, const Nodes &src, const Nodes &dst, const float *w, float *t,
-                float *grad, hipStream_t s, const PotWeights *pw = nullptr) {
+                float *grad, hipStream_t s, const PotWeights *pw = nullptr,
+                const PotUpdate *pu = nullptr) {
     switch (pl.pp.W) {
-        case 4: return launch_spread_gather<D, 4>(pl, src, dst, w, t, grad, s, pw);
-        case 6: return launch_spread_gather<D, 6>(pl, src, dst, w, t, grad, s, pw);
-        case 8: return launch_spread_gather<D, 8>(pl, src, dst, w, t, grad, s, pw);
-        case 10: return launch_spread_gather<D, 10>(pl, src, dst, w, t, grad, s, pw);
-        case 12: return launch_spread_gather<D, 12>(pl, src, dst, w, t, grad, s, pw);
-        case 14: return launch_spread_gather<D, 14>(pl, src, dst, w, t, grad, s, pw);
-        case 16: return launch_spread_gather<D, 16>(pl, src, dst, w, t, grad, s, pw);
+        case 4: return launch_spread_gather<D, 4>(pl, src, dst, w, t, grad, s, pw, pu);
+        case 6: return launch_spread_gather<D, 6>(pl, src, dst, w, t, grad, s, pw, pu);
+        case 8: return launch_spread_gather<D, 8>(pl, src, dst, w, t, grad, s, pw, pu);
+        case 10: return launch_spread_gather<D, 10>(pl, src, dst, w, t, grad, s, pw, pu);
+        case 12: return launch_spread_gather<D, 12>(pl, src, dst, w, t, grad, s, pw, pu);
+        case 14: return launch_spread_gather<D, 14>(pl, src, dst, w, t, grad, s, pw, pu);
+        case 16: return launch_spread_gather<D, 16>(pl, src, dst, w, t, grad, s, pw, pu);
         default: FS_REQUIRE(false, FS_EINVAL, "unsupported window %d", pl.pp.W);
     }
 }
@@ -2678,11 +2734,21 @@ bool plan_fuses_weights(const Plan &pl, int transpose) {
            src.nchunks > 0;
 }
 
+bool plan_fuses_update(const Plan &pl, int transpose) {
+    const Nodes &dst = pl.dst(transpose);
+    return plan_fuses_weights(pl, transpose) && use_mfma(pl, dst) && dst.nchunks > 0;
+}
+
+int plan_update_parts(const Plan &pl, int transpose) { return pl.dst(transpose).n_mblocks; }
+
 void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
-                           hipStream_t s) {
+                           hipStream_t s, const PotUpdate *pu) {
     FS_REQUIRE(plan_fuses_weights(pl, transpose), FS_EINVAL,
                "weights from potentials need the 3-D matrix-core spread without near field");
-    dispatch_w<3>(pl, pl.src(transpose), pl.dst(transpose), nullptr, t_sorted, nullptr, s, &pw);
+    FS_REQUIRE(!pu || plan_fuses_update(pl, transpose), FS_EINVAL,
+               "the fused update needs the 3-D matrix-core gather");
+    dispatch_w<3>(pl, pl.src(transpose), pl.dst(transpose), nullptr, t_sorted, nullptr, s, &pw,
+                  pu);
 }
 
 void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *grad,

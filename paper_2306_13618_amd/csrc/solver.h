@@ -41,6 +41,12 @@ struct Op {
     bool fuses_weights(int transpose) const;
     void apply_pot(const float *base, const double *pot, const double *parts, int nparts,
                    double eps, float *w, float *t, int transpose, hipStream_t s);
+    // The same, with the potential update applied to the sums inside the gather (no t): only
+    // where fuses_update; update_parts maxima are then written.
+    bool fuses_update(int transpose) const;
+    int update_parts(int transpose) const;
+    void apply_pot_update(const float *base, const double *pot, const double *parts, int nparts,
+                          double eps, const PotUpdate &pu, int transpose, hipStream_t s);
 };
 
 std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m, int d,

@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
             if (i < n) {
                 float vk = v[k];
                 if (!(vk > 0.0f)) { bad++; vk = FLT_MIN; }
-                const double f = -kappa * (sh + eps * log((double)vk));
+                const double f = -kappa * (sh + eps * sum_log(vk));
                 if (DELTA) dmx = fmax(dmx, fabs(f - o[k]));
                 pot[i] = f;
                 mx = fmax(mx, f);
@@ -479,6 +479,23 @@ void Op::apply_pot(const float *base, const double *pot, const double *parts, in
     apply(w, t, nullptr, transpose, s);
 }
 
+bool Op::fuses_update(int transpose) const {
+    return fuses_weights(transpose) && plan_fuses_update(*plan, transpose);
+}
+
+int Op::update_parts(int transpose) const { return plan_update_parts(*plan, transpose); }
+
+void Op::apply_pot_update(const float *base, const double *pot, const double *parts, int nparts,
+                          double eps, const PotUpdate &pu, int transpose, hipStream_t s) {
+    PotWeights pw;
+    pw.base = base;
+    pw.pot = pot;
+    pw.parts = parts;
+    pw.nparts = nparts;
+    pw.inv_eps = 1.0 / eps;
+    plan_apply_sorted_pot(*plan, pw, nullptr, transpose, s, &pu);
+}
+
 void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t s) {
     const int64_t nt = transpose ? m : n, ns = transpose ? n : m;
     if (nt == 0) return;
@@ -617,16 +634,44 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     double *fd = track ? sc.dparts.p : nullptr, *gd = track ? sc.dparts.p + UPD_BLOCKS : nullptr;
     int done = 0;
     for (int it = 0; it < iters; ++it) {
-        // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}
-        op.apply_pot(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, tX.p, 0, s);
-        if (n > 0)
-            sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
-                                  sc.nbad.p, fd, s);
-        // gamma half-step (Delta even): t~_j = sum_i k_ij a_i e^{f_i/eps}
-        op.apply_pot(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, tY.p, 1, s);
-        if (m > 0)
-            sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
-                                  sc.nbad.p, gd, s);
+        // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}, then the f update
+        if (n > 0 && op.fuses_update(0) && op.update_parts(0) <= UPD_BLOCKS) {
+            PotUpdate pu;
+            pu.shift_parts = sc.gparts.p;
+            pu.nshift = sc.ng;
+            pu.kappa = kappa;
+            pu.eps = eps;
+            pu.pot = f_o;
+            pu.out_parts = sc.fparts.p;
+            pu.delta_parts = fd;
+            pu.nbad = sc.nbad.p;
+            op.apply_pot_update(b_o, g_o, sc.gparts.p, sc.ng, eps, pu, 0, s);
+            sc.nf = op.update_parts(0);
+        } else {
+            op.apply_pot(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, tX.p, 0, s);
+            if (n > 0)
+                sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
+                                      sc.nbad.p, fd, s);
+        }
+        // gamma half-step (Delta even): t~_j = sum_i k_ij a_i e^{f_i/eps}, then the g update
+        if (m > 0 && op.fuses_update(1) && op.update_parts(1) <= UPD_BLOCKS) {
+            PotUpdate pu;
+            pu.shift_parts = sc.fparts.p;
+            pu.nshift = sc.nf;
+            pu.kappa = kappa;
+            pu.eps = eps;
+            pu.pot = g_o;
+            pu.out_parts = sc.gparts.p;
+            pu.delta_parts = gd;
+            pu.nbad = sc.nbad.p;
+            op.apply_pot_update(a_o, f_o, sc.fparts.p, sc.nf, eps, pu, 1, s);
+            sc.ng = op.update_parts(1);
+        } else {
+            op.apply_pot(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, tY.p, 1, s);
+            if (m > 0)
+                sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
+                                      sc.nbad.p, gd, s);
+        }
         ++done;
         if (track) {
             hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.dparts.p, 2 * UPD_BLOCKS,
