@@ -35,7 +35,10 @@ struct Nodes {
 };
 
 constexpr int BRICK_X = 4;
-constexpr int MIN_GROUPS_PER_BLOCK = 4;  // one per wave
+// Waves per workgroup of the 3-D matrix-core spread and gather (each wave takes a contiguous run
+// of the workgroup's groups; the workgroup shares one box of the tile).
+constexpr int MW = 8;
+constexpr int MIN_GROUPS_PER_BLOCK = MW;  // one per wave
 
 enum Regime { REGIME_CUBE = 0, REGIME_BALL = 1 };
 

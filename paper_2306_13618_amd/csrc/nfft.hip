@@ -243,14 +243,16 @@ __device__ __forceinline__ float wpoly_eval(const float *__restrict__ c, float u
     return v;
 }
 
-// Largest v over a workgroup of 256 threads (wave shuffles, then one value per wave through
-// red[4]); every thread gets the result.
+// Largest v over the workgroup (wave shuffles, then one value per wave through red, which holds
+// blockDim.x / 64 values); every thread gets the result.
 __device__ __forceinline__ double block_max_f64(double v, double *red) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     __syncthreads();  // red may still be read by a previous call
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double m = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+    return m;
 }
 
 constexpr int FFT_THREADS = 256;
@@ -1299,7 +1301,7 @@ __device__ __forceinline__ void split_f16(float a, float b, f16x2 &hi, f16x2 &lo
 // chunk_scale).  With POT the weights are w_k = base_k exp((pot_k - pmax) / eps), evaluated here
 // (weight_exp: FP64 exponent, FP32 result) instead of read from w.
 template <int W, bool POT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
                 const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups, SpreadArgs sa,
                 float *__restrict__ scratch, PotWeights pw) {
@@ -1310,11 +1312,11 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
     constexpr int PX = W + 1;            // row stride of the x table (odd: no bank conflicts)
     static_assert(XR <= 16, "brick and window exceed the 16 matrix rows");
     __shared__ int box[BOX];
-    __shared__ float phx[4][16 * PX];     // per wave: alpha px, node-major
-    __shared__ float phyz[4][2][W][16];   // per wave: py and pz, offset-major
-    __shared__ int oxs[4][16];
+    __shared__ float phx[MW][16 * PX];     // per wave: alpha px, node-major
+    __shared__ float phyz[MW][2][W][16];   // per wave: py and pz, offset-major
+    __shared__ int oxs[MW][16];
     __shared__ float red[16];
-    __shared__ double pmx[4];
+    __shared__ double pmx[MW];
     const int4 mb = mblocks[blockIdx.x];
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
@@ -1323,10 +1325,7 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
     if (POT) {
         double mx = -INFINITY;
         for (int b = threadIdx.x; b < pw.nparts; b += blockDim.x) mx = fmax(mx, pw.parts[b]);
-        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
-        if ((threadIdx.x & 63) == 0) pmx[threadIdx.x >> 6] = mx;
-        __syncthreads();
-        mx = fmax(fmax(pmx[0], pmx[1]), fmax(pmx[2], pmx[3]));
+        mx = block_max_f64(mx, pmx);
         pmax = (mx == -INFINITY) ? 0.0 : mx;
     }
     auto weight = [&](int k) -> float {
@@ -1353,7 +1352,7 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
     float *px = phx[wave];
     float(*pyz)[W][16] = phyz[wave];
     int *ox = oxs[wave];
-    const int per = (mb.z + 3) / 4;
+    const int per = (mb.z + MW - 1) / MW;
     const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
     f32x4 acc[NB];
 #pragma unroll
@@ -1457,7 +1456,7 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
 // four rows.  With UPD the sums are not stored; the potential update (PotUpdate) is applied to
 // them and each workgroup writes its maxima.
 template <int W, bool UPD>
-__global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict__ rec,
+__global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restrict__ rec,
                                                        const int4 *__restrict__ mblocks,
                                                        const int4 *__restrict__ mgroups,
                                                        SpreadArgs sa,
@@ -1466,12 +1465,13 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
     constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
     constexpr int NC = 5;  // groups of 4 columns per row: x < 20 covers 4 + 16 columns
     constexpr int NZ = (W + 3) / 4;
-    constexpr int PER = (BOX + 255) / 256;
+    constexpr int NT = 64 * MW;
+    constexpr int PER = (BOX + NT - 1) / NT;
     static_assert(W + BRICK_X - 1 <= 16 && S <= 4 * NC, "brick and window exceed the 16 columns");
     __shared__ __align__(16) _Float16 bx[S * S][NC][8];
-    __shared__ float phi[4][3][W][16];
-    __shared__ float red[4];
-    __shared__ double dred[4];
+    __shared__ float phi[MW][3][W][16];
+    __shared__ float red[MW];
+    __shared__ double dred[MW];
     const int4 mb = mblocks[blockIdx.x];
     int tc[3];
     tile_coords<3>(mb.x, sa.ntd, tc);
@@ -1481,7 +1481,7 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
     float mx = 0.0f;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int q = threadIdx.x + 256 * i;
+        const int q = threadIdx.x + NT * i;
         v[i] = 0.0f;
         if (q < BOX) {
             const int l0 = q % S, l1 = (q / S) % S, l2 = q / (S * S);
@@ -1495,13 +1495,14 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
     for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     // columns x >= S of every row are zero
-    for (int q = threadIdx.x; q < S * S * (4 * NC - S); q += 256) {
+    for (int q = threadIdx.x; q < S * S * (4 * NC - S); q += NT) {
         const int row = q / (4 * NC - S), x = S + q % (4 * NC - S);
         bx[row][x >> 2][x & 3] = (_Float16)0.0f;
         bx[row][x >> 2][4 + (x & 3)] = (_Float16)0.0f;
     }
     __syncthreads();
-    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    mx = red[0];
+    for (int i = 1; i < MW; ++i) mx = fmaxf(mx, red[i]);
     // power-of-two scale: largest |value| in [2^13, 2^14)
     int ex = 0;
     frexpf(mx, &ex);
@@ -1509,7 +1510,7 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
     const float unscale = (mx > 0.0f) ? ldexpf(1.0f, ex - 14) : 1.0f;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int q = threadIdx.x + 256 * i;
+        const int q = threadIdx.x + NT * i;
         if (q < BOX) {
             const float u = v[i] * scale;
             const _Float16 h = (_Float16)u;
@@ -1538,7 +1539,7 @@ __global__ void __launch_bounds__(256) k_gather_mfma16(const float4 *__restrict_
         for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
     }
     float(*ph)[W][16] = phi[wave];
-    const int per = (mb.z + 3) / 4;
+    const int per = (mb.z + MW - 1) / MW;
     const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
     int4 grn = make_int4(0, 1, 0, 0);
     float4 rn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -1938,8 +1939,8 @@ void exclusive_scan(const int *in, int64_t n, int *out, hipStream_t s,
 template <int W>
 int mfma_blocks_per_cu() {
     int a = 0, b = 0;
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W, true>, 256, 0));
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W, true>, 256, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W, true>, 64 * MW, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W, true>, 64 * MW, 0));
     return std::max(1, std::min(a, b));
 }
 
@@ -2542,11 +2543,11 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                     if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                         if (pw)
                             hipLaunchKernelGGL((k_spread_mfma16<W, true>), dim3(src.n_mblocks),
-                                               dim3(256), 0, s, src.rec.p, w, src.mblocks.p,
+                                               dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
                                                src.mgroups.p, sa, pl.scratch.p, *pw);
                         else
                             hipLaunchKernelGGL((k_spread_mfma16<W, false>), dim3(src.n_mblocks),
-                                               dim3(256), 0, s, src.rec.p, w, src.mblocks.p,
+                                               dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
                                                src.mgroups.p, sa, pl.scratch.p, PotWeights{});
                     }
                     tile_boxes = src.mtile_block.p;
@@ -2670,11 +2671,11 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                     FS_REQUIRE(!pu || mf, FS_EINVAL, "the fused update needs the matrix-core gather");
                     if (mf && pu)
                         hipLaunchKernelGGL((k_gather_mfma16<W, true>), dim3(dst.n_mblocks),
-                                           dim3(256), 0, s, dst.rec.p, dst.mblocks.p,
+                                           dim3(64 * MW), 0, s, dst.rec.p, dst.mblocks.p,
                                            dst.mgroups.p, sa, pl.grid.p, nullptr, *pu);
                     else if (mf)
                         hipLaunchKernelGGL((k_gather_mfma16<W, false>), dim3(dst.n_mblocks),
-                                           dim3(256), 0, s, dst.rec.p, dst.mblocks.p,
+                                           dim3(64 * MW), 0, s, dst.rec.p, dst.mblocks.p,
                                            dst.mgroups.p, sa, pl.grid.p, t, PotUpdate{});
                 }
                 if (mf) {
