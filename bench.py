@@ -358,7 +358,7 @@ def main():
     hbm = {}
     G = args.grid
     for name, nbytes in (("spread", bytes_per_launch),
-                         ("gather", n * (16 + 4) + 4 * G ** d),
+                         ("gather", n * (16 + 8) + 4 * G ** d),  # record, FP64 potential out
                          ("fft", 2 * 4 * G ** d)):
         t = passes[name]["avg_ms"]
         hbm[name] = {"algorithmic_bytes": nbytes,

@@ -472,13 +472,17 @@ __global__ void k_brick_groups(const int *__restrict__ key_start, int64_t nbrick
     gcount[b] = (s1 - s0 + 15) / 16;
 }
 
-// Sum of `per` consecutive entries per tile.
-__global__ void k_tile_sum(const int *__restrict__ in, int ntiles, int per, int *__restrict__ out) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
+// Sum of `per` consecutive entries per tile: one workgroup of 256 threads per tile.
+__global__ void __launch_bounds__(256) k_tile_sum(const int *__restrict__ in, int ntiles, int per,
+                                                  int *__restrict__ out) {
+    __shared__ int red[4];
+    const int t = blockIdx.x;
     int acc = 0;
-    for (int i = 0; i < per; ++i) acc += in[(int64_t)t * per + i];
-    out[t] = acc;
+    for (int i = threadIdx.x; i < per; i += blockDim.x) acc += in[(int64_t)t * per + i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[t] = red[0] + red[1] + red[2] + red[3];
 }
 
 // groups[gstart[b] + j] = (first node, node count, brick offset inside the tile's box, 0)
@@ -1985,7 +1989,7 @@ void mgroups_count(MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles
     hipLaunchKernelGGL(k_brick_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
                        mg.nbricks, (int)n, mg.gcount.p);
     FS_LAUNCHED();
-    hipLaunchKernelGGL(k_tile_sum, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, mg.gcount.p,
+    hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntiles), dim3(256), 0, s, mg.gcount.p,
                        (int)ntiles, (int)(cells_per_tile / BRICK_X), mg.tgroups.p);
     FS_LAUNCHED();
     FS_HIP(hipMemcpyAsync(mg.tg.data(), mg.tgroups.p, ntiles * sizeof(int),
