@@ -303,8 +303,11 @@ struct ScaleArgs {
 
 // Sort key of a node: its tile, and (when the key space is small enough) its cell inside the
 // tile, so that nodes are ordered by tile and, within a tile, by grid cell.
+// The node's rank among the nodes of its key (the counter's old value) is kept, so that the
+// scatter needs no second round of atomics.
 __global__ void k_keys(const float *__restrict__ p, int64_t n, ScaleArgs sa, int cell_keys,
-                       int *__restrict__ key, float4 *__restrict__ tmp, int *__restrict__ hist) {
+                       int *__restrict__ key, int *__restrict__ rank, float4 *__restrict__ tmp,
+                       int *__restrict__ hist) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     int cell[3] = {0, 0, 0};
@@ -333,7 +336,7 @@ __global__ void k_keys(const float *__restrict__ p, int64_t n, ScaleArgs sa, int
     const int kk = cell_keys ? tk * cells_per_tile + loc : tk;
     key[i] = kk;
     tmp[i] = make_float4(fr[0], fr[1], fr[2], __int_as_float(packed));
-    atomicAdd(&hist[kk], 1);
+    rank[i] = atomicAdd(&hist[kk], 1);
 }
 
 // Multi-block exclusive scan of an int array (up to 2^31 elements): block sums, a scan of the
@@ -437,14 +440,13 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(const int *__restrict__ his
 }
 
 __global__ void k_scatter_nodes(const float *__restrict__ p, int64_t n, int d,
-                                const int *__restrict__ key, const float4 *__restrict__ tmp,
-                                const int *__restrict__ tile_start, int *__restrict__ cursor,
-                                float4 *__restrict__ rec, int *__restrict__ perm,
-                                float *__restrict__ xs) {
+                                const int *__restrict__ key, const int *__restrict__ rank,
+                                const float4 *__restrict__ tmp,
+                                const int *__restrict__ tile_start, float4 *__restrict__ rec,
+                                int *__restrict__ perm, float *__restrict__ xs) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int t = key[i];
-    const int pos = tile_start[t] + atomicAdd(&cursor[t], 1);
+    const int pos = tile_start[key[i]] + rank[i];
     rec[pos] = tmp[i];
     perm[pos] = (int)i;
     for (int k = 0; k < d; ++k) xs[(int64_t)pos * d + k] = p[i * d + k];
@@ -2086,11 +2088,10 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     nd.perm.alloc(n + 1);
     nd.xs.alloc(n * d + 1);
     nd.tile_chunk.alloc(2 * ntiles);
-    DevBuf<int> key(n + 1), hist(nkeys), cursor(nkeys), kstart(nkeys), tcount(ntiles),
+    DevBuf<int> key(n + 1), rank(n + 1), hist(nkeys), kstart(nkeys), tcount(ntiles),
         tstart(ntiles), totals(2);
     DevBuf<float4> tmp(n + 1);
     fill_i32(hist.p, nkeys, 0, s);
-    fill_i32(cursor.p, nkeys, 0, s);
     ScaleArgs sa{};
     for (int k = 0; k < 3; ++k) sa.c[k] = pp.center[k];
     sa.inv_P = 1.0 / pp.P;
@@ -2101,7 +2102,7 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     sa.S = T + pp.W - 1;
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256), 0, s,
-                           pts, n, sa, (int)cell_keys, key.p, tmp.p, hist.p);
+                           pts, n, sa, (int)cell_keys, key.p, rank.p, tmp.p, hist.p);
         FS_LAUNCHED();
     }
     // device temporaries released, and host arrays kept alive, until the final synchronisation
@@ -2120,8 +2121,8 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     FS_LAUNCHED();
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter_nodes, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256),
-                           0, s, pts, n, d, key.p, tmp.p, kstart.p, cursor.p, nd.rec.p,
-                           nd.perm.p, nd.xs.p);
+                           0, s, pts, n, d, key.p, rank.p, tmp.p, kstart.p, nd.rec.p, nd.perm.p,
+                           nd.xs.p);
         FS_LAUNCHED();
     }
     // matrix-core groups (d = 3): per-brick and per-tile counts, read back with the chunk table
