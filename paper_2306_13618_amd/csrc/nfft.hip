@@ -206,12 +206,94 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Eight-point DFT in registers, V[k] = sum_m v[m] w^{mk}, w = e^{DIR 2 pi i / 8} (radix 2,
+// decimation in frequency; the outputs are written back in natural order).
+template <int DIR>
+__device__ __forceinline__ void dft8(float2 *v) {
+    constexpr float r = 0.70710678118654752f;
+    // stage 1: pairs (m, m + 4)
+    float2 t[8];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        t[m] = make_float2(v[m].x + v[m + 4].x, v[m].y + v[m + 4].y);
+        t[m + 4] = make_float2(v[m].x - v[m + 4].x, v[m].y - v[m + 4].y);
+    }
+    // twiddles w^m on the difference half: m = 1: (1 -/+ i) r, m = 2: -/+ i, m = 3: (-1 -/+ i) r
+    const float s = (DIR < 0) ? -1.0f : 1.0f;
+    {
+        const float2 a = t[5];
+        t[5] = make_float2(r * (a.x - s * a.y), r * (a.y + s * a.x));
+        const float2 b = t[6];
+        t[6] = make_float2(-s * b.y, s * b.x);
+        const float2 c = t[7];
+        t[7] = make_float2(r * (-c.x - s * c.y), r * (-c.y + s * c.x));
+    }
+    // stage 2: within each half, pairs (m, m + 2); twiddle w^{2m} = -/+ i on m = 1 (odd index)
+    float2 u[8];
+#pragma unroll
+    for (int h = 0; h < 8; h += 4) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            u[h + m] = make_float2(t[h + m].x + t[h + m + 2].x, t[h + m].y + t[h + m + 2].y);
+            u[h + m + 2] = make_float2(t[h + m].x - t[h + m + 2].x, t[h + m].y - t[h + m + 2].y);
+        }
+        const float2 d = u[h + 3];
+        u[h + 3] = make_float2(-s * d.y, s * d.x);
+    }
+    // stage 3: pairs (m, m + 1); the first half gives the even outputs, the second the odd ones
+    const float2 y0 = make_float2(u[0].x + u[1].x, u[0].y + u[1].y);
+    const float2 y4 = make_float2(u[0].x - u[1].x, u[0].y - u[1].y);
+    const float2 y2 = make_float2(u[2].x + u[3].x, u[2].y + u[3].y);
+    const float2 y6 = make_float2(u[2].x - u[3].x, u[2].y - u[3].y);
+    const float2 y1 = make_float2(u[4].x + u[5].x, u[4].y + u[5].y);
+    const float2 y5 = make_float2(u[4].x - u[5].x, u[4].y - u[5].y);
+    const float2 y3 = make_float2(u[6].x + u[7].x, u[6].y + u[7].y);
+    const float2 y7 = make_float2(u[6].x - u[7].x, u[6].y - u[7].y);
+    v[0] = y0; v[1] = y1; v[2] = y2; v[3] = y3; v[4] = y4; v[5] = y5; v[6] = y6; v[7] = y7;
+}
+
+// Batched 64-point FFTs as 8 x 8 (same contract as lds_fft with logL = 6): thread (t, j) takes the
+// 8-point DFT over m of a[t][j + 8 m], multiplies output k1 by w64^{j k1} and stores it at
+// b[t][8 k1 + j]; then thread (t, k1) takes the 8-point DFT over j of b[t][8 k1 + j] and stores
+// output k2 at a[t][k1 + 8 k2].  Two passes over LDS instead of six.
+template <int DIR>
+__device__ float2 *lds_fft64(float2 *a, float2 *b, int NB, const float2 *__restrict__ tw) {
+    for (int q = threadIdx.x; q < NB * 8; q += blockDim.x) {
+        const int t = q >> 3, j = q & 7;
+        float2 v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = a[t * 64 + j + 8 * m];
+        dft8<DIR>(v);
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) {
+            const int e = j * k1;  // < 64
+            float2 w = tw[e & 31];
+            if (e & 32) w = make_float2(-w.x, -w.y);
+            if (DIR > 0) w.y = -w.y;
+            b[t * 64 + 8 * k1 + j] = cmul(v[k1], w);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NB * 8; q += blockDim.x) {
+        const int t = q >> 3, k1 = q & 7;
+        float2 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = b[t * 64 + 8 * k1 + j];
+        dft8<DIR>(v);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) a[t * 64 + k1 + 8 * k2] = v[k2];
+    }
+    __syncthreads();
+    return a;
+}
+
 // Batched complex FFT of NB transforms of length L = 2^logL held in LDS (transform t at
 // a[t L .. t L + L)), Stockham radix-2, natural order in and out.  DIR = -1 forward
 // (e^{-2 pi i jk/L}), +1 inverse (unnormalised).  Returns the buffer holding the result.
 // tw[q] = exp(-2 pi i q / L) for q < L/2.  All threads of the block must call it.
 template <int DIR>
 __device__ float2 *lds_fft(float2 *a, float2 *b, int logL, int NB, const float2 *__restrict__ tw) {
+    if (logL == 6) return lds_fft64<DIR>(a, b, NB, tw);
     const int L = 1 << logL, H = L >> 1;
     for (int ls = 0; (1 << ls) < L; ++ls) {
         const int Ns = 1 << ls;
