@@ -960,7 +960,7 @@ __global__ void __launch_bounds__(256) k_fold_tiles(const float *__restrict__ sc
                                                     int T, int ntd, int m, int S,
                                                     float *__restrict__ grid) {
     constexpr int NN = (D == 1) ? 3 : (D == 2 ? 9 : 27);
-    __shared__ int nc0[NN], nnc[NN], norg[NN][3];
+    __shared__ int nc0[NN], nnc[NN];
     const int t = tiles ? tiles[blockIdx.x] : (int)blockIdx.x;
     int tc[3] = {0, 0, 0};
     tile_coords<D>(t, ntd, tc);
@@ -972,40 +972,52 @@ __global__ void __launch_bounds__(256) k_fold_tiles(const float *__restrict__ sc
             const int tk = (tc[k] + dk + ntd) % ntd;
             tid += tk * mul;
             mul *= ntd;
-            norg[threadIdx.x][k] = tk * T - (m - 1);
         }
-        nc0[threadIdx.x] = tile_chunk[2 * tid];
         nnc[threadIdx.x] = tile_chunk[2 * tid + 1];
+        int box = S;
+        if (D > 1) box *= S;
+        if (D > 2) box *= S;
+        nc0[threadIdx.x] = tile_chunk[2 * tid] * box;  // offset of the neighbour's reduced box
     }
     __syncthreads();
-    int box = S;
-    if (D > 1) box *= S;
-    if (D > 2) box *= S;
     int npts = T;
     if (D > 1) npts *= T;
     if (D > 2) npts *= T;
     for (int q = blockIdx.y * blockDim.x + threadIdx.x; q < npts; q += gridDim.y * blockDim.x) {
         int p[3] = {0, 0, 0};
+        // the point's offset inside the box of the neighbour d (d = -1, 0, 1) along each axis:
+        // i + m - 1 - d T (independent of the periodic wrap), inside when in [0, S)
+        int loc[3][3] = {};
+        bool in[3][3] = {};
         {
             int rem = q;
             for (int k = 0; k < D; ++k) {
-                p[k] = tc[k] * T + rem % T;
+                const int i = rem % T;
                 rem /= T;
+                p[k] = tc[k] * T + i;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    loc[k][e] = i + m - 1 - (e - 1) * T;
+                    in[k][e] = loc[k][e] >= 0 && loc[k][e] < S;
+                }
             }
         }
         // the covering boxes are read together (all loads in flight), then summed in order
         float v[NN];
 #pragma unroll
         for (int j = 0; j < NN; ++j) {
-            int l = 0, mul = 1;
-            bool inside = nnc[j] > 0;
-            for (int k = 0; k < D; ++k) {
-                const int loc = (p[k] - norg[j][k] + G) & (G - 1);
-                inside &= loc < S;
-                l += loc * mul;
-                mul *= S;
+            const int e0 = j % 3, e1 = (j / 3) % 3, e2 = j / 9;
+            int l = loc[0][e0];
+            bool inside = nnc[j] > 0 && in[0][e0];
+            if (D > 1) {
+                l += S * loc[1][e1];
+                inside = inside && in[1][e1];
             }
-            v[j] = inside ? scratch[(int64_t)nc0[j] * box + l] : 0.0f;
+            if (D > 2) {
+                l += S * S * loc[2][e2];
+                inside = inside && in[2][e2];
+            }
+            v[j] = inside ? scratch[nc0[j] + l] : 0.0f;
         }
         float acc = 0.0f;
 #pragma unroll
