@@ -77,6 +77,36 @@ struct DevBuf {
     T *get() const { return p; }
 };
 
+// ------------------------------------------------------------------ pinned staging
+// Small host <-> device copies of a plan build go through pinned host memory: a copy from or to
+// pageable memory makes the host wait for the stream, a pinned one is queued like a kernel.  The
+// pinned blocks come from a per-process pool and go back to it when the stage is destroyed,
+// after a synchronisation of its stream (a queued copy may still read them until then).
+class HostStage {
+public:
+    explicit HostStage(hipStream_t s) : s_(s) {}
+    HostStage(const HostStage &) = delete;
+    HostStage &operator=(const HostStage &) = delete;
+    ~HostStage();
+    // pinned host memory for `bytes`, valid until the stage is destroyed
+    void *pinned(size_t bytes);
+    // queue a copy of host memory (any kind) to the device through the stage
+    void upload(void *dst, const void *src, size_t bytes);
+    // queue a copy of device memory into pinned memory; its contents are valid after a
+    // synchronisation of the stream
+    template <class T>
+    T *download(const T *src, size_t count) {
+        T *h = static_cast<T *>(pinned(count * sizeof(T)));
+        if (count) FS_HIP(hipMemcpyAsync(h, src, count * sizeof(T), hipMemcpyDeviceToHost, s_));
+        return h;
+    }
+
+private:
+    hipStream_t s_;
+    std::vector<std::pair<char *, size_t>> blocks_;  // pinned blocks held: pointer, size
+    size_t used_ = 0;                                  // bytes used in the last block
+};
+
 // ------------------------------------------------------------------ launch helpers
 inline unsigned blocks_for(int64_t work, int threads, int64_t cap = 1 << 20) {
     int64_t b = (work + threads - 1) / threads;

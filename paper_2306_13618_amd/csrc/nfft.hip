@@ -2071,42 +2071,40 @@ int mfma_slots(int W) {
 struct MGroupBuild {
     int64_t nbricks = 0;
     DevBuf<int> gcount, tgroups;
-    std::vector<int> tg;  // groups per tile (host)
+    const int *tg = nullptr;  // groups per tile (pinned host copy, valid after the synchronisation)
 };
 
 // Stage 1 (before the synchronisation): groups per brick and per tile; the per-tile counts are
 // copied to mg.tg.
 void mgroups_count(MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles,
-                   int64_t cells_per_tile, hipStream_t s) {
+                   int64_t cells_per_tile, hipStream_t s, HostStage &hs) {
     mg.nbricks = ntiles * cells_per_tile / BRICK_X;
     mg.gcount.alloc(mg.nbricks + 1);
     mg.tgroups.alloc(ntiles);
-    mg.tg.assign(ntiles, 0);
     hipLaunchKernelGGL(k_brick_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
                        mg.nbricks, (int)n, mg.gcount.p);
     FS_LAUNCHED();
     hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntiles), dim3(256), 0, s, mg.gcount.p,
                        (int)ntiles, (int)(cells_per_tile / BRICK_X), mg.tgroups.p);
     FS_LAUNCHED();
-    FS_HIP(hipMemcpyAsync(mg.tg.data(), mg.tgroups.p, ntiles * sizeof(int),
-                          hipMemcpyDeviceToHost, s));
+    mg.tg = hs.download(mg.tgroups.p, (size_t)ntiles);
 }
 
 // Stage 2 (after it): block size from the per-tile counts, then the group and block tables.
-// Temporaries go to `keep`; host arrays whose copies may still be in flight go to `hkeep`.
+// Temporaries go to `keep`; the host tables are uploaded through the pinned stage `hs`.
 void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles,
                   const PlanParams &pp, int slots, hipStream_t s,
-                  std::vector<DevBuf<int>> &keep, std::vector<std::vector<int>> &hkeep) {
-    const std::vector<int> &tg = mg.tg;
+                  std::vector<DevBuf<int>> &keep, HostStage &hs) {
+    const int *tg = mg.tg;
     int64_t total = 0;
     int tmax = 0;
-    for (int v : tg) {
-        total += v;
-        tmax = std::max(tmax, v);
+    for (int64_t t = 0; t < ntiles; ++t) {
+        total += tg[t];
+        tmax = std::max(tmax, tg[t]);
     }
     auto blocks_at = [&](int g) {
         int64_t b = 0;
-        for (int v : tg) b += (v + g - 1) / g;
+        for (int64_t t = 0; t < ntiles; ++t) b += (tg[t] + g - 1) / g;
         return b;
     };
     int lo = (int)std::max<int64_t>(MIN_GROUPS_PER_BLOCK, (total + slots - 1) / std::max(slots, 1));
@@ -2140,13 +2138,9 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
     nd.mgroups.alloc(std::max<int64_t>(total, 1));
     nd.mblocks.alloc(nd.n_mblocks + 1);
     nd.mmulti_tiles.alloc(std::max<size_t>(multi.size(), 1));
-    FS_HIP(hipMemcpyAsync(dtgstart.p, tgstart.data(), ntiles * sizeof(int), hipMemcpyHostToDevice,
-                          s));
-    FS_HIP(hipMemcpyAsync(nd.mtile_block.p, tblock.data(), 2 * ntiles * sizeof(int),
-                          hipMemcpyHostToDevice, s));
-    if (!multi.empty())
-        FS_HIP(hipMemcpyAsync(nd.mmulti_tiles.p, multi.data(), multi.size() * sizeof(int),
-                              hipMemcpyHostToDevice, s));
+    hs.upload(dtgstart.p, tgstart.data(), ntiles * sizeof(int));
+    hs.upload(nd.mtile_block.p, tblock.data(), 2 * ntiles * sizeof(int));
+    hs.upload(nd.mmulti_tiles.p, multi.data(), multi.size() * sizeof(int));
     exclusive_scan(mg.gcount.p, mg.nbricks, gstart.p, s, &keep);
     hipLaunchKernelGGL(k_fill_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
                        gstart.p, mg.nbricks, (int)n, pp.T, pp.T + pp.W - 1, nd.mgroups.p);
@@ -2161,9 +2155,6 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
     keep.push_back(std::move(dtgstart));
     keep.push_back(std::move(mg.gcount));
     keep.push_back(std::move(mg.tgroups));
-    hkeep.push_back(std::move(tgstart));
-    hkeep.push_back(std::move(tblock));
-    hkeep.push_back(std::move(multi));
 }
 
 void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s) {
@@ -2199,9 +2190,9 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                            pts, n, sa, (int)cell_keys, key.p, rank.p, tmp.p, hist.p);
         FS_LAUNCHED();
     }
-    // device temporaries released, and host arrays kept alive, until the final synchronisation
+    // device temporaries released, and pinned staging kept, until the final synchronisation
     std::vector<DevBuf<int>> keep;
-    std::vector<std::vector<int>> hkeep;
+    HostStage hs(s);
     exclusive_scan(hist.p, nkeys, kstart.p, s, &keep);
     const int *tile_hist = hist.p;
     if (cell_keys) {
@@ -2223,12 +2214,9 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     const bool mgroups = d == 3 && cell_keys && T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 &&
                          n > 0;
     MGroupBuild mg;
-    if (mgroups) mgroups_count(mg, kstart.p, n, ntiles, cells_per_tile, s);
-    int tot[2] = {0, 0};
-    std::vector<int> tch(2 * ntiles);
-    FS_HIP(hipMemcpyAsync(tot, totals.p, sizeof(tot), hipMemcpyDeviceToHost, s));
-    FS_HIP(hipMemcpyAsync(tch.data(), nd.tile_chunk.p, 2 * ntiles * sizeof(int),
-                          hipMemcpyDeviceToHost, s));
+    if (mgroups) mgroups_count(mg, kstart.p, n, ntiles, cells_per_tile, s, hs);
+    const int *tot = hs.download(totals.p, 2);
+    const int *tch = hs.download(nd.tile_chunk.p, (size_t)(2 * ntiles));
     FS_HIP(hipStreamSynchronize(s));
     nd.nchunks = tot[1];
     std::vector<int> multi;
@@ -2254,13 +2242,9 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
         if (occ[t]) touched.push_back((int)t);
     nd.n_touched = (int)touched.size();
     nd.touched_tiles.alloc(std::max<size_t>(touched.size(), 1));
-    if (!touched.empty())
-        FS_HIP(hipMemcpyAsync(nd.touched_tiles.p, touched.data(), touched.size() * sizeof(int),
-                              hipMemcpyHostToDevice, s));
+    hs.upload(nd.touched_tiles.p, touched.data(), touched.size() * sizeof(int));
     nd.multi_tiles.alloc(std::max<size_t>(multi.size(), 1));
-    if (!multi.empty())
-        FS_HIP(hipMemcpyAsync(nd.multi_tiles.p, multi.data(), multi.size() * sizeof(int),
-                              hipMemcpyHostToDevice, s));
+    hs.upload(nd.multi_tiles.p, multi.data(), multi.size() * sizeof(int));
     nd.chunks.alloc(nd.nchunks + 1);
     if (nd.nchunks > 0) {
         hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
@@ -2269,7 +2253,7 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
         FS_LAUNCHED();
     }
     nd.n_mgroups = nd.n_mblocks = nd.n_mmulti = 0;
-    if (mgroups) mgroups_fill(nd, mg, kstart.p, n, ntiles, pp, mfma_slots(pp.W), s, keep, hkeep);
+    if (mgroups) mgroups_fill(nd, mg, kstart.p, n, ntiles, pp, mfma_slots(pp.W), s, keep, hs);
     FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
 }
 
@@ -2371,6 +2355,8 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     while (ch < 2048 && ch * 1024 < nmax) ch *= 2;
     pp.chunk = ch;
 
+    // small host <-> device copies of the build (pinned staging, released at the end)
+    HostStage hs(s);
     // ---- bounding box of both point sets (A1)
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     {
@@ -2387,12 +2373,10 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
             hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, y, m, d, part.p + nb * 6, bad.p);
             FS_LAUNCHED();
         }
-        std::vector<float> h(nb * 12);
-        int hb = 0;
-        FS_HIP(hipMemcpyAsync(h.data(), part.p, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
-        FS_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        const float *h = hs.download(part.p, (size_t)(nb * 12));
+        const int *hb = hs.download(bad.p, 1);
         FS_HIP(hipStreamSynchronize(s));
-        FS_REQUIRE(hb == 0, FS_EDOMAIN, "non-finite point coordinates");
+        FS_REQUIRE(*hb == 0, FS_EDOMAIN, "non-finite point coordinates");
         for (int set = 0; set < 2; ++set) {
             if ((set == 0 && n == 0) || (set == 1 && (m == 0 || y == x))) continue;
             for (int b = 0; b < nb; ++b)
@@ -2471,8 +2455,7 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
             for (int k = 0; k < WPOLY; ++k) hp[(pp.W + a) * WPOLY + k] = (float)c[k];
         }
         pl.wpoly.alloc(hp.size());
-        FS_HIP(hipMemcpyAsync(pl.wpoly.p, hp.data(), hp.size() * sizeof(float),
-                              hipMemcpyHostToDevice, s));
+        hs.upload(pl.wpoly.p, hp.data(), hp.size() * sizeof(float));
     }
 
     // ---- bin the point sets (A2)
@@ -2531,8 +2514,8 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
             const double ph = kb_hat(pp.m, b, pp.G, k);
             hd[k] = 1.0 / ((double)pp.G * pp.G * ph * ph);
         }
-        FS_HIP(hipMemcpyAsync(costab.p, hc.data(), N * sizeof(double), hipMemcpyHostToDevice, s));
-        FS_HIP(hipMemcpyAsync(dconv.p, hd.data(), H * sizeof(double), hipMemcpyHostToDevice, s));
+        hs.upload(costab.p, hc.data(), N * sizeof(double));
+        hs.upload(dconv.p, hd.data(), H * sizeof(double));
         RegArgs ra{};
         ra.kind = pp.kind;
         ra.regime = pp.regime;
@@ -2588,8 +2571,7 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
             tw[q] = make_float2((float)std::cos(a), (float)std::sin(a));
         }
         pl.twiddle.alloc(G / 2);
-        FS_HIP(hipMemcpyAsync(pl.twiddle.p, tw.data(), tw.size() * sizeof(float2),
-                              hipMemcpyHostToDevice, s));
+        hs.upload(pl.twiddle.p, tw.data(), tw.size() * sizeof(float2));
         const int S = pp.T + pp.W - 1;
         int64_t box = 1;
         for (int k = 0; k < d; ++k) box *= S;

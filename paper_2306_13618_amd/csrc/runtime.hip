@@ -1,5 +1,7 @@
 // Error state, workspace cache and small utility kernels of libfastuot.
+#include <algorithm>
 #include <cstdarg>
+#include <cstring>
 #include <map>
 #include <mutex>
 
@@ -84,6 +86,70 @@ void ws_release_all() {
     for (auto &kv : c.free_blocks) (void)hipFree(kv.second);
     c.free_blocks.clear();
     c.free_bytes = 0;
+}
+
+// ------------------------------------------------------------------ pinned staging
+namespace {
+struct PinnedPool {
+    std::mutex mu;
+    std::multimap<size_t, char *> free_blocks;  // size -> pointer, never freed
+};
+PinnedPool &pinned_pool() {
+    static PinnedPool *p = new PinnedPool();
+    return *p;
+}
+constexpr size_t PIN_BLOCK = size_t(1) << 20;
+}  // namespace
+
+void *HostStage::pinned(size_t bytes) {
+    used_ = (used_ + 63) & ~size_t(63);
+    if (blocks_.empty() || used_ + bytes > blocks_.back().second) {
+        const size_t want = std::max(PIN_BLOCK, (bytes + PIN_BLOCK - 1) & ~(PIN_BLOCK - 1));
+        char *b = nullptr;
+        size_t got = 0;
+        {
+            PinnedPool &pp = pinned_pool();
+            std::lock_guard<std::mutex> lk(pp.mu);
+            auto it = pp.free_blocks.lower_bound(want);
+            if (it != pp.free_blocks.end()) {
+                got = it->first;
+                b = it->second;
+                pp.free_blocks.erase(it);
+            }
+        }
+        if (!b) {
+            void *q = nullptr;
+            const hipError_t e = hipHostMalloc(&q, want, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                set_error("pinned host allocation of %zu bytes failed: %s", want,
+                          hipGetErrorString(e));
+                throw Error{FS_ENOMEM};
+            }
+            b = static_cast<char *>(q);
+            got = want;
+        }
+        blocks_.emplace_back(b, got);
+        used_ = 0;
+    }
+    char *p = blocks_.back().first + used_;
+    used_ += bytes;
+    return p;
+}
+
+void HostStage::upload(void *dst, const void *src, size_t bytes) {
+    if (!bytes) return;
+    void *h = pinned(bytes);
+    std::memcpy(h, src, bytes);
+    FS_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s_));
+}
+
+HostStage::~HostStage() {
+    if (blocks_.empty()) return;
+    (void)hipStreamSynchronize(s_);  // queued copies may still read the blocks
+    PinnedPool &pp = pinned_pool();
+    std::lock_guard<std::mutex> lk(pp.mu);
+    for (auto &b : blocks_) pp.free_blocks.emplace(b.second, b.first);
 }
 
 // ------------------------------------------------------------------ pass timing
