@@ -75,13 +75,22 @@ struct DevBuf {
         n = 0;
     }
     T *get() const { return p; }
+    // give up ownership (the caller frees the block with ws_free)
+    T *release() {
+        T *q = p;
+        p = nullptr;
+        n = 0;
+        return q;
+    }
 };
 
 // ------------------------------------------------------------------ pinned staging
 // Small host <-> device copies of a plan build go through pinned host memory: a copy from or to
 // pageable memory makes the host wait for the stream, a pinned one is queued like a kernel.  The
 // pinned blocks come from a per-process pool and go back to it when the stage is destroyed,
-// after a synchronisation of its stream (a queued copy may still read them until then).
+// after a synchronisation of its stream (a queued copy may still read them until then).  Device
+// temporaries whose last use is queued can be handed to the stage too: they are freed after that
+// same synchronisation, so the build synchronises once at its end instead of after each step.
 class HostStage {
 public:
     explicit HostStage(hipStream_t s) : s_(s) {}
@@ -100,11 +109,17 @@ public:
         if (count) FS_HIP(hipMemcpyAsync(h, src, count * sizeof(T), hipMemcpyDeviceToHost, s_));
         return h;
     }
+    // free the device buffer after the final synchronisation
+    template <class T>
+    void hold(DevBuf<T> &b) {
+        if (T *q = b.release()) held_.push_back(q);
+    }
 
 private:
     hipStream_t s_;
     std::vector<std::pair<char *, size_t>> blocks_;  // pinned blocks held: pointer, size
     size_t used_ = 0;                                  // bytes used in the last block
+    std::vector<void *> held_;                         // device blocks to free at the end
 };
 
 // ------------------------------------------------------------------ launch helpers

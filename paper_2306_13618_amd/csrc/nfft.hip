@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <cfloat>
 #include <cstring>
+#include <memory>
+#include <mutex>
 
 #include "nfft.h"
 
@@ -2157,7 +2159,10 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
     keep.push_back(std::move(mg.tgroups));
 }
 
-void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s) {
+// Tile/cell binning of one point set.  Temporaries go to the build's stage `hs` (freed after its
+// final synchronisation).
+void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s,
+               HostStage &hs) {
     nd.n = n;
     const int d = pp.d, G = pp.G, T = pp.T, ntd = G / T;
     int64_t ntiles = 1, cells_per_tile = 1;
@@ -2190,9 +2195,7 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                            pts, n, sa, (int)cell_keys, key.p, rank.p, tmp.p, hist.p);
         FS_LAUNCHED();
     }
-    // device temporaries released, and pinned staging kept, until the final synchronisation
     std::vector<DevBuf<int>> keep;
-    HostStage hs(s);
     exclusive_scan(hist.p, nkeys, kstart.p, s, &keep);
     const int *tile_hist = hist.p;
     if (cell_keys) {
@@ -2254,7 +2257,15 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     }
     nd.n_mgroups = nd.n_mblocks = nd.n_mmulti = 0;
     if (mgroups) mgroups_fill(nd, mg, kstart.p, n, ntiles, pp, mfma_slots(pp.W), s, keep, hs);
-    FS_HIP(hipStreamSynchronize(s));  // temporaries are released after this
+    for (auto &b : keep) hs.hold(b);
+    hs.hold(key);
+    hs.hold(rank);
+    hs.hold(hist);
+    hs.hold(kstart);
+    hs.hold(tcount);
+    hs.hold(tstart);
+    hs.hold(totals);
+    hs.hold(tmp);
 }
 
 void build_nearfield_cells(Nodes &nd, const PlanParams &pp, hipStream_t s) {
@@ -2313,6 +2324,48 @@ void build_nearfield_cells(Nodes &nd, const PlanParams &pp, hipStream_t s) {
     FS_HIP(hipStreamSynchronize(s));
 }
 
+}  // namespace
+
+namespace {
+// Multipliers M_k of recent plans, keyed by everything they depend on, so that a plan of the same
+// kernel, grid and scaling (a repeated solve on the same clouds) copies them instead of sampling
+// K_R and transforming it again.  At most MULT_CACHE entries, least recently used first; `ready`
+// is recorded after an entry's last write, and readers wait for it on their own stream.  An
+// entry is freed only after a device synchronisation, since copies from it may still be queued
+// on other streams.
+struct MultKey {
+    int dev, d, N, G, m, kind, regime, p;
+    double b, lambda, P, epsI, epsB, ci[16], cb[32];
+};
+struct MultEntry {
+    MultKey key;
+    DevBuf<float> mk;
+    hipEvent_t ready = nullptr;
+};
+constexpr size_t MULT_CACHE = 4;
+std::mutex g_mult_mu;
+std::vector<std::unique_ptr<MultEntry>> g_mult;
+
+MultKey mult_key(const PlanParams &pp, double b) {
+    MultKey k;
+    std::memset(&k, 0, sizeof(k));  // padding included: keys are compared bytewise
+    FS_HIP(hipGetDevice(&k.dev));
+    k.d = pp.d;
+    k.N = pp.N;
+    k.G = pp.G;
+    k.m = pp.m;
+    k.kind = pp.kind;
+    k.regime = pp.regime;
+    k.p = pp.p;
+    k.b = b;
+    k.lambda = pp.lambda;
+    k.P = pp.P;
+    k.epsI = pp.epsI;
+    k.epsB = pp.epsB;
+    std::memcpy(k.ci, pp.ci, sizeof(k.ci));
+    std::memcpy(k.cb, pp.cb, sizeof(k.cb));
+    return k;
+}
 }  // namespace
 
 void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, int d,
@@ -2460,8 +2513,8 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
 
     // ---- bin the point sets (A2)
     pl.same = (y == x && m == n);
-    bin_nodes(pl.X, x, n, pp, s);
-    if (!pl.same) bin_nodes(pl.Y, y, m, pp, s);
+    bin_nodes(pl.X, x, n, pp, s, hs);
+    if (!pl.same) bin_nodes(pl.Y, y, m, pp, s, hs);
 
     if (pp.nearfield) {
         // cells of side about radius / R, R chosen so that a cell holds about 32 points: blocks of
@@ -2503,7 +2556,26 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     }
 
     // ---- Fourier coefficients b_k of K_R and the multiplier M_k (A3)
+    const MultKey mkey = mult_key(pp, b);
+    bool mult_cached = false;
     {
+        const int N = pp.N, H = N / 2 + 1;
+        int64_t nh = 1;
+        for (int k = 0; k < d; ++k) nh *= H;
+        std::lock_guard<std::mutex> lk(g_mult_mu);
+        for (size_t i = 0; i < g_mult.size(); ++i)
+            if (std::memcmp(&g_mult[i]->key, &mkey, sizeof(mkey)) == 0) {
+                const MultEntry &e = *g_mult[i];
+                pl.Mk.alloc(nh);
+                FS_HIP(hipStreamWaitEvent(s, e.ready, 0));
+                FS_HIP(hipMemcpyAsync(pl.Mk.p, e.mk.p, nh * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s));
+                std::rotate(g_mult.begin() + i, g_mult.begin() + i + 1, g_mult.end());
+                mult_cached = true;
+                break;
+            }
+    }
+    if (!mult_cached) {
         const int N = pp.N, H = N / 2 + 1;
         int64_t nsamp = 1, nh = 1;
         for (int k = 0; k < d; ++k) { nsamp *= N; nh *= H; }
@@ -2554,7 +2626,27 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
         hipLaunchKernelGGL(k_build_mult, dim3(blocks_for(nh, 256, 65536)), dim3(256), 0, s, in, N,
                            d, dconv.p, scale, pl.Mk.p);
         FS_LAUNCHED();
-        FS_HIP(hipStreamSynchronize(s));
+        hs.hold(samp);
+        hs.hold(t1);
+        hs.hold(t2);
+        hs.hold(costab);
+        hs.hold(dconv);
+        std::lock_guard<std::mutex> lk(g_mult_mu);
+        if (g_mult.size() >= MULT_CACHE) {
+            FS_HIP(hipDeviceSynchronize());  // no queued copy still reads the oldest entry
+            FS_HIP(hipEventDestroy(g_mult.front()->ready));
+            g_mult.erase(g_mult.begin());
+        }
+        {
+            auto e = std::make_unique<MultEntry>();
+            e->key = mkey;
+            e->mk.alloc(nh);
+            FS_HIP(hipMemcpyAsync(e->mk.p, pl.Mk.p, nh * sizeof(float), hipMemcpyDeviceToDevice,
+                                  s));
+            FS_HIP(hipEventCreateWithFlags(&e->ready, hipEventDisableTiming));
+            FS_HIP(hipEventRecord(e->ready, s));
+            g_mult.push_back(std::move(e));
+        }
     }
 
     // ---- FFT buffers and twiddles
@@ -2580,8 +2672,8 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
         pl.scratch.alloc((int64_t)std::max(nch, 1) * box);
         pl.wbuf.alloc(std::max(n, m) + 1);
         pl.tbuf.alloc(std::max(n, m) + 1);
-        FS_HIP(hipStreamSynchronize(s));
     }
+    // the stage's destructor synchronises the stream: the plan is complete on return
 }
 
 // ------------------------------------------------------------------ apply

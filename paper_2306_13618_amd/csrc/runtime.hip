@@ -145,8 +145,9 @@ void HostStage::upload(void *dst, const void *src, size_t bytes) {
 }
 
 HostStage::~HostStage() {
-    if (blocks_.empty()) return;
-    (void)hipStreamSynchronize(s_);  // queued copies may still read the blocks
+    if (blocks_.empty() && held_.empty()) return;
+    (void)hipStreamSynchronize(s_);  // queued copies and kernels may still use the blocks
+    for (void *q : held_) ws_free(q);
     PinnedPool &pp = pinned_pool();
     std::lock_guard<std::mutex> lk(pp.mu);
     for (auto &b : blocks_) pp.free_blocks.emplace(b.second, b.first);

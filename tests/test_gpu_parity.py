@@ -179,6 +179,34 @@ def test_fastsum_matrix_core_tiny_clusters(n, m):
     assert relinf(got, ref) < TOL
 
 
+def test_plan_multiplier_reuse():
+    """Plans that differ in kernel, lambda, grid, window or dimension, then the same plans again in
+    reverse order: the multipliers M_k come from the library's cache of recent plans (four
+    entries, least recently used first) for the last ones and are recomputed for the first ones
+    after their eviction.  Every result against the oracle, and the second run against the
+    first."""
+    x3, y3, v3 = clouds(3, 3001, 2777, 2)
+    x2, y2, v2 = clouds(2, 3001, 2777, 2)
+    cases = [
+        ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=64, window=6)),
+        ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=64, window=4)),
+        ((x2, y2, v2), dict(kernel="gauss", lam=0.02, grid=64, window=6)),
+        ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=128, window=6)),
+        ((x3, y3, v3), dict(kernel="laplace", lam=0.01, grid=128, window=6)),
+        ((x3, y3, v3), dict(kernel="gauss", lam=0.005, grid=128, window=5)),
+    ]
+    first = []
+    for (x, y, v), args in cases:
+        got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
+        ref = oracle.direct_sum(x, y, v, args["kernel"], args["lam"])
+        assert relinf(got, ref) < TOL, args
+        first.append(got)
+    for i in reversed(range(len(cases))):
+        (x, y, v), args = cases[i]
+        got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
+        assert relinf(got, first[i]) < 2e-6, args
+
+
 def test_uot_matrix_core_groups():
     """A Sinkhorn solve whose kernel sums take the 3-D matrix-core spread and gather (dense
     clusters, grid 64^3) against the oracle's iterates."""
