@@ -254,17 +254,18 @@ __device__ __forceinline__ void dft8(float2 *v) {
     v[0] = y0; v[1] = y1; v[2] = y2; v[3] = y3; v[4] = y4; v[5] = y5; v[6] = y6; v[7] = y7;
 }
 
-// Batched 64-point FFTs as 8 x 8 (same contract as lds_fft with logL = 6): thread (t, j) takes the
+// Batched 64-point FFTs as 8 x 8 (same contract as lds_fft with logL = 6, transform t at
+// a[t ST .. t ST + 64), ST = 64 unless padded against bank conflicts): thread (t, j) takes the
 // 8-point DFT over m of a[t][j + 8 m], multiplies output k1 by w64^{j k1} and stores it at
 // b[t][8 k1 + j]; then thread (t, k1) takes the 8-point DFT over j of b[t][8 k1 + j] and stores
 // output k2 at a[t][k1 + 8 k2].  Two passes over LDS instead of six.
-template <int DIR>
+template <int DIR, int ST = 64>
 __device__ float2 *lds_fft64(float2 *a, float2 *b, int NB, const float2 *__restrict__ tw) {
     for (int q = threadIdx.x; q < NB * 8; q += blockDim.x) {
         const int t = q >> 3, j = q & 7;
         float2 v[8];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = a[t * 64 + j + 8 * m];
+        for (int m = 0; m < 8; ++m) v[m] = a[t * ST + j + 8 * m];
         dft8<DIR>(v);
 #pragma unroll
         for (int k1 = 0; k1 < 8; ++k1) {
@@ -272,7 +273,7 @@ __device__ float2 *lds_fft64(float2 *a, float2 *b, int NB, const float2 *__restr
             float2 w = tw[e & 31];
             if (e & 32) w = make_float2(-w.x, -w.y);
             if (DIR > 0) w.y = -w.y;
-            b[t * 64 + 8 * k1 + j] = cmul(v[k1], w);
+            b[t * ST + 8 * k1 + j] = cmul(v[k1], w);
         }
     }
     __syncthreads();
@@ -280,13 +281,46 @@ __device__ float2 *lds_fft64(float2 *a, float2 *b, int NB, const float2 *__restr
         const int t = q >> 3, k1 = q & 7;
         float2 v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = b[t * 64 + 8 * k1 + j];
+        for (int j = 0; j < 8; ++j) v[j] = b[t * ST + 8 * k1 + j];
         dft8<DIR>(v);
 #pragma unroll
-        for (int k2 = 0; k2 < 8; ++k2) a[t * 64 + k1 + 8 * k2] = v[k2];
+        for (int k2 = 0; k2 < 8; ++k2) a[t * ST + k1 + 8 * k2] = v[k2];
     }
     __syncthreads();
     return a;
+}
+
+// lds_fft64 whose second pass hands every output to out(t, k, value) (k = frequency or sample
+// index of transform t) instead of storing it in natural order; `a` may be overwritten by out.
+template <int DIR, int ST, class Out>
+__device__ void lds_fft64_out(float2 *a, float2 *b, int NB, const float2 *__restrict__ tw,
+                              Out out) {
+    for (int q = threadIdx.x; q < NB * 8; q += blockDim.x) {
+        const int t = q >> 3, j = q & 7;
+        float2 v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = a[t * ST + j + 8 * m];
+        dft8<DIR>(v);
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) {
+            const int e = j * k1;  // < 64
+            float2 w = tw[e & 31];
+            if (e & 32) w = make_float2(-w.x, -w.y);
+            if (DIR > 0) w.y = -w.y;
+            b[t * ST + 8 * k1 + j] = cmul(v[k1], w);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NB * 8; q += blockDim.x) {
+        const int t = q >> 3, k1 = q & 7;
+        float2 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = b[t * ST + 8 * k1 + j];
+        dft8<DIR>(v);
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) out(t, k1 + 8 * k2, v[k2]);
+    }
+    __syncthreads();
 }
 
 // Batched complex FFT of NB transforms of length L = 2^logL held in LDS (transform t at
@@ -1089,6 +1123,9 @@ struct FftArgs {
     int nbx;  // columns per block in the strided passes
 };
 
+// First axis, forward: two real rows as one complex row.  PM: the spectrum is stored plane-major,
+// specA[kx][row], instead of specA[row][kx] (the layout of the fused y-z pass).
+template <bool PM>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_r2c(const float *__restrict__ grid,
                                                             int rows, FftArgs fa,
                                                             const float2 *__restrict__ tw,
@@ -1111,17 +1148,25 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_r2c(const float *__restri
     __syncthreads();
     float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, NB, tw);
     for (int q = threadIdx.x; q < NB * fa.KX; q += blockDim.x) {
-        const int t = q / fa.KX, k = q - t * fa.KX;
+        // plane-major: consecutive threads take consecutive row pairs of one kx
+        const int t = PM ? q % NB : q / fa.KX, k = PM ? q / NB : q - t * fa.KX;
         if (t >= nb) continue;
         const float2 z = res[t * G + k], zm = res[t * G + ((G - k) & (G - 1))];
         const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
         const float2 B = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
         const int64_t r0 = (int64_t)(p0 + t) * 2;
-        specA[r0 * fa.KX + k] = A;
-        specA[(r0 + 1) * fa.KX + k] = B;
+        if (PM) {
+            *reinterpret_cast<float4 *>(specA + (int64_t)k * rows + r0) =
+                make_float4(A.x, A.y, B.x, B.y);
+        } else {
+            specA[r0 * fa.KX + k] = A;
+            specA[(r0 + 1) * fa.KX + k] = B;
+        }
     }
 }
 
+// First axis, inverse (PM: plane-major spectrum, as in k_fft_x_r2c).
+template <bool PM>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restrict__ specA,
                                                             int rows, FftArgs fa,
                                                             const float2 *__restrict__ tw,
@@ -1138,11 +1183,27 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restr
         if (t < nb) {
             const int64_t r0 = (int64_t)(p0 + t) * 2;
             if (k <= h) {
-                const float2 A = specA[r0 * fa.KX + k], B = specA[(r0 + 1) * fa.KX + k];
+                float2 A, B;
+                if (PM) {
+                    const float4 ab = *reinterpret_cast<const float4 *>(specA + (int64_t)k * rows + r0);
+                    A = make_float2(ab.x, ab.y);
+                    B = make_float2(ab.z, ab.w);
+                } else {
+                    A = specA[r0 * fa.KX + k];
+                    B = specA[(r0 + 1) * fa.KX + k];
+                }
                 z = make_float2(A.x - B.y, A.y + B.x);
             } else if (k >= G - h) {
                 const int kk = G - k;
-                float2 A = specA[r0 * fa.KX + kk], B = specA[(r0 + 1) * fa.KX + kk];
+                float2 A, B;
+                if (PM) {
+                    const float4 ab = *reinterpret_cast<const float4 *>(specA + (int64_t)kk * rows + r0);
+                    A = make_float2(ab.x, ab.y);
+                    B = make_float2(ab.z, ab.w);
+                } else {
+                    A = specA[r0 * fa.KX + kk];
+                    B = specA[(r0 + 1) * fa.KX + kk];
+                }
                 A.y = -A.y;
                 B.y = -B.y;
                 z = make_float2(A.x - B.y, A.y + B.x);
@@ -1279,6 +1340,51 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_z_conv(float2 *__restrict__
         if (c >= nbx) continue;
         specB[((int64_t)zz * NB1 + kyb) * KX + kx0 + c] = res[c * G + zz];
     }
+}
+
+// 3-D, G = 64: the three strided passes (forward along y, forward + multiply + inverse along z,
+// inverse along y) for one kx per workgroup, with the whole y-z plane (64 x 64) in LDS.  Same
+// transforms and multiply as k_fft_y<0>, k_fft_z_conv and k_fft_y<2>, in place in the
+// plane-major spectrum specA[kx][z][y] (one contiguous 32 KB plane per workgroup).
+__global__ void __launch_bounds__(512) k_fft_yz_conv64(float2 *__restrict__ specA, FftArgs fa,
+                                                      const float2 *__restrict__ tw,
+                                                      const float *__restrict__ M) {
+    constexpr int G = 64, ST = G + 7;  // padded rows: few LDS bank conflicts in the FFT and transposes
+    __shared__ float2 pa[G * ST], pb[G * ST], twl[G / 2];
+    __shared__ float ml[(G / 2) * (G / 2)];  // multiplier of this kx: [akz][aky], h + 1 <= G / 2
+    const int h = fa.N / 2, NB1 = fa.N + 1, H = h + 1;
+    const int kx = blockIdx.x;
+    float2 *plane = specA + (int64_t)kx * G * G;  // plane-major spectrum: [kx][z][y]
+    // plane [z][y]; twiddles and this kx's multipliers to LDS
+    for (int q = threadIdx.x; q < G * G; q += blockDim.x) pa[(q / G) * ST + q % G] = plane[q];
+    if (threadIdx.x < G / 2) twl[threadIdx.x] = tw[threadIdx.x];
+    for (int q = threadIdx.x; q < H * H; q += blockDim.x) ml[q] = M[(int64_t)q * H + kx];
+    __syncthreads();
+    // along y for every z; the band ky in [-h, h] goes to pa[ky + h][z]
+    lds_fft64_out<-1, ST>(pa, pb, G, twl, [&](int z, int yi, float2 v) {
+        const int ky = (yi <= G / 2) ? yi : yi - G;
+        if (ky >= -h && ky <= h) pa[(ky + h) * ST + z] = v;
+    });
+    // along z for every ky of the band, times the multiplier (zero outside the band)
+    lds_fft64_out<-1, ST>(pa, pb, NB1, twl, [&](int kyb, int zi, float2 v) {
+        const int ky = kyb - h, aky = ky < 0 ? -ky : ky;
+        const int kz = (zi <= G / 2) ? zi : zi - G;
+        const int akz = kz < 0 ? -kz : kz;
+        const float mk = (akz <= h) ? ml[akz * H + aky] : 0.0f;
+        pa[kyb * ST + zi] = make_float2(v.x * mk, v.y * mk);
+    });
+    // inverse along z; back to pa[z][y], with zeros outside the band (no thread reads pa in this
+    // second pass, and the zeros and the band values go to different elements)
+    lds_fft64_out<1, ST>(pa, pb, NB1, twl, [&](int kyb, int z, float2 v) {
+        pa[z * ST + ((kyb - h) & (G - 1))] = v;
+    });
+    for (int q = threadIdx.x; q < G * (G - NB1); q += blockDim.x) {
+        const int z = q / (G - NB1), yi = h + 1 + q % (G - NB1);  // ky = h + 1 .. G - h - 1
+        pa[z * ST + yi] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    // inverse along y, stored to the plane
+    lds_fft64_out<1, ST>(pa, pb, G, twl, [&](int z, int y, float2 v) { plane[z * G + y] = v; });
 }
 
 // ------------------------------------------------------------------ gather (NFFT)
@@ -2810,12 +2916,22 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 nkb = (fa.KX + fa.nbx - 1) / fa.nbx;
                 const size_t lds_x = 2 * (size_t)fa.nb * pp.G * sizeof(float2);
                 const size_t lds_y = 2 * (size_t)fa.nbx * pp.G * sizeof(float2);
-                hipLaunchKernelGGL(k_fft_x_r2c, dim3(xblocks), dim3(threads_for(fa.nb)), lds_x, s,
-                                   pl.grid.p, rows, fa, pl.twiddle.p, pl.specA.p);
+                // 3-D on a 64^3 grid: plane-major spectrum and one fused pass for y and z
+                const bool yz = D == 3 && pp.G == 64;
+                if (yz)
+                    hipLaunchKernelGGL(k_fft_x_r2c<true>, dim3(xblocks), dim3(threads_for(fa.nb)),
+                                       lds_x, s, pl.grid.p, rows, fa, pl.twiddle.p, pl.specA.p);
+                else
+                    hipLaunchKernelGGL(k_fft_x_r2c<false>, dim3(xblocks), dim3(threads_for(fa.nb)),
+                                       lds_x, s, pl.grid.p, rows, fa, pl.twiddle.p, pl.specA.p);
                 FS_LAUNCHED();
                 if (D == 2) {
                     hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(threads_for(fa.nbx)), lds_y, s,
                                        pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    FS_LAUNCHED();
+                } else if (yz) {
+                    hipLaunchKernelGGL(k_fft_yz_conv64, dim3(fa.KX), dim3(512), 0, s, pl.specA.p,
+                                       fa, pl.twiddle.p, pl.Mk.p);
                     FS_LAUNCHED();
                 } else {
                     hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(threads_for(fa.nbx)), lds_y,
@@ -2828,8 +2944,12 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                                        s, pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
                     FS_LAUNCHED();
                 }
-                hipLaunchKernelGGL(k_fft_x_c2r, dim3(xblocks), dim3(threads_for(fa.nb)), lds_x, s,
-                                   pl.specA.p, rows, fa, pl.twiddle.p, pl.grid.p);
+                if (yz)
+                    hipLaunchKernelGGL(k_fft_x_c2r<true>, dim3(xblocks), dim3(threads_for(fa.nb)),
+                                       lds_x, s, pl.specA.p, rows, fa, pl.twiddle.p, pl.grid.p);
+                else
+                    hipLaunchKernelGGL(k_fft_x_c2r<false>, dim3(xblocks), dim3(threads_for(fa.nb)),
+                                       lds_x, s, pl.specA.p, rows, fa, pl.twiddle.p, pl.grid.p);
                 FS_LAUNCHED();
             }
         }
