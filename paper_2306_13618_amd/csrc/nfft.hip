@@ -69,12 +69,6 @@ void kernel_derivs(int kind, double lambda, double s, int cnt, double *out) {
     }
 }
 
-double kernel_value(int kind, double lambda, double s) {
-    double v;
-    kernel_derivs(kind, lambda, s, 1, &v);
-    return v;
-}
-
 // Solve A x = rhs (n <= 32) by Gaussian elimination with partial pivoting.
 void solve_dense(int n, std::vector<double> A, std::vector<double> rhs, double *x) {
     for (int c = 0; c < n; ++c) {
@@ -759,7 +753,6 @@ __global__ void __launch_bounds__(256) k_spread(const float4 *__restrict__ rec,
     const float scale = chunk_scale(w, ch.y, ch.z, red);
     const int lane = threadIdx.x & 63;
     const int ra = lane % W;
-    const float mm1 = (float)(sa.m - 1);
     for (int k = ch.y + threadIdx.x; k < ch.y + ch.z; k += blockDim.x) {
         const float4 r = rec[k];
         const int lb = __float_as_int(r.w);  // cell offset inside the tile's box
