@@ -88,7 +88,8 @@ const char *fs_last_error(void);
 /* Library version, (major << 16) | minor. */
 int fs_version(void);
 
-/* Release the cached workspace blocks (device memory) of the calling process. */
+/* Release the cached device memory of the calling process: workspace blocks and the multipliers
+ * kept from recent plans (the latter after a device synchronisation). */
 void fs_release_cache(void);
 
 /* Pass timing (instrumentation, not part of the method).  fs_profile_enable(1) makes every

@@ -142,6 +142,12 @@ def _opt(out):
     return _ptr(out) if out is not None else ctypes.c_void_p(0)
 
 
+def fs_release_cache():
+    """Release the library's cached device memory (workspace blocks and the multipliers kept from
+    recent plans)."""
+    _lib.fs_release_cache()
+
+
 def fs_profile_enable(enable=True):
     """Record HIP events around the library's passes (spread, fold, fft, gather, ...)."""
     _check(_lib.fs_profile_enable(int(bool(enable))))

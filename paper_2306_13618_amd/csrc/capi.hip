@@ -107,7 +107,13 @@ const char *fs_last_error(void) { return fs::last_error(); }
 
 int fs_version(void) { return (1 << 16) | 0; }
 
-void fs_release_cache(void) { ws_release_all(); }
+void fs_release_cache(void) {
+    try {
+        fs::plan_release_mult_cache();
+    } catch (...) {
+    }
+    ws_release_all();
+}
 
 int fs_profile_enable(int enable) { return fs::profile_enable(enable); }
 

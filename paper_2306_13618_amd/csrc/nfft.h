@@ -129,6 +129,8 @@ int plan_update_parts(const Plan &pl, int transpose);
 // With pu the sums are not stored: the gather applies the update (t_sorted may be null).
 void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
                            hipStream_t s, const PotUpdate *pu = nullptr);
+// Drop the cached multipliers of recent plans (after a device synchronisation).
+void plan_release_mult_cache();
 
 // Permutations between caller order and a node set's sorted order.
 void gather_to_sorted(const Nodes &nd, const float *v, float *v_sorted, hipStream_t s);

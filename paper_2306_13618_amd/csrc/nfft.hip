@@ -2445,6 +2445,17 @@ constexpr size_t MULT_CACHE = 4;
 std::mutex g_mult_mu;
 std::vector<std::unique_ptr<MultEntry>> g_mult;
 
+}  // namespace
+
+void plan_release_mult_cache() {
+    std::lock_guard<std::mutex> lk(g_mult_mu);
+    if (g_mult.empty()) return;
+    (void)hipDeviceSynchronize();  // no queued copy still reads an entry
+    for (auto &e : g_mult) (void)hipEventDestroy(e->ready);
+    g_mult.clear();
+}
+
+namespace {
 MultKey mult_key(const PlanParams &pp, double b) {
     MultKey k;
     std::memset(&k, 0, sizeof(k));  // padding included: keys are compared bytewise

@@ -195,8 +195,8 @@ def test_plan_multiplier_reuse():
     """Plans that differ in kernel, lambda, grid, window or dimension, then the same plans again in
     reverse order: the multipliers M_k come from the library's cache of recent plans (four
     entries, least recently used first) for the last ones and are recomputed for the first ones
-    after their eviction.  Every result against the oracle, and the second run against the
-    first."""
+    after their eviction, and again after fs_release_cache.  Every result against the oracle, and
+    the later runs against the first."""
     x3, y3, v3 = clouds(3, 3001, 2777, 2)
     x2, y2, v2 = clouds(2, 3001, 2777, 2)
     cases = [
@@ -217,6 +217,11 @@ def test_plan_multiplier_reuse():
         (x, y, v), args = cases[i]
         got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
         assert relinf(got, first[i]) < 2e-6, args
+    # an emptied cache: the multipliers are computed again
+    fu.fs_release_cache()
+    (x, y, v), args = cases[-1]
+    got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
+    assert relinf(got, first[-1]) < 2e-6
 
 
 def test_uot_matrix_core_groups():
