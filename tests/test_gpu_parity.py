@@ -179,13 +179,16 @@ def test_fastsum_matrix_core_tiny_clusters(n, m):
     assert relinf(got, ref) < TOL
 
 
-@pytest.mark.parametrize("bandwidth", [16, 24, 40])
-def test_fastsum_bandwidth_on_64_grid(bandwidth):
+@pytest.mark.parametrize("kind,lam,bandwidth", [("gauss", 0.05, 16), ("gauss", 0.05, 24),
+                                                ("gauss", 0.05, 40), ("laplace", 0.05, 24),
+                                                ("energy", 1.0, 40)])
+def test_fastsum_bandwidth_on_64_grid(kind, lam, bandwidth):
     """3-D sums with bandwidth N on a 64^3 grid (the plane-major spectrum and the one-pass y-z
     transform) against the same band-limited sums on a 128^3 grid (three strided passes): both
-    evaluate the same Fourier sum over |k| <= N/2, up to window errors far below FP32 rounding."""
+    evaluate the same Fourier sum over |k| <= N/2 (and the same near field, whose radius follows
+    N), up to window errors far below FP32 rounding."""
     x, y, v = clouds(3, 3001, 2777, 5)
-    args = dict(kernel="gauss", lam=0.05, window=6, bandwidth=bandwidth)
+    args = dict(kernel=kind, lam=lam, window=6, bandwidth=bandwidth)
     a = fu.fastsum_apply(T(x), T(y), T(v), grid=64, **args).cpu().numpy()
     b = fu.fastsum_apply(T(x), T(y), T(v), grid=128, **args).cpu().numpy()
     assert relinf(a, b) < 2e-6
