@@ -600,17 +600,26 @@ __global__ void __launch_bounds__(256) k_tile_sum(const int *__restrict__ in, in
 }
 
 // groups[gstart[b] + j] = (first node, node count, brick offset inside the tile's box, 0)
+// (d = 2 or 3; the brick's cells are consecutive along x)
 __global__ void k_fill_groups(const int *__restrict__ key_start, const int *__restrict__ gstart,
-                              int64_t nbricks, int total, int T, int S, int4 *__restrict__ groups) {
+                              int64_t nbricks, int total, int d, int T, int S,
+                              int4 *__restrict__ groups) {
     const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (b >= nbricks) return;
     const int s0 = key_start[b * BRICK_X];
     const int s1 = (b + 1 < nbricks) ? key_start[(b + 1) * BRICK_X] : total;
     const int cnt = s1 - s0, g0 = gstart[b];
     const int bpr = T / BRICK_X;  // bricks per tile row
-    const int lb = (int)(b % ((int64_t)bpr * T * T));
-    const int bx = lb % bpr, by = (lb / bpr) % T, bz = lb / (bpr * T);
-    const int off = (bz * S + by) * S + bx * BRICK_X;
+    int off;
+    if (d == 3) {
+        const int lb = (int)(b % ((int64_t)bpr * T * T));
+        const int bx = lb % bpr, by = (lb / bpr) % T, bz = lb / (bpr * T);
+        off = (bz * S + by) * S + bx * BRICK_X;
+    } else {
+        const int lb = (int)(b % ((int64_t)bpr * T));
+        const int bx = lb % bpr, by = lb / bpr;
+        off = by * S + bx * BRICK_X;
+    }
     for (int j = 0; 16 * j < cnt; ++j)
         groups[g0 + j] = make_int4(s0 + 16 * j, min(16, cnt - 16 * j), off, 0);
 }
@@ -1841,6 +1850,266 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
     }
 }
 
+// 2-D spreading on the FP16 matrix cores.  For the nodes of one brick (BRICK_X cells along x with
+// the same y cell), with alpha the weights divided by the block's largest |weight|,
+//   H[x][y] += sum_n (alpha_n px_n[x - ox_n]) py_n[y],
+// x over 16 box columns from the brick's first cell, y over the W rows from its cell: a plain
+// rank-16 product of the two window factors, two v_mfma_f32_16x16x32_f16 per group with both
+// factors split into FP16 hi + lo (as in the 3-D spread, whose y-z products are replaced here by
+// py itself).  Lane l holds H[4 (l / 16) + r][l % 16]; the sums stay in registers while the brick
+// stays the same and then go to the block's int32 LDS box (fixed point, see chunk_scale).
+template <int W, int T>
+__global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restrict__ rec,
+                                                       const float *__restrict__ w,
+                                                       const int4 *__restrict__ mblocks,
+                                                       const int4 *__restrict__ mgroups,
+                                                       SpreadArgs sa, float *__restrict__ scratch) {
+    constexpr int S = T + W - 1, BOX = S * S;
+    constexpr int NZ = (W + 3) / 4;      // window offsets per lane: slot + 4 e
+    constexpr int XR = W + BRICK_X - 1;  // box columns a brick reaches
+    constexpr int PX = W + 1;            // row stride of the x table (odd: no bank conflicts)
+    static_assert(XR <= 16, "brick and window exceed the 16 matrix rows");
+    __shared__ int box[BOX];
+    __shared__ float phx[MW][16 * PX];  // per wave: alpha px, node-major
+    __shared__ float phy[MW][W][16];    // per wave: py, offset-major
+    __shared__ int oxs[MW][16];
+    __shared__ float red[16];
+    const int4 mb = mblocks[blockIdx.x];
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
+    const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
+    const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
+    float wm = 0.0f;
+    const float scale = chunk_scale(w, k0, cnt, red, &wm);
+    const float wmax = (wm > 0.0f) ? wm : 1.0f;
+    const float inv_wmax = 1.0f / wmax, fscale = scale * wmax;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = lane & 15, slot = lane >> 4;
+    float wc[NZ][WPOLY];
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) {
+        const int a = slot + 4 * e;
+#pragma unroll
+        for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
+    }
+    float *px = phx[wave];
+    float(*py)[16] = phy[wave];
+    int *ox = oxs[wave];
+    const int per = (mb.z + MW - 1) / MW;
+    const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    int cur = -1;
+    auto flush = [&]() {
+        if (col < W) {  // rows y = col >= W hold no window
+            const int b0 = cur + col * S;  // row y = col of the brick's box rows
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = 4 * slot + r;
+                if (x < XR) atomicAdd(&box[b0 + x], __float2int_rn(acc[r] * fscale));
+            }
+        }
+        acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    };
+    for (int g = gb; g < ge; ++g) {
+        const int4 gr = mgroups[g];
+        const int nn = min(col, gr.y - 1);
+        const float4 r = rec[gr.x + nn];
+        const float alpha = (col < gr.y) ? w[gr.x + nn] * inv_wmax : 0.0f;
+        // window values of node `col` at offsets slot + 4 e
+#pragma unroll
+        for (int e = 0; e < NZ; ++e) {
+            const int a = slot + 4 * e;
+            if (W % 4 == 0 || a < W) {
+                px[col * PX + a] = alpha * wpoly_eval(wc[e], 2.0f * r.x - 1.0f);
+                py[a][col] = wpoly_eval(wc[e], 2.0f * r.y - 1.0f);
+            }
+        }
+        if (slot == 0) ox[col] = __float_as_int(r.w) % S - gr.z % S;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (gr.z != cur) {
+            if (cur >= 0) flush();
+            cur = gr.z;
+        }
+        // operand A: alpha px of nodes 4 slot .. + 3 at box column `col`, (hi, lo)
+        float av[4], bv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int n = 4 * slot + e;
+            const int a = col - ox[n];
+            av[e] = (a >= 0 && a < W) ? px[n * PX + (a < 0 ? 0 : (a >= W ? W - 1 : a))] : 0.0f;
+            // operand B: py of the same nodes at box row `col`
+            bv[e] = (col < W) ? py[col < W ? col : W - 1][n] : 0.0f;
+        }
+        f16x2 ah0, al0, ah1, al1, bh0, bl0, bh1, bl1;
+        split_f16(av[0], av[1], ah0, al0);
+        split_f16(av[2], av[3], ah1, al1);
+        split_f16(bv[0], bv[1], bh0, bl0);
+        split_f16(bv[2], bv[3], bh1, bl1);
+        const f16x8 A1 = {ah0[0], ah0[1], ah1[0], ah1[1], ah0[0], ah0[1], ah1[0], ah1[1]};
+        const f16x8 A2 = {al0[0], al0[1], al1[0], al1[1], al0[0], al0[1], al1[0], al1[1]};
+        const f16x8 B = {bh0[0], bh0[1], bh1[0], bh1[1], bl0[0], bl0[1], bl1[0], bl1[1]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B, acc, 0, 0, 0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (cur >= 0) flush();
+    __syncthreads();
+    const float inv = 1.0f / scale;
+    float *dst = scratch + (int64_t)blockIdx.x * BOX;
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) dst[q] = (float)box[q] * inv;
+}
+
+// 2-D gather on the FP16 matrix cores, the transpose of k_spread_mfma2d: for the nodes n of one
+// brick, t_n = sum_y py_n[y] E[y][n], E[y][n] = sum_x H[x][y] px_n[x - ox_n], x over 16 box
+// columns from the brick's first cell.  E is two v_mfma_f32_16x16x32_f16 per group (rows y,
+// columns the 16 nodes, K = 16 columns x the hi/lo cross products, the box kept in LDS as in the
+// 3-D gather, scaled by a power of two); lane l then holds E[4 (l / 16) + r][l % 16] and forms
+// its part of the y sum, the four parts of a node being added across lanes.
+template <int W, int T>
+__global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restrict__ rec,
+                                                       const int4 *__restrict__ mblocks,
+                                                       const int4 *__restrict__ mgroups,
+                                                       SpreadArgs sa,
+                                                       const float *__restrict__ grid,
+                                                       float *__restrict__ out) {
+    constexpr int S = T + W - 1, BOX = S * S;
+    constexpr int NC = (T + 12) / 4;  // groups of 4 columns: the last brick reaches x < T - 4 + 16
+    constexpr int NZ = (W + 3) / 4;
+    constexpr int NT = 64 * MW;
+    constexpr int PER = (BOX + NT - 1) / NT;
+    static_assert(W + BRICK_X - 1 <= 16 && S <= 4 * NC, "brick and window exceed the 16 columns");
+    __shared__ __align__(16) _Float16 bx[S][NC][8];
+    __shared__ float phi[MW][2][W][16];
+    __shared__ float red[MW];
+    const int4 mb = mblocks[blockIdx.x];
+    int tc[3];
+    tile_coords<2>(mb.x, sa.ntd, tc);
+    const int G = sa.G;
+    // the tile's box: values and their largest magnitude
+    float v[PER];
+    float mx = 0.0f;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = threadIdx.x + NT * i;
+        v[i] = 0.0f;
+        if (q < BOX) {
+            const int l0 = q % S, l1 = q / S;
+            const int g0 = (tc[0] * T - (sa.m - 1) + l0 + G) & (G - 1);
+            const int g1 = (tc[1] * T - (sa.m - 1) + l1 + G) & (G - 1);
+            v[i] = grid[(int64_t)g1 * G + g0];
+            mx = fmaxf(mx, fabsf(v[i]));
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    // columns x >= S of every row are zero
+    for (int q = threadIdx.x; q < S * (4 * NC - S); q += NT) {
+        const int row = q / (4 * NC - S), x = S + q % (4 * NC - S);
+        bx[row][x >> 2][x & 3] = (_Float16)0.0f;
+        bx[row][x >> 2][4 + (x & 3)] = (_Float16)0.0f;
+    }
+    __syncthreads();
+    mx = red[0];
+    for (int i = 1; i < MW; ++i) mx = fmaxf(mx, red[i]);
+    // power-of-two scale: largest |value| in [2^13, 2^14)
+    int ex = 0;
+    frexpf(mx, &ex);
+    const float scale = (mx > 0.0f) ? ldexpf(1.0f, 14 - ex) : 1.0f;
+    const float unscale = (mx > 0.0f) ? ldexpf(1.0f, ex - 14) : 1.0f;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = threadIdx.x + NT * i;
+        if (q < BOX) {
+            const float u = v[i] * scale;
+            const _Float16 h = (_Float16)u;
+            const int row = q / S, x = q % S;
+            bx[row][x >> 2][x & 3] = h;
+            bx[row][x >> 2][4 + (x & 3)] = (_Float16)(u - (float)h);
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int node = lane & 15, slot = lane >> 4;
+    float wc[NZ][WPOLY];
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) {
+        const int a = slot + 4 * e;
+#pragma unroll
+        for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
+    }
+    float(*ph)[W][16] = phi[wave];
+    const int per = (mb.z + MW - 1) / MW;
+    const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
+    int4 grn = make_int4(0, 1, 0, 0);
+    float4 rn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (gb < ge) {
+        grn = mgroups[gb];
+        rn = rec[grn.x + min(node, grn.y - 1)];
+    }
+    for (int g = gb; g < ge; ++g) {
+        const int4 gr = grn;
+        const float4 r = rn;
+        if (g + 1 < ge) {
+            grn = mgroups[g + 1];
+            rn = rec[grn.x + min(node, grn.y - 1)];
+        }
+        const float fr[2] = {r.x, r.y};
+#pragma unroll
+        for (int dim = 0; dim < 2; ++dim) {
+            const float u = 2.0f * fr[dim] - 1.0f;
+#pragma unroll
+            for (int e = 0; e < NZ; ++e) {
+                const int a = slot + 4 * e;
+                if (W % 4 == 0 || a < W) ph[dim][a][node] = wpoly_eval(wc[e], u);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cur = gr.z;
+        const int cx0 = cur % S, cy = cur / S;
+        const int ox = __float_as_int(r.w) % S - cx0;  // the node's x cell inside the brick
+        // operand B: px of node `node` at x = 4 slot .. + 3 as (hi, hi) and (lo, lo)
+        f16x8 B1, B2;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int a = 4 * slot + e - ox;
+            const float pv = (a >= 0 && a < W) ? ph[0][a < 0 ? 0 : (a >= W ? W - 1 : a)][node] : 0.0f;
+            const _Float16 h = (_Float16)pv;
+            const _Float16 l = (_Float16)(pv - (float)h);
+            B1[e] = h;
+            B1[4 + e] = h;
+            B2[e] = l;
+            B2[4 + e] = l;
+        }
+        // operand A: box row y = lane % 16 (rows at or beyond W read row W - 1; their py is zero)
+        const int yr = node < W ? node : W - 1;
+        const uint4 *arow = reinterpret_cast<const uint4 *>(&bx[cy + yr][(cx0 >> 2) + slot][0]);
+        const f16x8 A = __builtin_bit_cast(f16x8, arow[0]);
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B1, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, B2, acc, 0, 0, 0);
+        float part = 0.0f;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int y = 4 * slot + rr;
+            const float pyv = (y < W) ? ph[1][y < W ? y : W - 1][node] : 0.0f;
+            part = fmaf(pyv, acc[rr], part);
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (slot == 0 && node < gr.y) out[gr.x + node] = part * unscale;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // ------------------------------------------------------------------ permutations
 __global__ void k_gather_perm(const int *__restrict__ perm, int64_t n, const float *__restrict__ v,
                               float *__restrict__ vs) {
@@ -2144,24 +2413,54 @@ int mfma_blocks_per_cu() {
     FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W, true>, 64 * MW, 0));
     return std::max(1, std::min(a, b));
 }
+template <int W, int T>
+int mfma_blocks_per_cu_2d() {
+    int a = 0, b = 0;
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma2d<W, T>, 64 * MW, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma2d<W, T>, 64 * MW, 0));
+    return std::max(1, std::min(a, b));
+}
 
-int mfma_slots(int W) {
-    static int cache[16][17] = {};
+// Resident matrix-core workgroups on the chip for window width W (d = 3, or d = 2 with tile T).
+int mfma_slots(int W, int d, int T) {
+    static int cache[16][2][17] = {};
     int dev = 0;
     FS_HIP(hipGetDevice(&dev));
-    if (dev < 16 && W <= 16 && cache[dev][W] > 0) return cache[dev][W];
+    const int v = (d == 3) ? 0 : 1;
+    if (dev < 16 && W <= 16 && (d == 3 || T == 32) && cache[dev][v][W] > 0)
+        return cache[dev][v][W];
     int cus = 0, per = 1;
     FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    switch (W) {
-        case 4: per = mfma_blocks_per_cu<4>(); break;
-        case 6: per = mfma_blocks_per_cu<6>(); break;
-        case 8: per = mfma_blocks_per_cu<8>(); break;
-        case 10: per = mfma_blocks_per_cu<10>(); break;
-        case 12: per = mfma_blocks_per_cu<12>(); break;
-        default: per = 1;
+    if (d == 3) {
+        switch (W) {
+            case 4: per = mfma_blocks_per_cu<4>(); break;
+            case 6: per = mfma_blocks_per_cu<6>(); break;
+            case 8: per = mfma_blocks_per_cu<8>(); break;
+            case 10: per = mfma_blocks_per_cu<10>(); break;
+            case 12: per = mfma_blocks_per_cu<12>(); break;
+            default: per = 1;
+        }
+    } else if (T == 32) {
+        switch (W) {
+            case 4: per = mfma_blocks_per_cu_2d<4, 32>(); break;
+            case 6: per = mfma_blocks_per_cu_2d<6, 32>(); break;
+            case 8: per = mfma_blocks_per_cu_2d<8, 32>(); break;
+            case 10: per = mfma_blocks_per_cu_2d<10, 32>(); break;
+            case 12: per = mfma_blocks_per_cu_2d<12, 32>(); break;
+            default: per = 1;
+        }
+    } else {
+        switch (W) {
+            case 4: per = mfma_blocks_per_cu_2d<4, 16>(); break;
+            case 6: per = mfma_blocks_per_cu_2d<6, 16>(); break;
+            case 8: per = mfma_blocks_per_cu_2d<8, 16>(); break;
+            case 10: per = mfma_blocks_per_cu_2d<10, 16>(); break;
+            case 12: per = mfma_blocks_per_cu_2d<12, 16>(); break;
+            default: per = 1;
+        }
     }
     const int slots = std::max(1, cus * per);
-    if (dev < 16 && W <= 16) cache[dev][W] = slots;
+    if (dev < 16 && W <= 16 && (d == 3 || T == 32)) cache[dev][v][W] = slots;
     return slots;
 }
 
@@ -2244,7 +2543,7 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
     hs.upload(nd.mmulti_tiles.p, multi.data(), multi.size() * sizeof(int));
     exclusive_scan(mg.gcount.p, mg.nbricks, gstart.p, s, &keep);
     hipLaunchKernelGGL(k_fill_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
-                       gstart.p, mg.nbricks, (int)n, pp.T, pp.T + pp.W - 1, nd.mgroups.p);
+                       gstart.p, mg.nbricks, (int)n, pp.d, pp.T, pp.T + pp.W - 1, nd.mgroups.p);
     FS_LAUNCHED();
     if (nd.n_mblocks > 0) {
         hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
@@ -2312,9 +2611,9 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
                            nd.xs.p);
         FS_LAUNCHED();
     }
-    // matrix-core groups (d = 3): per-brick and per-tile counts, read back with the chunk table
-    const bool mgroups = d == 3 && cell_keys && T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 &&
-                         n > 0;
+    // matrix-core groups (d = 2, 3): per-brick and per-tile counts, read back with the chunk table
+    const bool mgroups = (d == 3 || (d == 2 && (T == 32 || T == 16))) && cell_keys &&
+                         T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 && n > 0;
     MGroupBuild mg;
     if (mgroups) mgroups_count(mg, kstart.p, n, ntiles, cells_per_tile, s, hs);
     const int *tot = hs.download(totals.p, 2);
@@ -2355,7 +2654,7 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
         FS_LAUNCHED();
     }
     nd.n_mgroups = nd.n_mblocks = nd.n_mmulti = 0;
-    if (mgroups) mgroups_fill(nd, mg, kstart.p, n, ntiles, pp, mfma_slots(pp.W), s, keep, hs);
+    if (mgroups) mgroups_fill(nd, mg, kstart.p, n, ntiles, pp, mfma_slots(pp.W, d, T), s, keep, hs);
     for (auto &b : keep) hs.hold(b);
     hs.hold(key);
     hs.hold(rank);
@@ -2820,9 +3119,15 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 hipLaunchKernelGGL((k_spread<D, W, T>), dim3(src.nchunks), dim3(256), 0, s,
                                    src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
             } else {
-                if constexpr (D == 3 && W + BRICK_X - 1 <= 16) mf = use_mfma(pl, src);
-                FS_REQUIRE(!pw || mf, FS_EINVAL, "weights from potentials need the matrix-core spread");
+                if constexpr (D >= 2 && W + BRICK_X - 1 <= 16) mf = use_mfma(pl, src);
+                FS_REQUIRE(!pw || (mf && D == 3), FS_EINVAL,
+                           "weights from potentials need the 3-D matrix-core spread");
                 if (mf) {
+                    if constexpr (D == 2 && W + BRICK_X - 1 <= 16) {
+                        hipLaunchKernelGGL((k_spread_mfma2d<W, T>), dim3(src.n_mblocks),
+                                           dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
+                                           src.mgroups.p, sa, pl.scratch.p);
+                    }
                     if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                         if (pw)
                             hipLaunchKernelGGL((k_spread_mfma16<W, true>), dim3(src.n_mblocks),
@@ -2963,6 +3268,14 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 const float gscale = (float)(pp.G / pp.P);
                 const unsigned split = (pp.chunk >= 512) ? 2 : 1;
                 bool mf = false;
+                if constexpr (D == 2 && W + BRICK_X - 1 <= 16) {
+                    mf = !grad && use_mfma(pl, dst);
+                    FS_REQUIRE(!pu, FS_EINVAL, "the fused update needs the 3-D matrix-core gather");
+                    if (mf)
+                        hipLaunchKernelGGL((k_gather_mfma2d<W, T>), dim3(dst.n_mblocks),
+                                           dim3(64 * MW), 0, s, dst.rec.p, dst.mblocks.p,
+                                           dst.mgroups.p, sa, pl.grid.p, t);
+                }
                 if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                     mf = !grad && use_mfma(pl, dst);
                     FS_REQUIRE(!pu || mf, FS_EINVAL, "the fused update needs the matrix-core gather");

@@ -248,6 +248,59 @@ def test_uot_matrix_core_groups():
     assert np.any(fv.cpu().numpy() != f.cpu().numpy())  # the matrix cores ran
 
 
+def dense_and_sparse_2d(n, m, seed, frac=0.8):
+    """2-D: a fraction `frac` of the points in a small square (many per grid cell), the rest
+    spread over the whole box: full, partial and single-node matrix-core groups."""
+    rng = np.random.default_rng([778, n, m, seed])
+
+    def pts(k):
+        kd = int(frac * k)
+        p = np.concatenate([rng.uniform(-0.03, 0.03, (kd, 2)),
+                            rng.uniform(-0.25, 0.25, (k - kd, 2))])
+        return rng.permutation(p).astype(np.float32)
+    return pts(n), pts(m), rng.uniform(0.5, 1.5, m).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind,lam,grid,window", [("gauss", 0.01, 128, 6), ("gauss", 0.01, 128, 4),
+                                                  ("gauss", 0.05, 64, 5), ("gauss", 0.05, 16, 3),
+                                                  ("laplace", 0.01, 256, 6),
+                                                  ("energy", 1.0, 256, 6)])
+def test_fastsum_2d_matrix_core_groups(kind, lam, grid, window):
+    """2-D spread and gather on the matrix cores (tiles of 32 or 16 cells, window widths 6..12)
+    against the oracle on sampled rows and against the lane-per-node kernels on every row."""
+    x, y, v = dense_and_sparse_2d(40_000, 37_001, grid + window)
+    args = dict(kernel=kind, lam=lam, grid=grid, window=window)
+    got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
+    valu = fu.fastsum_apply(T(x), T(y), T(v), flags=fu.FLAG_FORCE_VALU, **args).cpu().numpy()
+    rows = synth.sample_rows(len(x), 200, seed=grid)
+    ref = oracle.direct_sum_rows(x, rows, y, v, kind, lam)
+    if window >= 5:  # the narrow windows carry the NFFT error of their width
+        assert relinf(got[rows], ref) < TOL
+    assert relinf(got, valu) < 2e-6
+    assert np.any(got != valu)  # the two paths differ in rounding: the matrix cores ran
+
+
+def test_uot_2d_matrix_core_groups():
+    """A 2-D Sinkhorn solve whose kernel sums take the matrix-core spread and gather (dense
+    clusters, grid 128^2) against the oracle's iterates."""
+    x, y, _ = dense_and_sparse_2d(8000, 7001, 23, frac=0.95)
+    rng = np.random.default_rng(24)
+    a = rng.uniform(0.5, 1.5, len(x)).astype(np.float32)
+    b = rng.uniform(0.5, 1.5, len(y)).astype(np.float32)
+    a, b = a / a.sum(), (1.3 * b / b.sum()).astype(np.float32)
+    eps, rho, sweeps = 0.01, 0.5, 10
+    f, g, obj = fu.uot_sinkhorn(T(x), T(a), T(y), T(b), eps, rho, sweeps, kernel="gauss",
+                                grid=128, window=6)
+    beta, gamma = oracle.uot_sinkhorn(x, a, y, b, eps, rho, sweeps)
+    D = oracle.uot_dual(x, a, y, b, eps, rho, beta, gamma)
+    assert relinf(f.cpu().numpy(), beta) < TOL
+    assert relinf(g.cpu().numpy(), gamma) < TOL
+    assert abs(obj - D) < TOL * abs(D)
+    fv, _, _ = fu.uot_sinkhorn(T(x), T(a), T(y), T(b), eps, rho, sweeps, kernel="gauss",
+                               grid=128, window=6, flags=fu.FLAG_FORCE_VALU)
+    assert np.any(fv.cpu().numpy() != f.cpu().numpy())  # the matrix cores ran
+
+
 @pytest.mark.parametrize("kind,lam,grid", [("gauss", 0.02, 64), ("energy", 1.0, 128)])
 def test_mmd_matrix_core_groups(kind, lam, grid):
     """MMD^2 of dense 3-D clouds (matrix-core spread and gather) against the oracle."""
