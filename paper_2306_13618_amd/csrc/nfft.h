@@ -119,10 +119,10 @@ struct PotUpdate {
     int *nbad = nullptr;
 };
 
-// True when the kernel sum of this direction evaluates such weights inside its spread (3-D
-// matrix-core spread, no near field); plan_apply_sorted_pot then needs no weight array.
+// True when the kernel sum of this direction evaluates such weights inside its spread (2-D or
+// 3-D matrix-core spread, no near field); plan_apply_sorted_pot then needs no weight array.
 bool plan_fuses_weights(const Plan &pl, int transpose);
-// True when, in addition, the gather forms the potential update itself (3-D matrix-core gather);
+// True when, in addition, the gather forms the potential update itself (matrix-core gather);
 // plan_update_parts is then the number of maxima it writes.
 bool plan_fuses_update(const Plan &pl, int transpose);
 int plan_update_parts(const Plan &pl, int transpose);

@@ -1857,13 +1857,15 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
 // rank-16 product of the two window factors, two v_mfma_f32_16x16x32_f16 per group with both
 // factors split into FP16 hi + lo (as in the 3-D spread, whose y-z products are replaced here by
 // py itself).  Lane l holds H[4 (l / 16) + r][l % 16]; the sums stay in registers while the brick
-// stays the same and then go to the block's int32 LDS box (fixed point, see chunk_scale).
-template <int W, int T>
+// stays the same and then go to the block's int32 LDS box (fixed point, see chunk_scale).  With
+// POT the weights are formed from the potentials (weight_exp), as in the 3-D spread.
+template <int W, int T, bool POT>
 __global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restrict__ rec,
                                                        const float *__restrict__ w,
                                                        const int4 *__restrict__ mblocks,
                                                        const int4 *__restrict__ mgroups,
-                                                       SpreadArgs sa, float *__restrict__ scratch) {
+                                                       SpreadArgs sa, float *__restrict__ scratch,
+                                                       PotWeights pw) {
     constexpr int S = T + W - 1, BOX = S * S;
     constexpr int NZ = (W + 3) / 4;      // window offsets per lane: slot + 4 e
     constexpr int XR = W + BRICK_X - 1;  // box columns a brick reaches
@@ -1874,12 +1876,24 @@ __global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restr
     __shared__ float phy[MW][W][16];    // per wave: py, offset-major
     __shared__ int oxs[MW][16];
     __shared__ float red[16];
+    __shared__ double pmx[MW];
     const int4 mb = mblocks[blockIdx.x];
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
     const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
+    double pmax = 0.0;
+    if (POT) {
+        double mx = -INFINITY;
+        for (int b = threadIdx.x; b < pw.nparts; b += blockDim.x) mx = fmax(mx, pw.parts[b]);
+        mx = block_max_f64(mx, pmx);
+        pmax = (mx == -INFINITY) ? 0.0 : mx;
+    }
+    auto weight = [&](int k) -> float {
+        if (POT) return weight_exp(pw.base[k], (pw.pot[k] - pmax) * pw.inv_eps);
+        return w[k];
+    };
     float wm = 0.0f;
-    const float scale = chunk_scale(w, k0, cnt, red, &wm);
+    const float scale = chunk_scale_fn(weight, k0, cnt, red, &wm);
     const float wmax = (wm > 0.0f) ? wm : 1.0f;
     const float inv_wmax = 1.0f / wmax, fscale = scale * wmax;
     const int lane = threadIdx.x & 63;
@@ -1914,7 +1928,7 @@ __global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restr
         const int4 gr = mgroups[g];
         const int nn = min(col, gr.y - 1);
         const float4 r = rec[gr.x + nn];
-        const float alpha = (col < gr.y) ? w[gr.x + nn] * inv_wmax : 0.0f;
+        const float alpha = (col < gr.y) ? weight(gr.x + nn) * inv_wmax : 0.0f;
         // window values of node `col` at offsets slot + 4 e
 #pragma unroll
         for (int e = 0; e < NZ; ++e) {
@@ -1968,14 +1982,15 @@ __global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restr
 // columns from the brick's first cell.  E is two v_mfma_f32_16x16x32_f16 per group (rows y,
 // columns the 16 nodes, K = 16 columns x the hi/lo cross products, the box kept in LDS as in the
 // 3-D gather, scaled by a power of two); lane l then holds E[4 (l / 16) + r][l % 16] and forms
-// its part of the y sum, the four parts of a node being added across lanes.
-template <int W, int T>
+// its part of the y sum, the four parts of a node being added across lanes.  With UPD the
+// potential update is applied to the sums instead of storing them, as in the 3-D gather.
+template <int W, int T, bool UPD>
 __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restrict__ rec,
                                                        const int4 *__restrict__ mblocks,
                                                        const int4 *__restrict__ mgroups,
                                                        SpreadArgs sa,
                                                        const float *__restrict__ grid,
-                                                       float *__restrict__ out) {
+                                                       float *__restrict__ out, PotUpdate pu) {
     constexpr int S = T + W - 1, BOX = S * S;
     constexpr int NC = (T + 12) / 4;  // groups of 4 columns: the last brick reaches x < T - 4 + 16
     constexpr int NZ = (W + 3) / 4;
@@ -1985,6 +2000,7 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restr
     __shared__ __align__(16) _Float16 bx[S][NC][8];
     __shared__ float phi[MW][2][W][16];
     __shared__ float red[MW];
+    __shared__ double dred[MW];
     const int4 mb = mblocks[blockIdx.x];
     int tc[3];
     tile_coords<2>(mb.x, sa.ntd, tc);
@@ -2035,6 +2051,14 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restr
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int node = lane & 15, slot = lane >> 4;
+    double shift = 0.0, pmx = -INFINITY, dmx = 0.0;
+    int bad = 0;
+    if (UPD) {
+        double v = -INFINITY;
+        for (int b = threadIdx.x; b < pu.nshift; b += blockDim.x) v = fmax(v, pu.shift_parts[b]);
+        shift = block_max_f64(v, dred);
+        if (shift == -INFINITY) shift = 0.0;
+    }
     float wc[NZ][WPOLY];
 #pragma unroll
     for (int e = 0; e < NZ; ++e) {
@@ -2103,10 +2127,34 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restr
         }
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);
-        if (slot == 0 && node < gr.y) out[gr.x + node] = part * unscale;
+        if (slot == 0 && node < gr.y) {
+            const int k = gr.x + node;
+            float t = part * unscale;
+            if (!UPD) {
+                out[k] = t;
+            } else {
+                if (!(t > 0.0f)) {
+                    ++bad;
+                    t = FLT_MIN;
+                }
+                const double f = -pu.kappa * (shift + pu.eps * sum_log(t));
+                if (pu.delta_parts) dmx = fmax(dmx, fabs(f - pu.pot[k]));
+                pu.pot[k] = f;
+                pmx = fmax(pmx, f);
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (UPD) {
+        if (bad) atomicAdd(pu.nbad, bad);
+        pmx = block_max_f64(pmx, dred);
+        if (threadIdx.x == 0) pu.out_parts[blockIdx.x] = pmx;
+        if (pu.delta_parts) {
+            dmx = block_max_f64(dmx, dred);
+            if (threadIdx.x == 0) pu.delta_parts[blockIdx.x] = dmx;
+        }
     }
 }
 
@@ -2416,8 +2464,10 @@ int mfma_blocks_per_cu() {
 template <int W, int T>
 int mfma_blocks_per_cu_2d() {
     int a = 0, b = 0;
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma2d<W, T>, 64 * MW, 0));
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma2d<W, T>, 64 * MW, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma2d<W, T, true>, 64 * MW,
+                                                        0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma2d<W, T, true>, 64 * MW,
+                                                        0));
     return std::max(1, std::min(a, b));
 }
 
@@ -3120,13 +3170,17 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                                    src.rec.p, w, src.chunks.p, sa, pl.scratch.p);
             } else {
                 if constexpr (D >= 2 && W + BRICK_X - 1 <= 16) mf = use_mfma(pl, src);
-                FS_REQUIRE(!pw || (mf && D == 3), FS_EINVAL,
-                           "weights from potentials need the 3-D matrix-core spread");
+                FS_REQUIRE(!pw || mf, FS_EINVAL, "weights from potentials need the matrix-core spread");
                 if (mf) {
                     if constexpr (D == 2 && W + BRICK_X - 1 <= 16) {
-                        hipLaunchKernelGGL((k_spread_mfma2d<W, T>), dim3(src.n_mblocks),
-                                           dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
-                                           src.mgroups.p, sa, pl.scratch.p);
+                        if (pw)
+                            hipLaunchKernelGGL((k_spread_mfma2d<W, T, true>), dim3(src.n_mblocks),
+                                               dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
+                                               src.mgroups.p, sa, pl.scratch.p, *pw);
+                        else
+                            hipLaunchKernelGGL((k_spread_mfma2d<W, T, false>), dim3(src.n_mblocks),
+                                               dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
+                                               src.mgroups.p, sa, pl.scratch.p, PotWeights{});
                     }
                     if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                         if (pw)
@@ -3270,11 +3324,15 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 bool mf = false;
                 if constexpr (D == 2 && W + BRICK_X - 1 <= 16) {
                     mf = !grad && use_mfma(pl, dst);
-                    FS_REQUIRE(!pu, FS_EINVAL, "the fused update needs the 3-D matrix-core gather");
-                    if (mf)
-                        hipLaunchKernelGGL((k_gather_mfma2d<W, T>), dim3(dst.n_mblocks),
+                    FS_REQUIRE(!pu || mf, FS_EINVAL, "the fused update needs the matrix-core gather");
+                    if (mf && pu)
+                        hipLaunchKernelGGL((k_gather_mfma2d<W, T, true>), dim3(dst.n_mblocks),
                                            dim3(64 * MW), 0, s, dst.rec.p, dst.mblocks.p,
-                                           dst.mgroups.p, sa, pl.grid.p, t);
+                                           dst.mgroups.p, sa, pl.grid.p, nullptr, *pu);
+                    else if (mf)
+                        hipLaunchKernelGGL((k_gather_mfma2d<W, T, false>), dim3(dst.n_mblocks),
+                                           dim3(64 * MW), 0, s, dst.rec.p, dst.mblocks.p,
+                                           dst.mgroups.p, sa, pl.grid.p, t, PotUpdate{});
                 }
                 if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                     mf = !grad && use_mfma(pl, dst);
@@ -3341,8 +3399,8 @@ void dispatch_w(Plan &pl, const Nodes &src, const Nodes &dst, const float *w, fl
 
 bool plan_fuses_weights(const Plan &pl, int transpose) {
     const Nodes &src = pl.src(transpose);
-    return pl.pp.d == 3 && !pl.pp.nearfield && pl.pp.W + BRICK_X - 1 <= 16 && use_mfma(pl, src) &&
-           src.nchunks > 0;
+    return (pl.pp.d == 3 || pl.pp.d == 2) && !pl.pp.nearfield && pl.pp.W + BRICK_X - 1 <= 16 &&
+           use_mfma(pl, src) && src.nchunks > 0;
 }
 
 bool plan_fuses_update(const Plan &pl, int transpose) {
@@ -3355,11 +3413,15 @@ int plan_update_parts(const Plan &pl, int transpose) { return pl.dst(transpose).
 void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
                            hipStream_t s, const PotUpdate *pu) {
     FS_REQUIRE(plan_fuses_weights(pl, transpose), FS_EINVAL,
-               "weights from potentials need the 3-D matrix-core spread without near field");
+               "weights from potentials need the matrix-core spread without near field");
     FS_REQUIRE(!pu || plan_fuses_update(pl, transpose), FS_EINVAL,
-               "the fused update needs the 3-D matrix-core gather");
-    dispatch_w<3>(pl, pl.src(transpose), pl.dst(transpose), nullptr, t_sorted, nullptr, s, &pw,
-                  pu);
+               "the fused update needs the matrix-core gather");
+    if (pl.pp.d == 3)
+        dispatch_w<3>(pl, pl.src(transpose), pl.dst(transpose), nullptr, t_sorted, nullptr, s, &pw,
+                      pu);
+    else
+        dispatch_w<2>(pl, pl.src(transpose), pl.dst(transpose), nullptr, t_sorted, nullptr, s, &pw,
+                      pu);
 }
 
 void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *grad,
