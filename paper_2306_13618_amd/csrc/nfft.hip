@@ -2557,7 +2557,10 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
         for (int64_t t = 0; t < ntiles; ++t) b += (tg[t] + g - 1) / g;
         return b;
     };
-    int lo = (int)std::max<int64_t>(MIN_GROUPS_PER_BLOCK, (total + slots - 1) / std::max(slots, 1));
+    // 2-D groups are cheap (two matrix instructions each): blocks of at least four groups per wave
+    // keep the per-block fixed work and the number of boxes to reduce down
+    const int min_gpb = (pp.d == 2) ? 4 * MIN_GROUPS_PER_BLOCK : MIN_GROUPS_PER_BLOCK;
+    int lo = (int)std::max<int64_t>(min_gpb, (total + slots - 1) / std::max(slots, 1));
     int hi = std::max(lo, tmax);
     while (lo < hi) {
         const int mid = lo + (hi - lo) / 2;
