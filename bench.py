@@ -87,7 +87,7 @@ def extra_rows(fu, torch, dev, synth, keep):
     rows = {}
 
     # 2-D Gaussian-mixture Sinkhorn, n=m=100k, grid 128^2, 100 sweeps, fast vs direct
-    w = synth.make("cfg1")
+    w = synth.make("uot_d2_n100k")
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
     run = lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], w["iters"], grid=w["grid"],
                                   window=w["window"])
@@ -97,12 +97,12 @@ def extra_rows(fu, torch, dev, synth, keep):
     rows["uot_d2_n100k"] = {"sweeps_per_s": w["iters"] / t, "direct_sweeps_per_s": 2 / td,
                             "speedup_vs_direct": (w["iters"] / t) / (2 / td),
                             "err_sampled_last_halfstep": None}
-    keep["uot_d2_n100k"] = ("uot", "cfg1", 2, f.cpu().numpy(), g.cpu().numpy())
+    keep["uot_d2_n100k"] = ("uot", "uot_d2_n100k", 2, f.cpu().numpy(), g.cpu().numpy())
     log("2-D 100k: %.0f sweeps/s fast, %.1f direct" % (w["iters"] / t, 2 / td))
 
     # MMD^2 at d=3, n=m=1M: energy kernel (near-field radius 1/16), Gaussian lambda=0.02, and the
     # inverse multiquadric with c = 0.05 (near-field radius 1/16)
-    w = synth.make("cfg2")
+    w = synth.make("uot_d3_n1M")
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
     mmd_rows = {}
     for kind, opts in (("energy", {"grid": 256, "nearfield_radius": w["nearfield_radius"]}),
@@ -136,7 +136,7 @@ def extra_rows(fu, torch, dev, synth, keep):
     rows["mmd_accuracy_d2_n10k"] = acc
 
     # 4M Laplace Gibbs-kernel Sinkhorn (r = 1) with near field, grid 256^3
-    w = synth.make("cfg4a")
+    w = synth.make("laplace_d3_n4M")
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
     it = 5
     opts = {"kernel": "laplace", "grid": w["grid"], "window": w["window"],
@@ -147,13 +147,13 @@ def extra_rows(fu, torch, dev, synth, keep):
                                   "grid": w["grid"], "bandwidth": w["bandwidth"],
                                   "smoothness": w["smoothness"],
                                   "err_sampled_last_halfstep": None}
-    keep["uot_laplace_d3_n4M"] = ("uot", "cfg4a", 1, f.cpu().numpy(), g.cpu().numpy())
+    keep["uot_laplace_d3_n4M"] = ("uot", "laplace_d3_n4M", 1, f.cpu().numpy(), g.cpu().numpy())
     log("4M Laplace: %.1f sweeps/s (%d sweeps incl. plan)" % (it / t, it))
 
     # lambda-scaling (Section "lambda-scaling": Lambda = {1, 20, 100}, eta = 25, probability
     # measures): the 2-D mixtures normalised to mass 1, temperatures 1, 0.05, 0.01 against a
     # solve at 0.01 alone, both to the same stopping rule (largest change <= 1e-4 eps per sweep)
-    w = synth.make("cfg1")
+    w = synth.make("uot_d2_n100k")
     a1, b1 = w["a"] / w["a"].sum(dtype=np.float64), w["b"] / w["b"].sum(dtype=np.float64)
     x, a, y, b = (torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(dev)
                   for v in (w["x"], a1, w["y"], b1))
@@ -192,7 +192,7 @@ def extra_rows(fu, torch, dev, synth, keep):
 
     # upper bound of eq. (561) at the headline workload: r = 2 from moments, r = 1 through one
     # energy-kernel sum (grid 256, near-field radius 1/16)
-    w = synth.make("cfg2")
+    w = synth.make("uot_d3_n1M")
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
     ub = {}
     for label, opts in (("r2", {"kernel": "gauss"}),
@@ -205,7 +205,7 @@ def extra_rows(fu, torch, dev, synth, keep):
     rows["upper_bound_d3_n1M"] = ub
 
     # d = 32 direct Gaussian sum on the MFMA path (BF16 hi/lo Gram tiles), n=m=200k
-    w = synth.make("cfg4b")
+    w = synth.make("gauss_d32_n200k")
     x, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "y", "b"))
     fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0)
     out, t = timed(torch, lambda: fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0), 3)
@@ -216,7 +216,7 @@ def extra_rows(fu, torch, dev, synth, keep):
                      "unit": "TFLOP/s", "frac": flops / t / 1e12 / 2500.0,
                      "work": "3 BF16 products x 2 x d x n x m"},
         "pairs_per_s": w["n"] * w["m"] / t}
-    keep["mfma_gauss_d32_n200k"] = ("sum", "cfg4b", out.cpu().numpy())
+    keep["mfma_gauss_d32_n200k"] = ("sum", "gauss_d32_n200k", out.cpu().numpy())
     log("d=32 MFMA: %.2f ms" % (1e3 * t))
     return rows
 
@@ -278,7 +278,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the fast-summation path is built and timed on a "
-              "single MI355X (sharding across GPUs is described in DESIGN.md, not implemented).",
+              "single MI355X (sharding across GPUs is not implemented).",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -286,7 +286,7 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
-    w = synth.make("cfg2", n=args.n)
+    w = synth.make("uot_d3_n1M", n=args.n)
     n, m, d = w["n"], w["m"], w["d"]
     eps, rho, sweeps = w["eps"], w["rho"], w["iters"]
     x, a, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "a", "y", "b"))
@@ -378,7 +378,7 @@ def main():
     # ---- secondary: Sinkhorn divergence forward and forward+backward (d=2, n=m=200k)
     secondary = None
     if not args.no_secondary:
-        w3 = synth.make("cfg3")
+        w3 = synth.make("divergence_d2_n200k")
         x3, a3, y3, b3 = (torch.from_numpy(w3[k]).to(dev) for k in ("x", "a", "y", "b"))
         it3 = 300
         opts = {"grid": w3["grid"], "window": w3["window"]}

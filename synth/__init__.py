@@ -3,54 +3,55 @@
 This module only draws random numbers and holds the workload recipes.  It contains none of the
 method's arithmetic, and it is the one piece shared by the CPU oracle, the tests and the benchmark.
 
-Every array is drawn in float64 from ``numpy.random.default_rng([2306, 13618, cfg, rep])`` and cast
-to float32 once, so the GPU path and the oracle see bit-identical inputs (the oracle promotes the
+Every array is drawn in float64 from ``numpy.random.default_rng([2306, 13618, k, rep])`` (k: the
+workload's index) and cast to float32 once, so the GPU path and the oracle see bit-identical inputs (the oracle promotes the
 float32 values back to float64).
 
 Workloads (all coordinates inside the cube [-1/4, 1/4)^d, weights drawn U(0.5, 1.5) and rescaled to
 the stated total masses; the paper's own synthetic setup draws uniform points and uniform weights,
 Section "Empirical measures"):
 
-* ``cfg0``: d=1, n=m=2000; x ~ U[-1/4,1/4), y ~ N(0.05, 0.08^2) clipped; masses 1.0 / 1.5;
+* ``uot_d1_n2k``: d=1, n=m=2000; x ~ U[-1/4,1/4), y ~ N(0.05, 0.08^2) clipped; masses 1.0 / 1.5;
   Gibbs kernel exp(-|x-y|^2/eps), eps=0.05, rho=1 (the paper's lambda=20, eta=1); 200 sweeps.
-* ``cfg1``: d=2, n=m=100k; x from an 8-component, y from a 12-component Gaussian mixture (means
-  U[-0.15,0.15]^2, sigma=0.02, equal component weights), clipped; masses 1.0 / 1.3;
+* ``uot_d2_n100k``: d=2, n=m=100k; x from an 8-component, y from a 12-component Gaussian mixture
+  (means U[-0.15,0.15]^2, sigma=0.02, equal component weights), clipped; masses 1.0 / 1.3;
   eps=0.01, rho=0.5; grid 128^2, window cutoff 6; 100 sweeps.
-* ``cfg2``: d=3, n=m=1M; x ~ U[-1/4,1/4)^3, y = clip(x + N(0, 0.03^2 I)); masses 1.0 / 1.2;
+* ``uot_d3_n1M``: d=3, n=m=1M; x ~ U[-1/4,1/4)^3, y = clip(x + N(0, 0.03^2 I)); masses 1.0 / 1.2;
   UOT eps=0.02, rho=1, 50 sweeps; MMD with the energy kernel (near-field radius 1/16) and with the
   Gaussian lambda=0.02; grid 64^3, window cutoff 6.
-* ``cfg3``: d=2, n=m=200k, clouds as cfg1; Sinkhorn divergence (eps=0.01, rho=0.5) and Gaussian
-  MMD (lambda=0.01), forward and backward.
-* ``cfg4a``: d=3, n=m=4M, clouds as cfg2; Laplace Gibbs kernel exp(-|x-y|/eps), eps=0.01, near
-  field; grid 256^3; rho=1, 50 sweeps; masses 1.0 / 1.2.
-* ``cfg4b``: d=32, n=m=200k; x ~ N(0, I)/sqrt(32), y ~ N(0.1, I)/sqrt(32) (not clipped);
+* ``divergence_d2_n200k``: d=2, n=m=200k, clouds as uot_d2_n100k; Sinkhorn divergence (eps=0.01,
+  rho=0.5) and Gaussian MMD (lambda=0.01), forward and backward.
+* ``laplace_d3_n4M``: d=3, n=m=4M, clouds as uot_d3_n1M; Laplace Gibbs kernel exp(-|x-y|/eps),
+  eps=0.01, near field; grid 256^3; rho=1, 50 sweeps; masses 1.0 / 1.2.
+* ``gauss_d32_n200k``: d=32, n=m=200k; x ~ N(0, I)/sqrt(32), y ~ N(0.1, I)/sqrt(32) (not clipped);
   Gaussian lambda=1; masses 1.0 / 1.2; direct summation.
 """
 import numpy as np
 
 SEED_ROOT = (2306, 13618)
-CFG_INDEX = {"cfg0": 0, "cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4a": 4, "cfg4b": 5}
+CFG_INDEX = {"uot_d1_n2k": 0, "uot_d2_n100k": 1, "uot_d3_n1M": 2, "divergence_d2_n200k": 3,
+             "laplace_d3_n4M": 4, "gauss_d32_n200k": 5}
 
 # The largest float32 strictly below 1/4: "clipped to [-1/4, 1/4)".
 HI = float(np.nextafter(np.float32(0.25), np.float32(0.0)))
 LO = -0.25
 
 CONFIGS = {
-    "cfg0": dict(d=1, n=2000, mass_a=1.0, mass_b=1.5, kernel="gauss", eps=0.05, rho=1.0,
-                 iters=200, grid=64, window=6, points="cfg0"),
-    "cfg1": dict(d=2, n=100_000, mass_a=1.0, mass_b=1.3, kernel="gauss", eps=0.01, rho=0.5,
+    "uot_d1_n2k": dict(d=1, n=2000, mass_a=1.0, mass_b=1.5, kernel="gauss", eps=0.05, rho=1.0,
+                 iters=200, grid=64, window=6, points="uot_d1_n2k"),
+    "uot_d2_n100k": dict(d=2, n=100_000, mass_a=1.0, mass_b=1.3, kernel="gauss", eps=0.01, rho=0.5,
                  iters=100, grid=128, window=6, points="mixture"),
-    "cfg2": dict(d=3, n=1_000_000, mass_a=1.0, mass_b=1.2, kernel="gauss", eps=0.02, rho=1.0,
+    "uot_d3_n1M": dict(d=3, n=1_000_000, mass_a=1.0, mass_b=1.2, kernel="gauss", eps=0.02, rho=1.0,
                  iters=50, grid=64, window=6, points="perturbed", mmd_lambda=0.02,
                  nearfield_radius=1.0 / 16),
-    "cfg3": dict(d=2, n=200_000, mass_a=1.0, mass_b=1.3, kernel="gauss", eps=0.01, rho=0.5,
-                 iters=2000, grid=128, window=6, points="mixture", mmd_lambda=0.01,
-                 fd_h=1e-3, fd_coords=64),
-    "cfg4a": dict(d=3, n=4_000_000, mass_a=1.0, mass_b=1.2, kernel="laplace", eps=0.01,
+    "divergence_d2_n200k": dict(d=2, n=200_000, mass_a=1.0, mass_b=1.3, kernel="gauss", eps=0.01,
+                                rho=0.5, iters=2000, grid=128, window=6, points="mixture",
+                                mmd_lambda=0.01, fd_h=1e-3, fd_coords=64),
+    "laplace_d3_n4M": dict(d=3, n=4_000_000, mass_a=1.0, mass_b=1.2, kernel="laplace", eps=0.01,
                   rho=1.0, iters=50, grid=256, window=6, points="perturbed", bandwidth=192,
                   smoothness=6),
-    "cfg4b": dict(d=32, n=200_000, mass_a=1.0, mass_b=1.2, kernel="gauss", eps=1.0, rho=1.0,
-                  iters=50, grid=0, window=0, points="gauss32"),
+    "gauss_d32_n200k": dict(d=32, n=200_000, mass_a=1.0, mass_b=1.2, kernel="gauss", eps=1.0,
+                            rho=1.0, iters=50, grid=0, window=0, points="gauss32"),
 }
 
 
@@ -81,7 +82,7 @@ def make(cfg, rep=0, n=None, m=None):
     m = n if m is None else int(m)
     rng = rng_for(cfg, rep)
     kind = c["points"]
-    if kind == "cfg0":
+    if kind == "uot_d1_n2k":
         x = rng.uniform(LO, 0.25, (n, d))
         y = np.clip(rng.normal(0.05, 0.08, (m, d)), LO, HI)
     elif kind == "mixture":

@@ -35,7 +35,7 @@ def last_halfstep_error(w, f, g, eps, rho, r=2, k=96):
     return relmax(g[rows], ref)
 
 
-@pytest.mark.parametrize("cfg,grid,window", [("cfg2", 64, 6), ("cfg1", 128, 6)])
+@pytest.mark.parametrize("cfg,grid,window", [("uot_d3_n1M", 64, 6), ("uot_d2_n100k", 128, 6)])
 def test_uot_full_size(cfg, grid, window):
     w = synth.make(cfg)
     print("case", cfg, w["n"], "points", w["iters"], "sweeps", flush=True)
@@ -46,8 +46,8 @@ def test_uot_full_size(cfg, grid, window):
     assert last_halfstep_error(w, f, g, w["eps"], w["rho"]) < TOL
 
 
-def test_cfg2_fastsum_gauss_and_energy_full_size():
-    w = synth.make("cfg2")
+def test_d3_n1M_fastsum_gauss_and_energy_full_size():
+    w = synth.make("uot_d3_n1M")
     x, y = T(w["x"]), T(w["y"])
     rows = synth.sample_rows(w["n"], 96, seed=4)
     v = w["b"]
@@ -61,10 +61,10 @@ def test_cfg2_fastsum_gauss_and_energy_full_size():
     assert relmax(got[rows], ref) < TOL
 
 
-def test_cfg2_mmd_full_size_properties():
+def test_d3_n1M_mmd_full_size_properties():
     """MMD(mu, mu) = 0 at full size; the two-measure value is finite and the three double sums are
     consistent with the sampled kernel sums."""
-    w = synth.make("cfg2")
+    w = synth.make("uot_d3_n1M")
     x, a, y, b = T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"])
     for kind, opts in (("gauss", {"lam": w["mmd_lambda"], "grid": 64}),
                        ("energy", {"grid": 256, "nearfield_radius": w["nearfield_radius"]})):
@@ -74,8 +74,8 @@ def test_cfg2_mmd_full_size_properties():
         assert np.isfinite(v) and abs(v - (t3[0] - 2 * t3[1] + t3[2])) < 1e-12 * max(map(abs, t3))
 
 
-def test_cfg4b_mfma_full_size():
-    w = synth.make("cfg4b")
+def test_d32_n200k_mfma_full_size():
+    w = synth.make("gauss_d32_n200k")
     rows = synth.sample_rows(w["n"], 64, seed=5)
     v = w["b"] / w["b"].max()
     got = fu.fastsum_apply(T(w["x"]), T(w["y"]), T(v), kernel="gauss", lam=w["eps"],
@@ -84,10 +84,10 @@ def test_cfg4b_mfma_full_size():
     assert relmax(got[rows], ref) < TOL
 
 
-def test_cfg3_divergence_gradient_full_size_against_oracle_envelope():
+def test_d2_n200k_divergence_gradient_full_size_against_oracle_envelope():
     """Gradient of S at n=m=200k (fast path) against the FP64 direct envelope gradient at the GPU's
     potentials, on 64 sampled rows."""
-    w = synth.make("cfg3")
+    w = synth.make("divergence_d2_n200k")
     opts = {"grid": w["grid"], "window": w["window"]}
     x, a, y, b = T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"])
     val, _, pots = fu.sinkhorn_divergence(x, a, y, b, w["eps"], w["rho"], 300,
@@ -108,8 +108,8 @@ def test_cfg3_divergence_gradient_full_size_against_oracle_envelope():
     assert ex < 1e-4 and ea < 1e-4
 
 
-def test_cfg3_mmd_gradient_full_size():
-    w = synth.make("cfg3")
+def test_d2_n200k_mmd_gradient_full_size():
+    w = synth.make("divergence_d2_n200k")
     x, a, y, b = T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"])
     dx, da, _, _ = fu.mmd_grad(x, a, y, b, kernel="gauss", lam=w["mmd_lambda"], grid=w["grid"],
                                window=w["window"])
@@ -119,11 +119,11 @@ def test_cfg3_mmd_gradient_full_size():
     assert relmax(da.cpu().numpy()[rows], ra) < 1e-4
 
 
-def test_cfg3_gradient_against_central_differences():
+def test_d2_gradient_against_central_differences():
     """dS/dx and dS/da from the GPU (fast path, converged potentials) against central differences
     (h = 1e-3 in positions, 1e-3 of the mean weight in weights) of the oracle's converged FP64
     divergence, at a reduced size of the same workload."""
-    w = synth.make("cfg3", n=320, m=300)
+    w = synth.make("divergence_d2_n200k", n=320, m=300)
     eps, rho, sweeps = w["eps"], w["rho"], 700
     opts = {"grid": 128, "window": 6}
     x = T(w["x"]).requires_grad_()

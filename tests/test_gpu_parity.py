@@ -95,9 +95,9 @@ def test_fastsum_nearfield_smoothness_and_radius(kind, d, smooth, radius):
     assert relinf(got, ref) < TOL
 
 
-@pytest.mark.parametrize("cfg,kind,n,radius", [("cfg2", "energy", 200_000, 1 / 16),
-                                               ("cfg2", "laplace", 300_000, 0.0),
-                                               ("cfg1", "energy", 150_000, 0.02)])
+@pytest.mark.parametrize("cfg,kind,n,radius", [("uot_d3_n1M", "energy", 200_000, 1 / 16),
+                                               ("uot_d3_n1M", "laplace", 300_000, 0.0),
+                                               ("uot_d2_n100k", "energy", 150_000, 0.02)])
 def test_fastsum_nearfield_dense_sampled(cfg, kind, n, radius):
     """Dense clouds (several cells per radius, uniform and clustered): sampled rows against the
     oracle's direct sums."""
@@ -381,7 +381,7 @@ def test_bad_arguments_raise():
 
 @pytest.mark.parametrize("n,m", [(1000, 777), (64, 33)])
 def test_mfma_gram_gauss_d32(n, m):
-    w = synth.make("cfg4b", n=n, m=m)
+    w = synth.make("gauss_d32_n200k", n=n, m=m)
     v = w["b"] / w["b"].max()
     got = fu.fastsum_apply(T(w["x"]), T(w["y"]), T(v), kernel="gauss", lam=1.0,
                            grid=0).cpu().numpy()
@@ -411,7 +411,7 @@ def test_mfma_gram_gauss_other_dims(d, n, m, lam):
 
 def test_uot_mfma_d32():
     """The d = 32 Sinkhorn on the MFMA path (Gibbs kernel exp(-|x-y|^2/eps)) against the oracle."""
-    w = synth.make("cfg4b", n=1500, m=1300)
+    w = synth.make("gauss_d32_n200k", n=1500, m=1300)
     f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
                                 10, kernel="gauss", grid=0)
     beta, gamma = oracle.uot_sinkhorn(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], 10)
@@ -433,10 +433,11 @@ def oracle_uot(key, x, a, y, b, eps, rho, sweeps, r=2):
 
 
 @pytest.mark.parametrize("grid", [0, 64])
-def test_uot_cfg0(grid):
-    """cfg0 in full: d=1, n=m=2000, 200 sweeps, eps=0.05, rho=1 (the paper's lambda=20, eta=1)."""
-    w = synth.make("cfg0")
-    beta, gamma, D = oracle_uot("cfg0", w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"],
+def test_uot_d1_n2k(grid):
+    """The 1-D workload in full: d=1, n=m=2000, 200 sweeps, eps=0.05, rho=1 (the paper's lambda=20,
+    eta=1)."""
+    w = synth.make("uot_d1_n2k")
+    beta, gamma, D = oracle_uot("uot_d1_n2k", w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"],
                                 w["iters"])
     f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
                                 w["iters"], kernel="gauss", grid=grid, window=6)
@@ -445,9 +446,9 @@ def test_uot_cfg0(grid):
     assert abs(obj - D) < TOL * abs(D)
 
 
-@pytest.mark.parametrize("cfg,n,sweeps,grid,window", [("cfg1", 3000, 30, 128, 6),
-                                                      ("cfg2", 2500, 20, 64, 6),
-                                                      ("cfg2", 2500, 20, 64, 4)])
+@pytest.mark.parametrize("cfg,n,sweeps,grid,window", [("uot_d2_n100k", 3000, 30, 128, 6),
+                                                      ("uot_d3_n1M", 2500, 20, 64, 6),
+                                                      ("uot_d3_n1M", 2500, 20, 64, 4)])
 def test_uot_reduced(cfg, n, sweeps, grid, window):
     w = synth.make(cfg, n=n, m=n - 217)
     beta, gamma, D = oracle_uot((cfg, n, sweeps), w["x"], w["a"], w["y"], w["b"], w["eps"],
@@ -461,9 +462,9 @@ def test_uot_reduced(cfg, n, sweeps, grid, window):
 
 def test_uot_laplace_gibbs_kernel():
     """r = 1: Gibbs kernel exp(-|x-y|/eps) through the near-field-corrected fast sum."""
-    w = synth.make("cfg4a", n=2000, m=1800)
+    w = synth.make("laplace_d3_n4M", n=2000, m=1800)
     sweeps = 10
-    beta, gamma, D = oracle_uot("cfg4a-small", w["x"], w["a"], w["y"], w["b"], w["eps"],
+    beta, gamma, D = oracle_uot("laplace_d3_n4M-small", w["x"], w["a"], w["y"], w["b"], w["eps"],
                                 w["rho"], sweeps, r=1)
     for grid in (0, 128):
         f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"],
@@ -478,7 +479,7 @@ def test_uot_laplace_gibbs_kernel():
 def test_uot_upper_bound(kind, grid):
     """c* of eq. (561) and the objective at c* mu x nu against the oracle (r = 2 from moments,
     r = 1 through an energy-kernel sum)."""
-    w = synth.make("cfg3", n=2000, m=1700)
+    w = synth.make("divergence_d2_n200k", n=2000, m=1700)
     r = 2 if kind == "gauss" else 1
     c, ub = fu.uot_upper_bound(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
                                kernel=kind, grid=grid, window=6)
@@ -497,7 +498,7 @@ def test_uot_scaling_against_oracle(grid, init):
     The sweep counts agree with the oracle's under the same rule (the FP32 kernel sums put a noise
     floor under the measured change, so a stage may run a few sweeps longer); the potentials
     agree with the oracle's iterate after the same number of sweeps per stage."""
-    w = synth.make("cfg3", n=900, m=800)
+    w = synth.make("divergence_d2_n200k", n=900, m=800)
     stages, rho, tol = [1.0, 0.05, 0.01], 1.0, 1e-6
     f, g, counts, obj = fu.uot_sinkhorn_scaling(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), stages,
                                                 rho, 3000, tol, init=init, grid=grid, window=6)
@@ -517,7 +518,7 @@ def test_uot_scaling_against_oracle(grid, init):
 
 
 def test_uot_scaling_single_stage_is_uot_sinkhorn():
-    w = synth.make("cfg3", n=700, m=650)
+    w = synth.make("divergence_d2_n200k", n=700, m=650)
     args = (T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]))
     f1, g1, c1, o1 = fu.uot_sinkhorn_scaling(*args, [0.05], 1.0, 25, 0.0, grid=0)
     f2, g2, o2 = fu.uot_sinkhorn(*args, 0.05, 1.0, 25, grid=0)
@@ -527,7 +528,7 @@ def test_uot_scaling_single_stage_is_uot_sinkhorn():
 
 
 def test_uot_warm_start_continues_the_iteration():
-    w = synth.make("cfg0", n=700, m=650)
+    w = synth.make("uot_d1_n2k", n=700, m=650)
     x, a, y, b = (T(w[k]) for k in ("x", "a", "y", "b"))
     f1, g1, _ = fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 7, grid=64)
     f2, g2, o2 = fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 5, grid=64, f0=f1, g0=g1)
@@ -536,7 +537,7 @@ def test_uot_warm_start_continues_the_iteration():
 
 
 def test_uot_objective_without_sweeps():
-    w = synth.make("cfg0", n=300, m=280)
+    w = synth.make("uot_d1_n2k", n=300, m=280)
     _, _, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"], 0)
     D = oracle.uot_dual(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], np.zeros(300),
                         np.zeros(280))
@@ -544,7 +545,7 @@ def test_uot_objective_without_sweeps():
 
 
 def test_sinkhorn_divergence():
-    w = synth.make("cfg3", n=900, m=800)
+    w = synth.make("divergence_d2_n200k", n=900, m=800)
     sweeps = 60
     sd, terms = oracle.sinkhorn_divergence(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"],
                                            sweeps)
@@ -585,7 +586,7 @@ def test_divergence_energy_limit_experiment(eps, eta):
                                            ("energy", 1.0, 0), ("imq", 0.1, 128), ("imq", 0.1, 0)])
 @pytest.mark.parametrize("d", [2, 3])
 def test_mmd(kind, lam, grid, d):
-    w = synth.make("cfg2" if d == 3 else "cfg1", n=1800, m=1500)
+    w = synth.make("uot_d3_n1M" if d == 3 else "uot_d2_n100k", n=1800, m=1500)
     x, y = w["x"][:, :d], w["y"][:, :d]
     ref, terms = oracle.mmd2(x, w["a"], y, w["b"], kind, lam)
     val, t3 = fu.mmd(T(x), T(w["a"]), T(y), T(w["b"]), kernel=kind, lam=lam, grid=grid, window=6,
@@ -625,7 +626,7 @@ def test_mmd_accuracy_experiment(kind, lam, grid, n):
 
 
 def test_mmd_self_is_zero():
-    w = synth.make("cfg2", n=2000)
+    w = synth.make("uot_d3_n1M", n=2000)
     x, a = T(w["x"]), T(w["a"])
     val, t3 = fu.mmd(x, a, x, a, kernel="gauss", lam=0.02, grid=64, terms=True)
     assert abs(val) < 1e-6 * abs(t3[0])
@@ -641,7 +642,7 @@ def test_uot_grad_against_oracle_envelope(kind, grid, tol):
     FP32 absolute error floor (~1e-7 of the largest sum) is multiplied by exp((f_i + gmax)/eps),
     which is large at points far from the transported mass; the max-normalised error there is
     ~1e-3, so that case carries a wider tolerance (the Gaussian cases keep 1e-4)."""
-    w = synth.make("cfg3", n=1200, m=1000)
+    w = synth.make("divergence_d2_n200k", n=1200, m=1000)
     r = 2 if kind == "gauss" else 1
     beta, gamma = oracle.uot_sinkhorn(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], 40, r=r)
     ref = oracle.uot_grad(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], beta, gamma, r=r)
@@ -652,11 +653,13 @@ def test_uot_grad_against_oracle_envelope(kind, grid, tol):
     assert max(errs) < tol
 
 
-@pytest.mark.parametrize("kind,lam,grid,cfg", [("gauss", 0.02, 0, "cfg1"), ("gauss", 0.02, 64, "cfg1"),
-                                               ("energy", 1.0, 256, "cfg1"),
-                                               ("energy", 1.0, 256, "cfg2"),
-                                               ("laplace", 0.05, 128, "cfg2"),
-                                               ("imq", 0.1, 128, "cfg1"), ("imq", 0.05, 256, "cfg2")])
+@pytest.mark.parametrize("kind,lam,grid,cfg", [("gauss", 0.02, 0, "uot_d2_n100k"),
+                                               ("gauss", 0.02, 64, "uot_d2_n100k"),
+                                               ("energy", 1.0, 256, "uot_d2_n100k"),
+                                               ("energy", 1.0, 256, "uot_d3_n1M"),
+                                               ("laplace", 0.05, 128, "uot_d3_n1M"),
+                                               ("imq", 0.1, 128, "uot_d2_n100k"),
+                                               ("imq", 0.05, 256, "uot_d3_n1M")])
 def test_mmd_grad_against_oracle(kind, lam, grid, cfg):
     w = synth.make(cfg, n=1100, m=900)
     ref = oracle.mmd2_grad(w["x"], w["a"], w["y"], w["b"], kind, lam)
@@ -668,7 +671,7 @@ def test_mmd_grad_against_oracle(kind, lam, grid, cfg):
 
 
 def test_autograd_functions():
-    w = synth.make("cfg3", n=500, m=450)
+    w = synth.make("divergence_d2_n200k", n=500, m=450)
     x = T(w["x"]).requires_grad_()
     a = T(w["a"]).requires_grad_()
     y, b = T(w["y"]), T(w["b"])

@@ -502,19 +502,19 @@ def test_mmd_grad_vs_central_differences(kind):
 
 # --------------------------------------------------------------------------- workloads
 
-def test_cfg0_matches_paper_table_parameters():
-    """cfg0 is the paper's Table tab:Sinkhorn3 parameter set (r=2, lambda=20, eta=1) in the
+def test_d1_workload_matches_paper_table_parameters():
+    """uot_d1_n2k is the paper's Table tab:Sinkhorn3 parameter set (r=2, lambda=20, eta=1) in the
     temperature convention eps = 1/lambda."""
     g = json.load(open(os.path.join(GOLDEN, "paper_parameters.json")))["table_sinkhorn3"]
-    c = synth.CONFIGS["cfg0"]
+    c = synth.CONFIGS["uot_d1_n2k"]
     assert abs(c["eps"] - 1.0 / g["lambda_paper"]) < 1e-15 and c["rho"] == g["eta"]
 
 
 def test_generators_are_seeded_and_in_domain():
-    a = synth.make("cfg2", n=5000)
-    b = synth.make("cfg2", n=5000)
+    a = synth.make("uot_d3_n1M", n=5000)
+    b = synth.make("uot_d3_n1M", n=5000)
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["b"], b["b"])
-    for c in ("cfg0", "cfg1", "cfg2"):
+    for c in ("uot_d1_n2k", "uot_d2_n100k", "uot_d3_n1M"):
         w = synth.make(c, n=3000)
         assert w["x"].dtype == np.float32 and w["x"].min() >= -0.25 and w["x"].max() < 0.25
         assert w["y"].min() >= -0.25 and w["y"].max() < 0.25
