@@ -3236,8 +3236,8 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 if (!all) fill_f32(pl.grid.p, gsz, 0.0f, s);
                 const unsigned nfold = all ? (unsigned)ntiles : (unsigned)src.n_touched;
                 if (nfold > 0)
-                    hipLaunchKernelGGL(k_fold_tiles<D>, dim3(nfold, (unsigned)((npts + 63) / 64)),
-                                       dim3(64), 0, s, pl.scratch.p, tile_boxes,
+                    hipLaunchKernelGGL(k_fold_tiles<D>, dim3(nfold, (unsigned)((npts + 255) / 256)),
+                                       dim3(256), 0, s, pl.scratch.p, tile_boxes,
                                        all ? nullptr : src.touched_tiles.p, pp.G, T, ntd, pp.m, S,
                                        pl.grid.p);
             } else {
