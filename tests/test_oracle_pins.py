@@ -169,6 +169,34 @@ def test_direct_sum_grad_vs_central_differences(kind):
             assert abs(fd - g[i, k]) < 1e-6 * (1 + abs(fd))
 
 
+# Rows in scrambled order, with a repeat and a gap: a row function that used the position t in
+# the list instead of rows[t] fails every case below.
+_ROWS = np.array([37, 2, 19, 2, 40, 0, 23])
+
+
+@pytest.mark.parametrize("kind,lam", [("gauss", 0.02), ("laplace", 0.05), ("energy", 1.0),
+                                      ("imq", 0.3)])
+@pytest.mark.parametrize("d", [1, 3])
+def test_direct_sum_rows_are_the_selected_rows(kind, lam, d):
+    """The sampled-row sum of eq. (fast_sum) is row rows[t] of the full direct sum, and those rows
+    agree with a 40-digit brute force of the definition (an independent pin of the row function)."""
+    rng = np.random.default_rng([11, d])
+    x = rng.uniform(-0.25, 0.25, (41, d))
+    y = rng.uniform(-0.25, 0.25, (29, d))
+    v = rng.uniform(-1, 1, 29)
+    got = oracle.direct_sum_rows(x, _ROWS, y, v, kind, lam)
+    full = oracle.direct_sum(x, y, v, kind, lam)
+    assert np.max(np.abs(got - full[_ROWS])) <= 1e-15 * np.max(np.abs(full))
+    mp.mp.dps = 40
+    for t in (0, 2, 4):
+        i = int(_ROWS[t])
+        acc = mp.mpf(0)
+        for j in range(len(y)):
+            r = mp.sqrt(sum((mp.mpf(float(x[i, k])) - mp.mpf(float(y[j, k]))) ** 2 for k in range(d)))
+            acc += _mp_kernel(kind, lam, r) * mp.mpf(float(v[j]))
+        assert abs(got[t] - float(acc)) <= 1e-13 * max(abs(float(acc)), 1e-300)
+
+
 # --------------------------------------------------------------------------- unbalanced Sinkhorn
 
 def _single_point(r_cost, A, B, eps, eta, sweeps):
@@ -255,6 +283,30 @@ def _gamma_step(x, mu, y, nu, eps, eta, beta, gamma, r):
     # a gamma half-step is a beta half-step of the transposed problem
     g2, b2 = oracle.uot_halfsteps(y, nu, x, mu, eps, eta, 1, gamma, beta, r=r)
     return b2, g2
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_uot_beta_rows_are_rows_of_a_beta_halfstep(r):
+    """The sampled-row beta update (eq. (Sinkhorn_uot_iteration)) is row rows[t] of a full beta
+    half-step taken from the same gamma, which the closed-form and block-maximiser pins above fix."""
+    x, mu, y, nu = _small_problem(n=41, m=29)
+    eps, eta = 0.03, 0.7
+    beta, gamma = oracle.uot_sinkhorn(x, mu, y, nu, eps, eta, 3, r=r)
+    full, _ = oracle.uot_halfsteps(x, mu, y, nu, eps, eta, 1, beta, gamma, r=r)
+    got = oracle.uot_beta_rows(x, _ROWS, y, nu, gamma, eps, eta, r=r)
+    assert np.max(np.abs(got - full[_ROWS])) <= 1e-15 * np.max(np.abs(full))
+
+
+def test_uot_beta_rows_single_point_closed_form():
+    """n = m = 1: beta = kappa (C - gamma - eps log B) exactly, for any gamma."""
+    x = np.array([[0.1, -0.05], [0.2, 0.01]])
+    y = np.array([[-0.07, 0.12]])
+    B, eps, eta, g0 = 1.9, 0.05, 1.0, 0.013
+    kap = eta / (eta + eps)
+    got = oracle.uot_beta_rows(x, np.array([1, 0]), y, [B], [g0], eps, eta, r=2)
+    for t, i in enumerate((1, 0)):
+        C = float(np.sum((x[i] - y[0]) ** 2))
+        assert abs(got[t] - kap * (C - g0 - eps * math.log(B))) < 1e-15
 
 
 def test_uot_weak_and_strong_duality():
@@ -374,6 +426,36 @@ def test_sinkhorn_divergence_mass_term():
     sd, (uxy, uxx, uyy) = oracle.sinkhorn_divergence(x, mu, y, nu, eps, 1.0, 300)
     assert abs(sd - (uxy - 0.5 * uxx - 0.5 * uyy + 0.5 * eps * (mu.sum() - nu.sum()) ** 2)) < 1e-14
     assert sd > 0
+
+
+def _dirac_uot(A, B, eps, eta):
+    """UOT of eq. (W4) between A delta_z and B delta_z (zero cost): the plan is one number p >= 0
+    and the objective eps (p log(p/(AB)) - p + AB) + eta (p log(p/A) - p + A) + eta (p log(p/B)
+    - p + B) is minimised where eps log(p/(AB)) + eta log(p/A) + eta log(p/B) = 0, i.e.
+    p = (AB)^((eps + eta)/(eps + 2 eta))."""
+    p = (A * B) ** ((eps + eta) / (eps + 2 * eta))
+    return (eps * (p * math.log(p / (A * B)) - p + A * B)
+            + eta * (p * math.log(p / A) - p + A) + eta * (p * math.log(p / B) - p + B))
+
+
+@pytest.mark.parametrize("A,B", [(0.7, 1.9), (1.0, 1.0), (2.5, 0.4)])
+def test_sinkhorn_divergence_of_diracs_closed_form(A, B):
+    """eq. (586) for two Diracs at one location: every UOT term has the closed form above, so the
+    divergence, its mass term (1/(2 lambda))(mu(X) - nu(X))^2 included, is fixed without the
+    Sinkhorn iteration or the dual.  Several coincident points of the same total mass give the same
+    value."""
+    eps, eta = 0.5, 1.0
+    z = np.array([[0.03, -0.02]])
+    ref = (_dirac_uot(A, B, eps, eta) - 0.5 * _dirac_uot(A, A, eps, eta)
+           - 0.5 * _dirac_uot(B, B, eps, eta) + 0.5 * eps * (A - B) ** 2)
+    sd, (uxy, uxx, uyy) = oracle.sinkhorn_divergence(z, [A], z, [B], eps, eta, 200)
+    assert abs(uxy - _dirac_uot(A, B, eps, eta)) < 1e-13
+    assert abs(uxx - _dirac_uot(A, A, eps, eta)) < 1e-13
+    assert abs(sd - ref) < 1e-13
+    zs = np.tile(z, (3, 1))
+    sd3, _ = oracle.sinkhorn_divergence(zs, [A / 4, A / 2, A / 4], np.tile(z, (2, 1)),
+                                        [B / 3, 2 * B / 3], eps, eta, 200)
+    assert abs(sd3 - ref) < 1e-13
 
 
 @pytest.mark.parametrize("r", [1, 2])
