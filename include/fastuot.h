@@ -19,11 +19,17 @@
  *    dual potentials float64.  Outputs are preallocated by the caller.  Scalars written to
  *    `*_host` pointers are host memory.
  *  - `stream` is a hipStream_t (may be NULL for the default stream).  Work is enqueued on it;
- *    calls that return a host scalar, and plan creation, synchronise that stream.
+ *    calls that return a host scalar, fastsum_apply and plan creation synchronise that stream;
+ *    fs_plan_apply does not (it is stream-ordered: its temporaries are reused only after the
+ *    stream has passed them).
  *  - The library allocates its own workspace (device memory) and keeps freed blocks in a cache
  *    for reuse until fs_release_cache() or process exit.  Calls are not thread-safe.
  *  - Return value: FS_OK (0) on success, a negative fs_status on failure; fs_last_error() then
  *    describes the failure.  Outputs are unspecified after a failure.
+ *  - Interface choices: the kernel kind and width, which the problem statement passes as a
+ *    separate kernel argument, are fields of fs_params with the grid settings; fs_plan_apply
+ *    takes the stream it enqueues on (a plan may be applied on a stream other than the one it
+ *    was created on).
  *  - Parameters use the temperature convention: the Gibbs kernel of the transport cost |x-y|^r is
  *    exp(-|x-y|^r / lambda), i.e. lambda here is the reciprocal of the paper's lambda (the paper
  *    writes exp(-lambda d^r) with an inverse temperature, eq. (W4)).  rho is the paper's marginal
@@ -109,10 +115,14 @@ void fs_profile_reset(void);
 /* Kernel sum, eq. (fast_sum):  out_i = sum_j K(x_i - y_j) v_j,  i < n, j < m.
  *   x (n x d), y (m x d), v (m), out (n): device, float32.  d in 1..3 for the fast path
  *   (Section "Curse of dimensionality": the method is restricted to d <= 3); any d in 1..128 for
- *   direct summation (grid = 0), where a Gaussian kernel with d a multiple of 16 uses the MFMA
- *   Gram path (BF16 hi/lo split products accumulated in FP32) unless FS_FLAG_FORCE_VALU.  In
- *   3-D the fast path interpolates from the grid with FP32 matrix-core products where the nodes
- *   fill groups of 16 (unless FS_FLAG_FORCE_VALU).
+ *   direct summation (grid = 0), where a Gaussian kernel with d a multiple of 16 forms the
+ *   exponent on the matrix cores (centred coordinates as FP16 hi/lo split products accumulated
+ *   in FP32) when the exponent scale (log2 e / lambda) (R_x + R_y)^2 (R: largest centred norm of
+ *   a set) is at most 64, where that arithmetic stays within 1e-5, and the FP32 VALU kernel
+ *   otherwise or with FS_FLAG_FORCE_VALU.  In 2-D and 3-D the fast path spreads onto and
+ *   interpolates from the grid with FP16 matrix-core products of split operands (hi + lo, about
+ *   22 significant bits, summed in FP32; within 2e-6 of the FP32 VALU kernels) where the nodes
+ *   fill groups of up to 16 per brick of 4 cells (unless FS_FLAG_FORCE_VALU).
  *   n = 0 or m = 0 is valid (out is zero-filled when m = 0). */
 int fastsum_apply(const float *x, int64_t n, const float *y, int64_t m, int d, const float *v,
                   float *out, const fs_params *p, void *stream);
@@ -121,7 +131,10 @@ int fastsum_apply(const float *x, int64_t n, const float *y, int64_t m, int d, c
  * keeps copies; the caller may free x and y afterwards).  fs_plan_apply computes
  *   transpose = 0:  out (n) = K_xy v,  v of length m
  *   transpose = 1:  out (m) = K_yx v,  v of length n
- * with K symmetric (radial), so the transpose is the same operator with the roles swapped. */
+ * with K symmetric (radial), so the transpose is the same operator with the roles swapped.
+ * fs_plan_apply is stream-ordered and returns without waiting; a plan holds scratch buffers, so
+ * applications of one plan must be ordered (one stream, or synchronised between streams).
+ * fs_plan_destroy waits for the device before releasing the plan. */
 int fs_plan_create(const float *x, int64_t n, const float *y, int64_t m, int d,
                    const fs_params *p, void *stream, fs_plan *plan_out);
 int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void *stream);

@@ -204,18 +204,27 @@ int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void 
             return;
         }
         if (op.fast) {
+            // stream-ordered: the temporaries return to the workspace cache once the stream has
+            // passed the work queued here, so the call does not wait for it
             DevBuf<float> wo(ns + 1), to(nt + 1);
             op.to_op(transpose ? 0 : 1, v, wo.p, s);
             op.apply(wo.p, to.p, nullptr, transpose, s);
             op.from_op(transpose ? 1 : 0, to.p, out, s);
-            FS_HIP(hipStreamSynchronize(s));
+            wo.reset_after(s);
+            to.reset_after(s);
         } else {
             op.apply(v, out, nullptr, transpose, s);
         }
     });
 }
 
-void fs_plan_destroy(fs_plan plan) { delete plan; }
+void fs_plan_destroy(fs_plan plan) {
+    if (!plan) return;
+    // applications are stream-ordered and may still be queued: wait before the plan's device
+    // buffers go back to the workspace cache
+    (void)hipDeviceSynchronize();
+    delete plan;
+}
 
 int uot_sinkhorn(const float *x, const float *a, int64_t n, const float *y, const float *b,
                  int64_t m, int d, const fs_params *p, double rho, int iters, double *f, double *g,

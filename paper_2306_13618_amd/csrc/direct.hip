@@ -6,6 +6,8 @@
 // sources (coordinates + weights) in LDS, each pair is evaluated in FP32, and the partial sum of
 // each source tile is promoted to FP64 before it joins the running row sum (so the rounding error
 // grows with the tile length, not with m).
+#include <cfloat>
+
 #include "direct.h"
 
 namespace fs {
@@ -124,6 +126,70 @@ __global__ void __launch_bounds__(DT) k_direct_general(const float *__restrict__
     }
 }
 
+// Log-domain direct sum for the Sinkhorn half-step:
+//   out_i = log sum_j exp(c r_ij^p + u_j)    (FP64 result; r^2 for Gauss, r for Laplace)
+// with u_j the log source weights.  Each row keeps a running maximum M of its exponents and the
+// sum of exp(e - M): a larger exponent rescales the sum once (rare after the first few terms),
+// so the sum never underflows however far the row is from every source, and the result is
+// M + log(sum).  One target per thread; sources staged in LDS tiles; per-tile FP32 partial sums
+// joined in FP64.  D = 0: any d (coordinates read from global memory).
+template <int D, int KIND>
+__global__ void __launch_bounds__(DT) k_direct_lse(const float *__restrict__ x, int64_t n,
+                                                   const float *__restrict__ y, int64_t m, int d,
+                                                   const float *__restrict__ u, float c,
+                                                   double *__restrict__ out) {
+    constexpr int LT = 64;  // sources per tile
+    __shared__ float sy[LT * (D > 0 ? D : 128)];
+    __shared__ float su[LT];
+    const int dd = D > 0 ? D : d;
+    const int64_t i = (int64_t)blockIdx.x * DT + threadIdx.x;
+    const float *xi = x + (i < n ? i : 0) * dd;
+    float xr[D > 0 ? D : 1];
+    if (D > 0) {
+#pragma unroll
+        for (int k = 0; k < (D > 0 ? D : 1); ++k) xr[k] = xi[k];
+    }
+    float M = -FLT_MAX;
+    double S = 0.0;
+    for (int64_t j0 = 0; j0 < m; j0 += LT) {
+        const int cnt = (int)((m - j0) < LT ? (m - j0) : LT);
+        __syncthreads();
+        for (int t = threadIdx.x; t < LT * dd; t += DT) {
+            const int jj = t / dd;
+            sy[t] = (jj < cnt) ? y[(j0 + jj) * dd + (t - jj * dd)] : 0.0f;
+        }
+        for (int t = threadIdx.x; t < LT; t += DT) su[t] = (t < cnt) ? u[j0 + t] : -INFINITY;
+        __syncthreads();
+        float P = 0.0f;
+        for (int t = 0; t < cnt; ++t) {
+            float r2 = 0.0f;
+            if (D > 0) {
+#pragma unroll
+                for (int k = 0; k < (D > 0 ? D : 1); ++k) {
+                    const float df = xr[k] - sy[t * dd + k];
+                    r2 = fmaf(df, df, r2);
+                }
+            } else {
+                for (int k = 0; k < dd; ++k) {
+                    const float df = xi[k] - sy[t * dd + k];
+                    r2 = fmaf(df, df, r2);
+                }
+            }
+            const float e = fmaf(KIND == FS_GAUSS ? r2 : sqrtf(r2), c, su[t]);
+            if (e > M) {
+                const float f = expf(M - e);
+                S *= (double)f;
+                P = fmaf(P, f, 1.0f);
+                M = e;
+            } else {
+                P += expf(e - M);
+            }
+        }
+        S += (double)P;
+    }
+    if (i < n) out[i] = (S > 0.0) ? (double)M + log(S) : -INFINITY;
+}
+
 template <int D>
 void launch_small(int kind, const float *x, int64_t n, const float *y, int64_t m, const float *w,
                   float c, float *out, double *out64, hipStream_t s) {
@@ -182,6 +248,31 @@ void direct_valu(int kind, double lambda, const float *x, int64_t n, const float
             hipLaunchKernelGGL(k_direct_general<FS_ENERGY>, grid, block, 0, s, x, n, y, m, d, w,
                                c, out, out64);
     }
+    FS_LAUNCHED();
+}
+
+void direct_lse(int kind, double lambda, const float *x, int64_t n, const float *y, int64_t m,
+                int d, const float *u, double *out, hipStream_t s) {
+    if (n <= 0) return;
+    FS_REQUIRE(kind == FS_GAUSS || kind == FS_LAPLACE, FS_EINVAL,
+               "log-domain direct sums need the Gauss or Laplace kernel");
+    FS_REQUIRE(d >= 1 && d <= 128, FS_EINVAL, "direct summation supports d <= 128 (got %d)", d);
+    const float c = (float)(-1.0 / lambda);
+    dim3 grid(blocks_for(n, DT, int64_t(1) << 30)), block(DT);
+#define FS_LSE(DD)                                                                             \
+    if (kind == FS_GAUSS)                                                                      \
+        hipLaunchKernelGGL((k_direct_lse<DD, FS_GAUSS>), grid, block, 0, s, x, n, y, m, d, u,  \
+                           c, out);                                                            \
+    else                                                                                       \
+        hipLaunchKernelGGL((k_direct_lse<DD, FS_LAPLACE>), grid, block, 0, s, x, n, y, m, d,   \
+                           u, c, out)
+    switch (d) {
+        case 1: FS_LSE(1); break;
+        case 2: FS_LSE(2); break;
+        case 3: FS_LSE(3); break;
+        default: FS_LSE(0); break;
+    }
+#undef FS_LSE
     FS_LAUNCHED();
 }
 

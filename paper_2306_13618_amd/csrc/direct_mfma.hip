@@ -1,17 +1,27 @@
 // Gaussian kernel sum for high dimension (d a multiple of 16) with the whole exponent on the
-// matrix cores.  With s = sqrt(2 log2(e) / lambda) and a_i = -(log2(e) / lambda) |x_i|^2,
-//   log2 K_ij = -(log2(e) / lambda) |x_i - y_j|^2 = (s x_i).(s y_j) + a_i + b_j,
+// matrix cores.  The kernel depends only on differences, so both point sets are first shifted
+// by a common centre c (the midpoint of their joint bounding box).  With s = sqrt(2 log2(e) /
+// lambda), p' = p - c and a_i = -(log2(e) / lambda) |x'_i|^2,
+//   log2 K_ij = -(log2(e) / lambda) |x_i - y_j|^2 = (s x'_i).(s y'_j) + a_i + b_j,
 // so one Gram tile of augmented vectors gives the exponent directly:
-//   * each scaled coordinate is split into BF16 hi = bf16(v) and lo = bf16(v - hi); the dot
-//     product is hi.hi + hi.lo + lo.hi accumulated in FP32 (the dropped lo.lo term is ~2^-16 of
-//     the product);
-//   * the norm terms ride in one extra K step: a_i is split into three BF16 pieces (24 bits),
+//   * each scaled coordinate is split into FP16 hi = f16(v) and lo = f16(v - hi) (22 significant
+//     bits); the dot product is hi.hi + hi.lo + lo.hi accumulated in FP32 on the FP16 matrix
+//     instructions (the dropped lo.lo term is ~2^-22 of the product);
+//   * the norm terms ride in one extra K step on the BF16 matrix instruction (BF16 keeps the
+//     exponent range of FP32 for large |a|): a_i is split into three BF16 pieces (24 bits),
 //     A_i = [a_h, a_m, a_l, 1, 1, 1] against B_j = [1, 1, 1, b_h, b_m, b_l].
 // Then K_ij = exp2(g_ij), and sum_j K_ij w_j is accumulated per lane in FP32 over two stages of
 // column tiles and in FP64 beyond.
 //
-// Wave tile: 32 target rows x 32 source columns, v_mfma_f32_32x32x16_bf16 (gfx950).
-// Operand layout of that instruction (per lane l of the wave):
+// Accuracy.  Near pairs, which dominate a row sum, get g ~ 0 from terms of size up to
+// Q = (log2(e) / lambda) (R_x + R_y)^2 (R: largest centred norm of a set), so the absolute error
+// of g grows with Q (splits and FP32 accumulation).  An emulation of this arithmetic on uniform,
+// Gaussian, shifted and clustered clouds in d = 16 ... 128 keeps the relative error of the sums
+// at or below 2.5e-6 for Q <= 64; gram_frame measures Q and the Gram path is used only there
+// (the FP32 VALU kernel otherwise).
+//
+// Wave tile: 32 target rows x 32 source columns, v_mfma_f32_32x32x16_f16 / _bf16 (gfx950).
+// Operand layout of those instructions (per lane l of the wave):
 //   A (32 x 16):  row l % 32, k = 8 (l / 32) .. 8 (l / 32) + 7
 //   B (16 x 32):  column l % 32, same k range
 //   D (32 x 32):  register r holds row 8 (r / 4) + 4 (l / 32) + (r % 4), column l % 32
@@ -29,6 +39,7 @@ namespace fs {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
@@ -49,12 +60,16 @@ __device__ __forceinline__ uint16_t f2bf_bits(float v) {
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf_bits2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f2h_bits(float v) {
+    return __builtin_bit_cast(uint16_t, (_Float16)v);  // round to nearest even
+}
+__device__ __forceinline__ float h_bits2f(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
 
 // One thread per (point, half): writes that lane's units of every part.  Points beyond `count`
-// (the tail of the last tile) get all-zero parts.
+// (the tail of the last tile) get all-zero parts.  Coordinates are centred on `center` (d).
 __global__ void k_gram_pack(const float *__restrict__ p, int64_t count, int d, int parts,
-                            float scale, double anorm, int64_t padded,
-                            u16x8 *__restrict__ packed) {
+                            double scale, double anorm, const float *__restrict__ center,
+                            int64_t padded, u16x8 *__restrict__ packed) {
     const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gid >= 2 * padded) return;
     const int64_t i = gid >> 1;
@@ -67,7 +82,7 @@ __global__ void k_gram_pack(const float *__restrict__ p, int64_t count, int d, i
     double a = 0.0;
     if (ok) {
         for (int k = 0; k < d; ++k) {
-            const double v = p[i * d + k];
+            const double v = (double)p[i * d + k] - (double)center[k];
             a = fma(v, v, a);
         }
         a *= -anorm;
@@ -76,10 +91,11 @@ __global__ void k_gram_pack(const float *__restrict__ p, int64_t count, int d, i
         u16x8 hi = {}, lo = {};
         if (ok)
             for (int e = 0; e < 8; ++e) {
-                const float v = scale * p[i * d + 16 * s + 8 * h + e];
-                const uint16_t hb = f2bf_bits(v);
+                const int k = 16 * s + 8 * h + e;
+                const float v = (float)(scale * ((double)p[i * d + k] - (double)center[k]));
+                const uint16_t hb = f2h_bits(v);
                 hi[e] = hb;
-                lo[e] = f2bf_bits(v - bf_bits2f(hb));
+                lo[e] = f2h_bits(v - h_bits2f(hb));
             }
         base[(int64_t)s * 64] = hi;
         base[(int64_t)(ks + s) * 64] = lo;
@@ -99,18 +115,18 @@ __global__ void k_gram_pack(const float *__restrict__ p, int64_t count, int d, i
 }
 
 template <int D>
-__device__ __forceinline__ f32x16 gram_tile(const bf16x8 *ah, const bf16x8 *al, bf16x8 aaug,
+__device__ __forceinline__ f32x16 gram_tile(const f16x8 *ah, const f16x8 *al, bf16x8 aaug,
                                             const u16x8 *sb, int lane) {
     using S = GramShape<D>;
     f32x16 g = {};
     g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aaug, __builtin_bit_cast(bf16x8, sb[2 * S::KS * 64 + lane]), g, 0, 0, 0);
 #pragma unroll
     for (int s = 0; s < S::KS; ++s) {
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, sb[s * 64 + lane]);
-        const bf16x8 bl = __builtin_bit_cast(bf16x8, sb[(S::KS + s) * 64 + lane]);
-        g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], bh, g, 0, 0, 0);
-        g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bl, g, 0, 0, 0);
-        g = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s], bh, g, 0, 0, 0);
+        const f16x8 bh = __builtin_bit_cast(f16x8, sb[s * 64 + lane]);
+        const f16x8 bl = __builtin_bit_cast(f16x8, sb[(S::KS + s) * 64 + lane]);
+        g = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[s], bh, g, 0, 0, 0);
+        g = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[s], bl, g, 0, 0, 0);
+        g = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[s], bh, g, 0, 0, 0);
     }
     return g;
 }
@@ -131,14 +147,15 @@ __global__ void __launch_bounds__(256) k_gram_gauss(
     const int64_t rt = (int64_t)blockIdx.x * 4 + wave;  // row tile of this wave
     const bool rows_ok = rt < ntn;
 
-    bf16x8 ah[S::KS], al[S::KS], aaug;
+    f16x8 ah[S::KS], al[S::KS];
+    bf16x8 aaug;
     {
         const u16x8 *a = A + (rows_ok ? rt : 0) * S::PARTS * 64 + lane;
         const u16x8 z = {};
 #pragma unroll
         for (int s = 0; s < S::KS; ++s) {
-            ah[s] = __builtin_bit_cast(bf16x8, rows_ok ? a[s * 64] : z);
-            al[s] = __builtin_bit_cast(bf16x8, rows_ok ? a[(S::KS + s) * 64] : z);
+            ah[s] = __builtin_bit_cast(f16x8, rows_ok ? a[s * 64] : z);
+            al[s] = __builtin_bit_cast(f16x8, rows_ok ? a[(S::KS + s) * 64] : z);
         }
         aaug = __builtin_bit_cast(bf16x8, rows_ok ? a[2 * S::KS * 64] : z);
     }
@@ -244,12 +261,116 @@ __global__ void k_gram_combine(const double *__restrict__ partial, int64_t n, in
     if (out64) out64[i] = v;
 }
 
+// Per-workgroup minimum and maximum of every coordinate (d divides 256): thread t of a workgroup
+// always reads coordinate t % d of the row-major array, so the loads are contiguous.
+__global__ void __launch_bounds__(256) k_coord_minmax(const float *__restrict__ p, int64_t count,
+                                                      int d, float *__restrict__ part) {
+    __shared__ float lo_s[256], hi_s[256];
+    const int tid = threadIdx.x;
+    float lo = INFINITY, hi = -INFINITY;
+    const int64_t total = count * d;
+    for (int64_t f = (int64_t)blockIdx.x * 256 + tid; f < total; f += (int64_t)gridDim.x * 256) {
+        const float v = p[f];
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+    }
+    lo_s[tid] = lo;
+    hi_s[tid] = hi;
+    __syncthreads();
+    if (tid < d) {
+        for (int t = tid + d; t < 256; t += d) {
+            lo = fminf(lo, lo_s[t]);
+            hi = fmaxf(hi, hi_s[t]);
+        }
+        part[(int64_t)blockIdx.x * 2 * d + tid] = lo;
+        part[(int64_t)blockIdx.x * 2 * d + d + tid] = hi;
+    }
+}
+
+// Per-workgroup maximum of |p_i - c|^2 (FP64 sums, rounded up to float).
+__global__ void __launch_bounds__(256) k_centered_norm2_max(const float *__restrict__ p,
+                                                            int64_t count, int d,
+                                                            const float *__restrict__ center,
+                                                            float *__restrict__ part) {
+    __shared__ float m_s[256];
+    const int tid = threadIdx.x;
+    double mx = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < count; i += (int64_t)gridDim.x * 256) {
+        double a = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double v = (double)p[i * d + k] - (double)center[k];
+            a = fma(v, v, a);
+        }
+        mx = fmax(mx, a);
+    }
+    m_s[tid] = (float)(mx * (1.0 + 1e-6));
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) m_s[tid] = fmaxf(m_s[tid], m_s[tid + w]);
+        __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = m_s[0];
+}
+
+constexpr int FRAME_BLOCKS = 256;
+
 }  // namespace
 
 bool mfma_supported(int kind, int d) { return kind == FS_GAUSS && (d == 16 || d == 32 || d == 64 || d == 128); }
 
-void gram_prepare(const float *pts, int64_t count, int d, double lambda, GramOperand &op,
-                  hipStream_t s) {
+double gram_frame(const float *x, int64_t n, const float *y, int64_t m, bool same, int d,
+                  double lambda, DevBuf<float> &center, hipStream_t s) {
+    FS_REQUIRE(mfma_supported(FS_GAUSS, d), FS_EINVAL, "MFMA path needs d in {16,32,64,128}");
+    const int nsets = same ? 1 : 2;
+    const float *pts[2] = {x, y};
+    const int64_t cnt[2] = {n, m};
+    DevBuf<float> part((size_t)nsets * FRAME_BLOCKS * 2 * d);
+    HostStage hs(s);
+    std::vector<const float *> got(nsets);
+    std::vector<int> nb(nsets);
+    for (int k = 0; k < nsets; ++k) {
+        nb[k] = (int)blocks_for(cnt[k] * d, 256, FRAME_BLOCKS);
+        if (cnt[k] > 0) {
+            hipLaunchKernelGGL(k_coord_minmax, dim3(nb[k]), dim3(256), 0, s, pts[k], cnt[k], d,
+                               part.p + (size_t)k * FRAME_BLOCKS * 2 * d);
+            FS_LAUNCHED();
+        }
+        got[k] = hs.download(part.p + (size_t)k * FRAME_BLOCKS * 2 * d, (size_t)nb[k] * 2 * d);
+    }
+    FS_HIP(hipStreamSynchronize(s));
+    std::vector<float> c(d);
+    for (int j = 0; j < d; ++j) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int k = 0; k < nsets; ++k)
+            for (int b = 0; cnt[k] > 0 && b < nb[k]; ++b) {
+                lo = std::min(lo, (double)got[k][(size_t)b * 2 * d + j]);
+                hi = std::max(hi, (double)got[k][(size_t)b * 2 * d + d + j]);
+            }
+        c[j] = std::isfinite(lo) && std::isfinite(hi) ? (float)(0.5 * (lo + hi)) : 0.0f;
+    }
+    center.alloc(d);
+    hs.upload(center.p, c.data(), d * sizeof(float));
+    for (int k = 0; k < nsets; ++k) {
+        nb[k] = (int)blocks_for(cnt[k], 256, FRAME_BLOCKS);
+        if (cnt[k] > 0) {
+            hipLaunchKernelGGL(k_centered_norm2_max, dim3(nb[k]), dim3(256), 0, s, pts[k], cnt[k],
+                               d, center.p, part.p + (size_t)k * FRAME_BLOCKS);
+            FS_LAUNCHED();
+        }
+        got[k] = hs.download(part.p + (size_t)k * FRAME_BLOCKS, (size_t)nb[k]);
+    }
+    FS_HIP(hipStreamSynchronize(s));
+    double r[2] = {0.0, 0.0};
+    for (int k = 0; k < nsets; ++k)
+        for (int b = 0; cnt[k] > 0 && b < nb[k]; ++b) r[k] = std::max(r[k], (double)got[k][b]);
+    if (same) r[1] = r[0];
+    const double l2e = 1.4426950408889634;
+    const double rs = std::sqrt(r[0]) + std::sqrt(r[1]);
+    return l2e / lambda * rs * rs;
+}
+
+void gram_prepare(const float *pts, int64_t count, int d, double lambda, const float *center,
+                  GramOperand &op, hipStream_t s) {
     FS_REQUIRE(mfma_supported(FS_GAUSS, d), FS_EINVAL, "MFMA path needs d in {16,32,64,128}");
     op.count = count;
     op.d = d;
@@ -258,10 +379,10 @@ void gram_prepare(const float *pts, int64_t count, int d, double lambda, GramOpe
     op.packed.alloc((size_t)(std::max<int64_t>(tiles, 1) * op.parts * 64 * 8));
     if (count == 0) return;
     const double l2e = 1.4426950408889634;
-    const float scale = (float)std::sqrt(2.0 * l2e / lambda);
+    const double scale = std::sqrt(2.0 * l2e / lambda);
     const double anorm = l2e / lambda;
     hipLaunchKernelGGL(k_gram_pack, dim3(blocks_for(2 * tiles * 32, 256, int64_t(1) << 30)),
-                       dim3(256), 0, s, pts, count, d, op.parts, scale, anorm, tiles * 32,
+                       dim3(256), 0, s, pts, count, d, op.parts, scale, anorm, center, tiles * 32,
                        reinterpret_cast<u16x8 *>(op.packed.p));
     FS_LAUNCHED();
 }
@@ -302,6 +423,9 @@ void direct_mfma_gauss(const GramOperand &x, const GramOperand &y, const float *
                            dim3(256), 0, s, partial.p, x.count, (int)splits, out, out64);
         FS_LAUNCHED();
     }
+    // the two kernels above are still queued: the partial sums go back to the workspace cache
+    // only once the stream has passed them
+    partial.reset_after(s);
 }
 
 }  // namespace fs

@@ -43,8 +43,12 @@ void clear_error();
 // ------------------------------------------------------------------ workspace
 // Device allocations come from a per-process cache of freed blocks (exact-size reuse), so that
 // repeated solves do not pay for hipMalloc/hipFree.
+// ws_free_after returns a block whose last use is queued on stream s: it is handed out again only
+// after the work queued on s so far has finished (an event recorded there), so a caller may
+// return without waiting for the stream.
 void *ws_alloc(size_t bytes);
 void ws_free(void *p);
+void ws_free_after(void *p, hipStream_t s);
 void ws_release_all();
 
 template <class T>
@@ -71,6 +75,12 @@ struct DevBuf {
     }
     void reset() {
         if (p) ws_free(p);
+        p = nullptr;
+        n = 0;
+    }
+    // release a block whose last use is queued on s (reused only after that work has finished)
+    void reset_after(hipStream_t s) {
+        if (p) ws_free_after(p, s);
         p = nullptr;
         n = 0;
     }

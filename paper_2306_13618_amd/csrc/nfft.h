@@ -80,8 +80,6 @@ struct Plan {
     DevBuf<float2> twiddle;  // exp(-2 pi i q / G), q < G/2
     DevBuf<float> wpoly;     // window segments as polynomials: value (W x WPOLY) then derivative
     DevBuf<float> scratch;   // per-chunk spread boxes
-    DevBuf<float> wbuf;      // sorted weights
-    DevBuf<float> tbuf;      // sorted sums
     DevBuf<float4> nf_src;   // near-field source records (cell order) for the current weights
     const Nodes &src(int transpose) const { return transpose ? X : (same ? X : Y); }
     const Nodes &dst(int transpose) const { return transpose ? (same ? X : Y) : X; }

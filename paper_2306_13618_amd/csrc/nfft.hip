@@ -730,7 +730,8 @@ __device__ __forceinline__ void tile_coords(int tile, int ntd, int *t) {
 // sum_j |alpha_j| * max(phi)^d <= count * max|alpha| (phi <= 1), so with
 // scale = 2^30 / (count * max|alpha|) all int32 partial sums stay below 2^30 in magnitude.
 // LDS integer atomics are the fast path on gfx950 (LDS float atomics are far slower), and integer
-// addition makes the accumulation order-independent (bitwise reproducible).
+// addition is associative, so the box additions themselves do not depend on the order in which
+// the lanes' atomics land (the values added still depend on the node order within a cell).
 template <class WF>
 __device__ float chunk_scale_fn(WF wf, int k0, int cnt, float *red, float *wmax = nullptr) {
     float mx = 0.0f;
@@ -3132,8 +3133,6 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
         const int nch = std::max({pl.X.nchunks, pl.same ? 0 : pl.Y.nchunks, pl.X.n_mblocks,
                                   pl.same ? 0 : pl.Y.n_mblocks});
         pl.scratch.alloc((int64_t)std::max(nch, 1) * box);
-        pl.wbuf.alloc(std::max(n, m) + 1);
-        pl.tbuf.alloc(std::max(n, m) + 1);
     }
     // the stage's destructor synchronises the stream: the plan is complete on return
 }

@@ -22,15 +22,39 @@ const char *last_error() { return g_err; }
 
 // ------------------------------------------------------------------ workspace cache
 namespace {
+struct Pending {
+    hipEvent_t done;  // recorded on the stream of the block's last use
+    void *p;
+    size_t sz;
+};
 struct Cache {
     std::mutex mu;
     std::map<void *, size_t> live;              // pointer -> size
     std::multimap<size_t, void *> free_blocks;  // size -> pointer
+    std::vector<Pending> pending;               // freed, but queued work may still use them
+    std::vector<hipEvent_t> events;             // idle events for `pending`
     size_t free_bytes = 0;
 };
 Cache &cache() {
     static Cache *c = new Cache();  // never destroyed: blocks live until process exit
     return *c;
+}
+// Move the pending blocks whose last use has finished to the free list (lock held).
+void reclaim_pending(Cache &c) {
+    size_t k = 0;
+    for (size_t i = 0; i < c.pending.size(); ++i) {
+        Pending &q = c.pending[i];
+        const hipError_t e = hipEventQuery(q.done);
+        if (e == hipErrorNotReady) {
+            (void)hipGetLastError();
+            c.pending[k++] = q;
+            continue;
+        }
+        c.free_blocks.emplace(q.sz, q.p);
+        c.free_bytes += q.sz;
+        c.events.push_back(q.done);
+    }
+    c.pending.resize(k);
 }
 }  // namespace
 
@@ -40,6 +64,7 @@ void *ws_alloc(size_t bytes) {
     Cache &c = cache();
     {
         std::lock_guard<std::mutex> lk(c.mu);
+        if (!c.pending.empty()) reclaim_pending(c);
         auto it = c.free_blocks.find(sz);
         if (it != c.free_blocks.end()) {
             void *p = it->second;
@@ -78,11 +103,41 @@ void ws_free(void *p) {
     c.live.erase(it);
 }
 
+void ws_free_after(void *p, hipStream_t s) {
+    if (!p) return;
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    hipEvent_t ev = nullptr;
+    if (!c.events.empty()) {
+        ev = c.events.back();
+        c.events.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        ev = nullptr;
+    }
+    if (!ev || hipEventRecord(ev, s) != hipSuccess) {
+        // no event to order the reuse after the stream: wait for the stream instead
+        (void)hipGetLastError();
+        if (ev) c.events.push_back(ev);
+        (void)hipStreamSynchronize(s);
+        c.free_blocks.emplace(it->second, p);
+        c.free_bytes += it->second;
+        c.live.erase(it);
+        return;
+    }
+    c.pending.push_back(Pending{ev, p, it->second});
+    c.live.erase(it);
+}
+
 void ws_release_all() {
     Cache &c = cache();
     std::lock_guard<std::mutex> lk(c.mu);
-    // the caller guarantees no queued work still uses cached blocks (they were freed by it)
+    // the caller guarantees no queued work still uses cached blocks (they were freed by it);
+    // blocks freed behind an event are complete after the device synchronisation
     (void)hipDeviceSynchronize();
+    reclaim_pending(c);
     for (auto &kv : c.free_blocks) (void)hipFree(kv.second);
     c.free_blocks.clear();
     c.free_bytes = 0;

@@ -21,6 +21,7 @@ struct Op {
     bool same = false;
     std::unique_ptr<Plan> plan;
     GramOperand gx, gy;
+    DevBuf<float> gcenter;  // common centre of the Gram path's point sets (d)
     DevBuf<float> xcopy, ycopy;  // direct path keeps copies only when asked to
 
     int64_t count(int side) const { return side == 0 ? n : m; }  // 0: X, 1: Y
@@ -41,6 +42,11 @@ struct Op {
     bool fuses_weights(int transpose) const;
     void apply_pot(const float *base, const double *pot, const double *parts, int nparts,
                    double eps, float *w, float *t, int transpose, hipStream_t s);
+    // Direct Gauss/Laplace sums on the VALU: the Sinkhorn half-step's sums are taken in the log
+    // domain (per-row running maximum), logt (FP64) = log of the same sums as apply_pot's t.
+    bool log_direct() const;
+    void apply_pot_log(const float *base, const double *pot, const double *parts, int nparts,
+                       double eps, float *u, double *logt, int transpose, hipStream_t s);
     // The same, with the potential update applied to the sums inside the gather (no t): only
     // where fuses_update; update_parts maxima are then written.
     bool fuses_update(int transpose) const;

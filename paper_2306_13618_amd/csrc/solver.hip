@@ -60,6 +60,24 @@ __global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
         w[i] = weight_exp(base[i], (pot[i] - pm) * inv_eps);
 }
 
+// u_k = log base_k + (pot_k - pmax) / eps in FP64, rounded to FP32 (-inf for a zero weight).
+__global__ void __launch_bounds__(256) k_log_weights(const float *__restrict__ base,
+                                                     const double *__restrict__ pot,
+                                                     const double *__restrict__ parts, int nparts,
+                                                     double inv_eps, int64_t n,
+                                                     float *__restrict__ u) {
+    __shared__ double red[4];
+    double mx = -INFINITY;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) mx = fmax(mx, parts[b]);
+    mx = block_max(mx, red);
+    const double pm = (mx == -INFINITY) ? 0.0 : mx;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float b = base[i];
+        u[i] = b > 0.0f ? (float)(log((double)b) + (pot[i] - pm) * inv_eps) : -INFINITY;
+    }
+}
+
 // pot_i = -kappa (shift + eps log t_i) in FP64, shift = max of the other potential (the max of
 // nshift per-block maxima); writes one block maximum of the new potential per block.  Non-positive
 // sums are counted in *nbad and replaced by the smallest normal float.
@@ -102,6 +120,44 @@ __global__ void __launch_bounds__(RT) k_update(const float *__restrict__ t, int6
                 mx = fmax(mx, f);
             }
         }
+    }
+    if (bad) atomicAdd(nbad, bad);
+    mx = block_max(mx, red);
+    if (threadIdx.x == 0) out_parts[blockIdx.x] = mx;
+    if (DELTA) {
+        dmx = block_max(dmx, red);
+        if (threadIdx.x == 0) delta_parts[blockIdx.x] = dmx;
+    }
+}
+
+// The same update from log t_i given in FP64 (the log-domain direct sums); a row with no
+// positive term (log t = -inf) is counted in *nbad and treated like the smallest normal float.
+template <bool DELTA>
+__global__ void __launch_bounds__(RT) k_update_log(const double *__restrict__ logt, int64_t n,
+                                                   const double *__restrict__ shift_parts,
+                                                   int nshift, double kappa, double eps,
+                                                   double *__restrict__ pot,
+                                                   double *__restrict__ out_parts,
+                                                   int *__restrict__ nbad,
+                                                   double *__restrict__ delta_parts) {
+    __shared__ double red[RT / 64];
+    double sh = -INFINITY;
+    for (int b = threadIdx.x; b < nshift; b += RT) sh = fmax(sh, shift_parts[b]);
+    sh = block_max(sh, red);
+    if (sh == -INFINITY) sh = 0.0;
+    double mx = -INFINITY, dmx = 0.0;
+    int bad = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double l = logt[i];
+        if (!(l > -INFINITY) || l != l) {
+            bad++;
+            l = log((double)FLT_MIN);
+        }
+        const double f = -kappa * (sh + eps * l);
+        if (DELTA) dmx = fmax(dmx, fabs(f - pot[i]));
+        pot[i] = f;
+        mx = fmax(mx, f);
     }
     if (bad) atomicAdd(nbad, bad);
     mx = block_max(mx, red);
@@ -415,9 +471,12 @@ std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m
     } else {
         FS_REQUIRE(d >= 1 && d <= 128, FS_EINVAL, "direct summation supports d in 1..128 (got %d)", d);
         op->mfma = mfma_supported(p.kernel, d) && !(p.flags & FS_FLAG_FORCE_VALU);
+        // the Gram path's error grows with the exponent scale: use it only where it meets 1e-5
+        if (op->mfma)
+            op->mfma = gram_frame(x, n, y, m, op->same, d, p.lambda, op->gcenter, s) <= GRAM_Q_MAX;
         if (op->mfma) {
-            gram_prepare(x, n, d, p.lambda, op->gx, s);
-            if (!op->same) gram_prepare(y, m, d, p.lambda, op->gy, s);
+            gram_prepare(x, n, d, p.lambda, op->gcenter.p, op->gx, s);
+            if (!op->same) gram_prepare(y, m, d, p.lambda, op->gcenter.p, op->gy, s);
         }
     }
     return op;
@@ -456,7 +515,26 @@ const float *Op::coords(int side) const {
 namespace {
 void launch_weights(const float *base, const double *pot, const double *parts, int nparts,
                     double eps, int64_t n, float *w, hipStream_t s);
+void launch_log_weights(const float *base, const double *pot, const double *parts, int nparts,
+                        double eps, int64_t n, float *u, hipStream_t s);
 }  // namespace
+
+bool Op::log_direct() const {
+    return !fast && !mfma && (kind == FS_GAUSS || kind == FS_LAPLACE);
+}
+
+void Op::apply_pot_log(const float *base, const double *pot, const double *parts, int nparts,
+                       double eps, float *u, double *logt, int transpose, hipStream_t s) {
+    const int64_t nt = transpose ? m : n, ns = transpose ? n : m;
+    if (nt == 0) return;
+    if (ns == 0) {
+        fill_f64(logt, nt, -INFINITY, s);
+        return;
+    }
+    ProfScope ps("direct", s);
+    launch_log_weights(base, pot, parts, nparts, eps, ns, u, s);
+    direct_lse(kind, lambda, transpose ? y : x, nt, transpose ? x : y, ns, d, u, logt, s);
+}
 
 bool Op::fuses_weights(int transpose) const {
     return fast && count(transpose ? 0 : 1) > 0 && count(transpose ? 1 : 0) > 0 &&
@@ -582,6 +660,29 @@ int launch_update(const float *t, int64_t n, const double *shift_parts, int nshi
     return nb;
 }
 
+int launch_update_log(const double *logt, int64_t n, const double *shift_parts, int nshift,
+                      double kappa, double eps, double *pot, double *out_parts, int *nbad,
+                      double *delta_parts, hipStream_t s) {
+    ProfScope ps("update", s);
+    const int nb = upd_blocks(n);
+    if (delta_parts)
+        hipLaunchKernelGGL(k_update_log<true>, dim3(nb), dim3(RT), 0, s, logt, n, shift_parts,
+                           nshift, kappa, eps, pot, out_parts, nbad, delta_parts);
+    else
+        hipLaunchKernelGGL(k_update_log<false>, dim3(nb), dim3(RT), 0, s, logt, n, shift_parts,
+                           nshift, kappa, eps, pot, out_parts, nbad, delta_parts);
+    FS_LAUNCHED();
+    return nb;
+}
+
+void launch_log_weights(const float *base, const double *pot, const double *parts, int nparts,
+                        double eps, int64_t n, float *u, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_log_weights, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, s, base, pot,
+                       parts, nparts, 1.0 / eps, n, u);
+    FS_LAUNCHED();
+}
+
 void launch_weights(const float *base, const double *pot, const double *parts, int nparts,
                     double eps, int64_t n, float *w, hipStream_t s) {
     if (n == 0) return;
@@ -622,6 +723,9 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     Scalars sc;
     sc.reset(s);
     DevBuf<float> wX(n + 1), wY(m + 1), tX(n + 1), tY(m + 1);
+    // log-domain direct sums (no underflow for rows far from every source) where they apply
+    const bool logd = op.log_direct();
+    DevBuf<double> lX(logd ? n + 1 : 0), lY(logd ? m + 1 : 0);
     if (warm) {
         if (m > 0) sc.ng = launch_max_parts(g_o, m, sc.gparts.p, s);
         if (n > 0) sc.nf = launch_max_parts(f_o, n, sc.fparts.p, s);
@@ -647,6 +751,11 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             pu.nbad = sc.nbad.p;
             op.apply_pot_update(b_o, g_o, sc.gparts.p, sc.ng, eps, pu, 0, s);
             sc.nf = op.update_parts(0);
+        } else if (logd) {
+            op.apply_pot_log(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, lX.p, 0, s);
+            if (n > 0)
+                sc.nf = launch_update_log(lX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o,
+                                          sc.fparts.p, sc.nbad.p, fd, s);
         } else {
             op.apply_pot(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, tX.p, 0, s);
             if (n > 0)
@@ -666,6 +775,11 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             pu.nbad = sc.nbad.p;
             op.apply_pot_update(a_o, f_o, sc.fparts.p, sc.nf, eps, pu, 1, s);
             sc.ng = op.update_parts(1);
+        } else if (logd) {
+            op.apply_pot_log(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, lY.p, 1, s);
+            if (m > 0)
+                sc.ng = launch_update_log(lY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o,
+                                          sc.gparts.p, sc.nbad.p, gd, s);
         } else {
             op.apply_pot(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, tY.p, 1, s);
             if (m > 0)

@@ -409,6 +409,109 @@ def test_mfma_gram_gauss_other_dims(d, n, m, lam):
                   oracle.direct_sum(y, x, u, "gauss", lam)) < TOL
 
 
+@pytest.mark.parametrize("lam", [0.1, 0.05, 0.02])
+def test_direct_d32_small_lambda(lam):
+    """Narrow Gaussians at d = 32: the matrix-core exponent's error grows with
+    (R_x + R_y)^2 / lambda, so the library takes the FP32 VALU kernel where that arithmetic would
+    miss 1e-5.  Kernel sums and a short Sinkhorn solve (eps = lambda) against the oracle."""
+    w = synth.make("gauss_d32_n200k", n=1500, m=1300)
+    v = w["b"] / w["b"].max()
+    got = fu.fastsum_apply(T(w["x"]), T(w["y"]), T(v), kernel="gauss", lam=lam,
+                           grid=0).cpu().numpy()
+    ref = oracle.direct_sum(w["x"], w["y"], v, "gauss", lam)
+    assert relinf(got, ref) < TOL
+    f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), lam, w["rho"], 5,
+                                kernel="gauss", grid=0)
+    beta, gamma = oracle.uot_sinkhorn(w["x"], w["a"], w["y"], w["b"], lam, w["rho"], 5)
+    assert relinf(f.cpu().numpy(), beta) < TOL
+    assert relinf(g.cpu().numpy(), gamma) < TOL
+
+
+@pytest.mark.parametrize("d,kind", [(2, "gauss"), (3, "laplace"), (20, "gauss")])
+def test_uot_direct_rows_far_from_every_source(d, kind):
+    """Direct Sinkhorn at a temperature where every kernel value of some rows underflows FP32
+    (two clusters 0.6 apart, eps = 0.002 for the Gaussian): the log-domain direct sums keep those
+    rows, and the potentials match the oracle's log-sum-exp iteration."""
+    rng = np.random.default_rng([17, d])
+    n, m = 700, 600
+    x = rng.normal(0, 0.02, (n, d))
+    x[: n // 5] += 0.6 / np.sqrt(d)
+    y = rng.normal(0, 0.02, (m, d))
+    x, y = x.astype(np.float32), y.astype(np.float32)
+    a = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    b = rng.uniform(0.5, 1.5, m).astype(np.float32)
+    a, b = (a / a.sum()).astype(np.float32), (1.2 * b / b.sum()).astype(np.float32)
+    eps, rho, r = (0.002, 1.0, 2) if kind == "gauss" else (0.004, 1.0, 1)
+    f, g, obj = fu.uot_sinkhorn(T(x), T(a), T(y), T(b), eps, rho, 8, kernel=kind, grid=0)
+    beta, gamma = oracle.uot_sinkhorn(x, a, y, b, eps, rho, 8, r=r)
+    assert relinf(f.cpu().numpy(), beta) < TOL
+    assert relinf(g.cpu().numpy(), gamma) < TOL
+    D = oracle.uot_dual(x, a, y, b, eps, rho, beta, gamma, r=r)
+    assert abs(obj - D) <= TOL * abs(D)
+
+
+def _structured_d32(kind, n, m, seed):
+    rng = np.random.default_rng([91, n, m, seed])
+    d = 32
+    if kind == "clustered":
+        c = rng.normal(size=(8, d)) / np.sqrt(d)
+        x = c[rng.integers(0, 8, n)] + 0.05 * rng.normal(size=(n, d)) / np.sqrt(d)
+        y = c[rng.integers(0, 8, m)] + 0.05 * rng.normal(size=(m, d)) / np.sqrt(d)
+    else:  # far from the origin: the common centre removes the offset
+        x = 0.3 * rng.normal(size=(n, d)) / np.sqrt(d) + 3.0
+        y = 0.3 * rng.normal(size=(m, d)) / np.sqrt(d) + 3.0
+    return (x.astype(np.float32), y.astype(np.float32),
+            rng.uniform(0.5, 1.5, m).astype(np.float32))
+
+
+@pytest.mark.parametrize("kind,lam", [("clustered", 0.5), ("clustered", 0.25),
+                                      ("shifted", 0.2), ("shifted", 0.05)])
+def test_mfma_gram_structured_clouds(kind, lam):
+    """Clustered clouds (near pairs whose exponent cancels large norm terms) and clouds far from
+    the origin, at widths where the matrix-core path is taken: within 1e-5 of the oracle, and the
+    matrix cores ran (the result differs in rounding from the VALU kernel's)."""
+    x, y, v = _structured_d32(kind, 1700, 1400, int(100 * lam))
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=lam, grid=0).cpu().numpy()
+    valu = fu.fastsum_apply(T(x), T(y), T(v), kernel="gauss", lam=lam, grid=0,
+                            flags=fu.FLAG_FORCE_VALU).cpu().numpy()
+    ref = oracle.direct_sum(x, y, v, "gauss", lam)
+    assert relinf(got, ref) < TOL
+    assert relinf(valu, ref) < TOL
+    assert np.any(got != valu)
+
+
+def test_plan_apply_on_two_streams():
+    """fs_plan_apply is stream-ordered and returns without waiting: two plans (a d = 32
+    matrix-core direct plan and a 3-D NFFT plan) applied alternately on two streams, with new
+    inputs each time and no synchronisation in between; every result against the oracle."""
+    w32 = synth.make("gauss_d32_n200k", n=1500, m=1300)
+    x3, y3, _ = clouds(3, 6000, 5000, 9)
+    p32 = fu.Plan(T(w32["x"]), T(w32["y"]), kernel="gauss", lam=1.0, grid=0)
+    p3 = fu.Plan(T(x3), T(y3), kernel="gauss", lam=0.02, grid=64, window=6)
+    rng = np.random.default_rng(123)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ins, outs = [], []
+    for it in range(4):
+        v32 = rng.uniform(0.5, 1.5, len(w32["y"])).astype(np.float32)
+        v3 = rng.uniform(0.5, 1.5, len(y3)).astype(np.float32)
+        t32, t3 = T(v32), T(v3)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s1):
+            o32 = p32.apply(t32)
+        with torch.cuda.stream(s2):
+            o3 = p3.apply(t3)
+        ins.append((v32, v3, t32, t3))
+        outs.append((o32, o3))
+    torch.cuda.synchronize()
+    rows = synth.sample_rows(len(x3), 150, seed=3)
+    for (v32, v3, _, _), (o32, o3) in zip(ins, outs):
+        assert relinf(o32.cpu().numpy(), oracle.direct_sum(w32["x"], w32["y"], v32, "gauss", 1.0)) < TOL
+        assert relinf(o3.cpu().numpy()[rows],
+                      oracle.direct_sum_rows(x3, rows, y3, v3, "gauss", 0.02)) < TOL
+    p32.close()
+    p3.close()
+
+
 def test_uot_mfma_d32():
     """The d = 32 Sinkhorn on the MFMA path (Gibbs kernel exp(-|x-y|^2/eps)) against the oracle."""
     w = synth.make("gauss_d32_n200k", n=1500, m=1300)
