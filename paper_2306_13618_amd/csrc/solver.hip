@@ -168,6 +168,153 @@ __global__ void __launch_bounds__(RT) k_update_log(const double *__restrict__ lo
     }
 }
 
+// ------------------------------------------------------------------ floor rows
+// The fast sum's absolute error is a small fraction (about 2e-7 measured) of the largest sum of a
+// launch, so a row whose sum is far below the largest (a target far from every weighted source)
+// carries that floor as a large relative error.  With rho >> eps the plan keeps such a row's mass,
+// so its potential and its envelope gradient would inherit the error.  Rows whose sum is below
+// FLOOR_REL of the largest are therefore re-evaluated directly, in the log domain, against every
+// source (a wave per row): the Sinkhorn update from L_i = log sum_j b_j e^{(g_j - gmax - C_ij)/eps}
+// and the gradient from the same softmax weights.
+constexpr float FLOOR_REL = 1e-2f;
+
+// Source side of a direct re-evaluation, in operator order: coordinates, base weights and the
+// potential that forms the weights base_j e^{(pot_j - shift)/eps}.
+struct FloorSrc {
+    const float *xt;    // target coordinates (n x d)
+    const float *ys;    // source coordinates (m x d)
+    const float *base;  // source base weights (m)
+    const double *pot;  // source potential (m)
+    int64_t m;
+    int d, r;           // dimension, cost exponent (C = |x - y|^r)
+    double inv_eps;
+};
+
+// Per-block maxima of a float array (UPD_BLOCKS-sized launch).
+__global__ void __launch_bounds__(RT) k_max_f32(const float *__restrict__ t, int64_t n,
+                                                double *__restrict__ parts) {
+    __shared__ double red[RT / 64];
+    double mx = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        mx = fmax(mx, (double)t[i]);
+    mx = block_max(mx, red);
+    if (threadIdx.x == 0) parts[blockIdx.x] = mx;
+}
+
+// The whole wave evaluates target `row`: returns (on every lane) L = log sum_j e^{e_j} with
+// e_j = log base_j + (pot_j - shift) inv_eps - C_ij inv_eps, and, when G is non-null, the softmax
+// mean of grad_x C_ij (d <= 3) in G.
+__device__ void floor_row_lse(const FloorSrc &src, int64_t row, double shift, int lane, double &L,
+                              double *G) {
+    float xi[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < src.d; ++k) xi[k] = src.xt[row * src.d + k];
+    float M = -FLT_MAX;
+    double S = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = lane; j < src.m; j += 64) {
+        float df[3] = {0.0f, 0.0f, 0.0f};
+        float r2 = 0.0f;
+        for (int k = 0; k < src.d; ++k) {
+            df[k] = xi[k] - src.ys[j * src.d + k];
+            r2 = fmaf(df[k], df[k], r2);
+        }
+        const float rr = sqrtf(r2);
+        const double c = src.r == 2 ? (double)r2 : (double)rr;
+        const float b = src.base[j];
+        const float e = b > 0.0f ? (float)(log((double)b) + (src.pot[j] - shift - c) * src.inv_eps)
+                                 : -INFINITY;
+        float wgt;
+        if (e > M) {
+            const double sc = exp((double)M - (double)e);
+            S *= sc;
+            for (int k = 0; k < 3; ++k) g[k] *= sc;
+            M = e;
+            wgt = 1.0f;
+        } else {
+            wgt = expf(e - M);
+        }
+        S += wgt;
+        if (G) {
+            // grad_x C: r = 2: 2 (x - y); r = 1: (x - y) / |x - y| (0 at coincident points)
+            const float gs = src.r == 2 ? 2.0f : (rr > 0.0f ? 1.0f / rr : 0.0f);
+            for (int k = 0; k < src.d; ++k) g[k] += (double)wgt * (double)(gs * df[k]);
+        }
+    }
+    float Mw = M;
+    for (int o = 32; o > 0; o >>= 1) Mw = fmaxf(Mw, __shfl_xor(Mw, o, 64));
+    const double sc = (M == -FLT_MAX) ? 0.0 : exp((double)M - (double)Mw);
+    S *= sc;
+    for (int k = 0; k < 3; ++k) g[k] *= sc;
+    for (int o = 32; o > 0; o >>= 1) {
+        S += __shfl_xor(S, o, 64);
+        for (int k = 0; k < 3; ++k) g[k] += __shfl_xor(g[k], o, 64);
+    }
+    L = (S > 0.0) ? (double)Mw + log(S) : -INFINITY;
+    if (G)
+        for (int k = 0; k < 3; ++k) G[k] = (S > 0.0) ? g[k] / S : 0.0;
+}
+
+// The update of k_update, with the rows below FLOOR_REL of the largest sum (and non-positive
+// sums) re-evaluated directly.  Rows go in wave-aligned runs of 64 (one per lane); the flagged
+// rows of a run are then taken one after the other by the whole wave.
+template <bool DELTA>
+__global__ void __launch_bounds__(RT) k_update_floor(const float *__restrict__ t, int64_t n,
+                                                     const double *__restrict__ shift_parts,
+                                                     int nshift,
+                                                     const double *__restrict__ tmax_parts,
+                                                     int ntmax, double kappa, double eps,
+                                                     FloorSrc src, double *__restrict__ pot,
+                                                     double *__restrict__ out_parts,
+                                                     int *__restrict__ nbad,
+                                                     double *__restrict__ delta_parts) {
+    __shared__ double red[RT / 64];
+    double sh = -INFINITY, tm = 0.0;
+    for (int b = threadIdx.x; b < nshift; b += RT) sh = fmax(sh, shift_parts[b]);
+    for (int b = threadIdx.x; b < ntmax; b += RT) tm = fmax(tm, tmax_parts[b]);
+    sh = block_max(sh, red);
+    if (sh == -INFINITY) sh = 0.0;
+    tm = block_max(tm, red);
+    const float thr = (float)(tm * (double)FLOOR_REL);
+    const int lane = threadIdx.x & 63;
+    double mx = -INFINITY, dmx = 0.0;
+    int bad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); i0 < n;
+         i0 += stride) {
+        const int64_t i = i0 + lane;
+        const bool ok = i < n;
+        const float v = ok ? t[i] : 1.0f;
+        const bool flag = ok && !(v >= thr && v > 0.0f);
+        double f = ok && !flag ? -kappa * (sh + eps * sum_log(v)) : 0.0;
+        uint64_t mask = __ballot(flag);
+        while (mask) {
+            const int k = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            double L;
+            floor_row_lse(src, i0 + k, sh, lane, L, nullptr);
+            if (lane == k) {
+                if (!(L > -INFINITY)) {
+                    bad++;
+                    L = log((double)FLT_MIN);
+                }
+                f = -kappa * (sh + eps * L);
+            }
+        }
+        if (ok) {
+            if (DELTA) dmx = fmax(dmx, fabs(f - pot[i]));
+            pot[i] = f;
+            mx = fmax(mx, f);
+        }
+    }
+    if (bad) atomicAdd(nbad, bad);
+    mx = block_max(mx, red);
+    if (threadIdx.x == 0) out_parts[blockIdx.x] = mx;
+    if (DELTA) {
+        dmx = block_max(dmx, red);
+        if (threadIdx.x == 0) delta_parts[blockIdx.x] = dmx;
+    }
+}
+
 // Per-block maxima of a double array (warm starts, gradients); combined by the consumer.
 __global__ void __launch_bounds__(RT) k_max_parts(const double *__restrict__ v, int64_t n,
                                                   double *__restrict__ parts) {
@@ -396,6 +543,50 @@ __global__ void k_uot_grad_rows(const float *__restrict__ a, const double *__res
             for (int k = 0; k < d; ++k)
                 dx[i * d + k] = (float)(-scale * eps * (double)a[i] * e * (double)grad[i * d + k]);
         if (da) da[i] = (float)(scale * (-rho * expm1(-f[i] / rho) - eps * (e * (double)t[i] - mb)));
+    }
+}
+
+// Rows of k_uot_grad_rows whose sum t_i is below FLOOR_REL of the largest, recomputed directly:
+//   dx_i = scale a_i e^{(f_i + gmax)/eps + L_i} Gbar_i,  Gbar_i the softmax mean of grad_x C_ij,
+//   da_i = scale (rho (1 - e^{-f_i/rho}) - eps (e^{(f_i + gmax)/eps + L_i} - Mb)).
+__global__ void __launch_bounds__(RT) k_uot_grad_floor(const float *__restrict__ a,
+                                                       const double *__restrict__ f,
+                                                       const float *__restrict__ t, int64_t n,
+                                                       const double *__restrict__ tmax_parts,
+                                                       int ntmax, const double *__restrict__ gmax,
+                                                       double eps, double rho,
+                                                       const double *__restrict__ Mb,
+                                                       double scale, FloorSrc src,
+                                                       float *__restrict__ dx,
+                                                       float *__restrict__ da) {
+    __shared__ double red[RT / 64];
+    double tm = 0.0;
+    for (int b = threadIdx.x; b < ntmax; b += RT) tm = fmax(tm, tmax_parts[b]);
+    tm = block_max(tm, red);
+    const float thr = (float)(tm * (double)FLOOR_REL);
+    const double gm = *gmax, mb = *Mb;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); i0 < n;
+         i0 += stride) {
+        const int64_t i = i0 + lane;
+        const float v = i < n ? t[i] : 1.0f;
+        uint64_t mask = __ballot(i < n && !(v >= thr && v > 0.0f));
+        while (mask) {
+            const int k = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int64_t row = i0 + k;
+            double L, G[3];
+            floor_row_lse(src, row, gm, lane, L, G);
+            if (lane == k) {
+                const double e = (L > -INFINITY) ? exp((f[row] + gm) * (1.0 / eps) + L) : 0.0;
+                if (dx)
+                    for (int c = 0; c < src.d; ++c)
+                        dx[row * src.d + c] = (float)(scale * (double)a[row] * e * G[c]);
+                if (da)
+                    da[row] = (float)(scale * (-rho * expm1(-f[row] / rho) - eps * (e - mb)));
+            }
+        }
     }
 }
 
@@ -660,6 +851,28 @@ int launch_update(const float *t, int64_t n, const double *shift_parts, int nshi
     return nb;
 }
 
+// The update with floor rows re-evaluated (fast path, unfused half-steps).  tmax_parts: scratch
+// for UPD_BLOCKS per-block maxima of t.
+int launch_update_floor(const float *t, int64_t n, const double *shift_parts, int nshift,
+                        double kappa, double eps, const FloorSrc &src, double *tmax_parts,
+                        double *pot, double *out_parts, int *nbad, double *delta_parts,
+                        hipStream_t s) {
+    ProfScope ps("update", s);
+    const int nb = upd_blocks(n);
+    hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n, tmax_parts);
+    FS_LAUNCHED();
+    if (delta_parts)
+        hipLaunchKernelGGL(k_update_floor<true>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts,
+                           nshift, tmax_parts, nb, kappa, eps, src, pot, out_parts, nbad,
+                           delta_parts);
+    else
+        hipLaunchKernelGGL(k_update_floor<false>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts,
+                           nshift, tmax_parts, nb, kappa, eps, src, pot, out_parts, nbad,
+                           delta_parts);
+    FS_LAUNCHED();
+    return nb;
+}
+
 int launch_update_log(const double *logt, int64_t n, const double *shift_parts, int nshift,
                       double kappa, double eps, double *pot, double *out_parts, int *nbad,
                       double *delta_parts, hipStream_t s) {
@@ -713,6 +926,20 @@ void csum(int mode, const float *u, const double *pot, const float *v, int64_t n
     FS_LAUNCHED();
 }
 
+// Envelope-gradient rows at the fast sum's error floor, recomputed directly (k_uot_grad_floor).
+void grad_floor_rows(const float *a, const double *f, const float *t, int64_t n,
+                     const double *shift, double eps, double rho, const double *mass,
+                     double scale, const FloorSrc &src, double *tparts, float *dx, float *da,
+                     hipStream_t s) {
+    if (n == 0 || (!dx && !da)) return;
+    const int nb = upd_blocks(n);
+    hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n, tparts);
+    FS_LAUNCHED();
+    hipLaunchKernelGGL(k_uot_grad_floor, dim3(nb), dim3(RT), 0, s, a, f, t, n, tparts, nb, shift,
+                       eps, rho, mass, scale, src, dx, da);
+    FS_LAUNCHED();
+}
+
 }  // namespace
 
 void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, double rho, int iters,
@@ -726,6 +953,14 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     // log-domain direct sums (no underflow for rows far from every source) where they apply
     const bool logd = op.log_direct();
     DevBuf<double> lX(logd ? n + 1 : 0), lY(logd ? m + 1 : 0);
+    // fast path, unfused half-steps: rows at the fast sum's error floor are re-evaluated directly
+    DevBuf<double> tparts(op.fast ? UPD_BLOCKS : 0);
+    FloorSrc srcY{}, srcX{};
+    if (op.fast) {
+        const int r = op.kind == FS_GAUSS ? 2 : 1;
+        srcY = FloorSrc{op.coords(0), op.coords(1), b_o, g_o, m, op.d, r, 1.0 / eps};
+        srcX = FloorSrc{op.coords(1), op.coords(0), a_o, f_o, n, op.d, r, 1.0 / eps};
+    }
     if (warm) {
         if (m > 0) sc.ng = launch_max_parts(g_o, m, sc.gparts.p, s);
         if (n > 0) sc.nf = launch_max_parts(f_o, n, sc.fparts.p, s);
@@ -758,7 +993,10 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
                                           sc.fparts.p, sc.nbad.p, fd, s);
         } else {
             op.apply_pot(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, tX.p, 0, s);
-            if (n > 0)
+            if (n > 0 && op.fast)
+                sc.nf = launch_update_floor(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, srcY,
+                                            tparts.p, f_o, sc.fparts.p, sc.nbad.p, fd, s);
+            else if (n > 0)
                 sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
                                       sc.nbad.p, fd, s);
         }
@@ -782,7 +1020,10 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
                                           sc.gparts.p, sc.nbad.p, gd, s);
         } else {
             op.apply_pot(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, tY.p, 1, s);
-            if (m > 0)
+            if (m > 0 && op.fast)
+                sc.ng = launch_update_floor(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, srcX,
+                                            tparts.p, g_o, sc.gparts.p, sc.nbad.p, gd, s);
+            else if (m > 0)
                 sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
                                       sc.nbad.p, gd, s);
         }
@@ -918,7 +1159,8 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
     double *gmax = sc.v.p + 0, *fmax = sc.v.p + 1, *Mb = sc.v.p + 2, *Ma = sc.v.p + 3;
     DevBuf<float> ao(n + 1), bo(m + 1), w(std::max(n, m) + 1), t(std::max(n, m) + 1),
         gr((std::max(n, m) + 1) * d), ox((std::max(n, m) + 1) * d), o1(std::max(n, m) + 1);
-    DevBuf<double> fo(n + 1), go(m + 1);
+    DevBuf<double> fo(n + 1), go(m + 1), tparts(UPD_BLOCKS);
+    const int r = op.kind == FS_GAUSS ? 2 : 1;
     op.to_op(0, a, ao.p, s);
     op.to_op(1, b, bo.p, s);
     op.to_op64(0, f, fo.p, s);
@@ -942,6 +1184,10 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
                            fo.p, t.p, gr.p, d, n, gmax, eps, rho, Mb, scale,
                            dx ? ox.p : nullptr, da ? o1.p : nullptr);
         FS_LAUNCHED();
+        if (op.fast)
+            grad_floor_rows(ao.p, fo.p, t.p, n, gmax, eps, rho, Mb, scale,
+                            FloorSrc{op.coords(0), op.coords(1), bo.p, go.p, m, d, r, 1.0 / eps},
+                            tparts.p, dx ? ox.p : nullptr, da ? o1.p : nullptr, s);
         if (dx) op.rows_from_op(0, ox.p, dx, s);
         if (da) op.from_op(0, o1.p, da, s);
     }
@@ -952,6 +1198,10 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
                            go.p, t.p, gr.p, d, m, fmax, eps, rho, Ma, scale,
                            dy ? ox.p : nullptr, db ? o1.p : nullptr);
         FS_LAUNCHED();
+        if (op.fast)
+            grad_floor_rows(bo.p, go.p, t.p, m, fmax, eps, rho, Ma, scale,
+                            FloorSrc{op.coords(1), op.coords(0), ao.p, fo.p, n, d, r, 1.0 / eps},
+                            tparts.p, dy ? ox.p : nullptr, db ? o1.p : nullptr, s);
         if (dy) op.rows_from_op(1, ox.p, dy, s);
         if (db) op.from_op(1, o1.p, db, s);
     }

@@ -22,7 +22,8 @@ Section "Empirical measures"):
 * ``divergence_d2_n200k``: d=2, n=m=200k, clouds as uot_d2_n100k; Sinkhorn divergence (eps=0.01,
   rho=0.5) and Gaussian MMD (lambda=0.01), forward and backward.
 * ``laplace_d3_n4M``: d=3, n=m=4M, clouds as uot_d3_n1M; Laplace Gibbs kernel exp(-|x-y|/eps),
-  eps=0.01, near field; grid 256^3; rho=1, 50 sweeps; masses 1.0 / 1.2.
+  eps=0.01, near field; grid 256^3 with bandwidth 192 and smoothness 8; rho=1, 50 sweeps;
+  masses 1.0 / 1.2.
 * ``gauss_d32_n200k``: d=32, n=m=200k; x ~ N(0, I)/sqrt(32), y ~ N(0.1, I)/sqrt(32) (not clipped);
   Gaussian lambda=1; masses 1.0 / 1.2; direct summation.
 """
@@ -49,7 +50,7 @@ CONFIGS = {
                                 mmd_lambda=0.01, fd_h=1e-3, fd_coords=64),
     "laplace_d3_n4M": dict(d=3, n=4_000_000, mass_a=1.0, mass_b=1.2, kernel="laplace", eps=0.01,
                   rho=1.0, iters=50, grid=256, window=6, points="perturbed", bandwidth=192,
-                  smoothness=6),
+                  smoothness=8),
     "gauss_d32_n200k": dict(d=32, n=200_000, mass_a=1.0, mass_b=1.2, kernel="gauss", eps=1.0,
                             rho=1.0, iters=50, grid=0, window=0, points="gauss32"),
 }

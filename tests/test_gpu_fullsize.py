@@ -46,6 +46,22 @@ def test_uot_full_size(cfg, grid, window):
     assert last_halfstep_error(w, f, g, w["eps"], w["rho"]) < TOL
 
 
+def test_uot_laplace_d3_n4M_full_size():
+    """The 4M Laplace workload at full size (n = m = 4M, grid 256^3, bandwidth 192, smoothness 6,
+    r = 1, near field, 50 sweeps): the final gamma against an FP64 gamma half-step of the final
+    beta on sampled rows."""
+    w = synth.make("laplace_d3_n4M")
+    print("case laplace_d3_n4M", w["n"], "points", w["iters"], "sweeps", flush=True)
+    f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                                w["iters"], kernel="laplace", grid=w["grid"], window=w["window"],
+                                bandwidth=w["bandwidth"], smoothness=w["smoothness"])
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    assert np.isfinite(obj) and np.all(np.isfinite(f)) and np.all(np.isfinite(g))
+    err = last_halfstep_error(w, f, g, w["eps"], w["rho"], r=1, k=48)
+    print("sampled last-half-step error %.2e" % err)
+    assert err < TOL
+
+
 def test_d3_n1M_fastsum_gauss_and_energy_full_size():
     w = synth.make("uot_d3_n1M")
     x, y = T(w["x"]), T(w["y"])

@@ -227,25 +227,33 @@ def test_plan_multiplier_reuse():
     assert relinf(got, first[-1]) < 2e-6
 
 
-def test_uot_matrix_core_groups():
-    """A Sinkhorn solve whose kernel sums take the 3-D matrix-core spread and gather (dense
-    clusters, grid 64^3) against the oracle's iterates."""
-    x, y, _ = dense_and_sparse(8000, 7001, 21, frac=0.95)
+@pytest.mark.parametrize("n,m,sweeps", [(8000, 7001, 10), (24000, 22001, 50)])
+def test_uot_matrix_core_groups(n, m, sweeps):
+    """A Sinkhorn solve whose kernel sums take the headline's kernels (3-D matrix-core spread with
+    the weights formed inside, matrix-core gather with the potential update applied inside; dense
+    clusters, grid 64^3, window 6, eps = 0.02, rho = 1) against the oracle's iterates, up to the
+    headline's 50 sweeps (Algorithm 2).  Reports the dual residual of Table
+    Accuracy_analysis2, |b~ - b|/|b| + |g~ - g|/|g|."""
+    x, y, _ = dense_and_sparse(n, m, 21, frac=0.95)
     rng = np.random.default_rng(22)
     a = rng.uniform(0.5, 1.5, len(x)).astype(np.float32)
     b = rng.uniform(0.5, 1.5, len(y)).astype(np.float32)
     a, b = a / a.sum(), (1.2 * b / b.sum()).astype(np.float32)
-    eps, rho, sweeps = 0.02, 1.0, 10
+    eps, rho = 0.02, 1.0
+    print("case matrix-core UOT n=%d m=%d sweeps=%d" % (n, m, sweeps), flush=True)
     f, g, obj = fu.uot_sinkhorn(T(x), T(a), T(y), T(b), eps, rho, sweeps, kernel="gauss",
                                 grid=64, window=6)
     beta, gamma = oracle.uot_sinkhorn(x, a, y, b, eps, rho, sweeps)
     D = oracle.uot_dual(x, a, y, b, eps, rho, beta, gamma)
-    assert relinf(f.cpu().numpy(), beta) < TOL
-    assert relinf(g.cpu().numpy(), gamma) < TOL
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    print("dual residual %.2e (relinf f %.2e g %.2e, objective %.2e)" % (
+        rel2(f, beta) + rel2(g, gamma), relinf(f, beta), relinf(g, gamma), abs(obj - D) / abs(D)))
+    assert relinf(f, beta) < TOL
+    assert relinf(g, gamma) < TOL
     assert abs(obj - D) < TOL * abs(D)
     fv, _, _ = fu.uot_sinkhorn(T(x), T(a), T(y), T(b), eps, rho, sweeps, kernel="gauss",
                                grid=64, window=6, flags=fu.FLAG_FORCE_VALU)
-    assert np.any(fv.cpu().numpy() != f.cpu().numpy())  # the matrix cores ran
+    assert np.any(fv.cpu().numpy() != f)  # the matrix cores ran
 
 
 def dense_and_sparse_2d(n, m, seed, frac=0.8):
@@ -563,6 +571,42 @@ def test_uot_reduced(cfg, n, sweeps, grid, window):
     assert abs(obj - D) < TOL * abs(D)
 
 
+def test_uot_laplace_4M_plan_reduced():
+    """The 4M Laplace workload's plan (grid 256^3, bandwidth N = 192, i.e. a non-integer
+    oversampling 4/3, smoothness 8, window 6, default near-field radius p/N; r = 1 Gibbs kernel
+    exp(-|x-y|/eps), eps = 0.01) at reduced n: 10 sweeps against the oracle's iterates, with the
+    dual residual of Table Accuracy_analysis2.  At this sparse size most of every sum comes from
+    the smooth part, whose regularisation error with smoothness 6 (4.5e-6 of the largest sum)
+    drove the potentials to 2e-5 after 10 sweeps; smoothness 8 gives 3e-7 and 1.5e-6."""
+    w = synth.make("laplace_d3_n4M", n=2000, m=1800)
+    sweeps = 10
+    beta, gamma, D = oracle_uot("laplace_d3_n4M-small", w["x"], w["a"], w["y"], w["b"], w["eps"],
+                                w["rho"], sweeps, r=1)
+    f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), w["eps"], w["rho"],
+                                sweeps, kernel="laplace", grid=w["grid"], window=w["window"],
+                                bandwidth=w["bandwidth"], smoothness=w["smoothness"])
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    print("dual residual %.2e" % (rel2(f, beta) + rel2(g, gamma)))
+    assert relinf(f, beta) < TOL and relinf(g, gamma) < TOL
+    assert abs(obj - D) < TOL * abs(D)
+
+
+@pytest.mark.parametrize("grid", [128, 256])
+def test_uot_laplace_rows_far_from_the_mass(grid):
+    """r = 1 Gibbs kernel on the 2-D mixture clouds (eps = 0.01, rho = 0.5): many targets lie far
+    from every source (sums down to 1e-5 of the largest), where the update takes the direct
+    re-evaluation; 40 sweeps against the oracle's iterates."""
+    w = synth.make("divergence_d2_n200k", n=1200, m=1000)
+    eps, rho, sweeps = w["eps"], w["rho"], 40
+    beta, gamma, D = oracle_uot("mixture-laplace-1200", w["x"], w["a"], w["y"], w["b"], eps, rho,
+                                sweeps, r=1)
+    f, g, obj = fu.uot_sinkhorn(T(w["x"]), T(w["a"]), T(w["y"]), T(w["b"]), eps, rho, sweeps,
+                                kernel="laplace", grid=grid, window=6)
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    assert relinf(f, beta) < TOL and relinf(g, gamma) < TOL
+    assert abs(obj - D) < TOL * abs(D)
+
+
 def test_uot_laplace_gibbs_kernel():
     """r = 1: Gibbs kernel exp(-|x-y|/eps) through the near-field-corrected fast sum."""
     w = synth.make("laplace_d3_n4M", n=2000, m=1800)
@@ -738,13 +782,14 @@ def test_mmd_self_is_zero():
 # --------------------------------------------------------------------------- gradients
 
 @pytest.mark.parametrize("kind,grid,tol", [("gauss", 0, 1e-4), ("gauss", 64, 1e-4),
-                                           ("laplace", 0, 1e-4), ("laplace", 256, 2e-3)])
+                                           ("laplace", 0, 1e-4), ("laplace", 256, 1e-4),
+                                           ("laplace", 128, 1e-4)])
 def test_uot_grad_against_oracle_envelope(kind, grid, tol):
     """Backward kernels: the GPU envelope gradient at given potentials equals the oracle's direct
-    FP64 gradient at the same potentials.  For the r = 1 (Laplace Gibbs) kernel the fast sum's
-    FP32 absolute error floor (~1e-7 of the largest sum) is multiplied by exp((f_i + gmax)/eps),
-    which is large at points far from the transported mass; the max-normalised error there is
-    ~1e-3, so that case carries a wider tolerance (the Gaussian cases keep 1e-4)."""
+    FP64 gradient at the same potentials.  With the r = 1 (Laplace Gibbs) kernel at eps = 0.01 on
+    these mixture clouds, about half the rows have kernel sums below 1e-2 of the largest (targets
+    far from every source) while the plan keeps their mass; there the fast sum's absolute error
+    floor would be a large relative error, so those rows are re-evaluated directly."""
     w = synth.make("divergence_d2_n200k", n=1200, m=1000)
     r = 2 if kind == "gauss" else 1
     beta, gamma = oracle.uot_sinkhorn(w["x"], w["a"], w["y"], w["b"], w["eps"], w["rho"], 40, r=r)
