@@ -140,6 +140,21 @@ int fs_plan_create(const float *x, int64_t n, const float *y, int64_t m, int d,
 int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void *stream);
 void fs_plan_destroy(fs_plan plan);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): fs_plan_apply with no allocation of any kind.  Same
+ * arguments, result and kernels as fs_plan_apply; its temporaries (the operator-order weights
+ * and sums of the fast path, the partial row sums of the direct matrix-core path) live in a
+ * static 16 MiB device array, one copy per GPU, held until the process ends.  Limit: on the fast
+ * path 4 (ns + 1) + 4 (nt + 1) bytes, each rounded up to 256, must fit (about 4.19 million
+ * source plus target points); larger plans return FS_EINVAL with a message, and nothing is
+ * launched.  On the direct matrix-core path the array bounds the column splits instead (no
+ * size limit).  Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams or threads) race and must be ordered by the caller.  The calling thread's
+ * current device must be the stream's device.  Pass timing (fs_profile_enable) creates events
+ * and should stay off in such callers. */
+int fs_plan_apply_noalloc(fs_plan plan, const float *v, float *out, int transpose,
+                          void *stream);
+
 /* Unbalanced Sinkhorn, Algorithm 2 (the NFFT-accelerated form of Algorithm 1):
  *   iters full sweeps; each sweep does the beta half-step then the gamma half-step,
  *     f_i = -(rho lambda/(rho + lambda)) log sum_j k_ij b_j exp(g_j/lambda)

@@ -31,7 +31,7 @@ FLAG_FORCE_VALU = 0x2
 EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fs_profile_enable",
             "fs_profile_select",
             "fs_profile_query", "fs_profile_reset", "fastsum_apply", "fs_plan_create",
-            "fs_plan_apply", "fs_plan_destroy", "uot_sinkhorn", "uot_upper_bound",
+            "fs_plan_apply", "fs_plan_apply_noalloc", "fs_plan_destroy", "uot_sinkhorn", "uot_upper_bound",
             "uot_sinkhorn_scaling", "uot_sinkhorn_grad", "sinkhorn_divergence",
             "sinkhorn_divergence_grad", "mmd", "mmd_grad")
 INITS = {"zero": 0, "cstar": 1, "warm": 2}
@@ -71,6 +71,7 @@ def _load():
         "fastsum_apply": (I, [P, I64, P, I64, I, P, P, PP, P]),
         "fs_plan_create": (I, [P, I64, P, I64, I, PP, P, ctypes.POINTER(P)]),
         "fs_plan_apply": (I, [P, P, P, I, P]),
+        "fs_plan_apply_noalloc": (I, [P, P, P, I, P]),
         "fs_plan_destroy": (None, [P]),
         "uot_sinkhorn": (I, [P, P, I64, P, P, I64, I, PP, D, I, P, P, P, P]),
         "uot_upper_bound": (I, [P, P, I64, P, P, I64, I, PP, D, P, P, P]),
@@ -201,6 +202,18 @@ class Plan:
         out = torch.empty(self.m if transpose else self.n, dtype=torch.float32, device=self.device)
         _check(_lib.fs_plan_apply(self._h, _ptr(v), _ptr(out), int(bool(transpose)),
                                   _stream(self.device)))
+        return out
+
+    def apply_noalloc(self, v, out, transpose=False):
+        """fs_plan_apply_noalloc: the same product into the caller's `out`, with the library's
+        temporaries in its static device scratch (no allocation by the library)."""
+        v = _dev(v, name="v").reshape(-1)
+        nt = self.m if transpose else self.n
+        if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float32 \
+                or not out.is_contiguous() or out.numel() != nt:
+            raise ValueError("out must be a contiguous float32 HIP tensor of %d elements" % nt)
+        _check(_lib.fs_plan_apply_noalloc(self._h, _ptr(v), _ptr(out), int(bool(transpose)),
+                                          _stream(self.device)))
         return out
 
     def close(self):

@@ -2,8 +2,16 @@
 // Every entry point validates its arguments, runs the work on the caller's stream, converts
 // internal failures (fs::Error) into a negative fs_status and records the message.
 #include <algorithm>
+#include <mutex>
 
 #include "solver.h"
+
+// Scratch of fs_plan_apply_noalloc: the operator-order weights and sums of the fast path, or the
+// partial row sums of the direct matrix-core path.  One copy per GPU, held until the process
+// ends.  Host code never passes this name to a kernel: it is a host-side stand-in, and the
+// device address of each GPU's copy comes from hipGetSymbolAddress (noalloc_scratch below).
+constexpr size_t FS_NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[FS_NOALLOC_SCRATCH_BYTES];
 
 namespace fs {
 const char *last_error();
@@ -15,6 +23,26 @@ void profile_reset();
 namespace {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Device address of the current GPU's copy of `scratch`, looked up once per device (with that
+// device current) and kept.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+char *noalloc_scratch() {
+    int dev = 0;
+    FS_HIP(hipGetDevice(&dev));
+    FS_REQUIRE(dev >= 0 && dev < MAX_DEVICES, FS_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        FS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        FS_REQUIRE(ptr != nullptr, FS_EHIP, "no device address for the scratch array");
+        g_scratch_dev[dev] = ptr;
+    }
+    return static_cast<char *>(g_scratch_dev[dev]);
+}
 
 void check_params(const fs_params *p) {
     FS_REQUIRE(p != nullptr, FS_EINVAL, "params is NULL");
@@ -212,6 +240,44 @@ int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void 
             op.from_op(transpose ? 1 : 0, to.p, out, s);
             wo.reset_after(s);
             to.reset_after(s);
+        } else {
+            op.apply(v, out, nullptr, transpose, s);
+        }
+    });
+}
+
+int fs_plan_apply_noalloc(fs_plan plan, const float *v, float *out, int transpose,
+                          void *stream) {
+    return guarded([&] {
+        FS_REQUIRE(plan != nullptr && plan->op, FS_EINVAL, "plan is NULL");
+        Op &op = *plan->op;
+        const int64_t nt = transpose ? op.m : op.n, ns = transpose ? op.n : op.m;
+        check_points(v, ns, "v");
+        check_points(out, nt, "out");
+        hipStream_t s = as_stream(stream);
+        if (nt == 0) return;
+        if (ns == 0) {
+            fill_f32(out, nt, 0.0f, s);
+            return;
+        }
+        if (op.fast) {
+            // operator-order weights and sums, each rounded up to 256 bytes
+            const size_t wbytes = ((size_t)(ns + 1) * sizeof(float) + 255) & ~size_t(255);
+            const size_t tbytes = ((size_t)(nt + 1) * sizeof(float) + 255) & ~size_t(255);
+            FS_REQUIRE(wbytes + tbytes <= FS_NOALLOC_SCRATCH_BYTES, FS_EINVAL,
+                       "fs_plan_apply_noalloc: %lld sources + %lld targets need %zu bytes of "
+                       "scratch, more than the %zu available (at most about 4.19 million points "
+                       "in total)",
+                       (long long)ns, (long long)nt, wbytes + tbytes, FS_NOALLOC_SCRATCH_BYTES);
+            char *sp = noalloc_scratch();
+            float *wo = reinterpret_cast<float *>(sp);
+            float *to = reinterpret_cast<float *>(sp + wbytes);
+            op.to_op(transpose ? 0 : 1, v, wo, s);
+            op.apply(wo, to, nullptr, transpose, s);
+            op.from_op(transpose ? 1 : 0, to, out, s);
+        } else if (op.mfma) {
+            double *part = reinterpret_cast<double *>(noalloc_scratch());
+            op.apply(v, out, nullptr, transpose, s, part, FS_NOALLOC_SCRATCH_BYTES / sizeof(double));
         } else {
             op.apply(v, out, nullptr, transpose, s);
         }

@@ -34,7 +34,10 @@ double gram_frame(const float *x, int64_t n, const float *y, int64_t m, bool sam
 // Packs the points for kernel width lambda (the scaling depends on it), centred on `center`.
 void gram_prepare(const float *pts, int64_t count, int d, double lambda, const float *center,
                   GramOperand &op, hipStream_t s);
+// ext_partial (nullable): caller-owned FP64 buffer of ext_count elements for the per-split
+// partial row sums; the splits are then limited to ext_count / x.count and nothing is allocated.
 void direct_mfma_gauss(const GramOperand &x, const GramOperand &y, const float *w, float *out,
-                       double *out64, hipStream_t s);
+                       double *out64, hipStream_t s, double *ext_partial = nullptr,
+                       size_t ext_count = 0);
 
 }  // namespace fs

@@ -388,7 +388,7 @@ void gram_prepare(const float *pts, int64_t count, int d, double lambda, const f
 }
 
 void direct_mfma_gauss(const GramOperand &x, const GramOperand &y, const float *w, float *out,
-                       double *out64, hipStream_t s) {
+                       double *out64, hipStream_t s, double *ext_partial, size_t ext_count) {
     FS_REQUIRE(x.d == y.d && mfma_supported(FS_GAUSS, x.d), FS_EINVAL,
                "MFMA path needs matching d in {16,32,64,128}");
     if (x.count == 0) return;
@@ -400,16 +400,19 @@ void direct_mfma_gauss(const GramOperand &x, const GramOperand &y, const float *
     int64_t splits = std::max<int64_t>(1, (8192 + rblocks - 1) / rblocks);
     splits = std::min<int64_t>(splits, std::max<int64_t>(1, ntm / 64));
     splits = std::min<int64_t>(splits, 65535);
+    // a caller-provided partial-sum buffer bounds the number of splits (one split needs none)
+    if (ext_partial) splits = std::min<int64_t>(splits, std::max<int64_t>(1, (int64_t)(ext_count / (size_t)x.count)));
     const int64_t per = (ntm + splits - 1) / splits;
     splits = std::max<int64_t>(1, (ntm + per - 1) / per);
     DevBuf<double> partial;
-    if (splits > 1) partial.alloc((size_t)(splits * x.count));
+    if (splits > 1 && !ext_partial) partial.alloc((size_t)(splits * x.count));
+    double *part = ext_partial ? ext_partial : partial.p;
     const u16x8 *A = reinterpret_cast<const u16x8 *>(x.packed.p);
     const u16x8 *B = reinterpret_cast<const u16x8 *>(y.packed.p);
     dim3 grid((unsigned)rblocks, (unsigned)splits), block(256);
 #define FS_GRAM(DD)                                                                           \
     hipLaunchKernelGGL(k_gram_gauss<DD>, grid, block, 0, s, A, x.count, B, y.count, w,       \
-                       (int)per, splits > 1 ? partial.p : nullptr, out, out64)
+                       (int)per, splits > 1 ? part : nullptr, out, out64)
     switch (x.d) {
         case 16: FS_GRAM(16); break;
         case 32: FS_GRAM(32); break;
@@ -420,7 +423,7 @@ void direct_mfma_gauss(const GramOperand &x, const GramOperand &y, const float *
     FS_LAUNCHED();
     if (splits > 1) {
         hipLaunchKernelGGL(k_gram_combine, dim3(blocks_for(x.count, 256, int64_t(1) << 30)),
-                           dim3(256), 0, s, partial.p, x.count, (int)splits, out, out64);
+                           dim3(256), 0, s, part, x.count, (int)splits, out, out64);
         FS_LAUNCHED();
     }
     // the two kernels above are still queued: the partial sums go back to the workspace cache

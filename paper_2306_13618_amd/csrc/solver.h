@@ -35,7 +35,10 @@ struct Op {
     const float *coords(int side) const;
     // transpose = 0: t (X, op order) = K w (Y, op order); 1: t (Y) = K^T w (X).
     // grad (nullable): gradient of t with respect to the target positions (op order, x d).
-    void apply(const float *w, float *t, float *grad, int transpose, hipStream_t s);
+    // ext_partial / ext_count: caller-owned scratch for the direct matrix-core path's partial
+    // sums (no allocation then); ignored elsewhere.
+    void apply(const float *w, float *t, float *grad, int transpose, hipStream_t s,
+               double *ext_partial = nullptr, size_t ext_count = 0);
     // The same sum with source weights base_k exp((pot_k - max) / eps) (max: the largest of
     // nparts per-block maxima), formed inside the spread where the plan supports it
     // (fuses_weights), else through the weight array w.

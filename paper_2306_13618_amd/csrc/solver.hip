@@ -765,7 +765,8 @@ void Op::apply_pot_update(const float *base, const double *pot, const double *pa
     plan_apply_sorted_pot(*plan, pw, nullptr, transpose, s, &pu);
 }
 
-void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t s) {
+void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t s,
+               double *ext_partial, size_t ext_count) {
     const int64_t nt = transpose ? m : n, ns = transpose ? n : m;
     if (nt == 0) return;
     if (ns == 0) {
@@ -798,7 +799,7 @@ void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t
     if (mfma) {
         const GramOperand &gt = transpose ? (same ? gx : gy) : gx;
         const GramOperand &gs = transpose ? gx : (same ? gx : gy);
-        direct_mfma_gauss(gt, gs, w, t, nullptr, s);
+        direct_mfma_gauss(gt, gs, w, t, nullptr, s, ext_partial, ext_count);
     } else {
         direct_valu(kind, lambda, xt, nt, ys, ns, d, w, t, nullptr, s);
     }
