@@ -65,6 +65,10 @@ enum {
 /* flags */
 #define FS_FLAG_WARM_START 0x1u   /* uot_sinkhorn: f and g hold starting potentials on entry     */
 #define FS_FLAG_FORCE_VALU 0x2u   /* use the FP32 VALU kernels even where matrix-core ones apply */
+#define FS_FLAG_DETERMINISTIC 0x4u /* bitwise reproducible results: nodes that share a grid cell
+                                      or a near-field cell keep their input order (stable sorts in
+                                      the plan build), and the near field adds no partial sums
+                                      through atomics; costs a radix sort per point set */
 
 /* Parameters of one kernel sum.  Zero-initialise and set what you need; zeros mean defaults. */
 typedef struct fs_params {

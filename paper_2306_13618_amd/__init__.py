@@ -28,6 +28,7 @@ _LIBPATH = os.path.join(_HERE, "libfastuot.so")
 KERNELS = {"gauss": 0, "laplace": 1, "energy": 2, "imq": 3}
 FLAG_WARM_START = 0x1
 FLAG_FORCE_VALU = 0x2
+FLAG_DETERMINISTIC = 0x4
 EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fs_profile_enable",
             "fs_profile_select",
             "fs_profile_query", "fs_profile_reset", "fastsum_apply", "fs_plan_create",

@@ -132,6 +132,12 @@ private:
     std::vector<void *> held_;                         // device blocks to free at the end
 };
 
+// ------------------------------------------------------------------ stable ranks
+// rank[i] = position of node i among the nodes with its key, in input order (a stable counting
+// sort's ranks), given the keys (0 <= key < nkeys) and each key's exclusive start kstart.
+void stable_ranks(const int *key, int64_t n, int64_t nkeys, const int *kstart, int *rank,
+                  hipStream_t s);
+
 // ------------------------------------------------------------------ launch helpers
 inline unsigned blocks_for(int64_t work, int threads, int64_t cap = 1 << 20) {
     int64_t b = (work + threads - 1) / threads;

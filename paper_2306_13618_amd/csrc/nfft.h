@@ -61,6 +61,7 @@ struct PlanParams {
     double ci[16] = {0};  // inner polynomial  sum_k ci[k] r^(2k), k < p   (torus units)
     double cb[32] = {0};  // boundary polynomial sum_k cb[k] (r - 1/2)^k, k <= 2p-2
     bool nearfield = false;
+    bool stable = false;  // deterministic mode: stable node order, no atomic partial sums
     // near-field cell grid (data units)
     double nf_h = 0.0;
     int nf_R = 2;  // stencil half-width in cells: nf_R * nf_h >= radius

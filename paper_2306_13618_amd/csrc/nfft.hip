@@ -2219,13 +2219,15 @@ __global__ void k_nf_keys(const float *__restrict__ xs, int64_t n, NearArgs na,
     atomicAdd(&hist[kk], 1);
 }
 
+// rank (nullable): each point's position inside its cell (deterministic mode); else the cell's
+// atomic cursor.
 __global__ void k_nf_scatter(const float *__restrict__ xs, int64_t n, int d,
                              const int *__restrict__ key, const int *__restrict__ start,
-                             int *__restrict__ cursor, int *__restrict__ order,
-                             float *__restrict__ cxs) {
+                             int *__restrict__ cursor, const int *__restrict__ rank,
+                             int *__restrict__ order, float *__restrict__ cxs) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int pos = start[key[i]] + atomicAdd(&cursor[key[i]], 1);
+    const int pos = start[key[i]] + (rank ? rank[i] : atomicAdd(&cursor[key[i]], 1));
     order[pos] = (int)i;
     for (int c = 0; c < d; ++c) cxs[(int64_t)pos * d + c] = xs[i * d + c];
 }
@@ -2649,6 +2651,8 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     }
     std::vector<DevBuf<int>> keep;
     exclusive_scan(hist.p, nkeys, kstart.p, s, &keep);
+    // deterministic mode: ranks inside a key in input order instead of the atomic counter's
+    if (pp.stable) stable_ranks(key.p, n, nkeys, kstart.p, rank.p, s);
     const int *tile_hist = hist.p;
     if (cell_keys) {
         hipLaunchKernelGGL(k_tile_counts, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, kstart.p,
@@ -2747,9 +2751,11 @@ void build_nearfield_cells(Nodes &nd, const PlanParams &pp, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, hist.p, (int)(ncells + 1), 1 << 30,
                        nd.nf_cell_start.p, chunkdummy.p, totals.p);
     FS_LAUNCHED();
+    DevBuf<int> nrank(pp.stable ? nd.n + 1 : 0);
+    if (pp.stable) stable_ranks(key.p, nd.n, ncells + 1, nd.nf_cell_start.p, nrank.p, s);
     if (nd.n > 0) {
         hipLaunchKernelGGL(k_nf_scatter, dim3(blocks_for(nd.n, 256, int64_t(1) << 30)), dim3(256),
-                           0, s, nd.xs.p, nd.n, d, key.p, nd.nf_cell_start.p, cursor.p,
+                           0, s, nd.xs.p, nd.n, d, key.p, nd.nf_cell_start.p, cursor.p, nrank.p,
                            nd.nf_order.p, nd.nf_xs.p);
         FS_LAUNCHED();
     }
@@ -2835,6 +2841,7 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
                 const fs_params &p, hipStream_t s) {
     PlanParams &pp = pl.pp;
     pl.flags = p.flags;
+    pp.stable = (p.flags & FS_FLAG_DETERMINISTIC) != 0;
     pp.d = d;
     pp.kind = p.kernel;
     pp.lambda = p.lambda;
@@ -3464,7 +3471,8 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
         const int np = (pp.p <= 4) ? 4 : (pp.p <= 8) ? 8 : (pp.p <= 12) ? 12 : 16;
         // few target blocks (small or low-dimensional sets): split every block's sources over
         // several waves so that the launch still fills the chip
-        const int split = (int)std::min<int64_t>(64, std::max<int64_t>(1, (8192 + dst.nf_nblocks - 1) / dst.nf_nblocks));
+        // (deterministic mode: one wave per block, the partial sums would meet through atomics)
+        const int split = pp.stable ? 1 : (int)std::min<int64_t>(64, std::max<int64_t>(1, (8192 + dst.nf_nblocks - 1) / dst.nf_nblocks));
         const dim3 g((unsigned)dst.nf_nblocks, (unsigned)split), b(64);
 #define FS_NF(DD, KK, NN, GG)                                                                    \
     hipLaunchKernelGGL((k_nearfield<DD, KK, NN, GG>), g, b, 0, s, dst.nf_blocks.p, dst.nf_xs.p, \

@@ -1,5 +1,8 @@
 """GPU parity at the workloads' full sizes, on sampled outputs the FP64 oracle computes one by one,
 and the gradient check against central differences of the oracle's converged divergence."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -173,4 +176,25 @@ def test_d2_gradient_against_central_differences():
         gota.append(ga[i])
     ex, ea = relmax(got, fd), relmax(gota, fda)
     print("FD check: dx %.2e  da %.2e" % (ex, ea))
+    assert ex < 1e-4 and ea < 1e-4
+
+
+def test_d2_gradient_against_golden_central_differences_64_coordinates():
+    """dS/dx on 64 random position coordinates and dS/da on 16 random weights of the Sinkhorn
+    divergence (eq. (586)) at n = 2000, m = 1800 of the d = 2 mixture workload (eps = 0.01,
+    rho = 0.5), from the GPU (fast path, SinkhornDivergence backward) against central differences
+    (h = 1e-3) of the oracle's converged FP64 divergence, stored in tests/golden by the committed
+    script beside it.  Error normalised by the largest |gradient| of the sample."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "divergence_fd_d2_n2000.json")))
+    w = synth.make(g["workload"], n=g["n"], m=g["m"])
+    x = T(w["x"]).requires_grad_()
+    a = T(w["a"]).requires_grad_()
+    s = fu.SinkhornDivergence.apply(x, a, T(w["y"]), T(w["b"]), g["eps"], g["rho"], g["sweeps"],
+                                    {"grid": 128, "window": 6})
+    s.backward()
+    gx = x.grad.cpu().numpy()[np.array(g["rows"]), np.array(g["comps"])]
+    ga = a.grad.cpu().numpy()[np.array(g["weight_rows"])]
+    ex, ea = relmax(gx, g["fd_dx"]), relmax(ga, g["fd_da"])
+    print("golden FD check (64 positions, 16 weights): dx %.2e  da %.2e" % (ex, ea))
     assert ex < 1e-4 and ea < 1e-4

@@ -618,3 +618,16 @@ def test_row_gradients_match_full_gradients():
         rx, rm = oracle.mmd2_grad_rows(x, mu, rows, y, nu, kind, 0.1)
         assert np.allclose(rx, dx[rows], rtol=1e-12, atol=1e-15)
         assert np.allclose(rm, dmu[rows], rtol=1e-12, atol=1e-15)
+
+
+def test_golden_divergence_differences_match_the_envelope_gradient():
+    """The stored central differences of the converged divergence (written by
+    tests/golden/make_divergence_fd.py from the oracle alone) agree with the oracle's envelope
+    gradient at the same entries (Theorem "dualization": the gradient of the dual value at the
+    maximiser), to the O(h^2) truncation of the differences; the file matches its workload."""
+    g = json.load(open(os.path.join(GOLDEN, "divergence_fd_d2_n2000.json")))
+    c = synth.CONFIGS[g["workload"]]
+    assert (g["eps"], g["rho"]) == (c["eps"], c["rho"]) and len(g["rows"]) == 64
+    assert len(g["weight_rows"]) == 16 and g["h"] == c["fd_h"]
+    assert rel(g["envelope_dx"], g["fd_dx"]) < 1e-4
+    assert rel(g["envelope_da"], g["fd_da"]) < 1e-4
