@@ -1,6 +1,8 @@
 // Error state, workspace cache and small utility kernels of libfastuot.
 #include <algorithm>
 #include <cstdarg>
+#include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -30,6 +32,7 @@ struct Pending {
 struct Cache {
     std::mutex mu;
     std::map<void *, size_t> live;              // pointer -> size
+    size_t live_bytes = 0;
     std::multimap<size_t, void *> free_blocks;  // size -> pointer
     std::vector<Pending> pending;               // freed, but queued work may still use them
     std::vector<hipEvent_t> events;             // idle events for `pending`
@@ -58,12 +61,29 @@ void reclaim_pending(Cache &c) {
 }
 }  // namespace
 
+// Failure injection: FASTUOT_WORKSPACE_LIMIT (bytes) caps the live workspace; an allocation that
+// would exceed it fails as a device allocation failure would (FS_ENOMEM).
+static size_t workspace_limit() {
+    const char *e = std::getenv("FASTUOT_WORKSPACE_LIMIT");
+    if (!e || !*e) return SIZE_MAX;
+    char *end = nullptr;
+    const unsigned long long v = std::strtoull(e, &end, 10);
+    return (end && *end == 0) ? (size_t)v : SIZE_MAX;
+}
+
 void *ws_alloc(size_t bytes) {
     // round to 256 B so that nearby sizes share blocks
     size_t sz = (bytes + 255) & ~size_t(255);
     Cache &c = cache();
     {
         std::lock_guard<std::mutex> lk(c.mu);
+        const size_t limit = workspace_limit();
+        if (c.live_bytes + sz > limit) {
+            set_error("device allocation of %zu bytes refused: the workspace limit "
+                      "(FASTUOT_WORKSPACE_LIMIT = %zu bytes, %zu in use) would be exceeded",
+                      sz, limit, c.live_bytes);
+            throw Error{FS_ENOMEM};
+        }
         if (!c.pending.empty()) reclaim_pending(c);
         auto it = c.free_blocks.find(sz);
         if (it != c.free_blocks.end()) {
@@ -71,6 +91,7 @@ void *ws_alloc(size_t bytes) {
             c.free_blocks.erase(it);
             c.free_bytes -= sz;
             c.live[p] = sz;
+            c.live_bytes += sz;
             return p;
         }
     }
@@ -89,6 +110,7 @@ void *ws_alloc(size_t bytes) {
     }
     std::lock_guard<std::mutex> lk(c.mu);
     c.live[p] = sz;
+    c.live_bytes += sz;
     return p;
 }
 
@@ -100,6 +122,7 @@ void ws_free(void *p) {
     if (it == c.live.end()) return;
     c.free_blocks.emplace(it->second, p);
     c.free_bytes += it->second;
+    c.live_bytes -= it->second;
     c.live.erase(it);
 }
 
@@ -124,10 +147,12 @@ void ws_free_after(void *p, hipStream_t s) {
         (void)hipStreamSynchronize(s);
         c.free_blocks.emplace(it->second, p);
         c.free_bytes += it->second;
+        c.live_bytes -= it->second;
         c.live.erase(it);
         return;
     }
     c.pending.push_back(Pending{ev, p, it->second});
+    c.live_bytes -= it->second;
     c.live.erase(it);
 }
 

@@ -54,3 +54,20 @@ def test_binding_requires_device_tensors():
     import paper_2306_13618_amd as fu
     with pytest.raises(TypeError):
         fu.fastsum_apply(torch.zeros(4, 2), torch.zeros(3, 2), torch.zeros(3))
+
+
+def test_compute_call_without_a_gpu_fails_cleanly():
+    """Without a GPU a compute call returns a negative status and a message (no crash); the
+    arguments are valid host addresses, which no kernel ever reads because none launches."""
+    import numpy as np
+    import torch
+    import paper_2306_13618_amd as fu
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    x = np.zeros((16, 3), np.float32)
+    v = np.ones(16, np.float32)
+    out = np.zeros(16, np.float32)
+    p = fu._params("gauss", 0.1, 64, 6)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    st = fu._lib.fastsum_apply(ptr(x), 16, ptr(x), 16, 3, ptr(v), ptr(out), ctypes.byref(p), None)
+    assert st < 0 and fu._lib.fs_last_error()

@@ -424,6 +424,31 @@ def test_deterministic_mode_is_bitwise_reproducible(case):
         assert relinf(first[1].numpy(), beta) < TOL and relinf(first[2].numpy(), gamma) < TOL
 
 
+def test_failure_paths_report_and_recover(monkeypatch):
+    """Failure handling, forced from the host: (1) zero source weights make every Sinkhorn kernel
+    sum zero, so the update's count of non-positive sums reports FS_ENUMERIC (fast fused path,
+    fast path with the near field, direct path); (2) the workspace limit of the failure-injection
+    hook refuses an allocation inside the plan build, reported as FS_ENOMEM.  After each failure
+    the library still computes correct sums."""
+    w = synth.make("uot_d3_n1M", n=20_000, m=18_000)
+    x, a, y = T(w["x"]), T(w["a"]), T(w["y"])
+    zero = torch.zeros(18_000, dtype=torch.float32, device=DEV)
+    for kw in (dict(kernel="gauss", grid=64, window=6), dict(kernel="laplace", grid=128, window=6),
+               dict(kernel="gauss", grid=0)):
+        lam = 0.02 if kw["kernel"] == "gauss" else 0.01
+        with pytest.raises(fu.FastsumError, match="status -5"):
+            fu.uot_sinkhorn(x, a, y, zero, lam, 1.0, 3, **kw)
+    monkeypatch.setenv("FASTUOT_WORKSPACE_LIMIT", str(1 << 20))
+    with pytest.raises(fu.FastsumError, match="status -3.*FASTUOT_WORKSPACE_LIMIT"):
+        fu.fastsum_apply(x, y, T(w["b"]), kernel="gauss", lam=0.02, grid=64, window=6)
+    monkeypatch.delenv("FASTUOT_WORKSPACE_LIMIT")
+    got = fu.fastsum_apply(x, y, T(w["b"]), kernel="gauss", lam=0.02, grid=64,
+                           window=6).cpu().numpy()
+    rows = synth.sample_rows(20_000, 64, seed=8)
+    assert relinf(got[rows], oracle.direct_sum_rows(w["x"], rows, w["y"], w["b"], "gauss",
+                                                    0.02)) < TOL
+
+
 def test_bad_arguments_raise():
     x, y, v = clouds(2, 40, 30, 7)
     with pytest.raises(fu.FastsumError):
