@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X published dense FP16 matrix peak
 PEAK_HBM_GBS = 8000.0          # MI355X published HBM3E bandwidth
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak (256 CUs x 2.4 GHz x 256)
+NF_FLOPS_PER_PAIR = 30         # near-field flops per pair inside the radius (see nearfield_row)
 SPREAD_SAMPLE = 5              # time every 5th spread launch of the timed steps
 
 
@@ -81,6 +83,44 @@ def timed(torch, fn, reps=1):
     return out, (time.perf_counter() - t0) / reps
 
 
+def nearfield_pairs(xt, ys, radius, k=4096, seed=0):
+    """Pairs (target, source) closer than `radius`, estimated from k sampled targets counted
+    exactly against every source with a k-d tree on the host (the near field's algorithmic work
+    per kernel sum)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(xt), size=min(k, len(xt)), replace=False)
+    tree = cKDTree(ys)
+    cnt = tree.query_ball_point(xt[idx], radius, return_length=True)
+    return float(np.mean(cnt)) * len(xt)
+
+
+def nearfield_row(fu, torch, run, pairs, label):
+    """Average near-field pass time of `run` (events around every near-field launch of one call)
+    and its throughput against the FP32 vector roofline: each pair inside the radius costs
+    NF_FLOPS_PER_PAIR flops (3 differences and 3 multiply-adds for r^2, the square root, the inner
+    polynomial in r^2 (8 coefficients: 16 flops), the kernel's exponential, the difference and the
+    weighted accumulation)."""
+    fu.fs_profile_reset()
+    fu.fs_profile_select("nearfield", 1)
+    fu.fs_profile_enable(True)
+    run()
+    torch.cuda.synchronize()
+    fu.fs_profile_enable(False)
+    ms, cnt = fu.fs_profile_query("nearfield")
+    fu.fs_profile_reset()
+    t = ms / cnt * 1e-3
+    tflops = pairs * NF_FLOPS_PER_PAIR / t / 1e12
+    log("near field %s: %.2f ms per pass, %.3g pairs, %.3g pairs/s" % (label, 1e3 * t, pairs,
+                                                                        pairs / t))
+    return {"avg_ms": 1e3 * t, "passes": cnt, "pairs_in_radius": pairs, "pairs_per_s": pairs / t,
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_VALU_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_VALU_TFLOPS,
+                         "work": "%d flops per pair inside the radius; pairs from %s"
+                                 % (NF_FLOPS_PER_PAIR,
+                                    "4096 sampled targets counted exactly (k-d tree)")}}
+
+
 def extra_rows(fu, torch, dev, synth, keep):
     """The other workloads of the hot path, timed on the GPU.  Outputs needed for the sampled
     error checks go to `keep`; the checks themselves run in the CPU-baseline leg."""
@@ -112,6 +152,12 @@ def extra_rows(fu, torch, dev, synth, keep):
         v, t = timed(torch, lambda: fu.mmd(x, a, y, b, kernel=kind, window=6, **opts), 2)
         mmd_rows[kind] = {"ms": 1e3 * t, "mmd2": v, **{k: o for k, o in opts.items()}}
         log("MMD %s 1M: %.1f ms" % (kind, 1e3 * t))
+    # the energy MMD's near field: one kernel sum on the union of both sets
+    z = np.concatenate([w["x"], w["y"]])
+    mmd_rows["energy"]["nearfield"] = nearfield_row(
+        fu, torch, lambda: fu.mmd(x, a, y, b, kernel="energy", window=6, grid=256,
+                                  nearfield_radius=w["nearfield_radius"]),
+        nearfield_pairs(z, z, w["nearfield_radius"]), "energy MMD 1M")
     rows["mmd_d3_n1M"] = mmd_rows
 
     # the MMD accuracy experiment (Table Accuracy_analysis3): d = 2, n = m = 10000 points and
@@ -147,6 +193,16 @@ def extra_rows(fu, torch, dev, synth, keep):
                                   "grid": w["grid"], "bandwidth": w["bandwidth"],
                                   "smoothness": w["smoothness"],
                                   "err_sampled_last_halfstep": None}
+    # near field of this plan: default radius smoothness / N in torus units
+    pl = fu.Plan(x, y, kernel="laplace", lam=w["eps"], **{k: v for k, v in opts.items()
+                                                          if k != "kernel"})
+    _, _, period, bw = pl.multiplier()
+    pl.close()
+    radius = w["smoothness"] / bw * period
+    rows["uot_laplace_d3_n4M"]["nearfield"] = nearfield_row(
+        fu, torch, lambda: fu.uot_sinkhorn(x, a, y, b, w["eps"], w["rho"], 1, **opts),
+        nearfield_pairs(w["x"], w["y"], radius), "4M Laplace")
+    rows["uot_laplace_d3_n4M"]["nearfield"]["radius"] = radius
     keep["uot_laplace_d3_n4M"] = ("uot", "laplace_d3_n4M", 1, f.cpu().numpy(), g.cpu().numpy())
     log("4M Laplace: %.1f sweeps/s (%d sweeps incl. plan)" % (it / t, it))
 
@@ -204,7 +260,8 @@ def extra_rows(fu, torch, dev, synth, keep):
         log("upper bound %s: c* %.6g, bound %.6g, %.2f ms" % (label, c, bound, 1e3 * t))
     rows["upper_bound_d3_n1M"] = ub
 
-    # d = 32 direct Gaussian sum on the MFMA path (BF16 hi/lo Gram tiles), n=m=200k
+    # d = 32 direct Gaussian sum on the matrix-core path (FP16 hi/lo Gram tiles of the centred
+    # coordinates, BF16 norm step), n=m=200k
     w = synth.make("gauss_d32_n200k")
     x, y, b = (torch.from_numpy(w[k]).to(dev) for k in ("x", "y", "b"))
     fu.fastsum_apply(x, y, b, kernel="gauss", lam=w["eps"], grid=0)
@@ -214,7 +271,8 @@ def extra_rows(fu, torch, dev, synth, keep):
         "ms": 1e3 * t, "err_sampled": None,
         "roofline": {"bound": "mfma", "achieved": flops / t / 1e12, "peak": 2500.0,
                      "unit": "TFLOP/s", "frac": flops / t / 1e12 / 2500.0,
-                     "work": "3 BF16 products x 2 x d x n x m"},
+                     "work": "3 FP16 products x 2 x d x n x m (coordinate K steps; the "
+                             "norm step not counted)"},
         "pairs_per_s": w["n"] * w["m"] / t}
     keep["mfma_gauss_d32_n200k"] = ("sum", "gauss_d32_n200k", out.cpu().numpy())
     log("d=32 MFMA: %.2f ms" % (1e3 * t))

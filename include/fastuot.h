@@ -144,6 +144,18 @@ int fs_plan_create(const float *x, int64_t n, const float *y, int64_t m, int d,
 int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void *stream);
 void fs_plan_destroy(fs_plan plan);
 
+/* Inspection of a fast-summation plan (eq. (ansatz_NFFT)): the Fourier multiplier applied
+ * between the forward and the inverse transform,
+ *   M_k = b_k / (G^2 phihat(k_1)^2 ... phihat(k_d)^2) x (1/2 per coordinate with |k_i| = N/2),
+ *   b_k = N^-d sum_{j in I_N} K_R(j/N) e^{-2 pi i j.k/N}  (real and even),
+ * for k in [0, N/2]^d (first coordinate fastest; the values at negative k are the same), as
+ * float32 into mult_host (count >= (N/2+1)^d), the window transform phihat(k), k = 0..N/2, into
+ * phihat_host (float64, N/2+1 values), the torus period in data units (torus coordinates are
+ * data coordinates divided by it) and N.  Host pointers; any may be NULL except that count must
+ * cover the multiplier.  Synchronises the stream.  FS_EINVAL for a direct-summation plan. */
+int fs_plan_multiplier(fs_plan plan, float *mult_host, double *phihat_host, int64_t count,
+                       double *period_host, int *bandwidth_host, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): fs_plan_apply with no allocation of any kind.  Same
  * arguments, result and kernels as fs_plan_apply; its temporaries (the operator-order weights

@@ -13,6 +13,8 @@ marginal penalty eta.  Kernels: "gauss" exp(-r^2/lam), "laplace" exp(-r/lam), "e
 import ctypes
 import os
 
+import numpy as np
+
 import torch
 
 __all__ = [
@@ -32,7 +34,7 @@ FLAG_DETERMINISTIC = 0x4
 EXPORTED = ("fs_last_error", "fs_version", "fs_release_cache", "fs_profile_enable",
             "fs_profile_select",
             "fs_profile_query", "fs_profile_reset", "fastsum_apply", "fs_plan_create",
-            "fs_plan_apply", "fs_plan_apply_noalloc", "fs_plan_destroy", "uot_sinkhorn", "uot_upper_bound",
+            "fs_plan_apply", "fs_plan_apply_noalloc", "fs_plan_multiplier", "fs_plan_destroy", "uot_sinkhorn", "uot_upper_bound",
             "uot_sinkhorn_scaling", "uot_sinkhorn_grad", "sinkhorn_divergence",
             "sinkhorn_divergence_grad", "mmd", "mmd_grad")
 INITS = {"zero": 0, "cstar": 1, "warm": 2}
@@ -73,6 +75,7 @@ def _load():
         "fs_plan_create": (I, [P, I64, P, I64, I, PP, P, ctypes.POINTER(P)]),
         "fs_plan_apply": (I, [P, P, P, I, P]),
         "fs_plan_apply_noalloc": (I, [P, P, P, I, P]),
+        "fs_plan_multiplier": (I, [P, P, P, I64, ctypes.POINTER(D), ctypes.POINTER(I), P]),
         "fs_plan_destroy": (None, [P]),
         "uot_sinkhorn": (I, [P, P, I64, P, P, I64, I, PP, D, I, P, P, P, P]),
         "uot_upper_bound": (I, [P, P, I64, P, P, I64, I, PP, D, P, P, P]),
@@ -216,6 +219,21 @@ class Plan:
         _check(_lib.fs_plan_apply_noalloc(self._h, _ptr(v), _ptr(out), int(bool(transpose)),
                                           _stream(self.device)))
         return out
+
+    def multiplier(self):
+        """fs_plan_multiplier: (M_k as a float32 array of shape (N/2+1,)*d indexed [k_d..k_1],
+        phihat(k) for k = 0..N/2, torus period in data units, N)."""
+        P, N = ctypes.c_double(0.0), ctypes.c_int(0)
+        # first call: the sizes only (no array written)
+        _check(_lib.fs_plan_multiplier(self._h, None, None, 1 << 62, ctypes.byref(P),
+                                       ctypes.byref(N), _stream(self.device)))
+        H = N.value // 2 + 1
+        mult = np.empty((H,) * self.d, dtype=np.float32)
+        phat = np.empty(H, dtype=np.float64)
+        _check(_lib.fs_plan_multiplier(self._h, mult.ctypes.data_as(ctypes.c_void_p),
+                                       phat.ctypes.data_as(ctypes.c_void_p), mult.size,
+                                       ctypes.byref(P), ctypes.byref(N), _stream(self.device)))
+        return mult, phat, P.value, N.value
 
     def close(self):
         if getattr(self, "_h", None):

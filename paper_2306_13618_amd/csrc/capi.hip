@@ -284,6 +284,16 @@ int fs_plan_apply_noalloc(fs_plan plan, const float *v, float *out, int transpos
     });
 }
 
+int fs_plan_multiplier(fs_plan plan, float *mult_host, double *phihat_host, int64_t count,
+                       double *period_host, int *bandwidth_host, void *stream) {
+    return guarded([&] {
+        FS_REQUIRE(plan != nullptr && plan->op, FS_EINVAL, "plan is NULL");
+        FS_REQUIRE(plan->op->fast, FS_EINVAL, "a direct-summation plan has no multiplier");
+        plan_multiplier(*plan->op->plan, mult_host, phihat_host, count, period_host,
+                        bandwidth_host, as_stream(stream));
+    });
+}
+
 void fs_plan_destroy(fs_plan plan) {
     if (!plan) return;
     // applications are stream-ordered and may still be queued: wait before the plan's device

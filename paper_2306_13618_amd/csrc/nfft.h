@@ -128,6 +128,11 @@ int plan_update_parts(const Plan &pl, int transpose);
 // With pu the sums are not stored: the gather applies the update (t_sorted may be null).
 void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
                            hipStream_t s, const PotUpdate *pu = nullptr);
+// Inspection: the multiplier M_k ((N/2+1)^d floats, k >= 0 in every coordinate, first coordinate
+// fastest), the window transform phihat(k) used in its deconvolution (N/2+1 values), the torus
+// period in data units and the bandwidth N.  Either array may be null.
+void plan_multiplier(const Plan &pl, float *mult_host, double *phihat_host, int64_t count,
+                     double *period, int *bandwidth, hipStream_t s);
 // Drop the cached multipliers of recent plans (after a device synchronisation).
 void plan_release_mult_cache();
 

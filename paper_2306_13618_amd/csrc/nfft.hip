@@ -2806,6 +2806,25 @@ std::vector<std::unique_ptr<MultEntry>> g_mult;
 
 }  // namespace
 
+void plan_multiplier(const Plan &pl, float *mult_host, double *phihat_host, int64_t count,
+                     double *period, int *bandwidth, hipStream_t s) {
+    const PlanParams &pp = pl.pp;
+    const int H = pp.N / 2 + 1;
+    int64_t nh = 1;
+    for (int k = 0; k < pp.d; ++k) nh *= H;
+    FS_REQUIRE(count >= nh, FS_EINVAL, "the multiplier has %lld values (count %lld)",
+               (long long)nh, (long long)count);
+    if (mult_host) {
+        FS_HIP(hipMemcpyAsync(mult_host, pl.Mk.p, nh * sizeof(float), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipStreamSynchronize(s));
+    }
+    const double b = M_PI * (2.0 - (double)pp.N / pp.G);
+    if (phihat_host)
+        for (int k = 0; k < H; ++k) phihat_host[k] = kb_hat(pp.m, b, pp.G, k);
+    if (period) *period = pp.P;
+    if (bandwidth) *bandwidth = pp.N;
+}
+
 void plan_release_mult_cache() {
     std::lock_guard<std::mutex> lk(g_mult_mu);
     if (g_mult.empty()) return;

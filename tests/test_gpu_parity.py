@@ -194,6 +194,44 @@ def test_fastsum_bandwidth_on_64_grid(kind, lam, bandwidth):
     assert relinf(a, b) < 2e-6
 
 
+@pytest.mark.parametrize("d,grid,bandwidth,lam", [(1, 64, 0, 0.02), (2, 128, 0, 0.01),
+                                                  (3, 64, 0, 0.02), (3, 256, 192, 0.004)])
+def test_plan_multiplier_against_the_gaussian_fourier_series(d, grid, bandwidth, lam):
+    """Unit pin of b_k (eq. (ansatz_NFFT)): for the Gaussian exp(-|x|^2/lam) the plan's multiplier
+    M_k, with its window deconvolution divided out, equals the Fourier coefficients of the
+    periodised kernel sampled on the N-grid, prod_i sum_l sqrt(pi lam') exp(-pi^2 lam' (k_i +
+    l N)^2) with lam' = lam / P^2 in torus units (Poisson summation).  The window transform the
+    plan divides by is itself checked against the Kaiser-Bessel transform
+    I0(m sqrt(b^2 - (2 pi k / G)^2)) / (G phi(0)), phi(0) = sinh(b m) / (pi m), b = pi (2 - N/G)."""
+    from scipy.special import i0
+    rng = np.random.default_rng([55, d, grid])
+    x = rng.uniform(-0.25, 0.25, (500, d)).astype(np.float32)
+    pl = fu.Plan(T(x), T(x), kernel="gauss", lam=lam, grid=grid, window=6, bandwidth=bandwidth)
+    mult, phat, P, N = pl.multiplier()
+    pl.close()
+    assert N == (bandwidth or grid // 2)
+    m, G = 6, grid
+    b = np.pi * (2.0 - N / G)
+    k = np.arange(N // 2 + 1)
+    ref_phat = i0(m * np.sqrt(b * b - (2 * np.pi * k / G) ** 2)) / G / (np.sinh(b * m) / (np.pi * m))
+    assert np.max(np.abs(phat - ref_phat) / ref_phat) < 1e-12
+    lp = lam / P ** 2
+    beta = sum(np.sqrt(np.pi * lp) * np.exp(-np.pi ** 2 * lp * (k + l * N) ** 2) for l in (-2, -1, 0, 1, 2))
+    dec = 1.0 / (G * G * phat ** 2) * np.where(k == N // 2, 0.5, 1.0)
+    ref, decd = np.ones((1,) * 0), np.ones((1,) * 0)
+    for i in range(d):  # first coordinate fastest: the last array axis
+        shape = [1] * d
+        shape[d - 1 - i] = len(k)
+        ref = ref * beta.reshape(shape)
+        decd = decd * dec.reshape(shape)
+    # b_k recovered from the float32 multiplier; compared on the scale of the largest coefficient
+    # (the deconvolution amplifies the FP64 rounding floor of b_k near the band corner, ~1e-17)
+    bk = mult.astype(np.float64) / decd
+    err = np.max(np.abs(bk - ref)) / np.max(np.abs(ref))
+    print("b_k vs Gaussian Fourier series: d=%d G=%d N=%d P=%.4f: %.2e" % (d, G, N, P, err))
+    assert err < 1e-6
+
+
 def test_plan_multiplier_reuse():
     """Plans that differ in kernel, lambda, grid, window or dimension, then the same plans again in
     reverse order: the multipliers M_k come from the library's cache of recent plans (four
