@@ -11,7 +11,8 @@ void direct_valu(int kind, double lambda, const float *x, int64_t n, const float
                  int d, const float *w, float *out, double *out64, hipStream_t s);
 
 // out_i = log sum_j exp(-|x_i - y_j|^r / lambda + u_j) in FP64 (r = 2 Gauss, 1 Laplace), with a
-// running per-row maximum, so it holds for rows far from every source (no underflow).
+// running per-row maximum, so it holds for rows far from every source (no underflow); u is given
+// in log2 units (u_j log2 e).
 void direct_lse(int kind, double lambda, const float *x, int64_t n, const float *y, int64_t m,
                 int d, const float *u, double *out, hipStream_t s);
 

@@ -127,30 +127,41 @@ __global__ void __launch_bounds__(DT) k_direct_general(const float *__restrict__
 }
 
 // Log-domain direct sum for the Sinkhorn half-step:
-//   out_i = log sum_j exp(c r_ij^p + u_j)    (FP64 result; r^2 for Gauss, r for Laplace)
-// with u_j the log source weights.  Each row keeps a running maximum M of its exponents and the
-// sum of exp(e - M): a larger exponent rescales the sum once (rare after the first few terms),
-// so the sum never underflows however far the row is from every source, and the result is
-// M + log(sum).  One target per thread; sources staged in LDS tiles; per-tile FP32 partial sums
-// joined in FP64.  D = 0: any d (coordinates read from global memory).
+//   out_i = log sum_j exp(-r_ij^p / lambda + u_j)    (FP64 result; r^2 for Gauss, r for Laplace)
+// with u_j the log source weights, given in log2 units (u_j log2 e).  Each row keeps a running
+// maximum M of its exponents (log2 units) and the sum of 2^(e - M): a larger exponent rescales the
+// sum once (rare after the first few terms), so the sum never underflows however far the row is
+// from every source, and the result is (M + log2(sum)) ln 2.  DR targets per thread (coordinates
+// in registers for d <= 3); sources staged in LDS tiles; per-tile FP32 partial sums joined in
+// FP64.  D = 0: any d (coordinates read from global memory, one target per thread).
 template <int D, int KIND>
 __global__ void __launch_bounds__(DT) k_direct_lse(const float *__restrict__ x, int64_t n,
                                                    const float *__restrict__ y, int64_t m, int d,
-                                                   const float *__restrict__ u, float c,
+                                                   const float *__restrict__ u2, float c2,
                                                    double *__restrict__ out) {
-    constexpr int LT = 64;  // sources per tile
+    constexpr int R = D > 0 ? DR : 1;
+    constexpr int LT = D > 0 ? DTILE : 64;  // sources per tile
     __shared__ float sy[LT * (D > 0 ? D : 128)];
     __shared__ float su[LT];
     const int dd = D > 0 ? D : d;
-    const int64_t i = (int64_t)blockIdx.x * DT + threadIdx.x;
-    const float *xi = x + (i < n ? i : 0) * dd;
-    float xr[D > 0 ? D : 1];
+    const int64_t base = (int64_t)blockIdx.x * DT * R;
+    float xr[R][D > 0 ? D : 1];
+    const float *xg = x + (base + threadIdx.x < n ? base + threadIdx.x : 0) * dd;
     if (D > 0) {
 #pragma unroll
-        for (int k = 0; k < (D > 0 ? D : 1); ++k) xr[k] = xi[k];
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = base + threadIdx.x + r * DT;
+#pragma unroll
+            for (int k = 0; k < (D > 0 ? D : 1); ++k) xr[r][k] = (i < n) ? x[i * dd + k] : 0.0f;
+        }
     }
-    float M = -FLT_MAX;
-    double S = 0.0;
+    float M[R];
+    double S[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        M[r] = -FLT_MAX;
+        S[r] = 0.0;
+    }
     for (int64_t j0 = 0; j0 < m; j0 += LT) {
         const int cnt = (int)((m - j0) < LT ? (m - j0) : LT);
         __syncthreads();
@@ -158,36 +169,57 @@ __global__ void __launch_bounds__(DT) k_direct_lse(const float *__restrict__ x, 
             const int jj = t / dd;
             sy[t] = (jj < cnt) ? y[(j0 + jj) * dd + (t - jj * dd)] : 0.0f;
         }
-        for (int t = threadIdx.x; t < LT; t += DT) su[t] = (t < cnt) ? u[j0 + t] : -INFINITY;
+        for (int t = threadIdx.x; t < LT; t += DT) su[t] = (t < cnt) ? u2[j0 + t] : -INFINITY;
         __syncthreads();
-        float P = 0.0f;
-        for (int t = 0; t < cnt; ++t) {
-            float r2 = 0.0f;
-            if (D > 0) {
+        float P[R];
 #pragma unroll
-                for (int k = 0; k < (D > 0 ? D : 1); ++k) {
-                    const float df = xr[k] - sy[t * dd + k];
-                    r2 = fmaf(df, df, r2);
+        for (int r = 0; r < R; ++r) P[r] = 0.0f;
+        // chunks of CH sources: the running maximum is raised at most once per chunk (padded
+        // tile entries have u = -inf and contribute nothing)
+        constexpr int CH = 8;
+        for (int t0 = 0; t0 < cnt; t0 += CH) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float e[CH];
+                float mx = -FLT_MAX;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int t = t0 + c;  // t < LT: the tile is padded to LT entries
+                    float r2 = 0.0f;
+                    if (D > 0) {
+#pragma unroll
+                        for (int k = 0; k < (D > 0 ? D : 1); ++k) {
+                            const float df = xr[r][k] - sy[t * dd + k];
+                            r2 = fmaf(df, df, r2);
+                        }
+                    } else {
+                        for (int k = 0; k < dd; ++k) {
+                            const float df = xg[k] - sy[t * dd + k];
+                            r2 = fmaf(df, df, r2);
+                        }
+                    }
+                    e[c] = fmaf(KIND == FS_GAUSS ? r2 : __builtin_sqrtf(r2), c2, su[t]);
+                    mx = fmaxf(mx, e[c]);
                 }
-            } else {
-                for (int k = 0; k < dd; ++k) {
-                    const float df = xi[k] - sy[t * dd + k];
-                    r2 = fmaf(df, df, r2);
+                if (mx > M[r]) {
+                    const float f = exp2f(M[r] - mx);
+                    S[r] *= (double)f;
+                    P[r] *= f;
+                    M[r] = mx;
                 }
-            }
-            const float e = fmaf(KIND == FS_GAUSS ? r2 : sqrtf(r2), c, su[t]);
-            if (e > M) {
-                const float f = expf(M - e);
-                S *= (double)f;
-                P = fmaf(P, f, 1.0f);
-                M = e;
-            } else {
-                P += expf(e - M);
+#pragma unroll
+                for (int c = 0; c < CH; ++c) P[r] += exp2f(e[c] - M[r]);
             }
         }
-        S += (double)P;
+#pragma unroll
+        for (int r = 0; r < R; ++r) S[r] += (double)P[r];
     }
-    if (i < n) out[i] = (S > 0.0) ? (double)M + log(S) : -INFINITY;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = base + threadIdx.x + r * DT;
+        if (i < n)
+            out[i] = (S[r] > 0.0) ? ((double)M[r] + log2(S[r])) * 0.6931471805599453 : -INFINITY;
+    }
 }
 
 template <int D>
@@ -257,15 +289,16 @@ void direct_lse(int kind, double lambda, const float *x, int64_t n, const float 
     FS_REQUIRE(kind == FS_GAUSS || kind == FS_LAPLACE, FS_EINVAL,
                "log-domain direct sums need the Gauss or Laplace kernel");
     FS_REQUIRE(d >= 1 && d <= 128, FS_EINVAL, "direct summation supports d <= 128 (got %d)", d);
-    const float c = (float)(-1.0 / lambda);
-    dim3 grid(blocks_for(n, DT, int64_t(1) << 30)), block(DT);
+    const float c2 = (float)(-1.4426950408889634 / lambda);
+    const int per = d <= 3 ? DT * DR : DT;
+    dim3 grid(blocks_for(n, per, int64_t(1) << 30)), block(DT);
 #define FS_LSE(DD)                                                                             \
     if (kind == FS_GAUSS)                                                                      \
         hipLaunchKernelGGL((k_direct_lse<DD, FS_GAUSS>), grid, block, 0, s, x, n, y, m, d, u,  \
-                           c, out);                                                            \
+                           c2, out);                                                           \
     else                                                                                       \
         hipLaunchKernelGGL((k_direct_lse<DD, FS_LAPLACE>), grid, block, 0, s, x, n, y, m, d,   \
-                           u, c, out)
+                           u, c2, out)
     switch (d) {
         case 1: FS_LSE(1); break;
         case 2: FS_LSE(2); break;

@@ -60,7 +60,8 @@ __global__ void __launch_bounds__(256) k_weights(const float *__restrict__ base,
         w[i] = weight_exp(base[i], (pot[i] - pm) * inv_eps);
 }
 
-// u_k = log base_k + (pot_k - pmax) / eps in FP64, rounded to FP32 (-inf for a zero weight).
+// u_k = (log base_k + (pot_k - pmax) / eps) log2 e in FP64, rounded to FP32 (-inf for a zero
+// weight): the log source weights of the log-domain direct sums, in log2 units.
 __global__ void __launch_bounds__(256) k_log_weights(const float *__restrict__ base,
                                                      const double *__restrict__ pot,
                                                      const double *__restrict__ parts, int nparts,
@@ -74,7 +75,8 @@ __global__ void __launch_bounds__(256) k_log_weights(const float *__restrict__ b
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float b = base[i];
-        u[i] = b > 0.0f ? (float)(log((double)b) + (pot[i] - pm) * inv_eps) : -INFINITY;
+        u[i] = b > 0.0f ? (float)((log((double)b) + (pot[i] - pm) * inv_eps) * 1.4426950408889634)
+                        : -INFINITY;
     }
 }
 
@@ -190,10 +192,13 @@ struct FloorSrc {
     double inv_eps;
 };
 
-// Per-block maxima of a float array (UPD_BLOCKS-sized launch).
+// Per-block maxima of a float array (UPD_BLOCKS-sized launch); also clears *counter (nullable),
+// the number of rows the following re-evaluation kernel has taken.
 __global__ void __launch_bounds__(RT) k_max_f32(const float *__restrict__ t, int64_t n,
-                                                double *__restrict__ parts) {
+                                                double *__restrict__ parts,
+                                                int *__restrict__ counter) {
     __shared__ double red[RT / 64];
+    if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
     double mx = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -205,51 +210,73 @@ __global__ void __launch_bounds__(RT) k_max_f32(const float *__restrict__ t, int
 // The whole wave evaluates target `row`: returns (on every lane) L = log sum_j e^{e_j} with
 // e_j = log base_j + (pot_j - shift) inv_eps - C_ij inv_eps, and, when G is non-null, the softmax
 // mean of grad_x C_ij (d <= 3) in G.
+// Exponents in log2 units, e_j = log2 base_j + ((pot_j - shift) / eps - C_ij / eps) log2 e (the
+// potential difference in FP64, the rest in FP32), taken in chunks of FCH sources per lane: the
+// running maximum is raised at most once per chunk, then each term costs one exp2.
+constexpr int FCH = 8;
 __device__ void floor_row_lse(const FloorSrc &src, int64_t row, double shift, int lane, double &L,
                               double *G) {
     float xi[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < src.d; ++k) xi[k] = src.xt[row * src.d + k];
+    const float cs = (float)(src.inv_eps * 1.4426950408889634);
+    const double ps = src.inv_eps * 1.4426950408889634;
     float M = -FLT_MAX;
     double S = 0.0, g[3] = {0.0, 0.0, 0.0};
-    for (int64_t j = lane; j < src.m; j += 64) {
-        float df[3] = {0.0f, 0.0f, 0.0f};
-        float r2 = 0.0f;
-        for (int k = 0; k < src.d; ++k) {
-            df[k] = xi[k] - src.ys[j * src.d + k];
-            r2 = fmaf(df[k], df[k], r2);
+    for (int64_t j0 = lane; j0 < src.m; j0 += 64 * FCH) {
+        float e[FCH], gw[FCH][3];
+        float mx = -FLT_MAX;
+#pragma unroll
+        for (int c = 0; c < FCH; ++c) {
+            const int64_t j = j0 + 64 * c;
+            e[c] = -INFINITY;
+            gw[c][0] = gw[c][1] = gw[c][2] = 0.0f;
+            if (j < src.m) {
+                float df[3] = {0.0f, 0.0f, 0.0f}, r2 = 0.0f;
+                for (int k = 0; k < src.d; ++k) {
+                    df[k] = xi[k] - src.ys[j * src.d + k];
+                    r2 = fmaf(df[k], df[k], r2);
+                }
+                const float rr = __builtin_sqrtf(r2);
+                const float b = src.base[j];
+                if (b > 0.0f)
+                    e[c] = __builtin_amdgcn_logf(b) + (float)((src.pot[j] - shift) * ps) -
+                           (src.r == 2 ? r2 : rr) * cs;
+                if (G) {
+                    // grad_x C: r = 2: 2 (x - y); r = 1: (x - y) / |x - y| (0 at coincident points)
+                    const float gs = src.r == 2 ? 2.0f : (rr > 0.0f ? 1.0f / rr : 0.0f);
+                    for (int k = 0; k < src.d; ++k) gw[c][k] = gs * df[k];
+                }
+                mx = fmaxf(mx, e[c]);
+            }
         }
-        const float rr = sqrtf(r2);
-        const double c = src.r == 2 ? (double)r2 : (double)rr;
-        const float b = src.base[j];
-        const float e = b > 0.0f ? (float)(log((double)b) + (src.pot[j] - shift - c) * src.inv_eps)
-                                 : -INFINITY;
-        float wgt;
-        if (e > M) {
-            const double sc = exp((double)M - (double)e);
+        if (mx > M) {
+            const double sc = exp2((double)M - (double)mx);
             S *= sc;
             for (int k = 0; k < 3; ++k) g[k] *= sc;
-            M = e;
-            wgt = 1.0f;
-        } else {
-            wgt = expf(e - M);
+            M = mx;
         }
-        S += wgt;
-        if (G) {
-            // grad_x C: r = 2: 2 (x - y); r = 1: (x - y) / |x - y| (0 at coincident points)
-            const float gs = src.r == 2 ? 2.0f : (rr > 0.0f ? 1.0f / rr : 0.0f);
-            for (int k = 0; k < src.d; ++k) g[k] += (double)wgt * (double)(gs * df[k]);
+        float ps_ = 0.0f, pg[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < FCH; ++c) {
+            const float wgt = exp2f(e[c] - M);
+            ps_ += wgt;
+            if (G)
+                for (int k = 0; k < 3; ++k) pg[k] = fmaf(wgt, gw[c][k], pg[k]);
         }
+        S += ps_;
+        if (G)
+            for (int k = 0; k < 3; ++k) g[k] += pg[k];
     }
     float Mw = M;
     for (int o = 32; o > 0; o >>= 1) Mw = fmaxf(Mw, __shfl_xor(Mw, o, 64));
-    const double sc = (M == -FLT_MAX) ? 0.0 : exp((double)M - (double)Mw);
+    const double sc = (M == -FLT_MAX) ? 0.0 : exp2((double)M - (double)Mw);
     S *= sc;
     for (int k = 0; k < 3; ++k) g[k] *= sc;
     for (int o = 32; o > 0; o >>= 1) {
         S += __shfl_xor(S, o, 64);
         for (int k = 0; k < 3; ++k) g[k] += __shfl_xor(g[k], o, 64);
     }
-    L = (S > 0.0) ? (double)Mw + log(S) : -INFINITY;
+    L = (S > 0.0) ? ((double)Mw + log2(S)) * 0.6931471805599453 : -INFINITY;
     if (G)
         for (int k = 0; k < 3; ++k) G[k] = (S > 0.0) ? g[k] / S : 0.0;
 }
@@ -257,13 +284,16 @@ __device__ void floor_row_lse(const FloorSrc &src, int64_t row, double shift, in
 // The update of k_update, with the rows below FLOOR_REL of the largest sum (and non-positive
 // sums) re-evaluated directly.  Rows go in wave-aligned runs of 64 (one per lane); the flagged
 // rows of a run are then taken one after the other by the whole wave.
+// At most `cap` rows per launch are re-evaluated (the first to claim a slot of *taken); the
+// others keep the fast sum (a bounded cost per half-step: cap x m pairs).
 template <bool DELTA>
 __global__ void __launch_bounds__(RT) k_update_floor(const float *__restrict__ t, int64_t n,
                                                      const double *__restrict__ shift_parts,
                                                      int nshift,
                                                      const double *__restrict__ tmax_parts,
                                                      int ntmax, double kappa, double eps,
-                                                     FloorSrc src, double *__restrict__ pot,
+                                                     FloorSrc src, int *__restrict__ taken,
+                                                     int cap, double *__restrict__ pot,
                                                      double *__restrict__ out_parts,
                                                      int *__restrict__ nbad,
                                                      double *__restrict__ delta_parts) {
@@ -284,9 +314,26 @@ __global__ void __launch_bounds__(RT) k_update_floor(const float *__restrict__ t
         const int64_t i = i0 + lane;
         const bool ok = i < n;
         const float v = ok ? t[i] : 1.0f;
-        const bool flag = ok && !(v >= thr && v > 0.0f);
-        double f = ok && !flag ? -kappa * (sh + eps * sum_log(v)) : 0.0;
+        bool flag = ok && !(v >= thr && v > 0.0f);
+        // claim re-evaluation slots for this run's flagged rows (one atomic per run)
         uint64_t mask = __ballot(flag);
+        if (mask) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(taken, __popcll(mask));
+            base = __shfl(base, 0, 64);
+            const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+            flag = flag && base + rank < cap;
+            mask = __ballot(flag);
+        }
+        double f = 0.0;
+        if (ok && !flag) {
+            float vv = v;
+            if (!(vv > 0.0f)) {
+                bad++;
+                vv = FLT_MIN;
+            }
+            f = -kappa * (sh + eps * sum_log(vv));
+        }
         while (mask) {
             const int k = __ffsll((unsigned long long)mask) - 1;
             mask &= mask - 1;
@@ -546,46 +593,80 @@ __global__ void k_uot_grad_rows(const float *__restrict__ a, const double *__res
     }
 }
 
+// Decade histogram of the rows below FLOOR_REL of the largest sum: bin k < 15 counts
+// t_i / max t in [1e-(k+3), 1e-(k+2)), bin 15 everything smaller (or not positive).
+constexpr int FLOOR_BINS = 16;
+__global__ void __launch_bounds__(RT) k_floor_hist(const float *__restrict__ t, int64_t n,
+                                                   const double *__restrict__ tmax_parts,
+                                                   int ntmax, int *__restrict__ hist) {
+    __shared__ double red[RT / 64];
+    __shared__ int h[FLOOR_BINS];
+    if (threadIdx.x < FLOOR_BINS) h[threadIdx.x] = 0;
+    double tm = 0.0;
+    for (int b = threadIdx.x; b < ntmax; b += RT) tm = fmax(tm, tmax_parts[b]);
+    tm = block_max(tm, red);  // (its barrier also orders the clearing of h)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double r = (double)t[i] / tm;
+        if (!(r >= (double)FLOOR_REL)) {
+            int bin = FLOOR_BINS - 1;
+            if (r > 0.0) bin = min(FLOOR_BINS - 1, (int)floor(-log10(r)) - 2);
+            atomicAdd(&h[max(bin, 0)], 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < FLOOR_BINS && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
 // Rows of k_uot_grad_rows whose sum t_i is below FLOOR_REL of the largest, recomputed directly:
 //   dx_i = scale a_i e^{(f_i + gmax)/eps + L_i} Gbar_i,  Gbar_i the softmax mean of grad_x C_ij,
 //   da_i = scale (rho (1 - e^{-f_i/rho}) - eps (e^{(f_i + gmax)/eps + L_i} - Mb)).
-__global__ void __launch_bounds__(RT) k_uot_grad_floor(const float *__restrict__ a,
+// The rows with t_i < rel x (largest t) (rel <= FLOOR_REL, chosen by the host from the histogram
+// below so that the work stays within a budget), listed for k_uot_grad_floor.
+// The list holds at most `cap` rows (the count may run past it; readers clamp).
+__global__ void __launch_bounds__(RT) k_floor_list(const float *__restrict__ t, int64_t n,
+                                                   const double *__restrict__ tmax_parts,
+                                                   int ntmax, double rel, int *__restrict__ count,
+                                                   int cap, int *__restrict__ list) {
+    __shared__ double red[RT / 64];
+    double tm = 0.0;
+    for (int b = threadIdx.x; b < ntmax; b += RT) tm = fmax(tm, tmax_parts[b]);
+    tm = block_max(tm, red);
+    const float thr = (float)(tm * rel);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = t[i];
+        if (!(v >= thr && v > 0.0f)) {
+            const int q = atomicAdd(count, 1);
+            if (q < cap) list[q] = (int)i;
+        }
+    }
+}
+
+// One wave per listed row (min(*count, cap) rows).
+__global__ void __launch_bounds__(64) k_uot_grad_floor(const float *__restrict__ a,
                                                        const double *__restrict__ f,
-                                                       const float *__restrict__ t, int64_t n,
-                                                       const double *__restrict__ tmax_parts,
-                                                       int ntmax, const double *__restrict__ gmax,
+                                                       const int *__restrict__ list,
+                                                       const int *__restrict__ count, int cap,
+                                                       const double *__restrict__ gmax,
                                                        double eps, double rho,
                                                        const double *__restrict__ Mb,
                                                        double scale, FloorSrc src,
                                                        float *__restrict__ dx,
                                                        float *__restrict__ da) {
-    __shared__ double red[RT / 64];
-    double tm = 0.0;
-    for (int b = threadIdx.x; b < ntmax; b += RT) tm = fmax(tm, tmax_parts[b]);
-    tm = block_max(tm, red);
-    const float thr = (float)(tm * (double)FLOOR_REL);
     const double gm = *gmax, mb = *Mb;
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); i0 < n;
-         i0 += stride) {
-        const int64_t i = i0 + lane;
-        const float v = i < n ? t[i] : 1.0f;
-        uint64_t mask = __ballot(i < n && !(v >= thr && v > 0.0f));
-        while (mask) {
-            const int k = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const int64_t row = i0 + k;
-            double L, G[3];
-            floor_row_lse(src, row, gm, lane, L, G);
-            if (lane == k) {
-                const double e = (L > -INFINITY) ? exp((f[row] + gm) * (1.0 / eps) + L) : 0.0;
-                if (dx)
-                    for (int c = 0; c < src.d; ++c)
-                        dx[row * src.d + c] = (float)(scale * (double)a[row] * e * G[c]);
-                if (da)
-                    da[row] = (float)(scale * (-rho * expm1(-f[row] / rho) - eps * (e - mb)));
-            }
+    const int lane = threadIdx.x;
+    const int nlist = min(*count, cap);
+    for (int q = blockIdx.x; q < nlist; q += gridDim.x) {
+        const int64_t row = list[q];
+        double L, G[3];
+        floor_row_lse(src, row, gm, lane, L, G);
+        if (lane == 0) {
+            const double e = (L > -INFINITY) ? exp((f[row] + gm) * (1.0 / eps) + L) : 0.0;
+            if (dx)
+                for (int c = 0; c < src.d; ++c)
+                    dx[row * src.d + c] = (float)(scale * (double)a[row] * e * G[c]);
+            if (da) da[row] = (float)(scale * (-rho * expm1(-f[row] / rho) - eps * (e - mb)));
         }
     }
 }
@@ -854,22 +935,28 @@ int launch_update(const float *t, int64_t n, const double *shift_parts, int nshi
 
 // The update with floor rows re-evaluated (fast path, unfused half-steps).  tmax_parts: scratch
 // for UPD_BLOCKS per-block maxima of t.
+// Work budget of the floor-row re-evaluation, in (row, source) pairs: per Sinkhorn half-step, and
+// per gradient call.
+constexpr double FLOOR_PAIRS_HALFSTEP = 1 << 30;
+constexpr double FLOOR_PAIRS_GRAD = 1 << 30;
+
 int launch_update_floor(const float *t, int64_t n, const double *shift_parts, int nshift,
                         double kappa, double eps, const FloorSrc &src, double *tmax_parts,
-                        double *pot, double *out_parts, int *nbad, double *delta_parts,
-                        hipStream_t s) {
+                        int *taken, double *pot, double *out_parts, int *nbad,
+                        double *delta_parts, hipStream_t s) {
     ProfScope ps("update", s);
     const int nb = upd_blocks(n);
-    hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n, tmax_parts);
+    const int cap = (int)std::min<double>(2e9, FLOOR_PAIRS_HALFSTEP / std::max<int64_t>(src.m, 1));
+    hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n, tmax_parts, taken);
     FS_LAUNCHED();
     if (delta_parts)
         hipLaunchKernelGGL(k_update_floor<true>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts,
-                           nshift, tmax_parts, nb, kappa, eps, src, pot, out_parts, nbad,
-                           delta_parts);
+                           nshift, tmax_parts, nb, kappa, eps, src, taken, cap, pot, out_parts,
+                           nbad, delta_parts);
     else
         hipLaunchKernelGGL(k_update_floor<false>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts,
-                           nshift, tmax_parts, nb, kappa, eps, src, pot, out_parts, nbad,
-                           delta_parts);
+                           nshift, tmax_parts, nb, kappa, eps, src, taken, cap, pot, out_parts,
+                           nbad, delta_parts);
     FS_LAUNCHED();
     return nb;
 }
@@ -928,17 +1015,43 @@ void csum(int mode, const float *u, const double *pot, const float *v, int64_t n
 }
 
 // Envelope-gradient rows at the fast sum's error floor, recomputed directly (k_uot_grad_floor).
+// The rows are taken from the smallest sums up, whole decades at a time, within
+// FLOOR_PAIRS_GRAD pairs (the decade of the smallest sums is always taken).
 void grad_floor_rows(const float *a, const double *f, const float *t, int64_t n,
                      const double *shift, double eps, double rho, const double *mass,
-                     double scale, const FloorSrc &src, double *tparts, float *dx, float *da,
-                     hipStream_t s) {
+                     double scale, const FloorSrc &src, double *tparts, int *hist, float *dx,
+                     float *da, hipStream_t s) {
     if (n == 0 || (!dx && !da)) return;
     const int nb = upd_blocks(n);
-    hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n, tparts);
+    hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n, tparts, nullptr);
     FS_LAUNCHED();
-    hipLaunchKernelGGL(k_uot_grad_floor, dim3(nb), dim3(RT), 0, s, a, f, t, n, tparts, nb, shift,
-                       eps, rho, mass, scale, src, dx, da);
+    fill_i32(hist, FLOOR_BINS, 0, s);
+    hipLaunchKernelGGL(k_floor_hist, dim3(nb), dim3(RT), 0, s, t, n, tparts, nb, hist);
     FS_LAUNCHED();
+    int h[FLOOR_BINS];
+    FS_HIP(hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    const double cap_rows = FLOOR_PAIRS_GRAD / (double)std::max<int64_t>(src.m, 1);
+    double rel = 0.0, taken = 0.0;
+    for (int k = FLOOR_BINS - 1; k >= 0; --k) {
+        if (h[k] == 0) continue;
+        if (rel > 0.0 && taken + h[k] > cap_rows) break;
+        taken += h[k];
+        rel = (k == FLOOR_BINS - 1) ? std::pow(10.0, -(double)(FLOOR_BINS + 1))
+                                    : std::pow(10.0, -(double)(k + 2));
+    }
+    if (taken == 0.0) return;
+    // list the rows (counter in hist[0], rows after it), then one wave per row
+    DevBuf<int> list((size_t)taken + 1);
+    fill_i32(hist, 1, 0, s);
+    hipLaunchKernelGGL(k_floor_list, dim3(nb), dim3(RT), 0, s, t, n, tparts, nb, rel, hist,
+                       (int)taken, list.p);
+    FS_LAUNCHED();
+    hipLaunchKernelGGL(k_uot_grad_floor, dim3((unsigned)std::min<double>(taken, 65535.0)),
+                       dim3(64), 0, s, a, f, list.p, hist, (int)taken, shift, eps, rho, mass,
+                       scale, src, dx, da);
+    FS_LAUNCHED();
+    list.reset_after(s);
 }
 
 }  // namespace
@@ -956,6 +1069,7 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     DevBuf<double> lX(logd ? n + 1 : 0), lY(logd ? m + 1 : 0);
     // fast path, unfused half-steps: rows at the fast sum's error floor are re-evaluated directly
     DevBuf<double> tparts(op.fast ? UPD_BLOCKS : 0);
+    DevBuf<int> taken(op.fast ? 1 : 0);
     FloorSrc srcY{}, srcX{};
     if (op.fast) {
         const int r = op.kind == FS_GAUSS ? 2 : 1;
@@ -996,7 +1110,8 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             op.apply_pot(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, tX.p, 0, s);
             if (n > 0 && op.fast)
                 sc.nf = launch_update_floor(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, srcY,
-                                            tparts.p, f_o, sc.fparts.p, sc.nbad.p, fd, s);
+                                            tparts.p, taken.p, f_o, sc.fparts.p, sc.nbad.p, fd,
+                                            s);
             else if (n > 0)
                 sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
                                       sc.nbad.p, fd, s);
@@ -1023,7 +1138,8 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             op.apply_pot(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, tY.p, 1, s);
             if (m > 0 && op.fast)
                 sc.ng = launch_update_floor(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, srcX,
-                                            tparts.p, g_o, sc.gparts.p, sc.nbad.p, gd, s);
+                                            tparts.p, taken.p, g_o, sc.gparts.p, sc.nbad.p, gd,
+                                            s);
             else if (m > 0)
                 sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
                                       sc.nbad.p, gd, s);
@@ -1161,6 +1277,7 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
     DevBuf<float> ao(n + 1), bo(m + 1), w(std::max(n, m) + 1), t(std::max(n, m) + 1),
         gr((std::max(n, m) + 1) * d), ox((std::max(n, m) + 1) * d), o1(std::max(n, m) + 1);
     DevBuf<double> fo(n + 1), go(m + 1), tparts(UPD_BLOCKS);
+    DevBuf<int> fhist(FLOOR_BINS);
     const int r = op.kind == FS_GAUSS ? 2 : 1;
     op.to_op(0, a, ao.p, s);
     op.to_op(1, b, bo.p, s);
@@ -1188,7 +1305,7 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
         if (op.fast)
             grad_floor_rows(ao.p, fo.p, t.p, n, gmax, eps, rho, Mb, scale,
                             FloorSrc{op.coords(0), op.coords(1), bo.p, go.p, m, d, r, 1.0 / eps},
-                            tparts.p, dx ? ox.p : nullptr, da ? o1.p : nullptr, s);
+                            tparts.p, fhist.p, dx ? ox.p : nullptr, da ? o1.p : nullptr, s);
         if (dx) op.rows_from_op(0, ox.p, dx, s);
         if (da) op.from_op(0, o1.p, da, s);
     }
@@ -1202,7 +1319,7 @@ void uot_grad_core(Op &op, const float *a, const float *b, const double *f, cons
         if (op.fast)
             grad_floor_rows(bo.p, go.p, t.p, m, fmax, eps, rho, Ma, scale,
                             FloorSrc{op.coords(1), op.coords(0), ao.p, fo.p, n, d, r, 1.0 / eps},
-                            tparts.p, dy ? ox.p : nullptr, db ? o1.p : nullptr, s);
+                            tparts.p, fhist.p, dy ? ox.p : nullptr, db ? o1.p : nullptr, s);
         if (dy) op.rows_from_op(1, ox.p, dy, s);
         if (db) op.from_op(1, o1.p, db, s);
     }
