@@ -285,26 +285,33 @@ __device__ void floor_row_lse(const FloorSrc &src, int64_t row, double shift, in
 // sums) re-evaluated directly.  Rows go in wave-aligned runs of 64 (one per lane); the flagged
 // rows of a run are then taken one after the other by the whole wave.
 // At most `cap` rows per launch are re-evaluated (the first to claim a slot of *taken); the
-// others keep the fast sum (a bounded cost per half-step: cap x m pairs).
+// others keep the fast sum (a bounded cost per half-step: cap x m pairs).  The threshold is
+// FLOOR_REL of the largest sum of the previous half-step on the same side (tmax_prev; the first
+// half-step's own, from k_max_f32); this launch writes its own per-block maxima of t to tmax_out
+// and clears the slot counter of the next launch.
 template <bool DELTA>
 __global__ void __launch_bounds__(RT) k_update_floor(const float *__restrict__ t, int64_t n,
                                                      const double *__restrict__ shift_parts,
                                                      int nshift,
-                                                     const double *__restrict__ tmax_parts,
-                                                     int ntmax, double kappa, double eps,
-                                                     FloorSrc src, int *__restrict__ taken,
-                                                     int cap, double *__restrict__ pot,
+                                                     const double *__restrict__ tmax_prev,
+                                                     int ntmax, double *__restrict__ tmax_out,
+                                                     double kappa, double eps, FloorSrc src,
+                                                     int *__restrict__ taken,
+                                                     int *__restrict__ taken_next, int cap,
+                                                     double *__restrict__ pot,
                                                      double *__restrict__ out_parts,
                                                      int *__restrict__ nbad,
                                                      double *__restrict__ delta_parts) {
     __shared__ double red[RT / 64];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *taken_next = 0;
     double sh = -INFINITY, tm = 0.0;
     for (int b = threadIdx.x; b < nshift; b += RT) sh = fmax(sh, shift_parts[b]);
-    for (int b = threadIdx.x; b < ntmax; b += RT) tm = fmax(tm, tmax_parts[b]);
+    for (int b = threadIdx.x; b < ntmax; b += RT) tm = fmax(tm, tmax_prev[b]);
     sh = block_max(sh, red);
     if (sh == -INFINITY) sh = 0.0;
     tm = block_max(tm, red);
     const float thr = (float)(tm * (double)FLOOR_REL);
+    double tcur = 0.0;
     const int lane = threadIdx.x & 63;
     double mx = -INFINITY, dmx = 0.0;
     int bad = 0;
@@ -314,6 +321,7 @@ __global__ void __launch_bounds__(RT) k_update_floor(const float *__restrict__ t
         const int64_t i = i0 + lane;
         const bool ok = i < n;
         const float v = ok ? t[i] : 1.0f;
+        if (ok) tcur = fmax(tcur, (double)v);
         bool flag = ok && !(v >= thr && v > 0.0f);
         // claim re-evaluation slots for this run's flagged rows (one atomic per run)
         uint64_t mask = __ballot(flag);
@@ -356,6 +364,8 @@ __global__ void __launch_bounds__(RT) k_update_floor(const float *__restrict__ t
     if (bad) atomicAdd(nbad, bad);
     mx = block_max(mx, red);
     if (threadIdx.x == 0) out_parts[blockIdx.x] = mx;
+    tcur = block_max(tcur, red);
+    if (threadIdx.x == 0) tmax_out[blockIdx.x] = tcur;
     if (DELTA) {
         dmx = block_max(dmx, red);
         if (threadIdx.x == 0) delta_parts[blockIdx.x] = dmx;
@@ -940,24 +950,48 @@ int launch_update(const float *t, int64_t n, const double *shift_parts, int nshi
 constexpr double FLOOR_PAIRS_HALFSTEP = 1 << 30;
 constexpr double FLOOR_PAIRS_GRAD = 1 << 30;
 
+// Floor-row state of one side of a solve: per-block maxima of t and slot counters, both
+// alternating between two halves from one half-step of that side to the next (zero at the start).
+struct FloorState {
+    DevBuf<double> tparts;  // 2 x UPD_BLOCKS
+    DevBuf<int> taken;      // 2
+    int phase = 0;
+    bool first = true;  // the first half-step takes the largest sum of its own t
+    void init(hipStream_t s) {
+        tparts.alloc(2 * UPD_BLOCKS);
+        taken.alloc(2);
+        fill_f64(tparts.p, 2 * UPD_BLOCKS, 0.0, s);
+        fill_i32(taken.p, 2, 0, s);
+    }
+};
+
 int launch_update_floor(const float *t, int64_t n, const double *shift_parts, int nshift,
-                        double kappa, double eps, const FloorSrc &src, double *tmax_parts,
-                        int *taken, double *pot, double *out_parts, int *nbad,
-                        double *delta_parts, hipStream_t s) {
+                        double kappa, double eps, const FloorSrc &src, FloorState &fs,
+                        double *pot, double *out_parts, int *nbad, double *delta_parts,
+                        hipStream_t s) {
     ProfScope ps("update", s);
     const int nb = upd_blocks(n);
     const int cap = (int)std::min<double>(2e9, FLOOR_PAIRS_HALFSTEP / std::max<int64_t>(src.m, 1));
-    hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n, tmax_parts, taken);
-    FS_LAUNCHED();
+    const int ph = fs.phase;
+    const double *prev = fs.tparts.p + (1 - ph) * UPD_BLOCKS;
+    double *cur = fs.tparts.p + ph * UPD_BLOCKS;
+    int *tk = fs.taken.p + ph, *tk_next = fs.taken.p + (1 - ph);
+    if (fs.first) {
+        hipLaunchKernelGGL(k_max_f32, dim3(nb), dim3(RT), 0, s, t, n,
+                           fs.tparts.p + (1 - ph) * UPD_BLOCKS, nullptr);
+        FS_LAUNCHED();
+        fs.first = false;
+    }
     if (delta_parts)
         hipLaunchKernelGGL(k_update_floor<true>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts,
-                           nshift, tmax_parts, nb, kappa, eps, src, taken, cap, pot, out_parts,
-                           nbad, delta_parts);
+                           nshift, prev, UPD_BLOCKS, cur, kappa, eps, src, tk, tk_next, cap, pot,
+                           out_parts, nbad, delta_parts);
     else
         hipLaunchKernelGGL(k_update_floor<false>, dim3(nb), dim3(RT), 0, s, t, n, shift_parts,
-                           nshift, tmax_parts, nb, kappa, eps, src, taken, cap, pot, out_parts,
-                           nbad, delta_parts);
+                           nshift, prev, UPD_BLOCKS, cur, kappa, eps, src, tk, tk_next, cap, pot,
+                           out_parts, nbad, delta_parts);
     FS_LAUNCHED();
+    fs.phase = 1 - ph;
     return nb;
 }
 
@@ -1068,8 +1102,11 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     const bool logd = op.log_direct();
     DevBuf<double> lX(logd ? n + 1 : 0), lY(logd ? m + 1 : 0);
     // fast path, unfused half-steps: rows at the fast sum's error floor are re-evaluated directly
-    DevBuf<double> tparts(op.fast ? UPD_BLOCKS : 0);
-    DevBuf<int> taken(op.fast ? 1 : 0);
+    FloorState floorX, floorY;  // targets X (beta half-steps), Y (gamma half-steps)
+    if (op.fast) {
+        floorX.init(s);
+        floorY.init(s);
+    }
     FloorSrc srcY{}, srcX{};
     if (op.fast) {
         const int r = op.kind == FS_GAUSS ? 2 : 1;
@@ -1110,8 +1147,7 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             op.apply_pot(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, tX.p, 0, s);
             if (n > 0 && op.fast)
                 sc.nf = launch_update_floor(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, srcY,
-                                            tparts.p, taken.p, f_o, sc.fparts.p, sc.nbad.p, fd,
-                                            s);
+                                            floorX, f_o, sc.fparts.p, sc.nbad.p, fd, s);
             else if (n > 0)
                 sc.nf = launch_update(tX.p, n, sc.gparts.p, sc.ng, kappa, eps, f_o, sc.fparts.p,
                                       sc.nbad.p, fd, s);
@@ -1138,8 +1174,7 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             op.apply_pot(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, tY.p, 1, s);
             if (m > 0 && op.fast)
                 sc.ng = launch_update_floor(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, srcX,
-                                            tparts.p, taken.p, g_o, sc.gparts.p, sc.nbad.p, gd,
-                                            s);
+                                            floorY, g_o, sc.gparts.p, sc.nbad.p, gd, s);
             else if (m > 0)
                 sc.ng = launch_update(tY.p, m, sc.fparts.p, sc.nf, kappa, eps, g_o, sc.gparts.p,
                                       sc.nbad.p, gd, s);
