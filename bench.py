@@ -407,10 +407,10 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP16_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP16_MFMA_TFLOPS,
                 "traffic": traffic,
-                "kernel": "k_spread_mfma16 (spreading, adjoint NFFT, FP16 matrix cores with "
-                          "hi/lo split operands)",
-                "work_per_launch": "%d nodes x 2 x %d^%d flops (window products at FP32 accuracy; "
-                                   "four FP16 split products each, so frac <= 0.25)" % (n, W, d),
+                "kernel": "k_spread_mom16 (spreading, adjoint NFFT, Chebyshev moments of the "
+                          "(y, z) window on the FP16 matrix cores with hi/lo split operands)",
+                "work_per_launch": "%d nodes x 2 x %d^%d flops (the window products at FP32 "
+                                   "accuracy that the kernel's result equals)" % (n, W, d),
                 "timed_launches": sp_cnt}
     window_terms = n * float(W ** d)
     hbm = {}

@@ -79,6 +79,7 @@ struct Plan {
     DevBuf<float> grid;  // G^d real
     DevBuf<float2> specA, specB;
     DevBuf<float2> twiddle;  // exp(-2 pi i q / G), q < G/2
+    DevBuf<uint4> mom_cc;    // 3-D moment-form spread: Chebyshev transform operands
     DevBuf<float> wpoly;     // window segments as polynomials: value (W x WPOLY) then derivative
     DevBuf<float> scratch;   // per-chunk spread boxes
     DevBuf<float4> nf_src;   // near-field source records (cell order) for the current weights

@@ -717,7 +717,14 @@ struct SpreadArgs {
     KB kb;
     int G, T, ntd, m;
     const float *wp;  // window polynomials: value (W x WPOLY) then derivative (W x WPOLY)
+    // 3-D moment form: the transform from the WPOLY^2 Chebyshev moments of the (y, z) window
+    // factor to the W x W window products, CC[(y, z)][q] x 2^MOM_CC_SHIFT, as matrix-core A
+    // operands (FP16 hi and lo parts in separate operands, two K steps per operand)
+    const uint4 *cc;
 };
+// CC is stored times 2^15: with the moments scaled to at most 2^15 in magnitude (fixed-point
+// scale 2^30 / count, weights at most 1) both operands stay in FP16 range while |CC| < 2
+constexpr int MOM_CC_SHIFT = 15;
 
 template <int D>
 __device__ __forceinline__ void tile_coords(int tile, int ntd, int *t) {
@@ -1499,60 +1506,116 @@ __device__ __forceinline__ void split_f16(float a, float b, f16x2 &hi, f16x2 &lo
     lo = __builtin_convertvector(f32x2{a - back.x, b - back.y}, f16x2);
 }
 
-// 3-D spreading on the FP16 matrix cores with split operands, the transpose of the gather
-// below.  For the nodes of one brick, with alpha the weights (divided by the chunk's largest
-// |weight|) and px, py, pz the window values,
-//   H[x][(y, z)] += sum_n (alpha_n px_n[x - ox_n]) (py_n[y] pz_n[z]),
-// a 16 x (W x W) product over the group's 16 nodes.  Both factors are carried as FP16 pairs
-// (hi + lo) and two v_mfma_f32_16x16x32_f16 per 4 x 4 block of (y, z) sum the four cross products
-// in FP32: lane l covers nodes 4 (l / 16) .. + 3, its K elements being (hi, hi) and then (lo, lo)
-// of alpha px for box column l % 16 against (hi, lo) of py pz at column l % 16 of the block.
-// Lane l holds the sums for columns 4 (l / 16) + r, r < 4; they stay in registers while the brick
-// stays the same and then go to the chunk's LDS box with integer atomics (fixed point, see
-// chunk_scale).  With POT the weights are w_k = base_k exp((pot_k - pmax) / eps), evaluated here
-// (weight_exp: FP64 exponent, FP32 result) instead of read from w.
+// 3-D spreading on the matrix cores in moment form.  Each window segment is a degree-(WPOLY-1)
+// polynomial in u = 2t - 1 (t the node's offset inside its cell); in the Chebyshev basis,
+// phi_n[y] = sum_k C[y][k] T_k(u_n), so the (y, z) factor of a node's window is C (x) C applied to
+// the WPOLY^2 products Ty_n[k] Tz_n[l].  The nodes of one brick (BRICK_X cells along x with the
+// same y and z cell) share that transform, so the kernel accumulates their moments
+//   M[(k, l)][x] += sum_n Ty_n[k] Tz_n[l] (alpha_n px_n[x - ox_n])      (per group: 64 x 16)
+// (alpha the weights divided by the block's largest |weight|, px the x window, ox the node's
+// cell inside the brick) and, when the brick changes, adds
+//   H[(y, z)][x] = sum_(k,l) C[y][k] C[z][l] M[(k, l)][x]
+// to the block's LDS box as int32 fixed point (scale 2^30 / (count max|w|)).  Both products run on
+// v_mfma_f32_16x16x32_f16 with every FP32 factor carried as a pair of FP16 numbers, v = hi + lo
+// (hi = v rounded to FP16, lo = the remainder rounded to FP16, about 22 significant bits together):
+// per group, lane l holds nodes 4 (l / 16) .. + 3 as K elements, (hi, lo) of the moment products
+// for row q = 16 j + l % 16 against (hi, hi) and then (lo, lo) of alpha px at column x = l % 16
+// (two products per block j of 16 moment rows).  The accumulator layout of M (row
+// 16 j + 4 (l / 16) + r, column l % 16) is the B-operand layout of the second product, so the
+// moments never leave the registers; its constant operand (sa.cc, copied to LDS) holds hi and lo
+// of C[y][k] C[z][l] for two K steps each, and three products per pair of steps sum hi hi, lo hi
+// and hi lo.  A group thus costs 64 instead of W^2 window products and splits on the VALU, and only
+// the x window is evaluated per node.
 template <int W, bool POT>
 __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(4, 4)))
-k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
-                const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups, SpreadArgs sa,
-                float *__restrict__ scratch, PotWeights pw) {
+k_spread_mom16(const float4 *__restrict__ rec, const float *__restrict__ w,
+               const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups, SpreadArgs sa,
+               float *__restrict__ scratch, PotWeights pw) {
     constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
     constexpr int NZ = (W + 3) / 4;      // (y, z) offsets in blocks of 4
     constexpr int NB = NZ * NZ;          // 4 x 4 blocks of (y, z)
     constexpr int XR = W + BRICK_X - 1;  // box columns a brick reaches
     constexpr int PX = W + 1;            // row stride of the x table (odd: no bank conflicts)
+    constexpr int PD = WPOLY;            // Chebyshev terms per axis
+    constexpr int NJ = PD * PD / 16;     // moment row blocks
+    constexpr int NP = NJ / 2;           // K-step pairs of the transform
+    constexpr int NCC = NB * NP * 2 * 64;                 // transform operands
+    constexpr int CPT = (NCC + 64 * MW - 1) / (64 * MW);  // of them per thread
     static_assert(XR <= 16, "brick and window exceed the 16 matrix rows");
+    static_assert(PD == 8, "moment layout assumes 8 Chebyshev terms");
     __shared__ int box[BOX];
-    __shared__ float phx[MW][16 * PX];     // per wave: alpha px, node-major
-    __shared__ float phyz[MW][2][W][16];   // per wave: py and pz, offset-major
-    __shared__ int oxs[MW][16];
-    __shared__ float red[16];
-    __shared__ double pmx[MW];
+    __shared__ uint4 cct[NCC];               // copy of sa.cc
+    __shared__ float phx[MW][16 * PX];       // per wave: alpha px, node-major
+    __shared__ float4 tyz[MW][2][16][2];     // per wave, axis, node: T_0,2,4,6 then T_1,3,5,7
+    __shared__ int4 oxs[MW][4];              // per wave: x cell offsets of the 16 nodes
+    __shared__ double red2[2][MW];
     const int4 mb = mblocks[blockIdx.x];
-    for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
     const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
-    double pmax = 0.0;
-    if (POT) {
-        double mx = -INFINITY;
-        for (int b = threadIdx.x; b < pw.nparts; b += blockDim.x) mx = fmax(mx, pw.parts[b]);
-        mx = block_max_f64(mx, pmx);
-        pmax = (mx == -INFINITY) ? 0.0 : mx;
+    uint4 ccv[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        const int q = threadIdx.x + i * 64 * MW;
+        if (q < NCC) ccv[i] = sa.cc[q];
     }
-    auto weight = [&](int k) -> float {
-        if (POT) return weight_exp(pw.base[k], (pw.pot[k] - pmax) * pw.inv_eps);
-        return w[k];
-    };
-    // chunk_scale = 2^30 / (cnt max|w|): the weights enter the products as w / max|w| and the
-    // sums are converted with 2^30 / cnt
+    for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
+    // the block's largest |weight| in one pass: with potentials, w_k = base_k
+    // exp((pot_k - pmax) / eps), so max_k |w_k| = exp(max_k (log |base_k| + pot_k / eps) -
+    // pmax / eps), and the largest potential pmax is reduced alongside
+    double m0 = -INFINITY, m1 = -INFINITY;
+    // (node data read in batches of 8 per thread, all in flight before the first use)
+    constexpr int PB = 8;
+    if (POT)
+        for (int b = threadIdx.x; b < pw.nparts; b += blockDim.x) m0 = fmax(m0, pw.parts[b]);
+    for (int q0 = k0 + threadIdx.x; q0 < k0 + cnt; q0 += PB * 64 * MW) {
+        double pv[PB];
+        float bv[PB];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int q = q0 + i * 64 * MW;
+            const bool in = q < k0 + cnt;
+            if (POT) {
+                pv[i] = in ? pw.pot[q] : -INFINITY;
+                bv[i] = in ? pw.base[q] : 1.0f;
+            } else {
+                bv[i] = in ? w[q] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i)
+            m1 = POT ? fmax(m1, pv[i] * pw.inv_eps + (double)logf(fabsf(bv[i])))
+                     : fmax(m1, (double)fabsf(bv[i]));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        m0 = fmax(m0, __shfl_xor(m0, o, 64));
+        m1 = fmax(m1, __shfl_xor(m1, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red2[0][threadIdx.x >> 6] = m0;
+        red2[1][threadIdx.x >> 6] = m1;
+    }
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        const int q = threadIdx.x + i * 64 * MW;
+        if (q < NCC) cct[q] = ccv[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+        m0 = fmax(m0, red2[0][i]);
+        m1 = fmax(m1, red2[1][i]);
+    }
+    const double pmax = (m0 == -INFINITY) ? 0.0 : m0;
     float wm = 0.0f;
-    const float scale = chunk_scale_fn(weight, k0, cnt, red, &wm);
+    if (POT) wm = (m1 == -INFINITY) ? 0.0f : weight_exp(1.0f, m1 - pmax * pw.inv_eps);
+    else wm = (m1 > 0.0) ? (float)m1 : 0.0f;
+    const float scale = (wm > 0.0f && cnt > 0) ? 1073741824.0f / ((float)cnt * wm) : 1.0f;
     const float wmax = (wm > 0.0f) ? wm : 1.0f;
-    const float inv_wmax = 1.0f / wmax, fscale = scale * wmax;
+    const float inv_wmax = 1.0f / wmax;
+    const float mscale = scale * wmax * (1.0f / (float)(1 << MOM_CC_SHIFT));
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = lane & 15, slot = lane >> 4;
-    const int iy = col >> 2, iz = col & 3;
     float wc[NZ][WPOLY];
 #pragma unroll
     for (int e = 0; e < NZ; ++e) {
@@ -1561,90 +1624,152 @@ k_spread_mfma16(const float4 *__restrict__ rec, const float *__restrict__ w,
         for (int k = 0; k < WPOLY; ++k) wc[e][k] = (a < W) ? sa.wp[a * WPOLY + k] : 0.0f;
     }
     float *px = phx[wave];
-    float(*pyz)[W][16] = phyz[wave];
-    int *ox = oxs[wave];
+    float4(*tt)[16][2] = tyz[wave];
+    int *ox = reinterpret_cast<int *>(oxs[wave]);
     const int per = (mb.z + MW - 1) / MW;
     const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
-    f32x4 acc[NB];
+    f32x4 acc[NJ];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < NJ; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     int cur = -1;
     auto flush = [&]() {
+        // moments times fscale 2^-MOM_CC_SHIFT, at most 2^15 in magnitude, as B operands: K
+        // elements of steps 2 sp and 2 sp + 1 side by side, hi and lo parts apart (the lo x lo
+        // product is dropped: it is below the split's own rounding)
+        f16x8 Bh[NP], Bl[NP];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int y = 4 * (j / NZ) + iy, z = 4 * (j % NZ) + iz;
-            if (W % 4 == 0 || (y < W && z < W)) {
-                const int b0 = cur + y * S + z * S * S;
+        for (int sp = 0; sp < NP; ++sp) {
+            f16x2 h0, l0, h1, l1, h2, l2, h3, l3;
+            split_f16(acc[2 * sp][0] * mscale, acc[2 * sp][1] * mscale, h0, l0);
+            split_f16(acc[2 * sp][2] * mscale, acc[2 * sp][3] * mscale, h1, l1);
+            split_f16(acc[2 * sp + 1][0] * mscale, acc[2 * sp + 1][1] * mscale, h2, l2);
+            split_f16(acc[2 * sp + 1][2] * mscale, acc[2 * sp + 1][3] * mscale, h3, l3);
+            Bh[sp] = f16x8{h0[0], h0[1], h1[0], h1[1], h2[0], h2[1], h3[0], h3[1]};
+            Bl[sp] = f16x8{l0[0], l0[1], l1[0], l1[1], l2[0], l2[1], l3[0], l3[1]};
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        const int x = col;
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            f32x4 h = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int sp = 0; sp < NP; ++sp) {
+                const f16x8 Ah = __builtin_bit_cast(f16x8, cct[((jb * NP + sp) * 2 + 0) * 64 + lane]);
+                const f16x8 Al = __builtin_bit_cast(f16x8, cct[((jb * NP + sp) * 2 + 1) * 64 + lane]);
+                h = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Bh[sp], h, 0, 0, 0);
+                h = __builtin_amdgcn_mfma_f32_16x16x32_f16(Al, Bh[sp], h, 0, 0, 0);
+                h = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Bl[sp], h, 0, 0, 0);
+            }
+            // h[r] = H[(y, z)][x] with y = 4 (jb / NZ) + slot, z = 4 (jb % NZ) + r
+            const int y = 4 * (jb / NZ) + slot;
+            if (x < XR && (W % 4 == 0 || y < W)) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int x = 4 * slot + r;
-                    if (x < XR) atomicAdd(&box[b0 + x], __float2int_rn(acc[j][r] * fscale));
+                    const int z = 4 * (jb % NZ) + r;
+                    if (W % 4 == 0 || z < W)
+                        atomicAdd(&box[cur + y * S + z * S * S + x], __float2int_rn(h[r]));
                 }
             }
-            acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     };
-    for (int g = gb; g < ge; ++g) {
-        const int4 gr = mgroups[g];
-        const int nn = min(col, gr.y - 1);
-        const float4 r = rec[gr.x + nn];
-        const float alpha = (col < gr.y) ? weight(gr.x + nn) * inv_wmax : 0.0f;
-        // window values of node `col` at offsets slot + 4 e
-        const float fr[3] = {r.x, r.y, r.z};
+    // software pipeline: while group g is processed, the node data of g + 1 and the group
+    // record of g + 2 are in flight (the chain group record -> node record -> weight inputs
+    // would otherwise stall every group)
+    const int4 gnone = int4{0, 1, -1, 0};
+    int4 g1 = (gb < ge) ? mgroups[gb] : gnone;
+    int4 g2 = (gb + 1 < ge) ? mgroups[gb + 1] : gnone;
+    float4 r1 = float4{0.0f, 0.0f, 0.0f, 0.0f};
+    float b1 = 0.0f;
+    double p1 = 0.0;
+    auto fetch = [&](const int4 &q) {
+        const int kk = q.x + min(col, q.y - 1);
+        r1 = rec[kk];
+        if (POT) {
+            b1 = pw.base[kk];
+            p1 = pw.pot[kk];
+        } else {
+            b1 = w[kk];
+        }
+    };
+    if (gb < ge) fetch(g1);
+    for (int g = gb;; ++g) {
+        // one flush site: the pass after the last group flushes the last brick
+        const int gz = (g < ge) ? g1.z : -1;
+        if (gz != cur) {
+            if (cur >= 0) flush();
+            cur = gz;
+        }
+        if (g >= ge) break;
+        const int4 gr = g1;
+        const float4 r = r1;
+        const float wv = POT ? weight_exp(b1, (p1 - pmax) * pw.inv_eps) : b1;
+        g1 = g2;
+        if (g + 1 < ge) fetch(g1);
+        g2 = (g + 2 < ge) ? mgroups[g + 2] : gnone;
+        const float alpha = (col < gr.y) ? wv * inv_wmax : 0.0f;
+        // x window values of node `col` at offsets slot + 4 e
 #pragma unroll
         for (int e = 0; e < NZ; ++e) {
             const int a = slot + 4 * e;
-            if (W % 4 == 0 || a < W) {
-                px[col * PX + a] = alpha * wpoly_eval(wc[e], 2.0f * fr[0] - 1.0f);
-                pyz[0][a][col] = wpoly_eval(wc[e], 2.0f * fr[1] - 1.0f);
-                pyz[1][a][col] = wpoly_eval(wc[e], 2.0f * fr[2] - 1.0f);
-            }
+            if (W % 4 == 0 || a < W) px[col * PX + a] = alpha * wpoly_eval(wc[e], 2.0f * r.x - 1.0f);
+        }
+        // Chebyshev values T_k(u) of the offsets: slots 0, 1 take y and slots 2, 3 take z; the
+        // slot's parity picks the even or the odd degrees
+        {
+            const int axis = slot >> 1;
+            const float u = 2.0f * (axis ? r.z : r.y) - 1.0f;
+            float t[PD];
+            t[0] = 1.0f;
+            t[1] = u;
+#pragma unroll
+            for (int q = 2; q < PD; ++q) t[q] = fmaf(2.0f * u, t[q - 1], -t[q - 2]);
+            tt[axis][col][slot & 1] = (slot & 1) ? float4{t[1], t[3], t[5], t[7]}
+                                                 : float4{t[0], t[2], t[4], t[6]};
         }
         if (slot == 0) ox[col] = __float_as_int(r.w) % S - gr.z % S;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (gr.z != cur) {
-            if (cur >= 0) flush();
-            cur = gr.z;
-        }
-        // operand A: alpha px of nodes 4 slot .. + 3 at box column `col`, (hi, lo)
+        // operand B: alpha px of nodes 4 slot .. + 3 at box column `col`, (hi, lo) repeated
+        const int4 o4 = oxs[wave][slot];
+        const int oxn[4] = {o4.x, o4.y, o4.z, o4.w};
         float av[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int n = 4 * slot + e;
-            const int a = col - ox[n];
+            const int a = col - oxn[e];
             av[e] = (a >= 0 && a < W) ? px[n * PX + (a < 0 ? 0 : (a >= W ? W - 1 : a))] : 0.0f;
         }
         f16x2 ah0, al0, ah1, al1;
         split_f16(av[0], av[1], ah0, al0);
         split_f16(av[2], av[3], ah1, al1);
-        const f16x8 A1 = {ah0[0], ah0[1], ah1[0], ah1[1], ah0[0], ah0[1], ah1[0], ah1[1]};
-        const f16x8 A2 = {al0[0], al0[1], al1[0], al1[1], al0[0], al0[1], al1[0], al1[1]};
-        float py[NZ][4], pz[NZ][4];
+        const f16x8 P1 = {ah0[0], ah0[1], ah1[0], ah1[1], ah0[0], ah0[1], ah1[0], ah1[1]};
+        const f16x8 P2 = {al0[0], al0[1], al1[0], al1[1], al0[0], al0[1], al1[0], al1[1]};
+        // operand A per moment block j: Ty[k] Tz[l] of nodes 4 slot .. + 3 for moment row
+        // q = 16 j + col (k = q / 8 = 2 j + col / 8, l = col % 8), (hi, lo)
+        const int kc = col >> 3, l = col & 7;
+        f32x4 tyv[4];
+        float tzv[4];
 #pragma unroll
-        for (int j = 0; j < NZ; ++j)
+        for (int e = 0; e < 4; ++e) {
+            const float4 yv = tt[0][4 * slot + e][kc];
+            tyv[e] = f32x4{yv.x, yv.y, yv.z, yv.w};
+            tzv[e] = reinterpret_cast<const float *>(tt[1][4 * slot + e])[(l & 1) * 4 + (l >> 1)];
+        }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int n = 4 * slot + e;
-                py[j][e] = (W % 4 == 0 || 4 * j + iy < W) ? pyz[0][4 * j + iy][n] : 0.0f;
-                pz[j][e] = (W % 4 == 0 || 4 * j + iz < W) ? pyz[1][4 * j + iz][n] : 0.0f;
-            }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int jy = j / NZ, jz = j % NZ;
+        for (int j = 0; j < NJ; ++j) {
             f16x2 bh0, bl0, bh1, bl1;
-            split_f16(py[jy][0] * pz[jz][0], py[jy][1] * pz[jz][1], bh0, bl0);
-            split_f16(py[jy][2] * pz[jz][2], py[jy][3] * pz[jz][3], bh1, bl1);
-            const f16x8 B = {bh0[0], bh0[1], bh1[0], bh1[1], bl0[0], bl0[1], bl1[0], bl1[1]};
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A1, B, acc[j], 0, 0, 0);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A2, B, acc[j], 0, 0, 0);
+            split_f16(tyv[0][j] * tzv[0], tyv[1][j] * tzv[1], bh0, bl0);
+            split_f16(tyv[2][j] * tzv[2], tyv[3][j] * tzv[3], bh1, bl1);
+            const f16x8 A = {bh0[0], bh0[1], bh1[0], bh1[1], bl0[0], bl0[1], bl1[0], bl1[1]};
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, P1, acc[j], 0, 0, 0);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, P2, acc[j], 0, 0, 0);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (cur >= 0) flush();
     __syncthreads();
     const float inv = 1.0f / scale;
     float *dst = scratch + (int64_t)blockIdx.x * BOX;
@@ -2461,7 +2586,7 @@ template <int W>
 int mfma_blocks_per_cu() {
     int a = 0, b = 0;
     FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_gather_mfma16<W, true>, 64 * MW, 0));
-    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mfma16<W, true>, 64 * MW, 0));
+    FS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_spread_mom16<W, true>, 64 * MW, 0));
     return std::max(1, std::min(a, b));
 }
 template <int W, int T>
@@ -2988,16 +3113,62 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     {
         // window value phi(t + m - 1 - a) and derivative d phi/ds on t in [0, 1), u = 2t - 1
         std::vector<float> hp(2 * pp.W * WPOLY);
+        std::vector<double> cheb(pp.W * WPOLY);
         double c[WPOLY];
         for (int a = 0; a < pp.W; ++a) {
             const double off = pp.m - 1 - a;
             fit_poly([&](double u) { return kb_value(pp.m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
             for (int k = 0; k < WPOLY; ++k) hp[a * WPOLY + k] = (float)c[k];
+            // the same polynomial in the Chebyshev basis (exact: interpolation at WPOLY nodes)
+            for (int k = 0; k < WPOLY; ++k) {
+                double acc = 0.0;
+                for (int j = 0; j < WPOLY; ++j) {
+                    const double th = M_PI * (j + 0.5) / WPOLY, u = std::cos(th);
+                    double v = c[WPOLY - 1];
+                    for (int q = WPOLY - 2; q >= 0; --q) v = v * u + c[q];
+                    acc += v * std::cos(k * th);
+                }
+                cheb[a * WPOLY + k] = acc * (k == 0 ? 1.0 : 2.0) / WPOLY;
+            }
             fit_poly([&](double u) { return kb_deriv(pp.m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
             for (int k = 0; k < WPOLY; ++k) hp[(pp.W + a) * WPOLY + k] = (float)c[k];
         }
         pl.wpoly.alloc(hp.size());
         hs.upload(pl.wpoly.p, hp.data(), hp.size() * sizeof(float));
+        if (d == 3 && pp.W + BRICK_X - 1 <= 16) {
+            // transform of the moment-form spread, CC[(y, z)][q = 8 k + l] = C[y][k] C[z][l] x
+            // 2^MOM_CC_SHIFT, as A operands: per (yz block jb, K-step pair sp, part hi / lo,
+            // lane), row (y, z) from lane % 16, K elements q = 16 (2 sp) + 4 (lane / 16) + i
+            // then q = 16 (2 sp + 1) + 4 (lane / 16) + i, i < 4
+            const int NZ = (pp.W + 3) / 4, NB = NZ * NZ, NP = WPOLY * WPOLY / 32;
+            std::vector<uint16_t> cc((size_t)NB * NP * 2 * 64 * 8);
+            const double up = std::ldexp(1.0, MOM_CC_SHIFT);
+            double amax = 0.0;
+            for (int jb = 0; jb < NB; ++jb)
+                for (int sp = 0; sp < NP; ++sp)
+                    for (int ln = 0; ln < 64; ++ln) {
+                        const int col = ln & 15, grp = ln >> 4;
+                        const int y = 4 * (jb / NZ) + (col >> 2), z = 4 * (jb % NZ) + (col & 3);
+                        uint16_t *hi = cc.data() + ((size_t)((jb * NP + sp) * 2 + 0) * 64 + ln) * 8;
+                        uint16_t *lo = cc.data() + ((size_t)((jb * NP + sp) * 2 + 1) * 64 + ln) * 8;
+                        for (int t = 0; t < 8; ++t) {
+                            const int q = 16 * (2 * sp + t / 4) + 4 * grp + t % 4;
+                            const int k = q / WPOLY, l = q % WPOLY;
+                            const double v = (y < pp.W && z < pp.W)
+                                                 ? cheb[y * WPOLY + k] * cheb[z * WPOLY + l] * up
+                                                 : 0.0;
+                            amax = std::max(amax, std::fabs(v));
+                            const _Float16 h = (_Float16)(float)v;
+                            const _Float16 r = (_Float16)(float)(v - (double)(float)h);
+                            hi[t] = __builtin_bit_cast(uint16_t, h);
+                            lo[t] = __builtin_bit_cast(uint16_t, r);
+                        }
+                    }
+            FS_REQUIRE(amax < 65504.0, FS_EUNSUPPORTED,
+                       "window transform %g outside the FP16 range (window %d)", amax, pp.W);
+            pl.mom_cc.alloc(cc.size() / 8);
+            hs.upload(pl.mom_cc.p, cc.data(), cc.size() * sizeof(uint16_t));
+        }
     }
 
     // ---- bin the point sets (A2)
@@ -3182,7 +3353,7 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                           float *t, float *grad, hipStream_t s, const PotWeights *pw = nullptr,
                           const PotUpdate *pu = nullptr) {
     const PlanParams &pp = pl.pp;
-    SpreadArgs sa{pp.kb, pp.G, pp.T, pp.G / pp.T, pp.m, pl.wpoly.p};
+    SpreadArgs sa{pp.kb, pp.G, pp.T, pp.G / pp.T, pp.m, pl.wpoly.p, pl.mom_cc.p};
     // the tile side shrinks to the grid size for small grids
     auto run = [&](auto tconst) {
         constexpr int T = decltype(tconst)::value;
@@ -3212,11 +3383,11 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                     }
                     if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                         if (pw)
-                            hipLaunchKernelGGL((k_spread_mfma16<W, true>), dim3(src.n_mblocks),
+                            hipLaunchKernelGGL((k_spread_mom16<W, true>), dim3(src.n_mblocks),
                                                dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
                                                src.mgroups.p, sa, pl.scratch.p, *pw);
                         else
-                            hipLaunchKernelGGL((k_spread_mfma16<W, false>), dim3(src.n_mblocks),
+                            hipLaunchKernelGGL((k_spread_mom16<W, false>), dim3(src.n_mblocks),
                                                dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
                                                src.mgroups.p, sa, pl.scratch.p, PotWeights{});
                     }
