@@ -28,6 +28,7 @@ struct Nodes {
     // along x (same y and z cell); groups (first node, count, brick offset in the tile's box, 0)
     // and blocks of groups inside one tile (tile, first group, group count, 0)
     DevBuf<int4> mgroups, mblocks;
+    DevBuf<int2> mbnodes;  // per block: first node, node count
     int n_mgroups = 0, n_mblocks = 0;
     DevBuf<int> mtile_block;   // per tile: [first block, block count]
     DevBuf<int> mmulti_tiles;  // tiles holding more than one block

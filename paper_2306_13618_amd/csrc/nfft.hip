@@ -574,6 +574,17 @@ __global__ void k_fill_chunks(int ntiles, const int *__restrict__ tile_start,
     for (int c = 0; c < nc; ++c) chunks[c0 + c] = make_int4(t, s + c * chunk, min(chunk, cnt - c * chunk), 0);
 }
 
+// First node and node count of every block of groups (read by the spread without the
+// dependent load of the group records).
+__global__ void k_block_nodes(const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups,
+                              int nblocks, int2 *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    const int4 mb = mblocks[b];
+    const int4 g0 = mgroups[mb.y], gl = mgroups[mb.y + mb.z - 1];
+    out[b] = make_int2(g0.x, gl.x + gl.y - g0.x);
+}
+
 // Matrix-core groups (d = 3, nodes ordered by tile and cell, x fastest): a brick is BRICK_X
 // consecutive cell keys (cells along x with the same y and z), so its nodes are contiguous; each
 // brick is cut into groups of up to 16 nodes.
@@ -1133,9 +1144,7 @@ struct FftArgs {
     int nbx;  // columns per block in the strided passes
 };
 
-// First axis, forward: two real rows as one complex row.  PM: the spectrum is stored plane-major,
-// specA[kx][row], instead of specA[row][kx] (the layout of the fused y-z pass).
-template <bool PM>
+// First axis, forward: two real rows as one complex row (spectrum specA[row][kx]).
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_r2c(const float *__restrict__ grid,
                                                             int rows, FftArgs fa,
                                                             const float2 *__restrict__ tw,
@@ -1158,25 +1167,18 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_r2c(const float *__restri
     __syncthreads();
     float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, NB, tw);
     for (int q = threadIdx.x; q < NB * fa.KX; q += blockDim.x) {
-        // plane-major: consecutive threads take consecutive row pairs of one kx
-        const int t = PM ? q % NB : q / fa.KX, k = PM ? q / NB : q - t * fa.KX;
+        const int t = q / fa.KX, k = q - t * fa.KX;
         if (t >= nb) continue;
         const float2 z = res[t * G + k], zm = res[t * G + ((G - k) & (G - 1))];
         const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
         const float2 B = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
         const int64_t r0 = (int64_t)(p0 + t) * 2;
-        if (PM) {
-            *reinterpret_cast<float4 *>(specA + (int64_t)k * rows + r0) =
-                make_float4(A.x, A.y, B.x, B.y);
-        } else {
-            specA[r0 * fa.KX + k] = A;
-            specA[(r0 + 1) * fa.KX + k] = B;
-        }
+        specA[r0 * fa.KX + k] = A;
+        specA[(r0 + 1) * fa.KX + k] = B;
     }
 }
 
-// First axis, inverse (PM: plane-major spectrum, as in k_fft_x_r2c).
-template <bool PM>
+// First axis, inverse.
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restrict__ specA,
                                                             int rows, FftArgs fa,
                                                             const float2 *__restrict__ tw,
@@ -1193,27 +1195,11 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restr
         if (t < nb) {
             const int64_t r0 = (int64_t)(p0 + t) * 2;
             if (k <= h) {
-                float2 A, B;
-                if (PM) {
-                    const float4 ab = *reinterpret_cast<const float4 *>(specA + (int64_t)k * rows + r0);
-                    A = make_float2(ab.x, ab.y);
-                    B = make_float2(ab.z, ab.w);
-                } else {
-                    A = specA[r0 * fa.KX + k];
-                    B = specA[(r0 + 1) * fa.KX + k];
-                }
+                const float2 A = specA[r0 * fa.KX + k], B = specA[(r0 + 1) * fa.KX + k];
                 z = make_float2(A.x - B.y, A.y + B.x);
             } else if (k >= G - h) {
                 const int kk = G - k;
-                float2 A, B;
-                if (PM) {
-                    const float4 ab = *reinterpret_cast<const float4 *>(specA + (int64_t)kk * rows + r0);
-                    A = make_float2(ab.x, ab.y);
-                    B = make_float2(ab.z, ab.w);
-                } else {
-                    A = specA[r0 * fa.KX + kk];
-                    B = specA[(r0 + 1) * fa.KX + kk];
-                }
+                float2 A = specA[r0 * fa.KX + kk], B = specA[(r0 + 1) * fa.KX + kk];
                 A.y = -A.y;
                 B.y = -B.y;
                 z = make_float2(A.x - B.y, A.y + B.x);
@@ -1352,49 +1338,163 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_z_conv(float2 *__restrict__
     }
 }
 
-// 3-D, G = 64: the three strided passes (forward along y, forward + multiply + inverse along z,
-// inverse along y) for one kx per workgroup, with the whole y-z plane (64 x 64) in LDS.  Same
-// transforms and multiply as k_fft_y<0>, k_fft_z_conv and k_fft_y<2>, in place in the
-// plane-major spectrum specA[kx][z][y] (one contiguous 32 KB plane per workgroup).
-__global__ void __launch_bounds__(512) k_fft_yz_conv64(float2 *__restrict__ specA, FftArgs fa,
+// 3-D, G = 64, in z slabs, so that every pass runs on 64 or more workgroups (the x passes, the y
+// passes and the z convolution of the general path, k_fft_x_r2c, k_fft_y, k_fft_z_conv and
+// k_fft_x_c2r, in three launches).  The band spectrum is kept as S[z][ky + h][kx] (|ky| <= h =
+// N / 2, 0 <= kx <= h; N + 1 rows of N / 2 + 1; N < G, so that h + 1 <= 32 columns fit the LDS
+// tables).
+//   k_fft_xy_fwd64: one z slab per workgroup, forward along x (row pairs as complex rows) and
+//                   then along y, the band stored to S;
+//   k_fft_z_conv64: FFT_ZCOLS (ky, kx) columns per workgroup, forward along z, times M_k (zero
+//                   outside |kz| <= h), inverse along z, in place in S;
+//   k_fft_xy_inv64: one z slab per workgroup, inverse along y (zeros outside the band), then the
+//                   real rows along x back to the grid.
+// Every load of a workgroup is issued before its first store to LDS: the passes are short enough
+// that one memory round trip per step would dominate them.
+constexpr int FFT_ZCOLS = 8;
+constexpr int FFT_ST = 64 + 7;  // padded LDS rows (few bank conflicts in the radix-8 passes)
+
+__global__ void __launch_bounds__(256) k_fft_xy_fwd64(const float *__restrict__ grid, FftArgs fa,
                                                       const float2 *__restrict__ tw,
-                                                      const float *__restrict__ M) {
-    constexpr int G = 64, ST = G + 7;  // padded rows: few LDS bank conflicts in the FFT and transposes
-    __shared__ float2 pa[G * ST], pb[G * ST], twl[G / 2];
-    __shared__ float ml[(G / 2) * (G / 2)];  // multiplier of this kx: [akz][aky], h + 1 <= G / 2
-    const int h = fa.N / 2, NB1 = fa.N + 1, H = h + 1;
-    const int kx = blockIdx.x;
-    float2 *plane = specA + (int64_t)kx * G * G;  // plane-major spectrum: [kx][z][y]
-    // plane [z][y]; twiddles and this kx's multipliers to LDS
-    for (int q = threadIdx.x; q < G * G; q += blockDim.x) pa[(q / G) * ST + q % G] = plane[q];
-    if (threadIdx.x < G / 2) twl[threadIdx.x] = tw[threadIdx.x];
-    for (int q = threadIdx.x; q < H * H; q += blockDim.x) ml[q] = M[(int64_t)q * H + kx];
+                                                      float2 *__restrict__ S) {
+    constexpr int G = 64, ST = FFT_ST;
+    __shared__ float2 a[(G / 2) * ST], b[(G / 2) * ST], twl[G / 2];
+    const int h = fa.N / 2, KX = fa.KX, NB1 = fa.N + 1;
+    const int z = blockIdx.x;
+    const float *slab = grid + (int64_t)z * G * G;  // [y][x]
+    // rows 2t and 2t + 1 as the real and imaginary parts of complex row t (all loads in flight
+    // before the first store to LDS)
+    constexpr int NT = 256, PT = (G / 2) * G / NT;
+    float2 v[PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int q = threadIdx.x + i * NT, t = q / G, x = q % G;
+        v[i] = make_float2(slab[(2 * t) * G + x], slab[(2 * t + 1) * G + x]);
+    }
+    const float2 tv = tw[threadIdx.x & (G / 2 - 1)];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int q = threadIdx.x + i * NT;
+        a[(q / G) * ST + q % G] = v[i];
+    }
+    if (threadIdx.x < G / 2) twl[threadIdx.x] = tv;
     __syncthreads();
-    // along y for every z; the band ky in [-h, h] goes to pa[ky + h][z]
-    lds_fft64_out<-1, ST>(pa, pb, G, twl, [&](int z, int yi, float2 v) {
-        const int ky = (yi <= G / 2) ? yi : yi - G;
-        if (ky >= -h && ky <= h) pa[(ky + h) * ST + z] = v;
-    });
-    // along z for every ky of the band, times the multiplier (zero outside the band)
-    lds_fft64_out<-1, ST>(pa, pb, NB1, twl, [&](int kyb, int zi, float2 v) {
-        const int ky = kyb - h, aky = ky < 0 ? -ky : ky;
-        const int kz = (zi <= G / 2) ? zi : zi - G;
-        const int akz = kz < 0 ? -kz : kz;
-        const float mk = (akz <= h) ? ml[akz * H + aky] : 0.0f;
-        pa[kyb * ST + zi] = make_float2(v.x * mk, v.y * mk);
-    });
-    // inverse along z; back to pa[z][y], with zeros outside the band (no thread reads pa in this
-    // second pass, and the zeros and the band values go to different elements)
-    lds_fft64_out<1, ST>(pa, pb, NB1, twl, [&](int kyb, int z, float2 v) {
-        pa[z * ST + ((kyb - h) & (G - 1))] = v;
-    });
-    for (int q = threadIdx.x; q < G * (G - NB1); q += blockDim.x) {
-        const int z = q / (G - NB1), yi = h + 1 + q % (G - NB1);  // ky = h + 1 .. G - h - 1
-        pa[z * ST + yi] = make_float2(0.f, 0.f);
+    lds_fft64<-1, ST>(a, b, G / 2, twl);
+    // the two real rows' spectra at kx <= h, transposed to b[kx][y]
+    for (int q = threadIdx.x; q < (G / 2) * KX; q += blockDim.x) {
+        const int t = q / KX, k = q % KX;
+        const float2 zz = a[t * ST + k], zm = a[t * ST + ((G - k) & (G - 1))];
+        b[k * ST + 2 * t] = make_float2(0.5f * (zz.x + zm.x), 0.5f * (zz.y - zm.y));
+        b[k * ST + 2 * t + 1] = make_float2(0.5f * (zz.y + zm.y), 0.5f * (zm.x - zz.x));
     }
     __syncthreads();
-    // inverse along y, stored to the plane
-    lds_fft64_out<1, ST>(pa, pb, G, twl, [&](int z, int y, float2 v) { plane[z * G + y] = v; });
+    // along y for every kx; the band |ky| <= h goes to S
+    float2 *out = S + (int64_t)z * NB1 * KX;
+    lds_fft64_out<-1, ST>(b, a, KX, twl, [&](int kx, int yi, float2 v) {
+        const int ky = (yi <= G / 2) ? yi : yi - G;
+        if (ky >= -h && ky <= h) out[(ky + h) * KX + kx] = v;
+    });
+}
+
+__global__ void __launch_bounds__(64) k_fft_z_conv64(float2 *__restrict__ S, FftArgs fa,
+                                                     const float2 *__restrict__ tw,
+                                                     const float *__restrict__ M) {
+    constexpr int G = 64, ST = FFT_ST, C = FFT_ZCOLS;
+    __shared__ float2 a[C * ST], b[C * ST], twl[G / 2];
+    __shared__ float ml[C][G / 2];  // the columns' multipliers by |kz| (h + 1 <= G / 2)
+    const int h = fa.N / 2, KX = fa.KX, H = h + 1;
+    const int ncol = (fa.N + 1) * KX, rowlen = ncol;
+    const int c0 = blockIdx.x * C;
+    const int nc = min(C, ncol - c0);
+    // column data, twiddles and the columns' multipliers, all loads in flight before the first
+    // store to LDS
+    constexpr int NT = 64, PT = C * G / NT, MT = C * (G / 2) / NT;
+    float2 v[PT];
+    float mv[MT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int q = threadIdx.x + i * NT, zi = q / C, c = q % C;
+        v[i] = (c < nc) ? S[(int64_t)zi * rowlen + c0 + c] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        const int q = threadIdx.x + i * NT, c = q / (G / 2), akz = q % (G / 2);
+        const int col = min(c0 + c, ncol - 1);
+        const int kyb = col / KX, kx = col % KX;
+        const int aky = kyb >= h ? kyb - h : h - kyb;
+        mv[i] = (akz < H) ? M[((int64_t)akz * H + aky) * H + kx] : 0.0f;
+    }
+    const float2 tv = tw[threadIdx.x & (G / 2 - 1)];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int q = threadIdx.x + i * NT;
+        a[(q % C) * ST + q / C] = v[i];
+    }
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        const int q = threadIdx.x + i * NT;
+        ml[q / (G / 2)][q % (G / 2)] = mv[i];
+    }
+    if (threadIdx.x < G / 2) twl[threadIdx.x] = tv;
+    __syncthreads();
+    lds_fft64_out<-1, ST>(a, b, C, twl, [&](int c, int zi, float2 v) {
+        const int kz = (zi <= G / 2) ? zi : zi - G;
+        const int akz = kz < 0 ? -kz : kz;
+        const float mk = (akz <= h) ? ml[c][akz] : 0.0f;
+        a[c * ST + zi] = make_float2(v.x * mk, v.y * mk);
+    });
+    lds_fft64_out<1, ST>(a, b, C, twl, [&](int c, int zo, float2 v) {
+        if (c < nc) S[(int64_t)zo * rowlen + c0 + c] = v;
+    });
+}
+
+__global__ void __launch_bounds__(256) k_fft_xy_inv64(const float2 *__restrict__ S, FftArgs fa,
+                                                      const float2 *__restrict__ tw,
+                                                      float *__restrict__ grid) {
+    constexpr int G = 64, ST = FFT_ST;
+    __shared__ float2 a[(G / 2) * ST], b[(G / 2) * ST], twl[G / 2];
+    const int h = fa.N / 2, KX = fa.KX, NB1 = fa.N + 1;
+    const int z = blockIdx.x;
+    const float2 *in = S + (int64_t)z * NB1 * KX;
+    // a[kx][y frequency]: the band, zeros elsewhere (kx < G / 2; all loads in flight before the
+    // first store to LDS)
+    constexpr int NT = 256, PT = (G / 2) * G / NT;
+    float2 v[PT];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int q = threadIdx.x + i * NT, kx = q / G, yi = q % G;
+        const int ky = (yi <= G / 2) ? yi : yi - G;
+        v[i] = (kx < KX && ky >= -h && ky <= h) ? in[(ky + h) * KX + kx] : make_float2(0.f, 0.f);
+    }
+    const float2 tv = tw[threadIdx.x & (G / 2 - 1)];
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+        const int q = threadIdx.x + i * NT;
+        if (q / G < KX) a[(q / G) * ST + q % G] = v[i];
+    }
+    if (threadIdx.x < G / 2) twl[threadIdx.x] = tv;
+    __syncthreads();
+    lds_fft64<1, ST>(a, b, KX, twl);
+    // rows 2t, 2t + 1 as one complex row: A + i B at kx <= h, their conjugates at G - kx
+    for (int q = threadIdx.x; q < (G / 2) * G; q += blockDim.x) {
+        const int t = q / G, k = q % G;
+        float2 zz = make_float2(0.f, 0.f);
+        if (k <= h) {
+            const float2 A = a[k * ST + 2 * t], B = a[k * ST + 2 * t + 1];
+            zz = make_float2(A.x - B.y, A.y + B.x);
+        } else if (k >= G - h) {
+            const int kk = G - k;
+            const float2 A = a[kk * ST + 2 * t], B = a[kk * ST + 2 * t + 1];
+            zz = make_float2(A.x + B.y, -A.y + B.x);
+        }
+        b[t * ST + k] = zz;
+    }
+    __syncthreads();
+    float *slab = grid + (int64_t)z * G * G;
+    lds_fft64_out<1, ST>(b, a, G / 2, twl, [&](int t, int i, float2 v) {
+        slab[(2 * t) * G + i] = v.x;
+        slab[(2 * t + 1) * G + i] = v.y;
+    });
 }
 
 // ------------------------------------------------------------------ gather (NFFT)
@@ -1529,8 +1629,9 @@ __device__ __forceinline__ void split_f16(float a, float b, f16x2 &hi, f16x2 &lo
 template <int W, bool POT>
 __global__ void __launch_bounds__(64 * MW) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_spread_mom16(const float4 *__restrict__ rec, const float *__restrict__ w,
-               const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups, SpreadArgs sa,
-               float *__restrict__ scratch, PotWeights pw) {
+               const int4 *__restrict__ mblocks, const int4 *__restrict__ mgroups,
+               const int2 *__restrict__ mbnodes, SpreadArgs sa, float *__restrict__ scratch,
+               PotWeights pw) {
     constexpr int T = 8, S = T + W - 1, BOX = S * S * S;
     constexpr int NZ = (W + 3) / 4;      // (y, z) offsets in blocks of 4
     constexpr int NB = NZ * NZ;          // 4 x 4 blocks of (y, z)
@@ -1550,8 +1651,8 @@ k_spread_mom16(const float4 *__restrict__ rec, const float *__restrict__ w,
     __shared__ int4 oxs[MW][4];              // per wave: x cell offsets of the 16 nodes
     __shared__ double red2[2][MW];
     const int4 mb = mblocks[blockIdx.x];
-    const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
-    const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
+    const int2 kn = mbnodes[blockIdx.x];
+    const int k0 = kn.x, cnt = kn.y;
     uint4 ccv[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -1812,6 +1913,10 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
     int tc[3];
     tile_coords<3>(mb.x, sa.ntd, tc);
     const int G = sa.G;
+    // the largest of the shift maxima (read together with the box)
+    double sv = -INFINITY;
+    if (UPD)
+        for (int b = threadIdx.x; b < pu.nshift; b += blockDim.x) sv = fmax(sv, pu.shift_parts[b]);
     // the tile's box: values and their largest magnitude
     float v[PER];
     float mx = 0.0f;
@@ -1828,8 +1933,14 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
             mx = fmaxf(mx, fabsf(v[i]));
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    for (int off = 32; off >= 1; off >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        if (UPD) sv = fmax(sv, __shfl_xor(sv, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = mx;
+        dred[threadIdx.x >> 6] = sv;
+    }
     // columns x >= S of every row are zero
     for (int q = threadIdx.x; q < S * S * (4 * NC - S); q += NT) {
         const int row = q / (4 * NC - S), x = S + q % (4 * NC - S);
@@ -1839,6 +1950,11 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
     __syncthreads();
     mx = red[0];
     for (int i = 1; i < MW; ++i) mx = fmaxf(mx, red[i]);
+    double shift = 0.0;
+    if (UPD) {
+        for (int i = 0; i < MW; ++i) sv = fmax(sv, dred[i]);
+        shift = (sv == -INFINITY) ? 0.0 : sv;
+    }
     // power-of-two scale: largest |value| in [2^13, 2^14)
     int ex = 0;
     frexpf(mx, &ex);
@@ -1859,14 +1975,8 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int node = lane & 15, slot = lane >> 4;
-    double shift = 0.0, pmx = -INFINITY, dmx = 0.0;
+    double pmx = -INFINITY, dmx = 0.0;
     int bad = 0;
-    if (UPD) {
-        double v = -INFINITY;
-        for (int b = threadIdx.x; b < pu.nshift; b += blockDim.x) v = fmax(v, pu.shift_parts[b]);
-        shift = block_max_f64(v, dred);
-        if (shift == -INFINITY) shift = 0.0;
-    }
     float wc[NZ][WPOLY];
 #pragma unroll
     for (int e = 0; e < NZ; ++e) {
@@ -2731,6 +2841,10 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
                            (int)ntiles, dtgstart.p, mg.tgroups.p, nd.mtile_block.p, gpb,
                            nd.mblocks.p);
         FS_LAUNCHED();
+        nd.mbnodes.alloc(nd.n_mblocks);
+        hipLaunchKernelGGL(k_block_nodes, dim3(blocks_for(nd.n_mblocks, 256)), dim3(256), 0, s,
+                           nd.mblocks.p, nd.mgroups.p, nd.n_mblocks, nd.mbnodes.p);
+        FS_LAUNCHED();
     }
     keep.push_back(std::move(gstart));
     keep.push_back(std::move(dtgstart));
@@ -3385,11 +3499,13 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                         if (pw)
                             hipLaunchKernelGGL((k_spread_mom16<W, true>), dim3(src.n_mblocks),
                                                dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
-                                               src.mgroups.p, sa, pl.scratch.p, *pw);
+                                               src.mgroups.p, src.mbnodes.p, sa, pl.scratch.p,
+                                               *pw);
                         else
                             hipLaunchKernelGGL((k_spread_mom16<W, false>), dim3(src.n_mblocks),
                                                dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
-                                               src.mgroups.p, sa, pl.scratch.p, PotWeights{});
+                                               src.mgroups.p, src.mbnodes.p, sa, pl.scratch.p,
+                                               PotWeights{});
                     }
                     tile_boxes = src.mtile_block.p;
                     multi = src.mmulti_tiles.p;
@@ -3478,41 +3594,42 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 nkb = (fa.KX + fa.nbx - 1) / fa.nbx;
                 const size_t lds_x = 2 * (size_t)fa.nb * pp.G * sizeof(float2);
                 const size_t lds_y = 2 * (size_t)fa.nbx * pp.G * sizeof(float2);
-                // 3-D on a 64^3 grid: plane-major spectrum and one fused pass for y and z
-                const bool yz = D == 3 && pp.G == 64;
-                if (yz)
-                    hipLaunchKernelGGL(k_fft_x_r2c<true>, dim3(xblocks), dim3(threads_for(fa.nb)),
-                                       lds_x, s, pl.grid.p, rows, fa, pl.twiddle.p, pl.specA.p);
-                else
-                    hipLaunchKernelGGL(k_fft_x_r2c<false>, dim3(xblocks), dim3(threads_for(fa.nb)),
-                                       lds_x, s, pl.grid.p, rows, fa, pl.twiddle.p, pl.specA.p);
-                FS_LAUNCHED();
-                if (D == 2) {
-                    hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(threads_for(fa.nbx)), lds_y, s,
-                                       pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                // 3-D on a 64^3 grid: z slabs (forward x and y, the z columns, inverse y and x)
+                if (D == 3 && pp.G == 64 && pp.N < pp.G) {
+                    const int ncol = (pp.N + 1) * fa.KX;
+                    hipLaunchKernelGGL(k_fft_xy_fwd64, dim3(pp.G), dim3(256), 0, s, pl.grid.p, fa,
+                                       pl.twiddle.p, pl.specB.p);
                     FS_LAUNCHED();
-                } else if (yz) {
-                    hipLaunchKernelGGL(k_fft_yz_conv64, dim3(fa.KX), dim3(512), 0, s, pl.specA.p,
-                                       fa, pl.twiddle.p, pl.Mk.p);
+                    hipLaunchKernelGGL(k_fft_z_conv64, dim3((ncol + FFT_ZCOLS - 1) / FFT_ZCOLS),
+                                       dim3(64), 0, s, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    FS_LAUNCHED();
+                    hipLaunchKernelGGL(k_fft_xy_inv64, dim3(pp.G), dim3(256), 0, s, pl.specB.p, fa,
+                                       pl.twiddle.p, pl.grid.p);
                     FS_LAUNCHED();
                 } else {
-                    hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(threads_for(fa.nbx)), lds_y,
-                                       s, pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    hipLaunchKernelGGL(k_fft_x_r2c, dim3(xblocks), dim3(threads_for(fa.nb)), lds_x, s,
+                                       pl.grid.p, rows, fa, pl.twiddle.p, pl.specA.p);
                     FS_LAUNCHED();
-                    hipLaunchKernelGGL(k_fft_z_conv, dim3((pp.N + 1) * nkb), dim3(threads_for(fa.nbx)),
-                                       lds_y, s, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
-                    FS_LAUNCHED();
-                    hipLaunchKernelGGL(k_fft_y<2>, dim3(pp.G * nkb), dim3(threads_for(fa.nbx)), lds_y,
-                                       s, pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                    if (D == 2) {
+                        hipLaunchKernelGGL(k_fft_y<1>, dim3(nkb), dim3(threads_for(fa.nbx)), lds_y, s,
+                                           pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                        FS_LAUNCHED();
+                    } else {
+                        hipLaunchKernelGGL(k_fft_y<0>, dim3(pp.G * nkb), dim3(threads_for(fa.nbx)),
+                                           lds_y, s, pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                        FS_LAUNCHED();
+                        hipLaunchKernelGGL(k_fft_z_conv, dim3((pp.N + 1) * nkb),
+                                           dim3(threads_for(fa.nbx)), lds_y, s, pl.specB.p, fa,
+                                           pl.twiddle.p, pl.Mk.p);
+                        FS_LAUNCHED();
+                        hipLaunchKernelGGL(k_fft_y<2>, dim3(pp.G * nkb), dim3(threads_for(fa.nbx)),
+                                           lds_y, s, pl.specA.p, pl.specB.p, fa, pl.twiddle.p, pl.Mk.p);
+                        FS_LAUNCHED();
+                    }
+                    hipLaunchKernelGGL(k_fft_x_c2r, dim3(xblocks), dim3(threads_for(fa.nb)), lds_x, s,
+                                       pl.specA.p, rows, fa, pl.twiddle.p, pl.grid.p);
                     FS_LAUNCHED();
                 }
-                if (yz)
-                    hipLaunchKernelGGL(k_fft_x_c2r<true>, dim3(xblocks), dim3(threads_for(fa.nb)),
-                                       lds_x, s, pl.specA.p, rows, fa, pl.twiddle.p, pl.grid.p);
-                else
-                    hipLaunchKernelGGL(k_fft_x_c2r<false>, dim3(xblocks), dim3(threads_for(fa.nb)),
-                                       lds_x, s, pl.specA.p, rows, fa, pl.twiddle.p, pl.grid.p);
-                FS_LAUNCHED();
             }
         }
         if (dst.n > 0) {
