@@ -368,6 +368,7 @@ __device__ __forceinline__ double block_max_f64(double v, double *red) {
 }
 
 constexpr int FFT_THREADS = 256;
+constexpr int FFT_BATCH = 4;  // loads per thread in flight in the FFT passes' load loops
 constexpr int FFT_ELEMS = 4096;  // complex elements per LDS buffer (two buffers: 64 KB)
 
 // ------------------------------------------------------------------ scaling and binning
@@ -1155,14 +1156,23 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_r2c(const float *__restri
     const int pairs = rows / 2;
     const int p0 = blockIdx.x * NB;
     const int nb = min(NB, pairs - p0);
-    for (int q = threadIdx.x; q < NB * G; q += blockDim.x) {
-        const int t = q / G, i = q - t * G;
-        float2 v = make_float2(0.f, 0.f);
-        if (t < nb) {
-            const int64_t r0 = (int64_t)(p0 + t) * 2;
-            v = make_float2(grid[r0 * G + i], grid[(r0 + 1) * G + i]);
+    // FFT_BATCH loads per thread in flight before their stores to LDS
+    for (int q0 = threadIdx.x; q0 < NB * G; q0 += FFT_BATCH * blockDim.x) {
+        float2 v[FFT_BATCH];
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x, t = q / G, i = q - t * G;
+            v[u] = make_float2(0.f, 0.f);
+            if (q < NB * G && t < nb) {
+                const int64_t r0 = (int64_t)(p0 + t) * 2;
+                v[u] = make_float2(grid[r0 * G + i], grid[(r0 + 1) * G + i]);
+            }
         }
-        bufa[q] = v;
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x;
+            if (q < NB * G) bufa[q] = v[u];
+        }
     }
     __syncthreads();
     float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, NB, tw);
@@ -1189,23 +1199,31 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_x_c2r(const float2 *__restr
     const int pairs = rows / 2;
     const int p0 = blockIdx.x * NB;
     const int nb = min(NB, pairs - p0);
-    for (int q = threadIdx.x; q < NB * G; q += blockDim.x) {
-        const int t = q / G, k = q - t * G;
-        float2 z = make_float2(0.f, 0.f);
-        if (t < nb) {
-            const int64_t r0 = (int64_t)(p0 + t) * 2;
-            if (k <= h) {
-                const float2 A = specA[r0 * fa.KX + k], B = specA[(r0 + 1) * fa.KX + k];
-                z = make_float2(A.x - B.y, A.y + B.x);
-            } else if (k >= G - h) {
-                const int kk = G - k;
-                float2 A = specA[r0 * fa.KX + kk], B = specA[(r0 + 1) * fa.KX + kk];
-                A.y = -A.y;
-                B.y = -B.y;
-                z = make_float2(A.x - B.y, A.y + B.x);
+    // FFT_BATCH loads per thread in flight before their stores to LDS
+    for (int q0 = threadIdx.x; q0 < NB * G; q0 += FFT_BATCH * blockDim.x) {
+        float2 v[FFT_BATCH];
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x, t = q / G, k = q - t * G;
+            float2 z = make_float2(0.f, 0.f);
+            if (q < NB * G && t < nb) {
+                const int64_t r0 = (int64_t)(p0 + t) * 2;
+                if (k <= h) {
+                    const float2 A = specA[r0 * fa.KX + k], B = specA[(r0 + 1) * fa.KX + k];
+                    z = make_float2(A.x - B.y, A.y + B.x);
+                } else if (k >= G - h) {
+                    const int kk = G - k;
+                    const float2 A = specA[r0 * fa.KX + kk], B = specA[(r0 + 1) * fa.KX + kk];
+                    z = make_float2(A.x + B.y, -A.y + B.x);
+                }
             }
+            v[u] = z;
         }
-        bufa[q] = z;
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x;
+            if (q < NB * G) bufa[q] = v[u];
+        }
     }
     __syncthreads();
     float2 *res = lds_fft<1>(bufa, bufb, fa.logG, NB, tw);
@@ -1254,18 +1272,28 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_y(float2 *__restrict__ spec
     const int nkb = (KX + NBX - 1) / NBX;
     const int z = blockIdx.x / nkb, kb = blockIdx.x - z * nkb;
     const int kx0 = kb * NBX, nbx = min(NBX, KX - kx0);
-    for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
-        const int y = q / NBX, c = q - y * NBX;
-        float2 v = make_float2(0.f, 0.f);
-        if (c < nbx) {
-            if (MODE == 2) {
-                const int ky = (y <= G / 2) ? y : y - G;
-                if (ky >= -h && ky <= h) v = specB[((int64_t)z * NB1 + ky + h) * KX + kx0 + c];
-            } else {
-                v = specA[((int64_t)z * G + y) * KX + kx0 + c];
+    // FFT_BATCH loads per thread in flight before their stores to LDS
+    for (int q0 = threadIdx.x; q0 < NBX * G; q0 += FFT_BATCH * blockDim.x) {
+        float2 v[FFT_BATCH];
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x, y = q / NBX, c = q - y * NBX;
+            v[u] = make_float2(0.f, 0.f);
+            if (q < NBX * G && c < nbx) {
+                if (MODE == 2) {
+                    const int ky = (y <= G / 2) ? y : y - G;
+                    if (ky >= -h && ky <= h)
+                        v[u] = specB[((int64_t)z * NB1 + ky + h) * KX + kx0 + c];
+                } else {
+                    v[u] = specA[((int64_t)z * G + y) * KX + kx0 + c];
+                }
             }
         }
-        bufa[c * G + y] = v;
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x, y = q / NBX, c = q - y * NBX;
+            if (q < NBX * G) bufa[c * G + y] = v[u];
+        }
     }
     __syncthreads();
     float2 *res;
@@ -1276,12 +1304,20 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_y(float2 *__restrict__ spec
     }
     if (MODE == 1) {
         float2 *other = (res == bufa) ? bufb : bufa;
-        for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
-            const int c = q / G, yi = q - c * G;
-            const int ky = (yi <= G / 2) ? yi : yi - G;
-            const int aky = ky < 0 ? -ky : ky;
-            float mk = (aky <= h && c < nbx) ? M[aky * (h + 1) + kx0 + c] : 0.0f;
-            res[q] = make_float2(res[q].x * mk, res[q].y * mk);
+        for (int q0 = threadIdx.x; q0 < NBX * G; q0 += FFT_BATCH * blockDim.x) {
+            float mk[FFT_BATCH];
+#pragma unroll
+            for (int u = 0; u < FFT_BATCH; ++u) {
+                const int q = q0 + u * blockDim.x, c = q / G, yi = q - c * G;
+                const int ky = (yi <= G / 2) ? yi : yi - G;
+                const int aky = ky < 0 ? -ky : ky;
+                mk[u] = (q < NBX * G && aky <= h && c < nbx) ? M[aky * (h + 1) + kx0 + c] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < FFT_BATCH; ++u) {
+                const int q = q0 + u * blockDim.x;
+                if (q < NBX * G) res[q] = make_float2(res[q].x * mk[u], res[q].y * mk[u]);
+            }
         }
         __syncthreads();
         res = lds_fft<1>(res, other, fa.logG, NBX, tw);
@@ -1314,20 +1350,40 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_z_conv(float2 *__restrict__
     const int kyb = blockIdx.x / nkb, kb = blockIdx.x - kyb * nkb;
     const int kx0 = kb * NBX, nbx = min(NBX, KX - kx0);
     const int ky = kyb - h, aky = ky < 0 ? -ky : ky;
-    for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
-        const int zz = q / NBX, c = q - zz * NBX;
-        bufa[c * G + zz] = (c < nbx) ? specB[((int64_t)zz * NB1 + kyb) * KX + kx0 + c]
-                                     : make_float2(0.f, 0.f);
+    // FFT_BATCH loads per thread in flight before their stores to LDS
+    for (int q0 = threadIdx.x; q0 < NBX * G; q0 += FFT_BATCH * blockDim.x) {
+        float2 v[FFT_BATCH];
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x, zz = q / NBX, c = q - zz * NBX;
+            v[u] = (q < NBX * G && c < nbx) ? specB[((int64_t)zz * NB1 + kyb) * KX + kx0 + c]
+                                            : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x, zz = q / NBX, c = q - zz * NBX;
+            if (q < NBX * G) bufa[c * G + zz] = v[u];
+        }
     }
     __syncthreads();
     float2 *res = lds_fft<-1>(bufa, bufb, fa.logG, NBX, tw);
     float2 *other = (res == bufa) ? bufb : bufa;
-    for (int q = threadIdx.x; q < NBX * G; q += blockDim.x) {
-        const int c = q / G, zi = q - c * G;
-        const int kz = (zi <= G / 2) ? zi : zi - G;
-        const int akz = kz < 0 ? -kz : kz;
-        float mk = (akz <= h && c < nbx) ? M[((int64_t)akz * H + aky) * H + kx0 + c] : 0.0f;
-        res[q] = make_float2(res[q].x * mk, res[q].y * mk);
+    for (int q0 = threadIdx.x; q0 < NBX * G; q0 += FFT_BATCH * blockDim.x) {
+        float mk[FFT_BATCH];
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x, c = q / G, zi = q - c * G;
+            const int kz = (zi <= G / 2) ? zi : zi - G;
+            const int akz = kz < 0 ? -kz : kz;
+            mk[u] = (q < NBX * G && akz <= h && c < nbx)
+                        ? M[((int64_t)akz * H + aky) * H + kx0 + c]
+                        : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < FFT_BATCH; ++u) {
+            const int q = q0 + u * blockDim.x;
+            if (q < NBX * G) res[q] = make_float2(res[q].x * mk[u], res[q].y * mk[u]);
+        }
     }
     __syncthreads();
     res = lds_fft<1>(res, other, fa.logG, NBX, tw);
