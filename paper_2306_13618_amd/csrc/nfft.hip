@@ -2043,6 +2043,28 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
     float(*ph)[W][16] = phi[wave];
     const int per = (mb.z + MW - 1) / MW;
     const int gb = mb.y + wave * per, ge = min(mb.y + mb.z, gb + per);
+    // the sums of four consecutive groups wait in registers, one group per lane slot, and are
+    // stored (with the update) by all 64 lanes at once
+    float tq = 0.0f;
+    int kq = -1, nq = 0;
+    auto commit = [&]() {
+        if (kq >= 0) {
+            float t = tq;
+            if (!UPD) {
+                out[kq] = t;
+            } else {
+                if (!(t > 0.0f)) {
+                    ++bad;
+                    t = FLT_MIN;
+                }
+                const double f = -pu.kappa * (shift + pu.eps * sum_log(t));
+                if (pu.delta_parts) dmx = fmax(dmx, fabs(f - pu.pot[kq]));
+                pu.pot[kq] = f;
+                pmx = fmax(pmx, f);
+            }
+        }
+        kq = -1;
+    };
     int4 grn = make_int4(0, 1, 0, 0);
     float4 rn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (gb < ge) {
@@ -2111,26 +2133,20 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma16(const float4 *__restr
         for (int rr = 0; rr < 4; ++rr) part = fmaf(pz[rr], ty[rr], part);
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);
-        if (slot == 0 && node < gr.y) {
-            const int k = gr.x + node;
-            float t = part * unscale;
-            if (!UPD) {
-                out[k] = t;
-            } else {
-                if (!(t > 0.0f)) {
-                    ++bad;
-                    t = FLT_MIN;
-                }
-                const double f = -pu.kappa * (shift + pu.eps * sum_log(t));
-                if (pu.delta_parts) dmx = fmax(dmx, fabs(f - pu.pot[k]));
-                pu.pot[k] = f;
-                pmx = fmax(pmx, f);
-            }
+        // every lane of column `node` now holds the node's sum; slot nq keeps it
+        if (slot == nq) {
+            tq = part * unscale;
+            kq = (node < gr.y) ? gr.x + node : -1;
+        }
+        if (++nq == 4) {
+            commit();
+            nq = 0;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    commit();
     if (UPD) {
         if (bad) atomicAdd(pu.nbad, bad);
         pmx = block_max_f64(pmx, dred);
