@@ -1837,19 +1837,35 @@ k_spread_mom16(const float4 *__restrict__ rec, const float *__restrict__ w,
     int4 g1 = (gb < ge) ? mgroups[gb] : gnone;
     int4 g2 = (gb + 1 < ge) ? mgroups[gb + 1] : gnone;
     float4 r1 = float4{0.0f, 0.0f, 0.0f, 0.0f};
-    float b1 = 0.0f;
-    double p1 = 0.0;
-    auto fetch = [&](const int4 &q) {
-        const int kk = q.x + min(col, q.y - 1);
-        r1 = rec[kk];
-        if (POT) {
-            b1 = pw.base[kk];
-            p1 = pw.pot[kk];
-        } else {
-            b1 = w[kk];
+    if (gb < ge) r1 = rec[g1.x + min(col, g1.y - 1)];
+    // weights four groups at a time: lane slot s evaluates the weight of node `col` of group
+    // gq + s (the exponential once per node instead of once per lane), and a group takes its
+    // weights from the lanes of its slot by a shuffle; the node data of the next four groups is
+    // loaded a batch ahead
+    float bq = 0.0f;
+    double pq = 0.0;
+    auto fetchw = [&](int g0) {
+        const int gg = g0 + slot;
+        bq = 0.0f;
+        pq = 0.0;
+        if (gg < ge) {
+            const int4 q = mgroups[gg];
+            const int kk = q.x + min(col, q.y - 1);
+            if (POT) {
+                bq = pw.base[kk];
+                pq = pw.pot[kk];
+            } else {
+                bq = w[kk];
+            }
         }
     };
-    if (gb < ge) fetch(g1);
+    auto weight = [&]() -> float {
+        return POT ? weight_exp(bq, (pq - pmax) * pw.inv_eps) : bq;
+    };
+    int gq = gb;
+    fetchw(gb);
+    float wq = weight();
+    fetchw(gb + 4);
     for (int g = gb;; ++g) {
         // one flush site: the pass after the last group flushes the last brick
         const int gz = (g < ge) ? g1.z : -1;
@@ -1860,9 +1876,14 @@ k_spread_mom16(const float4 *__restrict__ rec, const float *__restrict__ w,
         if (g >= ge) break;
         const int4 gr = g1;
         const float4 r = r1;
-        const float wv = POT ? weight_exp(b1, (p1 - pmax) * pw.inv_eps) : b1;
+        if (g - gq == 4) {
+            gq = g;
+            wq = weight();
+            fetchw(g + 4);
+        }
+        const float wv = __shfl(wq, (g - gq) * 16 + col, 64);
         g1 = g2;
-        if (g + 1 < ge) fetch(g1);
+        if (g + 1 < ge) r1 = rec[g1.x + min(col, g1.y - 1)];
         g2 = (g + 2 < ge) ? mgroups[g + 2] : gnone;
         const float alpha = (col < gr.y) ? wv * inv_wmax : 0.0f;
         // x window values of node `col` at offsets slot + 4 e
