@@ -1711,10 +1711,7 @@ k_spread_mom16(const float4 *__restrict__ rec, const float *__restrict__ w,
     const int k0 = kn.x, cnt = kn.y;
     uint4 ccv[CPT];
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) {
-        const int q = threadIdx.x + i * 64 * MW;
-        if (q < NCC) ccv[i] = sa.cc[q];
-    }
+    for (int i = 0; i < CPT; ++i) ccv[i] = sa.cc[min((int)threadIdx.x + i * 64 * MW, NCC - 1)];
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
     // the block's largest |weight| in one pass: with potentials, w_k = base_k
     // exp((pot_k - pmax) / eps), so max_k |w_k| = exp(max_k (log |base_k| + pot_k / eps) -
