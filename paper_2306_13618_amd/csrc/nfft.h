@@ -100,11 +100,15 @@ void plan_apply_sorted(Plan &pl, const float *w_sorted, float *t_sorted, float *
 
 // Source weights given as w_k = base_k exp((pot_k - pmax) / eps), FP64 exponent, FP32 result
 // (a Sinkhorn half-step), pmax the largest of nparts per-block maxima (0 when all are -inf).
+// With bbase set, parts are instead the per-block maxima of pot over the source set's matrix-core
+// blocks (as the fused update over that set writes them) and bbase the blocks' largest |base|; the
+// 3-D spread then bounds its block's largest weight by them instead of reading the block's nodes.
 struct PotWeights {
     const float *base = nullptr;
     const double *pot = nullptr, *parts = nullptr;
     int nparts = 0;
     double inv_eps = 1.0;
+    const float *bbase = nullptr;
 };
 
 // The potential update of a Sinkhorn half-step applied to the kernel sums t_k as they are
@@ -127,6 +131,11 @@ bool plan_fuses_weights(const Plan &pl, int transpose);
 // plan_update_parts is then the number of maxima it writes.
 bool plan_fuses_update(const Plan &pl, int transpose);
 int plan_update_parts(const Plan &pl, int transpose);
+// Largest |base_k| over each matrix-core block of the direction's source set (base in sorted
+// order; out: plan_source_blocks values), for PotWeights::bbase.
+int plan_source_blocks(const Plan &pl, int transpose);
+void plan_block_base_max(const Plan &pl, const float *base_sorted, int transpose, float *out,
+                         hipStream_t s);
 // With pu the sums are not stored: the gather applies the update (t_sorted may be null).
 void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
                            hipStream_t s, const PotUpdate *pu = nullptr);

@@ -586,6 +586,20 @@ __global__ void k_block_nodes(const int4 *__restrict__ mblocks, const int4 *__re
     out[b] = make_int2(g0.x, gl.x + gl.y - g0.x);
 }
 
+// Largest |base_k| over the nodes of every block of groups, one workgroup per block.
+__global__ void __launch_bounds__(256) k_block_absmax(const float *__restrict__ base,
+                                                      const int2 *__restrict__ mbnodes,
+                                                      float *__restrict__ out) {
+    __shared__ float red[4];
+    const int2 kn = mbnodes[blockIdx.x];
+    float mx = 0.0f;
+    for (int k = kn.x + threadIdx.x; k < kn.x + kn.y; k += blockDim.x) mx = fmaxf(mx, fabsf(base[k]));
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
 // Matrix-core groups (d = 3, nodes ordered by tile and cell, x fastest): a brick is BRICK_X
 // consecutive cell keys (cells along x with the same y and z), so its nodes are contiguous; each
 // brick is cut into groups of up to 16 nodes.
@@ -1721,7 +1735,12 @@ k_spread_mom16(const float4 *__restrict__ rec, const float *__restrict__ w,
     constexpr int PB = 8;
     if (POT)
         for (int b = threadIdx.x; b < pw.nparts; b += blockDim.x) m0 = fmax(m0, pw.parts[b]);
-    for (int q0 = k0 + threadIdx.x; q0 < k0 + cnt; q0 += PB * 64 * MW) {
+    // with per-block maxima of the potential and of |base|, their sum bounds the block's largest
+    // log-weight and the block's nodes need not be read here
+    const bool bounded = POT && pw.bbase != nullptr;
+    if (bounded && threadIdx.x == 0)
+        m1 = pw.parts[blockIdx.x] * pw.inv_eps + (double)logf(pw.bbase[blockIdx.x]);
+    for (int q0 = k0 + threadIdx.x; !bounded && q0 < k0 + cnt; q0 += PB * 64 * MW) {
         double pv[PB];
         float bv[PB];
 #pragma unroll
@@ -3815,6 +3834,17 @@ bool plan_fuses_update(const Plan &pl, int transpose) {
 }
 
 int plan_update_parts(const Plan &pl, int transpose) { return pl.dst(transpose).n_mblocks; }
+
+int plan_source_blocks(const Plan &pl, int transpose) { return pl.src(transpose).n_mblocks; }
+
+void plan_block_base_max(const Plan &pl, const float *base_sorted, int transpose, float *out,
+                         hipStream_t s) {
+    const Nodes &src = pl.src(transpose);
+    if (src.n_mblocks == 0) return;
+    hipLaunchKernelGGL(k_block_absmax, dim3(src.n_mblocks), dim3(256), 0, s, base_sorted,
+                       src.mbnodes.p, out);
+    FS_LAUNCHED();
+}
 
 void plan_apply_sorted_pot(Plan &pl, const PotWeights &pw, float *t_sorted, int transpose,
                            hipStream_t s, const PotUpdate *pu) {

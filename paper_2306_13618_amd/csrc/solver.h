@@ -54,8 +54,14 @@ struct Op {
     // where fuses_update; update_parts maxima are then written.
     bool fuses_update(int transpose) const;
     int update_parts(int transpose) const;
+    // bbase (nullable): the source blocks' largest |base| (block_base_max), given when parts are
+    // the per-block maxima that the previous fused update over the same set wrote.
     void apply_pot_update(const float *base, const double *pot, const double *parts, int nparts,
-                          double eps, const PotUpdate &pu, int transpose, hipStream_t s);
+                          double eps, const PotUpdate &pu, int transpose, hipStream_t s,
+                          const float *bbase = nullptr);
+    // Matrix-core blocks of the direction's source set and their largest |base| (fast path).
+    int source_blocks(int transpose) const;
+    void block_base_max(const float *base, int transpose, float *out, hipStream_t s) const;
 };
 
 std::unique_ptr<Op> make_op(const float *x, int64_t n, const float *y, int64_t m, int d,

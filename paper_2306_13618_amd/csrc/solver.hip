@@ -846,14 +846,24 @@ bool Op::fuses_update(int transpose) const {
 int Op::update_parts(int transpose) const { return plan_update_parts(*plan, transpose); }
 
 void Op::apply_pot_update(const float *base, const double *pot, const double *parts, int nparts,
-                          double eps, const PotUpdate &pu, int transpose, hipStream_t s) {
+                          double eps, const PotUpdate &pu, int transpose, hipStream_t s,
+                          const float *bbase) {
     PotWeights pw;
     pw.base = base;
     pw.pot = pot;
     pw.parts = parts;
     pw.nparts = nparts;
     pw.inv_eps = 1.0 / eps;
+    pw.bbase = (bbase && nparts == source_blocks(transpose)) ? bbase : nullptr;
     plan_apply_sorted_pot(*plan, pw, nullptr, transpose, s, &pu);
+}
+
+int Op::source_blocks(int transpose) const {
+    return fast ? plan_source_blocks(*plan, transpose) : 0;
+}
+
+void Op::block_base_max(const float *base, int transpose, float *out, hipStream_t s) const {
+    if (fast) plan_block_base_max(*plan, base, transpose, out, s);
 }
 
 void Op::apply(const float *w, float *t, float *grad, int transpose, hipStream_t s,
@@ -1120,13 +1130,22 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
         fill_f64(g_o, m, 0.0, s);
         fill_f64(f_o, n, 0.0, s);
     }
+    // fused half-steps: each side's largest |base| per source block, and whether that side's
+    // potential maxima come from a fused update (then they are per source block)
+    const bool fuseX = n > 0 && op.fuses_update(0) && op.update_parts(0) <= UPD_BLOCKS;
+    const bool fuseY = m > 0 && op.fuses_update(1) && op.update_parts(1) <= UPD_BLOCKS;
+    DevBuf<float> bbY(fuseX ? std::max(1, op.source_blocks(0)) : 0);
+    DevBuf<float> bbX(fuseY ? std::max(1, op.source_blocks(1)) : 0);
+    if (fuseX) op.block_base_max(b_o, 0, bbY.p, s);
+    if (fuseY) op.block_base_max(a_o, 1, bbX.p, s);
+    bool fblocks = false, gblocks = false;
     // with a tolerance, a sweep that changes no potential by more than tol * eps ends the solve
     const bool track = tol > 0.0;
     double *fd = track ? sc.dparts.p : nullptr, *gd = track ? sc.dparts.p + UPD_BLOCKS : nullptr;
     int done = 0;
     for (int it = 0; it < iters; ++it) {
         // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}, then the f update
-        if (n > 0 && op.fuses_update(0) && op.update_parts(0) <= UPD_BLOCKS) {
+        if (fuseX) {
             PotUpdate pu;
             pu.shift_parts = sc.gparts.p;
             pu.nshift = sc.ng;
@@ -1136,8 +1155,10 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             pu.out_parts = sc.fparts.p;
             pu.delta_parts = fd;
             pu.nbad = sc.nbad.p;
-            op.apply_pot_update(b_o, g_o, sc.gparts.p, sc.ng, eps, pu, 0, s);
+            op.apply_pot_update(b_o, g_o, sc.gparts.p, sc.ng, eps, pu, 0, s,
+                                gblocks ? bbY.p : nullptr);
             sc.nf = op.update_parts(0);
+            fblocks = true;
         } else if (logd) {
             op.apply_pot_log(b_o, g_o, sc.gparts.p, sc.ng, eps, wY.p, lX.p, 0, s);
             if (n > 0)
@@ -1153,7 +1174,7 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
                                       sc.nbad.p, fd, s);
         }
         // gamma half-step (Delta even): t~_j = sum_i k_ij a_i e^{f_i/eps}, then the g update
-        if (m > 0 && op.fuses_update(1) && op.update_parts(1) <= UPD_BLOCKS) {
+        if (fuseY) {
             PotUpdate pu;
             pu.shift_parts = sc.fparts.p;
             pu.nshift = sc.nf;
@@ -1163,8 +1184,10 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
             pu.out_parts = sc.gparts.p;
             pu.delta_parts = gd;
             pu.nbad = sc.nbad.p;
-            op.apply_pot_update(a_o, f_o, sc.fparts.p, sc.nf, eps, pu, 1, s);
+            op.apply_pot_update(a_o, f_o, sc.fparts.p, sc.nf, eps, pu, 1, s,
+                                fblocks ? bbX.p : nullptr);
             sc.ng = op.update_parts(1);
+            gblocks = true;
         } else if (logd) {
             op.apply_pot_log(a_o, f_o, sc.fparts.p, sc.nf, eps, wX.p, lY.p, 1, s);
             if (m > 0)
