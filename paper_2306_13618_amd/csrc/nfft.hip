@@ -2209,6 +2209,7 @@ __global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restr
                                                        const float *__restrict__ w,
                                                        const int4 *__restrict__ mblocks,
                                                        const int4 *__restrict__ mgroups,
+                                                       const int2 *__restrict__ mbnodes,
                                                        SpreadArgs sa, float *__restrict__ scratch,
                                                        PotWeights pw) {
     constexpr int S = T + W - 1, BOX = S * S;
@@ -2224,8 +2225,8 @@ __global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restr
     __shared__ double pmx[MW];
     const int4 mb = mblocks[blockIdx.x];
     for (int q = threadIdx.x; q < BOX; q += blockDim.x) box[q] = 0;
-    const int4 gfirst = mgroups[mb.y], glast = mgroups[mb.y + mb.z - 1];
-    const int k0 = gfirst.x, cnt = glast.x + glast.y - k0;
+    const int2 kn = mbnodes[blockIdx.x];
+    const int k0 = kn.x, cnt = kn.y;
     double pmax = 0.0;
     if (POT) {
         double mx = -INFINITY;
@@ -2238,7 +2239,15 @@ __global__ void __launch_bounds__(64 * MW) k_spread_mfma2d(const float4 *__restr
         return w[k];
     };
     float wm = 0.0f;
-    const float scale = chunk_scale_fn(weight, k0, cnt, red, &wm);
+    float scale = 1.0f;
+    if (POT && pw.bbase) {
+        // per-block maxima of the potential and of |base| bound the block's largest weight
+        const double lb = pw.parts[blockIdx.x] * pw.inv_eps + (double)logf(pw.bbase[blockIdx.x]);
+        wm = (lb == -INFINITY) ? 0.0f : weight_exp(1.0f, lb - pmax * pw.inv_eps);
+        scale = (wm > 0.0f && cnt > 0) ? 1073741824.0f / ((float)cnt * wm) : 1.0f;
+    } else {
+        scale = chunk_scale_fn(weight, k0, cnt, red, &wm);
+    }
     const float wmax = (wm > 0.0f) ? wm : 1.0f;
     const float inv_wmax = 1.0f / wmax, fscale = scale * wmax;
     const int lane = threadIdx.x & 63;
@@ -2350,6 +2359,10 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restr
     int tc[3];
     tile_coords<2>(mb.x, sa.ntd, tc);
     const int G = sa.G;
+    // the largest of the shift maxima (read together with the box)
+    double sv = -INFINITY;
+    if (UPD)
+        for (int b = threadIdx.x; b < pu.nshift; b += blockDim.x) sv = fmax(sv, pu.shift_parts[b]);
     // the tile's box: values and their largest magnitude
     float v[PER];
     float mx = 0.0f;
@@ -2365,8 +2378,14 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restr
             mx = fmaxf(mx, fabsf(v[i]));
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    for (int off = 32; off >= 1; off >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        if (UPD) sv = fmax(sv, __shfl_xor(sv, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = mx;
+        dred[threadIdx.x >> 6] = sv;
+    }
     // columns x >= S of every row are zero
     for (int q = threadIdx.x; q < S * (4 * NC - S); q += NT) {
         const int row = q / (4 * NC - S), x = S + q % (4 * NC - S);
@@ -2376,6 +2395,11 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restr
     __syncthreads();
     mx = red[0];
     for (int i = 1; i < MW; ++i) mx = fmaxf(mx, red[i]);
+    double shift = 0.0;
+    if (UPD) {
+        for (int i = 0; i < MW; ++i) sv = fmax(sv, dred[i]);
+        shift = (sv == -INFINITY) ? 0.0 : sv;
+    }
     // power-of-two scale: largest |value| in [2^13, 2^14)
     int ex = 0;
     frexpf(mx, &ex);
@@ -2396,14 +2420,8 @@ __global__ void __launch_bounds__(64 * MW) k_gather_mfma2d(const float4 *__restr
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int node = lane & 15, slot = lane >> 4;
-    double shift = 0.0, pmx = -INFINITY, dmx = 0.0;
+    double pmx = -INFINITY, dmx = 0.0;
     int bad = 0;
-    if (UPD) {
-        double v = -INFINITY;
-        for (int b = threadIdx.x; b < pu.nshift; b += blockDim.x) v = fmax(v, pu.shift_parts[b]);
-        shift = block_max_f64(v, dred);
-        if (shift == -INFINITY) shift = 0.0;
-    }
     float wc[NZ][WPOLY];
 #pragma unroll
     for (int e = 0; e < NZ; ++e) {
@@ -3598,11 +3616,13 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                         if (pw)
                             hipLaunchKernelGGL((k_spread_mfma2d<W, T, true>), dim3(src.n_mblocks),
                                                dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
-                                               src.mgroups.p, sa, pl.scratch.p, *pw);
+                                               src.mgroups.p, src.mbnodes.p, sa, pl.scratch.p,
+                                               *pw);
                         else
                             hipLaunchKernelGGL((k_spread_mfma2d<W, T, false>), dim3(src.n_mblocks),
                                                dim3(64 * MW), 0, s, src.rec.p, w, src.mblocks.p,
-                                               src.mgroups.p, sa, pl.scratch.p, PotWeights{});
+                                               src.mgroups.p, src.mbnodes.p, sa, pl.scratch.p,
+                                               PotWeights{});
                     }
                     if constexpr (D == 3 && W + BRICK_X - 1 <= 16) {
                         if (pw)
