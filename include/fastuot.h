@@ -138,7 +138,9 @@ int fastsum_apply(const float *x, int64_t n, const float *y, int64_t m, int d, c
  * with K symmetric (radial), so the transpose is the same operator with the roles swapped.
  * fs_plan_apply is stream-ordered and returns without waiting; a plan holds scratch buffers, so
  * applications of one plan must be ordered (one stream, or synchronised between streams).
- * fs_plan_destroy waits for the device before releasing the plan. */
+ * fs_plan_destroy waits for the device before releasing the plan.  A 3-D plan whose window
+ * segments' Chebyshev transform (the 3-D spread's moment form) would leave FP16 range fails with
+ * FS_EUNSUPPORTED; the Kaiser-Bessel windows built here stay well inside it. */
 int fs_plan_create(const float *x, int64_t n, const float *y, int64_t m, int d,
                    const fs_params *p, void *stream, fs_plan *plan_out);
 int fs_plan_apply(fs_plan plan, const float *v, float *out, int transpose, void *stream);
