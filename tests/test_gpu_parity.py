@@ -156,13 +156,21 @@ def test_fastsum_nearfield_matrix_core_groups(kind, lam):
 @pytest.mark.parametrize("window", [2, 3])
 def test_fastsum_matrix_core_small_windows(window):
     """Windows of 4 and 6 points (two matrix rows of z offsets, partly empty operand columns): the
-    matrix-core spread and gather against the lane-per-node kernels on every row."""
+    matrix-core spread and gather against the lane-per-node kernels on every row, and against the
+    oracle's direct sums on sampled rows, where a window this short leaves its own approximation
+    error: the matrix-core path may not be further from the oracle than the lane-per-node one
+    (beyond the split operands' rounding)."""
     x, y, v = dense_and_sparse(30_000, 28_001, 40 + window)
     args = dict(kernel="gauss", lam=0.05, grid=64, window=window)
     got = fu.fastsum_apply(T(x), T(y), T(v), **args).cpu().numpy()
     valu = fu.fastsum_apply(T(x), T(y), T(v), flags=fu.FLAG_FORCE_VALU, **args).cpu().numpy()
     assert relinf(got, valu) < 2e-6
     assert np.any(got != valu)
+    rows = synth.sample_rows(len(x), 200, seed=60 + window)
+    ref = oracle.direct_sum_rows(x, rows, y, v, "gauss", 0.05)
+    e_mc, e_valu = relinf(got[rows], ref), relinf(valu[rows], ref)
+    print("window %d: matrix cores %.2e, lane-per-node %.2e from the oracle" % (window, e_mc, e_valu))
+    assert e_mc <= e_valu + 2e-6
 
 
 @pytest.mark.parametrize("n,m", [(64, 48), (17, 1), (1, 300)])
