@@ -979,13 +979,30 @@ def test_mmd_grad_against_oracle(kind, lam, grid, cfg):
 
 
 def test_autograd_functions():
+    """The autograd Functions: SinkhornDivergence's backward of 2.5 S (the scale reaches the
+    gradient call) against the FP64 oracle's envelope gradient (Theorem "dualization") at the
+    forward's potentials, on every row; MMD2's against the oracle's gradient."""
     w = synth.make("divergence_d2_n200k", n=500, m=450)
     x = T(w["x"]).requires_grad_()
     a = T(w["a"]).requires_grad_()
     y, b = T(w["y"]), T(w["b"])
     s = fu.SinkhornDivergence.apply(x, a, y, b, w["eps"], w["rho"], 300, {"grid": 64})
-    s.backward()
-    assert torch.isfinite(x.grad).all() and torch.isfinite(a.grad).all()
+    (2.5 * s).backward()
+    _, _, pots = fu.sinkhorn_divergence(x.detach(), a.detach(), y, b, w["eps"], w["rho"], 300,
+                                        return_potentials=True, grid=64)
+    fab, gab, faa, _ = (p.cpu().numpy() for p in pots)
+    rows = np.arange(len(w["x"]))
+    g1x, g1a = oracle.uot_grad_rows(w["x"], w["a"], rows, w["y"], w["b"], w["eps"], w["rho"],
+                                    fab, gab)
+    g2x, g2a = oracle.uot_grad_rows(w["x"], w["a"], rows, w["x"], w["a"], w["eps"], w["rho"],
+                                    faa, faa)
+    Ma, Mb = float(np.sum(w["a"], dtype=np.float64)), float(np.sum(w["b"], dtype=np.float64))
+    refx = 2.5 * (g1x - g2x)
+    refa = 2.5 * (g1a - g2a + w["eps"] * (Ma - Mb))
+    ex = relinf(x.grad.cpu().numpy(), refx)
+    ea = relinf(a.grad.cpu().numpy(), refa)
+    print("autograd divergence gradient: dx %.2e da %.2e" % (ex, ea))
+    assert ex < 1e-4 and ea < 1e-4
     x2 = T(w["x"]).requires_grad_()
     m2 = fu.MMD2.apply(x2, a.detach(), y, b, {"kernel": "gauss", "lam": 0.01, "grid": 64})
     m2.backward()
