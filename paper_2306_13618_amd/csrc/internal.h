@@ -150,6 +150,30 @@ inline unsigned blocks_for(int64_t work, int threads, int64_t cap = 1 << 20) {
 void fill_f32(float *p, int64_t n, float v, hipStream_t s);
 void fill_f64(double *p, int64_t n, double v, hipStream_t s);
 void fill_i32(int *p, int64_t n, int v, hipStream_t s);
+// Several fills in one launch: ranges are collected by add_* and written by launch() (also
+// called by add_* when the batch is full).  Elements of 4 or 8 bytes.
+class FillBatch {
+public:
+    static constexpr int MAX = 12;
+    struct Args {
+        void *p[MAX];
+        int64_t n[MAX];
+        uint64_t v[MAX];
+        int wide[MAX];  // 8-byte elements
+        int k;
+    };
+    explicit FillBatch(hipStream_t s) : s_(s) { a_.k = 0; }
+    void add_f64(double *p, int64_t n, double v);
+    void add_f32(float *p, int64_t n, float v);
+    void add_i32(int *p, int64_t n, int v);
+    void launch();
+
+private:
+    void add(void *p, int64_t n, uint64_t bits, int wide);
+    hipStream_t s_;
+    Args a_;
+    int64_t nmax_ = 0;
+};
 
 // ------------------------------------------------------------------ pass timing
 // When enabled (fs_profile_enable), a ProfScope records HIP events on the launch stream around

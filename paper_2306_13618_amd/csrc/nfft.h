@@ -13,10 +13,13 @@ struct Nodes {
     DevBuf<float> xs;       // sorted coordinates (n x d, data units)
     DevBuf<int4> chunks;    // (tile, first node, node count, 0)
     int nchunks = 0;
-    DevBuf<int> tile_chunk;  // per tile: [first chunk, chunk count]
-    DevBuf<int> multi_tiles;  // tiles holding more than one chunk
+    // per tile: [first chunk, chunk count] (then the binning's totals and groups per tile)
+    DevBuf<int> tile_chunk;
+    // tile lists built on the host in one upload; the pointers below point into it
+    DevBuf<int> tile_lists;
+    const int *multi_tiles = nullptr;  // tiles holding more than one chunk
     int n_multi = 0;
-    DevBuf<int> touched_tiles;  // tiles with a chunk in their 3^d neighbourhood
+    const int *touched_tiles = nullptr;  // tiles with a chunk in their 3^d neighbourhood
     int n_touched = 0;
     // near-field cell list (sources only): cell-sorted index -> tile-sorted position
     DevBuf<int> nf_cell_start;  // ncells + 1
@@ -30,8 +33,8 @@ struct Nodes {
     DevBuf<int4> mgroups, mblocks;
     DevBuf<int2> mbnodes;  // per block: first node, node count
     int n_mgroups = 0, n_mblocks = 0;
-    DevBuf<int> mtile_block;   // per tile: [first block, block count]
-    DevBuf<int> mmulti_tiles;  // tiles holding more than one block
+    const int *mtile_block = nullptr;   // per tile: [first block, block count]
+    const int *mmulti_tiles = nullptr;  // tiles holding more than one block
     int n_mmulti = 0;
 };
 

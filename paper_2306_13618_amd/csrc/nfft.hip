@@ -20,8 +20,10 @@
 //    first forward pass of each axis; the multiply by M_k is fused between the forward and inverse
 //    transform of the last axis.
 #include <algorithm>
+#include <array>
 #include <cfloat>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 
@@ -2885,31 +2887,30 @@ int mfma_slots(int W, int d, int T) {
 // workgroups): a second, partly filled round of workgroups would nearly double the pass.
 struct MGroupBuild {
     int64_t nbricks = 0;
-    DevBuf<int> gcount, tgroups;
-    const int *tg = nullptr;  // groups per tile (pinned host copy, valid after the synchronisation)
+    DevBuf<int> gcount;
+    int *tgroups = nullptr;   // groups per tile (device, in the binning's count table)
+    const int *tg = nullptr;  // pinned host copy of tgroups, valid after the synchronisation
 };
 
-// Stage 1 (before the synchronisation): groups per brick and per tile; the per-tile counts are
-// copied to mg.tg.
+// Stage 1 (before the synchronisation): groups per brick and per tile (into tgroups).
 void mgroups_count(MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles,
-                   int64_t cells_per_tile, hipStream_t s, HostStage &hs) {
+                   int64_t cells_per_tile, int *tgroups, hipStream_t s) {
     mg.nbricks = ntiles * cells_per_tile / BRICK_X;
     mg.gcount.alloc(mg.nbricks + 1);
-    mg.tgroups.alloc(ntiles);
+    mg.tgroups = tgroups;
     hipLaunchKernelGGL(k_brick_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
                        mg.nbricks, (int)n, mg.gcount.p);
     FS_LAUNCHED();
     hipLaunchKernelGGL(k_tile_sum, dim3((unsigned)ntiles), dim3(256), 0, s, mg.gcount.p,
-                       (int)ntiles, (int)(cells_per_tile / BRICK_X), mg.tgroups.p);
+                       (int)ntiles, (int)(cells_per_tile / BRICK_X), mg.tgroups);
     FS_LAUNCHED();
-    mg.tg = hs.download(mg.tgroups.p, (size_t)ntiles);
 }
 
-// Stage 2 (after it): block size from the per-tile counts, then the group and block tables.
-// Temporaries go to `keep`; the host tables are uploaded through the pinned stage `hs`.
-void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles,
-                  const PlanParams &pp, int slots, hipStream_t s,
-                  std::vector<DevBuf<int>> &keep, HostStage &hs) {
+// Stage 2 (after it), host part: block size from the per-tile counts, and per tile the first
+// group, then [first block, block count], then the tiles with several blocks, appended to `tab`
+// (at offset `off`, returned).  Returns the groups per block.
+int mgroups_plan(Nodes &nd, const MGroupBuild &mg, int64_t n, int64_t ntiles,
+                 const PlanParams &pp, int slots, std::vector<int> &tab, size_t &off) {
     const int *tg = mg.tg;
     int64_t total = 0;
     int tmax = 0;
@@ -2933,40 +2934,48 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
         else lo = mid + 1;
     }
     const int gpb = lo;
-    // per tile: first group, [first block, block count]; tiles with several blocks
-    std::vector<int> tgstart(ntiles), tblock(2 * ntiles), multi;
+    // at most n / 16 full groups plus one partial group per non-empty brick
+    const int64_t cap = n / 16 + std::min<int64_t>(n, mg.nbricks) + 1;
+    FS_REQUIRE(total <= cap, FS_EINVAL, "group count %lld above its bound", (long long)total);
+    off = tab.size();
+    tab.resize(off + 3 * ntiles);
+    int *tgstart = tab.data() + off, *tblock = tgstart + ntiles;
     int64_t g0 = 0, b0 = 0;
+    int nmulti = 0;
     for (int64_t t = 0; t < ntiles; ++t) {
         const int nb = (tg[t] + gpb - 1) / gpb;
         tgstart[t] = (int)g0;
         tblock[2 * t] = (int)b0;
         tblock[2 * t + 1] = nb;
-        if (nb > 1) multi.push_back((int)t);
+        nmulti += nb > 1;
         g0 += tg[t];
         b0 += nb;
     }
-    // at most n / 16 full groups plus one partial group per non-empty brick
-    const int64_t cap = n / 16 + std::min<int64_t>(n, mg.nbricks) + 1;
-    FS_REQUIRE(total <= cap, FS_EINVAL, "group count %lld above its bound", (long long)total);
+    for (int64_t t = 0; t < ntiles; ++t)
+        if (tab[off + ntiles + 2 * t + 1] > 1) tab.push_back((int)t);
     nd.n_mgroups = (int)total;
     nd.n_mblocks = (int)b0;
-    nd.n_mmulti = (int)multi.size();
-    DevBuf<int> gstart(mg.nbricks + 1), dtgstart(ntiles);
-    nd.mtile_block.alloc(2 * ntiles);
-    nd.mgroups.alloc(std::max<int64_t>(total, 1));
+    nd.n_mmulti = nmulti;
+    return gpb;
+}
+
+// Stage 2, device part: the group and block tables, given the uploaded per-tile tables `dtab`
+// (laid out as mgroups_plan writes them).  Temporaries go to `keep`.
+void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int64_t ntiles,
+                  const PlanParams &pp, int gpb, const int *dtab, hipStream_t s,
+                  std::vector<DevBuf<int>> &keep) {
+    nd.mtile_block = dtab + ntiles;
+    nd.mmulti_tiles = dtab + 3 * ntiles;
+    DevBuf<int> gstart(mg.nbricks + 1);
+    nd.mgroups.alloc(std::max<int64_t>(nd.n_mgroups, 1));
     nd.mblocks.alloc(nd.n_mblocks + 1);
-    nd.mmulti_tiles.alloc(std::max<size_t>(multi.size(), 1));
-    hs.upload(dtgstart.p, tgstart.data(), ntiles * sizeof(int));
-    hs.upload(nd.mtile_block.p, tblock.data(), 2 * ntiles * sizeof(int));
-    hs.upload(nd.mmulti_tiles.p, multi.data(), multi.size() * sizeof(int));
     exclusive_scan(mg.gcount.p, mg.nbricks, gstart.p, s, &keep);
     hipLaunchKernelGGL(k_fill_groups, dim3(blocks_for(mg.nbricks, 256)), dim3(256), 0, s, kstart,
                        gstart.p, mg.nbricks, (int)n, pp.d, pp.T, pp.T + pp.W - 1, nd.mgroups.p);
     FS_LAUNCHED();
     if (nd.n_mblocks > 0) {
         hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
-                           (int)ntiles, dtgstart.p, mg.tgroups.p, nd.mtile_block.p, gpb,
-                           nd.mblocks.p);
+                           (int)ntiles, dtab, mg.tgroups, nd.mtile_block, gpb, nd.mblocks.p);
         FS_LAUNCHED();
         nd.mbnodes.alloc(nd.n_mblocks);
         hipLaunchKernelGGL(k_block_nodes, dim3(blocks_for(nd.n_mblocks, 256)), dim3(256), 0, s,
@@ -2974,34 +2983,55 @@ void mgroups_fill(Nodes &nd, MGroupBuild &mg, const int *kstart, int64_t n, int6
         FS_LAUNCHED();
     }
     keep.push_back(std::move(gstart));
-    keep.push_back(std::move(dtgstart));
     keep.push_back(std::move(mg.gcount));
-    keep.push_back(std::move(mg.tgroups));
 }
 
-// Tile/cell binning of one point set.  Temporaries go to the build's stage `hs` (freed after its
-// final synchronisation).
-void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hipStream_t s,
-               HostStage &hs) {
+// Tile/cell binning of one point set, in two stages around a host synchronisation that the
+// caller makes (one for both point sets of a plan).  Temporaries go to the build's stage `hs`
+// (freed after its final synchronisation).
+struct BinBuild {
+    int64_t n = 0, ntiles = 1, cells_per_tile = 1, nkeys = 0;
+    bool cell_keys = false, mgroups = false;
+    DevBuf<int> key, rank, hist, kstart, tcount, tstart;
+    DevBuf<float4> tmp;
+    const int *tile_hist = nullptr;
+    const int *hcounts = nullptr;  // pinned copy of the plan's tile_chunk table (with the totals
+                                   // and groups per tile), valid after the synchronisation
+    MGroupBuild mg;
+    std::vector<DevBuf<int>> keep;
+};
+
+void bin_nodes_count(Nodes &nd, BinBuild &bb, const float *pts, int64_t n, const PlanParams &pp,
+                     hipStream_t s, HostStage &hs) {
     nd.n = n;
+    bb.n = n;
     const int d = pp.d, G = pp.G, T = pp.T, ntd = G / T;
     int64_t ntiles = 1, cells_per_tile = 1;
     for (int k = 0; k < d; ++k) {
         ntiles *= ntd;
         cells_per_tile *= T;
     }
+    bb.ntiles = ntiles;
+    bb.cells_per_tile = cells_per_tile;
     // order nodes by (tile, cell) when the cell key space is at most 2^24 (64 MB of counters)
     const int64_t ncellkeys = ntiles * cells_per_tile;
-    const bool cell_keys = ncellkeys <= (int64_t(1) << 24);
-    const int64_t nkeys = cell_keys ? ncellkeys : ntiles;
+    bb.cell_keys = ncellkeys <= (int64_t(1) << 24);
+    bb.nkeys = bb.cell_keys ? ncellkeys : ntiles;
     nd.rec.alloc(n + 1);
     nd.perm.alloc(n + 1);
     nd.xs.alloc(n * d + 1);
-    nd.tile_chunk.alloc(2 * ntiles);
-    DevBuf<int> key(n + 1), rank(n + 1), hist(nkeys), kstart(nkeys), tcount(ntiles),
-        tstart(ntiles), totals(2);
-    DevBuf<float4> tmp(n + 1);
-    fill_i32(hist.p, nkeys, 0, s);
+    // [first chunk, chunk count] per tile, then the totals (2), then the groups per tile: one
+    // download after the kernels
+    nd.tile_chunk.alloc(3 * ntiles + 2);
+    bb.key.alloc(n + 1);
+    bb.rank.alloc(n + 1);
+    bb.hist.alloc(bb.nkeys);
+    bb.kstart.alloc(bb.nkeys);
+    bb.tcount.alloc(ntiles);
+    bb.tstart.alloc(ntiles);
+    bb.tmp.alloc(n + 1);
+    int *totals = nd.tile_chunk.p + 2 * ntiles, *tgroups = totals + 2;
+    fill_i32(bb.hist.p, bb.nkeys, 0, s);
     ScaleArgs sa{};
     for (int k = 0; k < 3; ++k) sa.c[k] = pp.center[k];
     sa.inv_P = 1.0 / pp.P;
@@ -3012,42 +3042,48 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
     sa.S = T + pp.W - 1;
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256), 0, s,
-                           pts, n, sa, (int)cell_keys, key.p, rank.p, tmp.p, hist.p);
+                           pts, n, sa, (int)bb.cell_keys, bb.key.p, bb.rank.p, bb.tmp.p, bb.hist.p);
         FS_LAUNCHED();
     }
-    std::vector<DevBuf<int>> keep;
-    exclusive_scan(hist.p, nkeys, kstart.p, s, &keep);
+    exclusive_scan(bb.hist.p, bb.nkeys, bb.kstart.p, s, &bb.keep);
     // deterministic mode: ranks inside a key in input order instead of the atomic counter's
-    if (pp.stable) stable_ranks(key.p, n, nkeys, kstart.p, rank.p, s);
-    const int *tile_hist = hist.p;
-    if (cell_keys) {
-        hipLaunchKernelGGL(k_tile_counts, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s, kstart.p,
-                           (int)ntiles, (int)cells_per_tile, (int)n, tcount.p);
+    if (pp.stable) stable_ranks(bb.key.p, n, bb.nkeys, bb.kstart.p, bb.rank.p, s);
+    bb.tile_hist = bb.hist.p;
+    if (bb.cell_keys) {
+        hipLaunchKernelGGL(k_tile_counts, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
+                           bb.kstart.p, (int)ntiles, (int)cells_per_tile, (int)n, bb.tcount.p);
         FS_LAUNCHED();
-        tile_hist = tcount.p;
+        bb.tile_hist = bb.tcount.p;
     }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, tile_hist, (int)ntiles, pp.chunk,
-                       tstart.p, nd.tile_chunk.p, totals.p);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, s, bb.tile_hist, (int)ntiles,
+                       pp.chunk, bb.tstart.p, nd.tile_chunk.p, totals);
     FS_LAUNCHED();
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter_nodes, dim3(blocks_for(n, 256, int64_t(1) << 30)), dim3(256),
-                           0, s, pts, n, d, key.p, rank.p, tmp.p, kstart.p, nd.rec.p, nd.perm.p,
-                           nd.xs.p);
+                           0, s, pts, n, d, bb.key.p, bb.rank.p, bb.tmp.p, bb.kstart.p, nd.rec.p,
+                           nd.perm.p, nd.xs.p);
         FS_LAUNCHED();
     }
     // matrix-core groups (d = 2, 3): per-brick and per-tile counts, read back with the chunk table
-    const bool mgroups = (d == 3 || (d == 2 && (T == 32 || T == 16))) && cell_keys &&
-                         T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 && n > 0;
-    MGroupBuild mg;
-    if (mgroups) mgroups_count(mg, kstart.p, n, ntiles, cells_per_tile, s, hs);
-    const int *tot = hs.download(totals.p, 2);
-    const int *tch = hs.download(nd.tile_chunk.p, (size_t)(2 * ntiles));
-    FS_HIP(hipStreamSynchronize(s));
+    bb.mgroups = (d == 3 || (d == 2 && (T == 32 || T == 16))) && bb.cell_keys &&
+                 T % BRICK_X == 0 && pp.W + BRICK_X - 1 <= 16 && n > 0;
+    if (bb.mgroups) mgroups_count(bb.mg, bb.kstart.p, n, ntiles, cells_per_tile, tgroups, s);
+    bb.hcounts = hs.download(nd.tile_chunk.p, (size_t)(bb.mgroups ? 3 * ntiles + 2 : 2 * ntiles + 2));
+}
+
+void bin_nodes_finish(Nodes &nd, BinBuild &bb, const PlanParams &pp, hipStream_t s,
+                      HostStage &hs) {
+    const int d = pp.d, ntd = pp.G / pp.T;
+    const int64_t ntiles = bb.ntiles, n = bb.n;
+    const int *tch = bb.hcounts, *tot = bb.hcounts + 2 * ntiles;
+    bb.mg.tg = tot + 2;
     nd.nchunks = tot[1];
-    std::vector<int> multi;
+    // host tile lists, one upload: tiles with several chunks, touched tiles, then the
+    // matrix-core per-tile tables
+    std::vector<int> tab;
     for (int64_t t = 0; t < ntiles; ++t)
-        if (tch[2 * t + 1] > 1) multi.push_back((int)t);
-    nd.n_multi = (int)multi.size();
+        if (tch[2 * t + 1] > 1) tab.push_back((int)t);
+    nd.n_multi = (int)tab.size();
     // tiles whose 3^d neighbourhood (periodic) holds a chunk: the only ones the fold must sum
     // (occupied tiles dilated by one tile along each axis in turn)
     std::vector<char> occ(ntiles), tmpo(ntiles);
@@ -3062,32 +3098,37 @@ void bin_nodes(Nodes &nd, const float *pts, int64_t n, const PlanParams &pp, hip
         }
         occ.swap(tmpo);
     }
-    std::vector<int> touched;
+    const size_t touched_off = tab.size();
     for (int64_t t = 0; t < ntiles; ++t)
-        if (occ[t]) touched.push_back((int)t);
-    nd.n_touched = (int)touched.size();
-    nd.touched_tiles.alloc(std::max<size_t>(touched.size(), 1));
-    hs.upload(nd.touched_tiles.p, touched.data(), touched.size() * sizeof(int));
-    nd.multi_tiles.alloc(std::max<size_t>(multi.size(), 1));
-    hs.upload(nd.multi_tiles.p, multi.data(), multi.size() * sizeof(int));
+        if (occ[t]) tab.push_back((int)t);
+    nd.n_touched = (int)(tab.size() - touched_off);
+    nd.n_mgroups = nd.n_mblocks = nd.n_mmulti = 0;
+    int gpb = 0;
+    size_t mg_off = 0;
+    if (bb.mgroups)
+        gpb = mgroups_plan(nd, bb.mg, n, ntiles, pp, mfma_slots(pp.W, d, pp.T), tab, mg_off);
+    nd.tile_lists.alloc(std::max<size_t>(tab.size(), 1));
+    hs.upload(nd.tile_lists.p, tab.data(), tab.size() * sizeof(int));
+    nd.multi_tiles = nd.tile_lists.p;
+    nd.touched_tiles = nd.tile_lists.p + touched_off;
     nd.chunks.alloc(nd.nchunks + 1);
     if (nd.nchunks > 0) {
         hipLaunchKernelGGL(k_fill_chunks, dim3(blocks_for(ntiles, 256)), dim3(256), 0, s,
-                           (int)ntiles, tstart.p, tile_hist, nd.tile_chunk.p, pp.chunk,
+                           (int)ntiles, bb.tstart.p, bb.tile_hist, nd.tile_chunk.p, pp.chunk,
                            nd.chunks.p);
         FS_LAUNCHED();
     }
-    nd.n_mgroups = nd.n_mblocks = nd.n_mmulti = 0;
-    if (mgroups) mgroups_fill(nd, mg, kstart.p, n, ntiles, pp, mfma_slots(pp.W, d, T), s, keep, hs);
-    for (auto &b : keep) hs.hold(b);
-    hs.hold(key);
-    hs.hold(rank);
-    hs.hold(hist);
-    hs.hold(kstart);
-    hs.hold(tcount);
-    hs.hold(tstart);
-    hs.hold(totals);
-    hs.hold(tmp);
+    if (bb.mgroups)
+        mgroups_fill(nd, bb.mg, bb.kstart.p, n, ntiles, pp, gpb, nd.tile_lists.p + mg_off, s,
+                     bb.keep);
+    for (auto &b : bb.keep) hs.hold(b);
+    hs.hold(bb.key);
+    hs.hold(bb.rank);
+    hs.hold(bb.hist);
+    hs.hold(bb.kstart);
+    hs.hold(bb.tcount);
+    hs.hold(bb.tstart);
+    hs.hold(bb.tmp);
 }
 
 void build_nearfield_cells(Nodes &nd, const PlanParams &pp, hipStream_t s) {
@@ -3222,6 +3263,88 @@ MultKey mult_key(const PlanParams &pp, double b) {
 }
 }  // namespace
 
+namespace {
+// Host tables of the window (they depend on m, N and G only): the segment polynomials of value
+// and derivative, and for d = 3 the moment-form spread's transform operands.  Kept for the
+// process, so that repeated plans of one grid skip the fits and the FP16 split.
+struct WindowTables {
+    std::vector<float> hp;      // value (W x WPOLY) then derivative
+    std::vector<uint16_t> cc;   // empty unless requested
+};
+std::mutex g_win_mu;
+std::map<std::array<int, 4>, std::shared_ptr<const WindowTables>> g_win;
+constexpr size_t WIN_CACHE = 16;
+
+std::shared_ptr<const WindowTables> window_tables(int m, int N, int G, bool mom) {
+    const std::array<int, 4> key{m, N, G, (int)mom};
+    {
+        std::lock_guard<std::mutex> lk(g_win_mu);
+        auto it = g_win.find(key);
+        if (it != g_win.end()) return it->second;
+    }
+    auto wt = std::make_shared<WindowTables>();
+    const int W = 2 * m;
+    const double b = M_PI * (2.0 - (double)N / G);
+    // window value phi(t + m - 1 - a) and derivative d phi/ds on t in [0, 1), u = 2t - 1
+    wt->hp.assign(2 * W * WPOLY, 0.0f);
+    std::vector<double> cheb(W * WPOLY);
+    double c[WPOLY];
+    for (int a = 0; a < W; ++a) {
+        const double off = m - 1 - a;
+        fit_poly([&](double u) { return kb_value(m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
+        for (int k = 0; k < WPOLY; ++k) wt->hp[a * WPOLY + k] = (float)c[k];
+        // the same polynomial in the Chebyshev basis (exact: interpolation at WPOLY nodes)
+        for (int k = 0; k < WPOLY; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < WPOLY; ++j) {
+                const double th = M_PI * (j + 0.5) / WPOLY, u = std::cos(th);
+                double v = c[WPOLY - 1];
+                for (int q = WPOLY - 2; q >= 0; --q) v = v * u + c[q];
+                acc += v * std::cos(k * th);
+            }
+            cheb[a * WPOLY + k] = acc * (k == 0 ? 1.0 : 2.0) / WPOLY;
+        }
+        fit_poly([&](double u) { return kb_deriv(m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
+        for (int k = 0; k < WPOLY; ++k) wt->hp[(W + a) * WPOLY + k] = (float)c[k];
+    }
+    if (mom) {
+        // transform of the moment-form spread, CC[(y, z)][q = 8 k + l] = C[y][k] C[z][l] x
+        // 2^MOM_CC_SHIFT, as A operands: per (yz block jb, K-step pair sp, part hi / lo, lane),
+        // row (y, z) from lane % 16, K elements q = 16 (2 sp) + 4 (lane / 16) + i then
+        // q = 16 (2 sp + 1) + 4 (lane / 16) + i, i < 4
+        const int NZ = (W + 3) / 4, NB = NZ * NZ, NP = WPOLY * WPOLY / 32;
+        wt->cc.assign((size_t)NB * NP * 2 * 64 * 8, 0);
+        const double up = std::ldexp(1.0, MOM_CC_SHIFT);
+        double amax = 0.0;
+        for (int jb = 0; jb < NB; ++jb)
+            for (int sp = 0; sp < NP; ++sp)
+                for (int ln = 0; ln < 64; ++ln) {
+                    const int col = ln & 15, grp = ln >> 4;
+                    const int y = 4 * (jb / NZ) + (col >> 2), z = 4 * (jb % NZ) + (col & 3);
+                    uint16_t *hi = wt->cc.data() + ((size_t)((jb * NP + sp) * 2 + 0) * 64 + ln) * 8;
+                    uint16_t *lo = wt->cc.data() + ((size_t)((jb * NP + sp) * 2 + 1) * 64 + ln) * 8;
+                    for (int t = 0; t < 8; ++t) {
+                        const int q = 16 * (2 * sp + t / 4) + 4 * grp + t % 4;
+                        const int k = q / WPOLY, l = q % WPOLY;
+                        const double v =
+                            (y < W && z < W) ? cheb[y * WPOLY + k] * cheb[z * WPOLY + l] * up : 0.0;
+                        amax = std::max(amax, std::fabs(v));
+                        const _Float16 h = (_Float16)(float)v;
+                        const _Float16 r = (_Float16)(float)(v - (double)(float)h);
+                        hi[t] = __builtin_bit_cast(uint16_t, h);
+                        lo[t] = __builtin_bit_cast(uint16_t, r);
+                    }
+                }
+        FS_REQUIRE(amax < 65504.0, FS_EUNSUPPORTED,
+                   "window transform %g outside the FP16 range (window %d)", amax, W);
+    }
+    std::lock_guard<std::mutex> lk(g_win_mu);
+    if (g_win.size() >= WIN_CACHE) g_win.clear();
+    g_win.emplace(key, wt);
+    return wt;
+}
+}  // namespace
+
 void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, int d,
                 const fs_params &p, hipStream_t s) {
     PlanParams &pp = pl.pp;
@@ -3265,24 +3388,38 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
 
     // small host <-> device copies of the build (pinned staging, released at the end)
     HostStage hs(s);
+    // window shape for the effective oversampling ratio G / N
+    const double b = M_PI * (2.0 - (double)pp.N / pp.G);
+    pp.kb.m = (float)pp.m;
+    pp.kb.b = (float)b;
+    pp.kb.inv_one_minus = (float)(1.0 / (-std::expm1(-2.0 * b * pp.m)));
     // ---- bounding box of both point sets (A1)
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     {
         const int nb = 512;
-        DevBuf<float> part(nb * 6 * 2);
-        DevBuf<int> bad(1);
-        fill_i32(bad.p, 1, 0, s);
-        fill_f32(part.p, nb * 6 * 2, 0.0f, s);
+        // per-block partials of both sets, then the count of non-finite coordinates
+        DevBuf<float> part(nb * 6 * 2 + 1);
+        int *bad = reinterpret_cast<int *>(part.p + nb * 6 * 2);
+        fill_f32(part.p, nb * 6 * 2 + 1, 0.0f, s);
         if (n > 0) {
-            hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, x, n, d, part.p, bad.p);
+            hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, x, n, d, part.p, bad);
             FS_LAUNCHED();
         }
         if (m > 0 && y != x) {
-            hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, y, m, d, part.p + nb * 6, bad.p);
+            hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(256), 0, s, y, m, d, part.p + nb * 6, bad);
             FS_LAUNCHED();
         }
-        const float *h = hs.download(part.p, (size_t)(nb * 12));
-        const int *hb = hs.download(bad.p, 1);
+        const float *h = hs.download(part.p, (size_t)(nb * 12 + 1));
+        const int *hb = reinterpret_cast<const int *>(h + nb * 12);
+        // ---- window (independent of the data: prepared while the bounding box is reduced)
+        const bool mom = d == 3 && pp.W + BRICK_X - 1 <= 16;
+        const std::shared_ptr<const WindowTables> wt = window_tables(pp.m, pp.N, pp.G, mom);
+        pl.wpoly.alloc(wt->hp.size());
+        hs.upload(pl.wpoly.p, wt->hp.data(), wt->hp.size() * sizeof(float));
+        if (mom) {
+            pl.mom_cc.alloc(wt->cc.size() / 8);
+            hs.upload(pl.mom_cc.p, wt->cc.data(), wt->cc.size() * sizeof(uint16_t));
+        }
         FS_HIP(hipStreamSynchronize(s));
         FS_REQUIRE(*hb == 0, FS_EDOMAIN, "non-finite point coordinates");
         for (int set = 0; set < 2; ++set) {
@@ -3345,77 +3482,16 @@ void plan_build(Plan &pl, const float *x, int64_t n, const float *y, int64_t m, 
     }
     if (pp.regime == REGIME_BALL) boundary_poly(pp.kind, pp.lambda, pp.P, pp.epsB, pp.p, pp.cb);
 
-    // ---- window
-    // window shape for the effective oversampling ratio G / N
-    const double b = M_PI * (2.0 - (double)pp.N / pp.G);
-    pp.kb.m = (float)pp.m;
-    pp.kb.b = (float)b;
-    pp.kb.inv_one_minus = (float)(1.0 / (-std::expm1(-2.0 * b * pp.m)));
-    {
-        // window value phi(t + m - 1 - a) and derivative d phi/ds on t in [0, 1), u = 2t - 1
-        std::vector<float> hp(2 * pp.W * WPOLY);
-        std::vector<double> cheb(pp.W * WPOLY);
-        double c[WPOLY];
-        for (int a = 0; a < pp.W; ++a) {
-            const double off = pp.m - 1 - a;
-            fit_poly([&](double u) { return kb_value(pp.m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
-            for (int k = 0; k < WPOLY; ++k) hp[a * WPOLY + k] = (float)c[k];
-            // the same polynomial in the Chebyshev basis (exact: interpolation at WPOLY nodes)
-            for (int k = 0; k < WPOLY; ++k) {
-                double acc = 0.0;
-                for (int j = 0; j < WPOLY; ++j) {
-                    const double th = M_PI * (j + 0.5) / WPOLY, u = std::cos(th);
-                    double v = c[WPOLY - 1];
-                    for (int q = WPOLY - 2; q >= 0; --q) v = v * u + c[q];
-                    acc += v * std::cos(k * th);
-                }
-                cheb[a * WPOLY + k] = acc * (k == 0 ? 1.0 : 2.0) / WPOLY;
-            }
-            fit_poly([&](double u) { return kb_deriv(pp.m, b, 0.5 * (u + 1.0) + off); }, WPOLY, c);
-            for (int k = 0; k < WPOLY; ++k) hp[(pp.W + a) * WPOLY + k] = (float)c[k];
-        }
-        pl.wpoly.alloc(hp.size());
-        hs.upload(pl.wpoly.p, hp.data(), hp.size() * sizeof(float));
-        if (d == 3 && pp.W + BRICK_X - 1 <= 16) {
-            // transform of the moment-form spread, CC[(y, z)][q = 8 k + l] = C[y][k] C[z][l] x
-            // 2^MOM_CC_SHIFT, as A operands: per (yz block jb, K-step pair sp, part hi / lo,
-            // lane), row (y, z) from lane % 16, K elements q = 16 (2 sp) + 4 (lane / 16) + i
-            // then q = 16 (2 sp + 1) + 4 (lane / 16) + i, i < 4
-            const int NZ = (pp.W + 3) / 4, NB = NZ * NZ, NP = WPOLY * WPOLY / 32;
-            std::vector<uint16_t> cc((size_t)NB * NP * 2 * 64 * 8);
-            const double up = std::ldexp(1.0, MOM_CC_SHIFT);
-            double amax = 0.0;
-            for (int jb = 0; jb < NB; ++jb)
-                for (int sp = 0; sp < NP; ++sp)
-                    for (int ln = 0; ln < 64; ++ln) {
-                        const int col = ln & 15, grp = ln >> 4;
-                        const int y = 4 * (jb / NZ) + (col >> 2), z = 4 * (jb % NZ) + (col & 3);
-                        uint16_t *hi = cc.data() + ((size_t)((jb * NP + sp) * 2 + 0) * 64 + ln) * 8;
-                        uint16_t *lo = cc.data() + ((size_t)((jb * NP + sp) * 2 + 1) * 64 + ln) * 8;
-                        for (int t = 0; t < 8; ++t) {
-                            const int q = 16 * (2 * sp + t / 4) + 4 * grp + t % 4;
-                            const int k = q / WPOLY, l = q % WPOLY;
-                            const double v = (y < pp.W && z < pp.W)
-                                                 ? cheb[y * WPOLY + k] * cheb[z * WPOLY + l] * up
-                                                 : 0.0;
-                            amax = std::max(amax, std::fabs(v));
-                            const _Float16 h = (_Float16)(float)v;
-                            const _Float16 r = (_Float16)(float)(v - (double)(float)h);
-                            hi[t] = __builtin_bit_cast(uint16_t, h);
-                            lo[t] = __builtin_bit_cast(uint16_t, r);
-                        }
-                    }
-            FS_REQUIRE(amax < 65504.0, FS_EUNSUPPORTED,
-                       "window transform %g outside the FP16 range (window %d)", amax, pp.W);
-            pl.mom_cc.alloc(cc.size() / 8);
-            hs.upload(pl.mom_cc.p, cc.data(), cc.size() * sizeof(uint16_t));
-        }
-    }
-
     // ---- bin the point sets (A2)
     pl.same = (y == x && m == n);
-    bin_nodes(pl.X, x, n, pp, s, hs);
-    if (!pl.same) bin_nodes(pl.Y, y, m, pp, s, hs);
+    {
+        BinBuild bx, by;
+        bin_nodes_count(pl.X, bx, x, n, pp, s, hs);
+        if (!pl.same) bin_nodes_count(pl.Y, by, y, m, pp, s, hs);
+        FS_HIP(hipStreamSynchronize(s));
+        bin_nodes_finish(pl.X, bx, pp, s, hs);
+        if (!pl.same) bin_nodes_finish(pl.Y, by, pp, s, hs);
+    }
 
     if (pp.nearfield) {
         // cells of side about radius / R, R chosen so that a cell holds about 32 points: blocks of
@@ -3601,7 +3677,7 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
         // the spread writes one box per chunk (or per matrix-core block); tile_chunk maps a tile
         // to its boxes and multi_tiles lists the tiles with several
         bool mf = false;
-        const int *tile_boxes = src.tile_chunk.p, *multi = src.multi_tiles.p;
+        const int *tile_boxes = src.tile_chunk.p, *multi = src.multi_tiles;
         int n_multi = src.n_multi;
         if (src.nchunks > 0) {
             ProfScope ps("spread", s);
@@ -3636,8 +3712,8 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                                                src.mgroups.p, src.mbnodes.p, sa, pl.scratch.p,
                                                PotWeights{});
                     }
-                    tile_boxes = src.mtile_block.p;
-                    multi = src.mmulti_tiles.p;
+                    tile_boxes = src.mtile_block;
+                    multi = src.mmulti_tiles;
                     n_multi = src.n_mmulti;
                 } else {
                     hipLaunchKernelGGL((k_spread_wave<D, W, T>), dim3(src.nchunks), dim3(256), 0,
@@ -3679,7 +3755,7 @@ void launch_spread_gather(Plan &pl, const Nodes &src, const Nodes &dst, const fl
                 if (nfold > 0)
                     hipLaunchKernelGGL(k_fold_tiles<D>, dim3(nfold, (unsigned)((npts + 255) / 256)),
                                        dim3(256), 0, s, pl.scratch.p, tile_boxes,
-                                       all ? nullptr : src.touched_tiles.p, pp.G, T, ntd, pp.m, S,
+                                       all ? nullptr : src.touched_tiles, pp.G, T, ntd, pp.m, S,
                                        pl.grid.p);
             } else {
                 hipLaunchKernelGGL(k_fold<D>, dim3(blocks_for(gsz, 256, 1 << 16)), dim3(256), 0, s,

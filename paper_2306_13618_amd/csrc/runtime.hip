@@ -371,4 +371,45 @@ void fill_i32(int *p, int64_t n, int v, hipStream_t s) {
     FS_LAUNCHED();
 }
 
+
+__global__ void k_fill_batch(FillBatch::Args a) {
+    const int r = blockIdx.y;
+    const int64_t n = a.n[r];
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+    if (a.wide[r]) {
+        uint64_t *p = static_cast<uint64_t *>(a.p[r]);
+        for (int64_t i = i0; i < n; i += step) p[i] = a.v[r];
+    } else {
+        uint32_t *p = static_cast<uint32_t *>(a.p[r]);
+        const uint32_t v = (uint32_t)a.v[r];
+        for (int64_t i = i0; i < n; i += step) p[i] = v;
+    }
+}
+
+void FillBatch::add(void *p, int64_t n, uint64_t bits, int wide) {
+    if (n <= 0) return;
+    if (a_.k == MAX) launch();
+    a_.p[a_.k] = p;
+    a_.n[a_.k] = n;
+    a_.v[a_.k] = bits;
+    a_.wide[a_.k] = wide;
+    ++a_.k;
+    nmax_ = std::max(nmax_, n);
+}
+void FillBatch::add_f64(double *p, int64_t n, double v) {
+    add(p, n, __builtin_bit_cast(uint64_t, v), 1);
+}
+void FillBatch::add_f32(float *p, int64_t n, float v) {
+    add(p, n, __builtin_bit_cast(uint32_t, v), 0);
+}
+void FillBatch::add_i32(int *p, int64_t n, int v) { add(p, n, (uint32_t)v, 0); }
+void FillBatch::launch() {
+    if (a_.k == 0) return;
+    hipLaunchKernelGGL(k_fill_batch, dim3(blocks_for(nmax_, 256, 2048), a_.k), dim3(256), 0, s_,
+                       a_);
+    FS_LAUNCHED();
+    a_.k = 0;
+    nmax_ = 0;
+}
+
 }  // namespace fs

@@ -924,13 +924,18 @@ struct Scalars {
     Scalars()
         : v(32), fparts(UPD_BLOCKS), gparts(UPD_BLOCKS), dparts(2 * UPD_BLOCKS),
           partial(RBLK * 6), nbad(1) {}
-    void reset(hipStream_t s) {
-        fill_f64(v.p, 32, 0.0, s);
-        fill_f64(fparts.p, UPD_BLOCKS, 0.0, s);
-        fill_f64(gparts.p, UPD_BLOCKS, 0.0, s);
-        fill_f64(dparts.p, 2 * UPD_BLOCKS, 0.0, s);
-        fill_i32(nbad.p, 1, 0, s);
+    void reset(FillBatch &fb) {
+        fb.add_f64(v.p, 32, 0.0);
+        fb.add_f64(fparts.p, UPD_BLOCKS, 0.0);
+        fb.add_f64(gparts.p, UPD_BLOCKS, 0.0);
+        fb.add_f64(dparts.p, 2 * UPD_BLOCKS, 0.0);
+        fb.add_i32(nbad.p, 1, 0);
         nf = ng = 1;
+    }
+    void reset(hipStream_t s) {
+        FillBatch fb(s);
+        reset(fb);
+        fb.launch();
     }
 };
 
@@ -967,11 +972,11 @@ struct FloorState {
     DevBuf<int> taken;      // 2
     int phase = 0;
     bool first = true;  // the first half-step takes the largest sum of its own t
-    void init(hipStream_t s) {
+    void init(FillBatch &fb) {
         tparts.alloc(2 * UPD_BLOCKS);
         taken.alloc(2);
-        fill_f64(tparts.p, 2 * UPD_BLOCKS, 0.0, s);
-        fill_i32(taken.p, 2, 0, s);
+        fb.add_f64(tparts.p, 2 * UPD_BLOCKS, 0.0);
+        fb.add_i32(taken.p, 2, 0);
     }
 };
 
@@ -1106,7 +1111,8 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     const int64_t n = op.n, m = op.m;
     const double kappa = rho / (rho + eps);
     Scalars sc;
-    sc.reset(s);
+    FillBatch fb(s);  // the solve's initial fills, one launch
+    sc.reset(fb);
     DevBuf<float> wX(n + 1), wY(m + 1), tX(n + 1), tY(m + 1);
     // log-domain direct sums (no underflow for rows far from every source) where they apply
     const bool logd = op.log_direct();
@@ -1114,8 +1120,8 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     // fast path, unfused half-steps: rows at the fast sum's error floor are re-evaluated directly
     FloorState floorX, floorY;  // targets X (beta half-steps), Y (gamma half-steps)
     if (op.fast) {
-        floorX.init(s);
-        floorY.init(s);
+        floorX.init(fb);
+        floorY.init(fb);
     }
     FloorSrc srcY{}, srcX{};
     if (op.fast) {
@@ -1124,11 +1130,13 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
         srcX = FloorSrc{op.coords(1), op.coords(0), a_o, f_o, n, op.d, r, 1.0 / eps};
     }
     if (warm) {
+        fb.launch();  // before the maxima are written into the cleared parts
         if (m > 0) sc.ng = launch_max_parts(g_o, m, sc.gparts.p, s);
         if (n > 0) sc.nf = launch_max_parts(f_o, n, sc.fparts.p, s);
     } else {
-        fill_f64(g_o, m, 0.0, s);
-        fill_f64(f_o, n, 0.0, s);
+        fb.add_f64(g_o, m, 0.0);
+        fb.add_f64(f_o, n, 0.0);
+        fb.launch();
     }
     // fused half-steps: each side's largest |base| per source block, and whether that side's
     // potential maxima come from a fused update (then they are per source block)
