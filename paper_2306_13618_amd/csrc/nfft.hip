@@ -374,24 +374,38 @@ constexpr int FFT_BATCH = 4;  // loads per thread in flight in the FFT passes' l
 constexpr int FFT_ELEMS = 4096;  // complex elements per LDS buffer (two buffers: 64 KB)
 
 // ------------------------------------------------------------------ scaling and binning
-__global__ void k_bbox(const float *__restrict__ p, int64_t n, int d, float *__restrict__ part,
-                       int *__restrict__ nonfinite) {
+// Per-workgroup coordinate ranges of n points (n x d floats): the array is read flat with a grid
+// stride that is a multiple of d, so every thread sees one coordinate k; four loads per thread in
+// flight.  part[6 b + k] / part[6 b + 3 + k]: workgroup b's minimum and maximum of coordinate k.
+__global__ void __launch_bounds__(256) k_bbox(const float *__restrict__ p, int64_t n, int d,
+                                              float *__restrict__ part, int *__restrict__ nonfinite) {
     __shared__ float smin[256 * 3], smax[256 * 3];
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    int bad = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        for (int k = 0; k < d; ++k) {
-            float v = p[i * d + k];
-            if (!isfinite(v)) bad = 1;
-            lo[k] = fminf(lo[k], v);
-            hi[k] = fmaxf(hi[k], v);
+    const int64_t total = n * d;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t stride = nthreads / d * d;
+    const int64_t j0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int kc = (int)(j0 % d);
+    float l = INFINITY, h = -INFINITY;
+    bool bad = false;
+    if (j0 < stride) {
+        int64_t j = j0;
+        for (; j + 3 * stride < total; j += 4 * stride) {
+            const float v0 = p[j], v1 = p[j + stride], v2 = p[j + 2 * stride], v3 = p[j + 3 * stride];
+            bad |= !(isfinite(v0) && isfinite(v1) && isfinite(v2) && isfinite(v3));
+            l = fminf(l, fminf(fminf(v0, v1), fminf(v2, v3)));
+            h = fmaxf(h, fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)));
+        }
+        for (; j < total; j += stride) {
+            const float v = p[j];
+            bad |= !isfinite(v);
+            l = fminf(l, v);
+            h = fmaxf(h, v);
         }
     }
     if (bad) atomicAdd(nonfinite, 1);
     for (int k = 0; k < 3; ++k) {
-        smin[threadIdx.x * 3 + k] = lo[k];
-        smax[threadIdx.x * 3 + k] = hi[k];
+        smin[threadIdx.x * 3 + k] = (k == kc) ? l : INFINITY;
+        smax[threadIdx.x * 3 + k] = (k == kc) ? h : -INFINITY;
     }
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
