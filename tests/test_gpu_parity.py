@@ -241,17 +241,21 @@ def test_plan_multiplier_against_the_gaussian_fourier_series(d, grid, bandwidth,
 
 
 def test_plan_multiplier_reuse():
-    """Plans that differ in kernel, lambda, grid, window or dimension, then the same plans again in
-    reverse order: the multipliers M_k come from the library's cache of recent plans (four
-    entries, least recently used first) for the last ones and are recomputed for the first ones
-    after their eviction, and again after fs_release_cache.  Every result against the oracle, and
-    the later runs against the first."""
+    """Plans that differ in kernel, lambda, grid, window, bandwidth or dimension, then the same
+    plans again in reverse order: the multipliers M_k come from the library's cache of recent
+    plans (four entries, least recently used first) for the last ones and are recomputed for the
+    first ones after their eviction, and again after fs_release_cache.  The window tables are
+    cached per (window, bandwidth, grid, moment-form operands): the second and third plans share
+    the first one's window and grid but not its bandwidth or dimension, so a table taken from the
+    wrong entry would change their window shape.  Every result against the oracle, and the later
+    runs against the first."""
     x3, y3, v3 = clouds(3, 3001, 2777, 2)
     x2, y2, v2 = clouds(2, 3001, 2777, 2)
     cases = [
         ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=64, window=6)),
-        ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=64, window=4)),
+        ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=64, window=6, bandwidth=40)),
         ((x2, y2, v2), dict(kernel="gauss", lam=0.02, grid=64, window=6)),
+        ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=64, window=4)),
         ((x3, y3, v3), dict(kernel="gauss", lam=0.02, grid=128, window=6)),
         ((x3, y3, v3), dict(kernel="laplace", lam=0.01, grid=128, window=6)),
         ((x3, y3, v3), dict(kernel="gauss", lam=0.005, grid=128, window=5)),
