@@ -417,6 +417,19 @@ def test_fastsum_edge_cases():
     got = fu.fastsum_apply(T(xs), T(xs), T(np.ones(50, np.float32)), kernel="gauss", lam=0.05,
                            grid=32).cpu().numpy()
     assert np.allclose(got, 50.0, rtol=TOL)
+    # a 3-D set binned into matrix-core groups with an empty or a one-point partner set (both
+    # sets are binned around one synchronisation, the empty one with no node kernels)
+    x3, y3, v3 = dense_and_sparse(20_000, 18_001, 41, frac=0.95)
+    kw = dict(kernel="gauss", lam=0.02, grid=64, window=6)
+    out = fu.fastsum_apply(T(x3), T(y3[:0]), T(v3[:0]), **kw)
+    assert out.numel() == len(x3) and float(out.abs().max()) == 0.0
+    out = fu.fastsum_apply(T(x3[:0]), T(y3), T(v3), **kw)
+    assert out.numel() == 0
+    rows = synth.sample_rows(len(x3), 64, seed=3)
+    got = fu.fastsum_apply(T(x3), T(y3[:1]), T(v3[:1]), **kw).cpu().numpy()
+    assert relinf(got[rows], oracle.direct_sum_rows(x3, rows, y3[:1], v3[:1], "gauss", 0.02)) < TOL
+    got = fu.fastsum_apply(T(x3[:1]), T(y3), T(v3), **kw).cpu().numpy()
+    assert relinf(got, oracle.direct_sum(x3[:1], y3, v3, "gauss", 0.02)) < TOL
 
 
 @pytest.mark.parametrize("case", ["gauss_d3_matrix_cores", "laplace_d3_near_field",
