@@ -240,6 +240,21 @@ def test_plan_multiplier_against_the_gaussian_fourier_series(d, grid, bandwidth,
     assert err < 1e-6
 
 
+def test_fastsum_3d_grid512_tile_keys():
+    """A 512^3 grid: its 2^27 cells exceed the binning's cell-key space, so nodes are sorted by
+    tile only and every pass takes the chunk path (lane-per-node spread and gather, the fold over
+    the tiles with a chunk nearby after a clearing pass, the strided FFT passes at their largest
+    size).  Both directions of one plan against the oracle."""
+    x, y, v = clouds(3, 5000, 4001, 12)
+    w = np.random.default_rng(13).uniform(0.5, 1.5, len(x)).astype(np.float32)
+    pl = fu.Plan(T(x), T(y), kernel="gauss", lam=0.002, grid=512, window=6)
+    got = pl.apply(T(v)).cpu().numpy()
+    got_t = pl.apply(T(w), transpose=True).cpu().numpy()
+    pl.close()
+    assert relinf(got, oracle.direct_sum(x, y, v, "gauss", 0.002)) < TOL
+    assert relinf(got_t, oracle.direct_sum(y, x, w, "gauss", 0.002)) < TOL
+
+
 def test_plan_multiplier_reuse():
     """Plans that differ in kernel, lambda, grid, window, bandwidth or dimension, then the same
     plans again in reverse order: the multipliers M_k come from the library's cache of recent
