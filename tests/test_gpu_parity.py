@@ -240,6 +240,22 @@ def test_plan_multiplier_against_the_gaussian_fourier_series(d, grid, bandwidth,
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("d,grid,window,kind,lam", [(3, 64, 8, "gauss", 0.02),
+                                                     (3, 64, 7, "gauss", 0.005),
+                                                     (3, 64, 8, "laplace", 0.05),
+                                                     (2, 128, 8, "laplace", 0.05),
+                                                     (2, 128, 7, "energy", 1.0),
+                                                     (1, 64, 8, "gauss", 0.02)])
+def test_fastsum_wide_windows(d, grid, window, kind, lam):
+    """Windows of 14 and 16 points (cutoffs 7 and 8: too wide for the matrix-core groups, so the
+    lane-per-node spread and gather run with their widest boxes), with and without the near field,
+    against the oracle."""
+    x, y, v = clouds(d, 3000, 2777, 14)
+    got = fu.fastsum_apply(T(x), T(y), T(v), kernel=kind, lam=lam, grid=grid,
+                           window=window).cpu().numpy()
+    assert relinf(got, oracle.direct_sum(x, y, v, kind, lam)) < TOL
+
+
 def test_fastsum_3d_grid512_tile_keys():
     """A 512^3 grid: its 2^27 cells exceed the binning's cell-key space, so nodes are sorted by
     tile only and every pass takes the chunk path (lane-per-node spread and gather, the fold over
