@@ -3,6 +3,8 @@
 // internal failures (fs::Error) into a negative fs_status and records the message.
 #include <algorithm>
 #include <mutex>
+#include <string>
+#include <thread>
 
 #include "solver.h"
 
@@ -42,6 +44,83 @@ char *noalloc_scratch() {
         g_scratch_dev[dev] = ptr;
     }
     return static_cast<char *>(g_scratch_dev[dev]);
+}
+
+// Two streams of the library per device (default priority, not synchronising with the null
+// stream) for the terms of a Sinkhorn divergence that run beside the caller's stream; created on
+// first use and kept for the process.
+std::mutex g_side_mu;
+hipStream_t g_side[MAX_DEVICES][2] = {};
+
+hipStream_t side_stream(int k) {
+    int dev = 0;
+    FS_HIP(hipGetDevice(&dev));
+    FS_REQUIRE(dev >= 0 && dev < MAX_DEVICES, FS_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[dev][k]) FS_HIP(hipStreamCreateWithFlags(&g_side[dev][k], hipStreamNonBlocking));
+    return g_side[dev][k];
+}
+
+// Runs three independent pieces of work: f0 on the caller's stream s in this thread, f1 and f2
+// on the two side streams in threads of their own (the current device made current there).  The
+// side streams first wait for the work queued on s so far.  Each piece synchronises its own
+// stream before it returns, so all three have finished on return; an error in a side piece is
+// raised here with its status and message after every piece has ended.
+template <class F0, class F1, class F2>
+void run_three(hipStream_t s, F0 &&f0, F1 &&f1, F2 &&f2) {
+    int dev = 0;
+    FS_HIP(hipGetDevice(&dev));
+    hipStream_t s1 = side_stream(0), s2 = side_stream(1);
+    hipEvent_t ready = nullptr;
+    FS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    struct Result {
+        int code = FS_OK;
+        std::string msg;
+    };
+    Result r1, r2;
+    auto side = [dev](auto &f, hipStream_t st, Result &r) {
+        try {
+            clear_error();
+            FS_HIP(hipSetDevice(dev));
+            f(st);
+        } catch (const Error &e) {
+            r.code = e.code;
+            r.msg = last_error();
+        } catch (const std::bad_alloc &) {
+            r.code = FS_ENOMEM;
+            r.msg = "host allocation failed";
+        } catch (...) {
+            r.code = FS_EHIP;
+            r.msg = "unexpected internal error";
+        }
+    };
+    {
+        const hipError_t e0 = hipEventRecord(ready, s);
+        const hipError_t e1 = (e0 == hipSuccess) ? hipStreamWaitEvent(s1, ready, 0) : e0;
+        const hipError_t e2 = (e1 == hipSuccess) ? hipStreamWaitEvent(s2, ready, 0) : e1;
+        if (e2 != hipSuccess) {
+            (void)hipEventDestroy(ready);
+            FS_HIP(e2);
+        }
+    }
+    std::thread t1([&] { side(f1, s1, r1); });
+    std::thread t2([&] { side(f2, s2, r2); });
+    try {
+        f0(s);
+    } catch (...) {
+        t1.join();
+        t2.join();
+        (void)hipEventDestroy(ready);
+        throw;
+    }
+    t1.join();
+    t2.join();
+    (void)hipEventDestroy(ready);
+    for (const Result *r : {&r1, &r2})
+        if (r->code != FS_OK) {
+            set_error("%s", r->msg.c_str());
+            throw Error{r->code};
+        }
 }
 
 void check_params(const fs_params *p) {
@@ -423,9 +502,19 @@ int sinkhorn_divergence(const float *x, const float *a, int64_t n, const float *
         DevBuf<double> t1(n + 1), t2(m + 1), t3(n + 1), t4(n + 1), t5(m + 1), t6(m + 1);
         double *fab = f_ab ? f_ab : t1.p, *gab = g_ab ? g_ab : t2.p;
         double *faa = f_aa ? f_aa : t3.p, *fbb = f_bb ? f_bb : t5.p;
-        const double uab = solve_uot(x, a, n, y, b, m, d, q, rho, iters, false, fab, gab, s);
-        const double uaa = solve_uot(x, a, n, x, a, n, d, q, rho, iters, false, faa, t4.p, s);
-        const double ubb = solve_uot(y, b, m, y, b, m, d, q, rho, iters, false, fbb, t6.p, s);
+        // the three transport problems are independent: they run side by side
+        double uab = 0.0, uaa = 0.0, ubb = 0.0;
+        run_three(
+            s,
+            [&](hipStream_t st) {
+                uab = solve_uot(x, a, n, y, b, m, d, q, rho, iters, false, fab, gab, st);
+            },
+            [&](hipStream_t st) {
+                uaa = solve_uot(x, a, n, x, a, n, d, q, rho, iters, false, faa, t4.p, st);
+            },
+            [&](hipStream_t st) {
+                ubb = solve_uot(y, b, m, y, b, m, d, q, rho, iters, false, fbb, t6.p, st);
+            });
         const double Ma = device_sum(a, n, s), Mb = device_sum(b, m, s);
         // eq. (586) with the paper's 1/lambda equal to the temperature lambda here
         const double val = uab - 0.5 * uaa - 0.5 * ubb + 0.5 * p->lambda * (Ma - Mb) * (Ma - Mb);
@@ -462,24 +551,30 @@ int sinkhorn_divergence_grad(const float *x, const float *a, int64_t n, const fl
         // symmetric optimum is twice the one-slot envelope gradient, so the 1/2 cancels.
         DevBuf<float> gx1(n * d + 1), ga1(n + 1), gx2(n * d + 1), ga2(n + 1);
         DevBuf<float> gy1(m * d + 1), gb1(m + 1), gy2(m * d + 1), gb2(m + 1);
-        {
-            auto op = make_op(x, n, y, m, d, *p, s);
-            uot_grad_core(*op, a, b, f_ab, g_ab, eps, rho, 1.0, dx ? gx1.p : nullptr,
-                          da ? ga1.p : nullptr, dy ? gy1.p : nullptr, db ? gb1.p : nullptr, s);
-            FS_HIP(hipStreamSynchronize(s));
-        }
-        if (dx || da) {
-            auto op = make_op(x, n, x, n, d, *p, s);
-            uot_grad_core(*op, a, a, f_aa, f_aa, eps, rho, 1.0, dx ? gx2.p : nullptr,
-                          da ? ga2.p : nullptr, nullptr, nullptr, s);
-            FS_HIP(hipStreamSynchronize(s));
-        }
-        if (dy || db) {
-            auto op = make_op(y, m, y, m, d, *p, s);
-            uot_grad_core(*op, b, b, f_bb, f_bb, eps, rho, 1.0, dy ? gy2.p : nullptr,
-                          db ? gb2.p : nullptr, nullptr, nullptr, s);
-            FS_HIP(hipStreamSynchronize(s));
-        }
+        // the three envelope gradients are independent: they run side by side
+        run_three(
+            s,
+            [&](hipStream_t st) {
+                auto op = make_op(x, n, y, m, d, *p, st);
+                uot_grad_core(*op, a, b, f_ab, g_ab, eps, rho, 1.0, dx ? gx1.p : nullptr,
+                              da ? ga1.p : nullptr, dy ? gy1.p : nullptr, db ? gb1.p : nullptr,
+                              st);
+                FS_HIP(hipStreamSynchronize(st));
+            },
+            [&](hipStream_t st) {
+                if (!(dx || da)) return;
+                auto op = make_op(x, n, x, n, d, *p, st);
+                uot_grad_core(*op, a, a, f_aa, f_aa, eps, rho, 1.0, dx ? gx2.p : nullptr,
+                              da ? ga2.p : nullptr, nullptr, nullptr, st);
+                FS_HIP(hipStreamSynchronize(st));
+            },
+            [&](hipStream_t st) {
+                if (!(dy || db)) return;
+                auto op = make_op(y, m, y, m, d, *p, st);
+                uot_grad_core(*op, b, b, f_bb, f_bb, eps, rho, 1.0, dy ? gy2.p : nullptr,
+                              db ? gb2.p : nullptr, nullptr, nullptr, st);
+                FS_HIP(hipStreamSynchronize(st));
+            });
         if (dx) combine(gx1.p, gx2.p, n * d, scale, -scale, 0.0, dx, s);
         if (da) combine(ga1.p, ga2.p, n, scale, -scale, scale * eps * (Ma - Mb), da, s);
         if (dy) combine(gy1.p, gy2.p, m * d, scale, -scale, 0.0, dy, s);

@@ -21,6 +21,7 @@
 //    transform of the last axis.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cfloat>
 #include <cstring>
 #include <map>
@@ -2854,12 +2855,15 @@ int mfma_blocks_per_cu_2d() {
 
 // Resident matrix-core workgroups on the chip for window width W (d = 3, or d = 2 with tile T).
 int mfma_slots(int W, int d, int T) {
-    static int cache[16][2][17] = {};
+    // per device, kind and width (plans may be built from several host threads at once)
+    static std::atomic<int> cache[16][2][17];
     int dev = 0;
     FS_HIP(hipGetDevice(&dev));
     const int v = (d == 3) ? 0 : 1;
-    if (dev < 16 && W <= 16 && (d == 3 || T == 32) && cache[dev][v][W] > 0)
-        return cache[dev][v][W];
+    if (dev < 16 && W <= 16 && (d == 3 || T == 32)) {
+        const int c = cache[dev][v][W].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
     int cus = 0, per = 1;
     FS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (d == 3) {
@@ -2891,7 +2895,8 @@ int mfma_slots(int W, int d, int T) {
         }
     }
     const int slots = std::max(1, cus * per);
-    if (dev < 16 && W <= 16 && (d == 3 || T == 32)) cache[dev][v][W] = slots;
+    if (dev < 16 && W <= 16 && (d == 3 || T == 32))
+        cache[dev][v][W].store(slots, std::memory_order_relaxed);
     return slots;
 }
 
