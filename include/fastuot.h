@@ -232,14 +232,20 @@ int uot_sinkhorn_grad(const float *x, const float *a, int64_t n, const float *y,
  *   S = UOT(a,b) - UOT(a,a)/2 - UOT(b,b)/2 + (lambda/2) (sum a - sum b)^2,
  *   each UOT value the dual value after `iters` sweeps.  Potentials of the three problems are
  *   written to f_ab (n), g_ab (m), f_aa (n), f_bb (m) (device float64; each may be NULL) for the
- *   backward pass; terms3_host (nullable) receives the three UOT values. */
+ *   backward pass; terms3_host (nullable) receives the three UOT values.  The three problems are
+ *   independent and run side by side: UOT(a,b) on `stream`, the self terms on two streams the
+ *   library keeps per device (default priority) from host threads of its own, all ordered after
+ *   the work already queued on `stream`.  The call returns when all three have finished; an error
+ *   in any of them is returned with its message. */
 int sinkhorn_divergence(const float *x, const float *a, int64_t n, const float *y, const float *b,
                         int64_t m, int d, const fs_params *p, double rho, int iters,
                         double *f_ab, double *g_ab, double *f_aa, double *f_bb,
                         double *value_host, double *terms3_host, void *stream);
 
 /* Gradient of the Sinkhorn divergence from the potentials written by sinkhorn_divergence
- * (the symmetric problems contribute twice their one-slot envelope gradient), scaled by `scale`. */
+ * (the symmetric problems contribute twice their one-slot envelope gradient), scaled by `scale`.
+ * The three envelope gradients run side by side as the three problems do in
+ * sinkhorn_divergence; the call returns when the gradients are written. */
 int sinkhorn_divergence_grad(const float *x, const float *a, int64_t n, const float *y,
                              const float *b, int64_t m, int d, const fs_params *p, double rho,
                              const double *f_ab, const double *g_ab, const double *f_aa,
