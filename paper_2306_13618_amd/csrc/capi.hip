@@ -46,31 +46,16 @@ char *noalloc_scratch() {
     return static_cast<char *>(g_scratch_dev[dev]);
 }
 
-// Two streams of the library per device (default priority, not synchronising with the null
-// stream) for the terms of a Sinkhorn divergence that run beside the caller's stream; created on
-// first use and kept for the process.
-std::mutex g_side_mu;
-hipStream_t g_side[MAX_DEVICES][2] = {};
-
-hipStream_t side_stream(int k) {
-    int dev = 0;
-    FS_HIP(hipGetDevice(&dev));
-    FS_REQUIRE(dev >= 0 && dev < MAX_DEVICES, FS_EUNSUPPORTED, "device index %d out of range", dev);
-    std::lock_guard<std::mutex> lk(g_side_mu);
-    if (!g_side[dev][k]) FS_HIP(hipStreamCreateWithFlags(&g_side[dev][k], hipStreamNonBlocking));
-    return g_side[dev][k];
-}
-
 // Runs three independent pieces of work: f0 on the caller's stream s in this thread, f1 and f2
-// on the two side streams in threads of their own (the current device made current there).  The
-// side streams first wait for the work queued on s so far.  Each piece synchronises its own
+// on library streams 0 and 1 in threads of their own (the current device made current there).
+// The side streams first wait for the work queued on s so far.  Each piece synchronises its own
 // stream before it returns, so all three have finished on return; an error in a side piece is
 // raised here with its status and message after every piece has ended.
 template <class F0, class F1, class F2>
 void run_three(hipStream_t s, F0 &&f0, F1 &&f1, F2 &&f2) {
     int dev = 0;
     FS_HIP(hipGetDevice(&dev));
-    hipStream_t s1 = side_stream(0), s2 = side_stream(1);
+    hipStream_t s1 = library_stream(0), s2 = library_stream(1);
     hipEvent_t ready = nullptr;
     FS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     struct Result {

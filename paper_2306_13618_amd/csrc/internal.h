@@ -146,6 +146,12 @@ inline unsigned blocks_for(int64_t work, int threads, int64_t cap = 1 << 20) {
     return static_cast<unsigned>(b);
 }
 
+// Streams the library keeps per device (default priority, not synchronising with the null
+// stream), created on first use: they carry the self terms of a Sinkhorn divergence.  Work on
+// them is ordered against the caller's stream by events.
+constexpr int LIB_STREAMS = 2;
+hipStream_t library_stream(int k);
+
 // Device fill (used instead of hipMemsetAsync so that callers may capture the work in a graph).
 void fill_f32(float *p, int64_t n, float v, hipStream_t s);
 void fill_f64(double *p, int64_t n, double v, hipStream_t s);

@@ -347,6 +347,24 @@ void profile_reset() {
     p.totals.clear();
 }
 
+// ------------------------------------------------------------------ library streams
+namespace {
+constexpr int LIB_DEVICES = 64;
+std::mutex g_lib_stream_mu;
+hipStream_t g_lib_stream[LIB_DEVICES][LIB_STREAMS] = {};
+}  // namespace
+
+hipStream_t library_stream(int k) {
+    int dev = 0;
+    FS_HIP(hipGetDevice(&dev));
+    FS_REQUIRE(dev >= 0 && dev < LIB_DEVICES, FS_EUNSUPPORTED, "device index %d out of range", dev);
+    FS_REQUIRE(k >= 0 && k < LIB_STREAMS, FS_EINVAL, "library stream %d out of range", k);
+    std::lock_guard<std::mutex> lk(g_lib_stream_mu);
+    if (!g_lib_stream[dev][k])
+        FS_HIP(hipStreamCreateWithFlags(&g_lib_stream[dev][k], hipStreamNonBlocking));
+    return g_lib_stream[dev][k];
+}
+
 // ------------------------------------------------------------------ fills
 template <class T>
 __global__ void k_fill(T *p, int64_t n, T v) {
