@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <thread>
 
 #include "solver.h"
@@ -88,19 +89,31 @@ void run_three(hipStream_t s, F0 &&f0, F1 &&f1, F2 &&f2) {
             FS_HIP(e2);
         }
     }
-    std::thread t1([&] { side(f1, s1, r1); });
-    std::thread t2([&] { side(f2, s2, r2); });
+    // every thread that was started is joined, whatever throws (a thread that cannot be
+    // started leaves its piece to this thread)
+    std::thread t1, t2;
+    auto join_all = [&] {
+        if (t1.joinable()) t1.join();
+        if (t2.joinable()) t2.join();
+        (void)hipEventDestroy(ready);
+    };
     try {
+        try {
+            t1 = std::thread([&] { side(f1, s1, r1); });
+        } catch (const std::system_error &) {
+            side(f1, s1, r1);
+        }
+        try {
+            t2 = std::thread([&] { side(f2, s2, r2); });
+        } catch (const std::system_error &) {
+            side(f2, s2, r2);
+        }
         f0(s);
     } catch (...) {
-        t1.join();
-        t2.join();
-        (void)hipEventDestroy(ready);
+        join_all();
         throw;
     }
-    t1.join();
-    t2.join();
-    (void)hipEventDestroy(ready);
+    join_all();
     for (const Result *r : {&r1, &r2})
         if (r->code != FS_OK) {
             set_error("%s", r->msg.c_str());

@@ -521,9 +521,9 @@ def test_deterministic_mode_is_bitwise_reproducible(case):
 def test_failure_paths_report_and_recover(monkeypatch):
     """Failure handling, forced from the host: (1) zero source weights make every Sinkhorn kernel
     sum zero, so the update's count of non-positive sums reports FS_ENUMERIC (fast fused path,
-    fast path with the near field, direct path); (2) the workspace limit of the failure-injection
-    hook refuses an allocation inside the plan build, reported as FS_ENOMEM.  After each failure
-    the library still computes correct sums."""
+    fast path with the near field, direct path), also from the side-by-side terms of a divergence;
+    (2) the workspace limit of the failure-injection hook refuses an allocation inside the plan
+    build, reported as FS_ENOMEM.  After each failure the library still computes correct sums."""
     w = synth.make("uot_d3_n1M", n=20_000, m=18_000)
     x, a, y = T(w["x"]), T(w["a"]), T(w["y"])
     zero = torch.zeros(18_000, dtype=torch.float32, device=DEV)
@@ -532,6 +532,10 @@ def test_failure_paths_report_and_recover(monkeypatch):
         lam = 0.02 if kw["kernel"] == "gauss" else 0.01
         with pytest.raises(fu.FastsumError, match="status -5"):
             fu.uot_sinkhorn(x, a, y, zero, lam, 1.0, 3, **kw)
+    # the divergence's terms run in three threads: the failing (b, b) term reports from its own
+    # thread, and the call returns only after all three have ended
+    with pytest.raises(fu.FastsumError, match="status -5"):
+        fu.sinkhorn_divergence(x, a, y, zero, 0.02, 1.0, 3, kernel="gauss", grid=64, window=6)
     monkeypatch.setenv("FASTUOT_WORKSPACE_LIMIT", str(1 << 20))
     with pytest.raises(fu.FastsumError, match="status -3.*FASTUOT_WORKSPACE_LIMIT"):
         fu.fastsum_apply(x, y, T(w["b"]), kernel="gauss", lam=0.02, grid=64, window=6)
