@@ -244,8 +244,9 @@ int sinkhorn_divergence(const float *x, const float *a, int64_t n, const float *
 
 /* Gradient of the Sinkhorn divergence from the potentials written by sinkhorn_divergence
  * (the symmetric problems contribute twice their one-slot envelope gradient), scaled by `scale`.
- * The three envelope gradients run side by side as the three problems do in
- * sinkhorn_divergence; the call returns when the gradients are written. */
+ * The envelope gradients run side by side as the three problems do in sinkhorn_divergence
+ * (the (a,b) term's two sides and the two self terms, on `stream` and three library streams);
+ * the call returns when the gradients are written. */
 int sinkhorn_divergence_grad(const float *x, const float *a, int64_t n, const float *y,
                              const float *b, int64_t m, int d, const fs_params *p, double rho,
                              const double *f_ab, const double *g_ab, const double *f_aa,

@@ -2,6 +2,7 @@
 // Every entry point validates its arguments, runs the work on the caller's stream, converts
 // internal failures (fs::Error) into a negative fs_status and records the message.
 #include <algorithm>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <system_error>
@@ -47,77 +48,77 @@ char *noalloc_scratch() {
     return static_cast<char *>(g_scratch_dev[dev]);
 }
 
-// Runs three independent pieces of work: f0 on the caller's stream s in this thread, f1 and f2
-// on library streams 0 and 1 in threads of their own (the current device made current there).
-// The side streams first wait for the work queued on s so far.  Each piece synchronises its own
-// stream before it returns, so all three have finished on return; an error in a side piece is
-// raised here with its status and message after every piece has ended.
-template <class F0, class F1, class F2>
-void run_three(hipStream_t s, F0 &&f0, F1 &&f1, F2 &&f2) {
+// Runs independent pieces of work side by side: pieces[0] on the caller's stream s in this
+// thread, pieces[k] (k >= 1) on library stream k - 1 in a thread of its own (the current device
+// made current there).  The library streams first wait for the work queued on s so far.  Each
+// piece synchronises its own stream before it returns, so all have finished on return; an error
+// in a side piece is raised here with its status and message after every piece has ended.
+using Piece = std::function<void(hipStream_t)>;
+
+void run_side_by_side(hipStream_t s, const std::vector<Piece> &pieces) {
+    const int np = (int)pieces.size();
+    FS_REQUIRE(np >= 1 && np <= 1 + LIB_STREAMS, FS_EINVAL, "%d pieces of work", np);
     int dev = 0;
     FS_HIP(hipGetDevice(&dev));
-    hipStream_t s1 = library_stream(0), s2 = library_stream(1);
+    std::vector<hipStream_t> st(np, s);
+    for (int k = 1; k < np; ++k) st[k] = library_stream(k - 1);
     hipEvent_t ready = nullptr;
     FS_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     struct Result {
         int code = FS_OK;
         std::string msg;
     };
-    Result r1, r2;
-    auto side = [dev](auto &f, hipStream_t st, Result &r) {
+    std::vector<Result> res(np);
+    auto side = [&](int k) {
         try {
             clear_error();
             FS_HIP(hipSetDevice(dev));
-            f(st);
+            pieces[k](st[k]);
         } catch (const Error &e) {
-            r.code = e.code;
-            r.msg = last_error();
+            res[k].code = e.code;
+            res[k].msg = last_error();
         } catch (const std::bad_alloc &) {
-            r.code = FS_ENOMEM;
-            r.msg = "host allocation failed";
+            res[k].code = FS_ENOMEM;
+            res[k].msg = "host allocation failed";
         } catch (...) {
-            r.code = FS_EHIP;
-            r.msg = "unexpected internal error";
+            res[k].code = FS_EHIP;
+            res[k].msg = "unexpected internal error";
         }
     };
     {
-        const hipError_t e0 = hipEventRecord(ready, s);
-        const hipError_t e1 = (e0 == hipSuccess) ? hipStreamWaitEvent(s1, ready, 0) : e0;
-        const hipError_t e2 = (e1 == hipSuccess) ? hipStreamWaitEvent(s2, ready, 0) : e1;
-        if (e2 != hipSuccess) {
+        hipError_t e = hipEventRecord(ready, s);
+        for (int k = 1; k < np && e == hipSuccess; ++k) e = hipStreamWaitEvent(st[k], ready, 0);
+        if (e != hipSuccess) {
             (void)hipEventDestroy(ready);
-            FS_HIP(e2);
+            FS_HIP(e);
         }
     }
-    // every thread that was started is joined, whatever throws (a thread that cannot be
-    // started leaves its piece to this thread)
-    std::thread t1, t2;
+    // every thread that was started is joined, whatever throws (a thread that cannot be started
+    // leaves its piece to this thread)
+    std::vector<std::thread> th(np);
     auto join_all = [&] {
-        if (t1.joinable()) t1.join();
-        if (t2.joinable()) t2.join();
+        for (auto &t : th)
+            if (t.joinable()) t.join();
         (void)hipEventDestroy(ready);
     };
     try {
-        try {
-            t1 = std::thread([&] { side(f1, s1, r1); });
-        } catch (const std::system_error &) {
-            side(f1, s1, r1);
+        for (int k = 1; k < np; ++k) {
+            try {
+                th[k] = std::thread(side, k);
+            } catch (const std::system_error &) {
+                side(k);
+            }
         }
-        try {
-            t2 = std::thread([&] { side(f2, s2, r2); });
-        } catch (const std::system_error &) {
-            side(f2, s2, r2);
-        }
-        f0(s);
+        pieces[0](s);
     } catch (...) {
         join_all();
         throw;
     }
     join_all();
-    for (const Result *r : {&r1, &r2})
-        if (r->code != FS_OK) {
-            set_error("%s", r->msg.c_str());
-            throw Error{r->code};
+    for (int k = 1; k < np; ++k)
+        if (res[k].code != FS_OK) {
+            set_error("%s", res[k].msg.c_str());
+            throw Error{res[k].code};
         }
 }
 
@@ -502,17 +503,16 @@ int sinkhorn_divergence(const float *x, const float *a, int64_t n, const float *
         double *faa = f_aa ? f_aa : t3.p, *fbb = f_bb ? f_bb : t5.p;
         // the three transport problems are independent: they run side by side
         double uab = 0.0, uaa = 0.0, ubb = 0.0;
-        run_three(
-            s,
-            [&](hipStream_t st) {
-                uab = solve_uot(x, a, n, y, b, m, d, q, rho, iters, false, fab, gab, st);
-            },
-            [&](hipStream_t st) {
-                uaa = solve_uot(x, a, n, x, a, n, d, q, rho, iters, false, faa, t4.p, st);
-            },
-            [&](hipStream_t st) {
-                ubb = solve_uot(y, b, m, y, b, m, d, q, rho, iters, false, fbb, t6.p, st);
-            });
+        run_side_by_side(
+            s, {[&](hipStream_t st) {
+                    uab = solve_uot(x, a, n, y, b, m, d, q, rho, iters, false, fab, gab, st);
+                },
+                [&](hipStream_t st) {
+                    uaa = solve_uot(x, a, n, x, a, n, d, q, rho, iters, false, faa, t4.p, st);
+                },
+                [&](hipStream_t st) {
+                    ubb = solve_uot(y, b, m, y, b, m, d, q, rho, iters, false, fbb, t6.p, st);
+                }});
         const double Ma = device_sum(a, n, s), Mb = device_sum(b, m, s);
         // eq. (586) with the paper's 1/lambda equal to the temperature lambda here
         const double val = uab - 0.5 * uaa - 0.5 * ubb + 0.5 * p->lambda * (Ma - Mb) * (Ma - Mb);
@@ -549,30 +549,38 @@ int sinkhorn_divergence_grad(const float *x, const float *a, int64_t n, const fl
         // symmetric optimum is twice the one-slot envelope gradient, so the 1/2 cancels.
         DevBuf<float> gx1(n * d + 1), ga1(n + 1), gx2(n * d + 1), ga2(n + 1);
         DevBuf<float> gy1(m * d + 1), gb1(m + 1), gy2(m * d + 1), gb2(m + 1);
-        // the three envelope gradients are independent: they run side by side
-        run_three(
-            s,
-            [&](hipStream_t st) {
-                auto op = make_op(x, n, y, m, d, *p, st);
-                uot_grad_core(*op, a, b, f_ab, g_ab, eps, rho, 1.0, dx ? gx1.p : nullptr,
-                              da ? ga1.p : nullptr, dy ? gy1.p : nullptr, db ? gb1.p : nullptr,
-                              st);
-                FS_HIP(hipStreamSynchronize(st));
-            },
-            [&](hipStream_t st) {
-                if (!(dx || da)) return;
-                auto op = make_op(x, n, x, n, d, *p, st);
-                uot_grad_core(*op, a, a, f_aa, f_aa, eps, rho, 1.0, dx ? gx2.p : nullptr,
-                              da ? ga2.p : nullptr, nullptr, nullptr, st);
-                FS_HIP(hipStreamSynchronize(st));
-            },
-            [&](hipStream_t st) {
-                if (!(dy || db)) return;
-                auto op = make_op(y, m, y, m, d, *p, st);
-                uot_grad_core(*op, b, b, f_bb, f_bb, eps, rho, 1.0, dy ? gy2.p : nullptr,
-                              db ? gb2.p : nullptr, nullptr, nullptr, st);
-                FS_HIP(hipStreamSynchronize(st));
-            });
+        // the envelope gradients are independent: the (a, b) term's two sides (each with an
+        // operator of its own, as one plan may not be applied from two streams at once) and the
+        // two self terms run side by side
+        run_side_by_side(
+            s, {[&](hipStream_t st) {
+                    if (!(dx || da)) return;
+                    auto op = make_op(x, n, y, m, d, *p, st);
+                    uot_grad_core(*op, a, b, f_ab, g_ab, eps, rho, 1.0, dx ? gx1.p : nullptr,
+                                  da ? ga1.p : nullptr, nullptr, nullptr, st);
+                    FS_HIP(hipStreamSynchronize(st));
+                },
+                [&](hipStream_t st) {
+                    if (!(dy || db)) return;
+                    auto op = make_op(x, n, y, m, d, *p, st);
+                    uot_grad_core(*op, a, b, f_ab, g_ab, eps, rho, 1.0, nullptr, nullptr,
+                                  dy ? gy1.p : nullptr, db ? gb1.p : nullptr, st);
+                    FS_HIP(hipStreamSynchronize(st));
+                },
+                [&](hipStream_t st) {
+                    if (!(dx || da)) return;
+                    auto op = make_op(x, n, x, n, d, *p, st);
+                    uot_grad_core(*op, a, a, f_aa, f_aa, eps, rho, 1.0, dx ? gx2.p : nullptr,
+                                  da ? ga2.p : nullptr, nullptr, nullptr, st);
+                    FS_HIP(hipStreamSynchronize(st));
+                },
+                [&](hipStream_t st) {
+                    if (!(dy || db)) return;
+                    auto op = make_op(y, m, y, m, d, *p, st);
+                    uot_grad_core(*op, b, b, f_bb, f_bb, eps, rho, 1.0, dy ? gy2.p : nullptr,
+                                  db ? gb2.p : nullptr, nullptr, nullptr, st);
+                    FS_HIP(hipStreamSynchronize(st));
+                }});
         if (dx) combine(gx1.p, gx2.p, n * d, scale, -scale, 0.0, dx, s);
         if (da) combine(ga1.p, ga2.p, n, scale, -scale, scale * eps * (Ma - Mb), da, s);
         if (dy) combine(gy1.p, gy2.p, m * d, scale, -scale, 0.0, dy, s);

@@ -147,9 +147,10 @@ inline unsigned blocks_for(int64_t work, int threads, int64_t cap = 1 << 20) {
 }
 
 // Streams the library keeps per device (default priority, not synchronising with the null
-// stream), created on first use: they carry the self terms of a Sinkhorn divergence.  Work on
-// them is ordered against the caller's stream by events.
-constexpr int LIB_STREAMS = 2;
+// stream), created on first use: they carry the independent pieces of a Sinkhorn divergence
+// (its self terms, and in the backward its gradients) beside the caller's stream.  Work on them
+// is ordered against the caller's stream by events.
+constexpr int LIB_STREAMS = 3;
 hipStream_t library_stream(int k);
 
 // Device fill (used instead of hipMemsetAsync so that callers may capture the work in a graph).
