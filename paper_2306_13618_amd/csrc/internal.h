@@ -146,6 +146,27 @@ inline unsigned blocks_for(int64_t work, int threads, int64_t cap = 1 << 20) {
     return static_cast<unsigned>(b);
 }
 
+// Several device-to-device copies in one launch (byte counts multiples of 4): ranges collected
+// by add(), copied by launch() (also called by add() when the batch is full).
+class CopyBatch {
+public:
+    static constexpr int MAX = 8;
+    struct Args {
+        const void *src[MAX];
+        void *dst[MAX];
+        int64_t words[MAX];
+        int k;
+    };
+    explicit CopyBatch(hipStream_t s) : s_(s) { a_.k = 0; }
+    void add(void *dst, const void *src, size_t bytes);
+    void launch();
+
+private:
+    hipStream_t s_;
+    Args a_;
+    int64_t nmax_ = 0;
+};
+
 // Streams the library keeps per device (default priority, not synchronising with the null
 // stream), created on first use: they carry the independent pieces of a Sinkhorn divergence
 // (its self terms, and in the backward its gradients) beside the caller's stream.  Work on them

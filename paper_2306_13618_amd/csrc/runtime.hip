@@ -347,6 +347,36 @@ void profile_reset() {
     p.totals.clear();
 }
 
+// ------------------------------------------------------------------ batched copies
+__global__ void k_copy_batch(CopyBatch::Args a) {
+    const int r = blockIdx.y;
+    const uint32_t *src = static_cast<const uint32_t *>(a.src[r]);
+    uint32_t *dst = static_cast<uint32_t *>(a.dst[r]);
+    const int64_t n = a.words[r];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+void CopyBatch::add(void *dst, const void *src, size_t bytes) {
+    FS_REQUIRE(bytes % 4 == 0, FS_EINVAL, "batched copy of %zu bytes", bytes);
+    if (bytes == 0) return;
+    if (a_.k == MAX) launch();
+    a_.src[a_.k] = src;
+    a_.dst[a_.k] = dst;
+    a_.words[a_.k] = (int64_t)(bytes / 4);
+    nmax_ = std::max(nmax_, a_.words[a_.k]);
+    ++a_.k;
+}
+void CopyBatch::launch() {
+    if (a_.k == 0) return;
+    hipLaunchKernelGGL(k_copy_batch, dim3(blocks_for(nmax_, 256, 2048), a_.k), dim3(256), 0, s_,
+                       a_);
+    FS_LAUNCHED();
+    a_.k = 0;
+    nmax_ = 0;
+}
+
 // ------------------------------------------------------------------ library streams
 namespace {
 constexpr int LIB_DEVICES = 64;

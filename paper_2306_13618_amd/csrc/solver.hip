@@ -1150,6 +1150,44 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
     // with a tolerance, a sweep that changes no potential by more than tol * eps ends the solve
     const bool track = tol > 0.0;
     double *fd = track ? sc.dparts.p : nullptr, *gd = track ? sc.dparts.p + UPD_BLOCKS : nullptr;
+    // On fused half-steps the change of each sweep is read back one sweep late: sweep it + 1 is
+    // queued before the change of sweep it arrives, and the state after sweep it (both potentials,
+    // their per-block maxima and the count of non-positive sums) is kept, so that a sweep found to
+    // follow a converged one is undone.  The solve stops at the same sweep with the same state as
+    // with a check after every sweep, without the device draining each time.
+    const bool lag = track && fuseX && fuseY;
+    DevBuf<double> snapF(lag ? n + 1 : 0), snapG(lag ? m + 1 : 0);
+    DevBuf<double> snapP(lag ? 2 * UPD_BLOCKS : 0);
+    DevBuf<int> snapB(lag ? 1 : 0);
+    HostStage stage(s);
+    double *hchange = lag ? static_cast<double *>(stage.pinned(2 * sizeof(double))) : nullptr;
+    struct EventPair {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~EventPair() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    if (lag)
+        for (hipEvent_t &x : ev.e) FS_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    auto copy_state = [&](bool save) {
+        CopyBatch cb(s);
+        const size_t parts = UPD_BLOCKS * sizeof(double);
+        if (save) {
+            cb.add(snapF.p, f_o, n * sizeof(double));
+            cb.add(snapG.p, g_o, m * sizeof(double));
+            cb.add(snapP.p, sc.fparts.p, parts);
+            cb.add(snapP.p + UPD_BLOCKS, sc.gparts.p, parts);
+            cb.add(snapB.p, sc.nbad.p, sizeof(int));
+        } else {
+            cb.add(f_o, snapF.p, n * sizeof(double));
+            cb.add(g_o, snapG.p, m * sizeof(double));
+            cb.add(sc.fparts.p, snapP.p, parts);
+            cb.add(sc.gparts.p, snapP.p + UPD_BLOCKS, parts);
+            cb.add(sc.nbad.p, snapB.p, sizeof(int));
+        }
+        cb.launch();
+    };
     int done = 0;
     for (int it = 0; it < iters; ++it) {
         // beta half-step (Delta odd): t_i = sum_j k_ij b_j e^{g_j/eps}, then the f update
@@ -1211,7 +1249,24 @@ void sinkhorn_solve(Op &op, const float *a_o, const float *b_o, double eps, doub
                                       sc.nbad.p, gd, s);
         }
         ++done;
-        if (track) {
+        if (lag) {
+            hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.dparts.p, 2 * UPD_BLOCKS,
+                               sc.v.p + 24);
+            FS_LAUNCHED();
+            FS_HIP(hipMemcpyAsync(hchange + it % 2, sc.v.p + 24, sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            FS_HIP(hipEventRecord(ev.e[it % 2], s));
+            if (it > 0) {
+                // the previous sweep's change (it arrives while this sweep runs)
+                FS_HIP(hipEventSynchronize(ev.e[(it - 1) % 2]));
+                if (hchange[(it - 1) % 2] <= tol * eps) {
+                    copy_state(false);  // back to the state after the converged sweep
+                    --done;
+                    break;
+                }
+            }
+            if (it + 1 < iters) copy_state(true);
+        } else if (track) {
             hipLaunchKernelGGL(k_max_final, dim3(1), dim3(RT), 0, s, sc.dparts.p, 2 * UPD_BLOCKS,
                                sc.v.p + 24);
             FS_LAUNCHED();

@@ -852,6 +852,33 @@ def test_uot_scaling_single_stage_is_uot_sinkhorn():
     assert relinf(g1.cpu().numpy(), g2.cpu().numpy()) < 1e-12 and abs(o1 - o2) < 1e-12 * abs(o2)
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_tolerance_stop_is_the_fixed_sweep_solve(d):
+    """A solve that stops on its tolerance after k sweeps ends in the state of the solve of exactly
+    k sweeps, bit for bit in deterministic mode.  On fused half-steps (matrix-core clusters) the
+    change of a sweep is read back one sweep late and the sweep queued meanwhile is undone, so
+    this pins the stop sweep, the restored potentials and the objective."""
+    flags = fu.FLAG_DETERMINISTIC
+    if d == 2:
+        x, y, _ = dense_and_sparse_2d(30_000, 27_003, 51, frac=0.95)
+        kw = dict(kernel="gauss", grid=128, window=6)
+        eps, rho = 0.01, 0.5
+    else:
+        x, y, _ = dense_and_sparse(20_000, 18_001, 52, frac=0.95)
+        kw = dict(kernel="gauss", grid=64, window=6)
+        eps, rho = 0.02, 1.0
+    rng = np.random.default_rng(53)
+    a = rng.uniform(0.5, 1.5, len(x)).astype(np.float32)
+    b = rng.uniform(0.5, 1.5, len(y)).astype(np.float32)
+    a, b = (a / a.sum()).astype(np.float32), (1.2 * b / b.sum()).astype(np.float32)
+    args = (T(x), T(a), T(y), T(b))
+    f1, g1, counts, o1 = fu.uot_sinkhorn_scaling(*args, [eps], rho, 400, 1e-3, flags=flags, **kw)
+    k = counts[0]
+    assert 2 < k < 400  # stopped by the tolerance, with sweeps queued ahead of the check
+    f2, g2, o2 = fu.uot_sinkhorn(*args, eps, rho, k, flags=flags, **kw)
+    assert torch.equal(f1, f2) and torch.equal(g1, g2) and o1 == o2
+
+
 def test_uot_warm_start_continues_the_iteration():
     w = synth.make("uot_d1_n2k", n=700, m=650)
     x, a, y, b = (T(w[k]) for k in ("x", "a", "y", "b"))
